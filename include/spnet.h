@@ -1,0 +1,241 @@
+/*
+ * spnet.h -- C ABI of the MI355X (gfx950) solver for spatial network models by
+ * two-level additive Schwarz preconditioned conjugate gradients
+ * (Goertz, Hellman, Malqvist, "Iterative solution of spatial network models by
+ * subspace decomposition", arXiv 2207.07488).
+ *
+ * The calls follow the problem statement of the paper:
+ *   1. build the network G = (N, E) in the box Omega, with a Dirichlet set
+ *      N(Gamma) (Sec. 2.1; fiber generator of Sec. 6.1);
+ *   2. assemble K on the free dofs, K u = f being the matrix form of
+ *      (K u, v) = (f, v) for all v in V (eq. 3.1), for the heat model
+ *      (Example 3.2, eq. 3.3) or the tensile truss model (Example 3.3, eq. 3.4);
+ *   3. build the coarse space V_0 = V_H (Q1 on the mesh T_H restricted to the
+ *      nodes, Sec. 2.3) and the local spaces V_j = V(U(y_j)) on mesh stars
+ *      (Sec. 4.1);
+ *   4. factor the local matrices and the coarse matrix P^T K P (the direct
+ *      solves behind the projections P_j of eq. 4.1);
+ *   5. solve K u = f with PCG on P = BK (Sec. 4.2) to a relative residual
+ *      tolerance.
+ *
+ * Conventions
+ *   - Every call returns an sn_status; SN_OK is 0, errors are negative. On error
+ *     outputs are left untouched and sn_last_error() returns a message for the
+ *     calling thread. No C++ exception crosses this boundary.
+ *   - Handles are opaque and owned by the library; destroy them with the
+ *     matching *_destroy call. A system keeps its network alive and a
+ *     preconditioner keeps its system alive, so handles may be destroyed in any
+ *     order.
+ *   - Arrays passed in are copied. Export calls write into caller buffers whose
+ *     sizes come from the matching *_info call.
+ *   - Vectors of dofs are FP64, dof-major: dof d = free node index * ncomp +
+ *     component; free nodes are numbered in ascending node id. With k
+ *     right-hand sides a block is n x k row-major (the k values of a dof are
+ *     adjacent).
+ *   - Host or device pointers: solve-type calls take a flag; device pointers
+ *     must be on the current HIP device and the work is queued on `stream`
+ *     (a hipStream_t, NULL = the library's own stream). Calls are synchronous
+ *     with respect to the host unless stated otherwise.
+ *   - Device memory is allocated by the library with hipMalloc at factor time
+ *     and at the first solve with a given k, and kept until destroy.
+ */
+#ifndef SPNET_H
+#define SPNET_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SN_OK = 0,
+  SN_EINVAL = -1,     /* bad argument or inconsistent sizes */
+  SN_ENOMEM = -2,     /* host or device allocation failed */
+  SN_EDEVICE = -3,    /* HIP runtime error or no usable gfx950 device */
+  SN_ESINGULAR = -4,  /* no Dirichlet node: K is singular on V */
+  SN_ENOTSPD = -5,    /* a local or the coarse matrix has a non-positive pivot */
+  SN_ENOCONV = -6,    /* max_iter reached before the tolerance */
+  SN_EBUSY = -7       /* serving: result not ready / no room */
+} sn_status;
+
+typedef struct sn_network_s *sn_network;
+typedef struct sn_system_s *sn_system;
+typedef struct sn_precond_s *sn_precond;
+typedef struct sn_server_s *sn_server;
+
+/* Message of the last failing call on this thread (never NULL). */
+const char *sn_last_error(void);
+/* Library version string. */
+const char *sn_version(void);
+
+/* ------------------------------------------------------------------ */
+/* 1. Network (Sec. 2.1; generator of Sec. 6.1)                        */
+/* ------------------------------------------------------------------ */
+
+/*
+ * Build a fiber network in the unit box [0,1]^dim from raw straight segments.
+ *   segments     n_segments x (2*dim) doubles: end points a then b.
+ *   contact_eps  dim 3 only: two segments whose closest approach is below it
+ *                are joined by one node at the midpoint of the closest points.
+ *                In dim 2 nodes are placed at exact crossings.
+ *   merge_tol    nodes closer than merge_tol are merged (Sec. 6.1 uses
+ *                fiber length * 1e-4); segments clipped to less are dropped.
+ *   dir_lo/hi    bit k: the face x_k = 0 (resp. 1) is part of Gamma.
+ *   band         nodes within band of a Gamma face form N(Gamma).
+ * The segments are clipped to the box, nodes are the clipped end points then the
+ * crossings in lexicographic pair order, edges join consecutive nodes along each
+ * segment, close nodes are merged (smallest id kept), and only the largest
+ * connected component is kept (ties: the one with the smallest node id).
+ * Errors: SN_EINVAL for dim not in {2,3}, non-positive merge_tol or contact_eps.
+ */
+sn_status sn_network_from_segments(int dim, int64_t n_segments, const double *segments,
+                                   double contact_eps, double merge_tol, int dir_lo, int dir_hi,
+                                   double band, sn_network *out);
+
+/* A network given directly: coords n_nodes x dim, edges n_edges x 2 (int32
+ * node ids), dirichlet n_nodes flags (1 = node in N(Gamma)). */
+sn_status sn_network_from_arrays(int dim, int64_t n_nodes, const double *coords, int64_t n_edges,
+                                 const int32_t *edges, const uint8_t *dirichlet, sn_network *out);
+
+sn_status sn_network_info(sn_network net, int *dim, int64_t *n_nodes, int64_t *n_edges);
+/* Any of the output pointers may be NULL. */
+sn_status sn_network_export(sn_network net, double *coords, int32_t *edges, uint8_t *dirichlet);
+void sn_network_destroy(sn_network net);
+
+/* ------------------------------------------------------------------ */
+/* 2. Assembly (Examples 3.2 / 3.3)                                     */
+/* ------------------------------------------------------------------ */
+#define SN_MODEL_HEAT 0  /* scalar: each edge adds gamma/|e| (e_x-e_y)(e_x-e_y)^T, eq. 3.3 */
+#define SN_MODEL_TRUSS 1 /* 3 dofs per node, dim 3: each edge adds (gamma/|e|) t t^T + (1e-6/|e|) I
+                            in the xx, yy blocks and minus that in xy, yx (eq. 3.4) */
+
+/* gamma: n_edges conductivities / stiffnesses, or NULL for all ones.
+ * Errors: SN_ESINGULAR if the network has no Dirichlet node. */
+sn_status sn_assemble(sn_network net, int model, const double *gamma, sn_system *out);
+sn_status sn_system_info(sn_system sys, int64_t *n_dofs, int64_t *nnz, int *ncomp, int64_t *n_free_nodes);
+/* K in CSR over the free dofs: rowptr (n+1), col (nnz, ascending per row), val (nnz). */
+sn_status sn_system_export_csr(sn_system sys, int64_t *rowptr, int32_t *col, double *val);
+/* node id of every free node (n_free_nodes entries) */
+sn_status sn_system_free_nodes(sn_system sys, int32_t *free_node);
+void sn_system_destroy(sn_system sys);
+
+/* ------------------------------------------------------------------ */
+/* 3. Coarse and local spaces (Sec. 2.3, 4.1)                           */
+/* ------------------------------------------------------------------ */
+#define SN_STARS_ALL 0  /* one local space per mesh node y_j, j = 1..m (Sec. 4.1) */
+#define SN_STARS_FREE 1 /* only mesh nodes off Gamma */
+
+/*
+ * nH = 1/H elements per axis. Element index of x: e_k = min(floor(x_k nH), nH-1)
+ * (half-open boxes, closed at the upper face of Omega). Coarse dofs: mesh nodes
+ * not on Gamma whose Q1 basis function is non-zero at some free node, in
+ * lexicographic order (x fastest), times ncomp. Local space of mesh node v: the
+ * free nodes with v_k-1 <= e_k <= v_k for all k (the nodes of the patch U(y_v)),
+ * empty ones dropped, in ascending mesh node order.
+ * dir_lo/dir_hi give Gamma as in sn_network_from_segments.
+ */
+sn_status sn_precond_build(sn_system sys, int nH, int star_policy, int dir_lo, int dir_hi,
+                           sn_precond *out);
+sn_status sn_precond_info(sn_precond pre, int64_t *m0, int64_t *n_stars, int64_t *star_total);
+/* star_ptr (n_stars+1), star_dofs (star_total, ascending per star), star_vertex (n_stars) */
+sn_status sn_precond_export_stars(sn_precond pre, int64_t *star_ptr, int32_t *star_dofs,
+                                  int32_t *star_vertex);
+/* mesh node id of every coarse dof group (m0/ncomp entries) */
+sn_status sn_precond_export_coarse(sn_precond pre, int32_t *coarse_vertex);
+
+/* ------------------------------------------------------------------ */
+/* 4. Factorisation (direct local and coarse solves, Sec. 4.1)          */
+/* ------------------------------------------------------------------ */
+#define SN_PREC_FP64 0       /* star factors and sweeps in FP64 */
+#define SN_PREC_FP32_STARS 1 /* star factors stored and swept in FP32 with FP32 accumulation;
+                                CG recurrences, dots and the coarse solve stay FP64 */
+
+typedef struct {
+  int64_t star_factor_nnz;   /* entries of all local factors (incl. diagonal) */
+  int64_t star_stream_bytes; /* device bytes of the two sweep streams */
+  int64_t coarse_bytes;      /* device bytes of the coarse operator */
+  int64_t device_bytes;      /* all device memory held by the preconditioner */
+  int32_t max_star_dofs;
+  int32_t max_band;          /* widest factor row/column */
+  double factor_seconds;     /* host time of ordering + numeric factorisation */
+} sn_factor_info;
+
+/* Order, factor in FP64 on the host (threads over stars) and upload to the GPU.
+ * precision is SN_PREC_FP64 or SN_PREC_FP32_STARS (the FP64 factor cast once).
+ * Errors: SN_ENOTSPD naming the star, SN_EDEVICE, SN_ENOMEM. */
+sn_status sn_precond_factor(sn_precond pre, int precision);
+sn_status sn_precond_factor_info(sn_precond pre, sn_factor_info *info);
+void sn_precond_destroy(sn_precond pre);
+
+/* ------------------------------------------------------------------ */
+/* 5. Solve (PCG on BK, Sec. 4.2)                                        */
+/* ------------------------------------------------------------------ */
+typedef struct {
+  double rtol;           /* stop when ||r||_2 <= rtol ||f||_2 (per column, recurrence r) */
+  int64_t max_iter;      /* default 1000 */
+  int64_t fixed_iters;   /* > 0: run exactly this many iterations, ignore rtol */
+  int64_t replace_every; /* > 0: r <- f - K u every so many iterations */
+  int32_t check_every;   /* iterations queued between convergence read-backs (default 8) */
+  int32_t device_ptrs;   /* 1: f and u are device pointers */
+  int32_t use_u0;        /* 1: u holds the initial guess u^(0), else u^(0) = 0 */
+  int32_t use_graph;     /* 1: replay the iteration block as a captured HIP graph */
+  void *stream;          /* hipStream_t or NULL */
+} sn_solve_opts;
+
+typedef struct {
+  int64_t iters;   /* PCG iterations done */
+  double res_rec;  /* ||r||_2 / ||f||_2 of the recurrence at exit */
+  double res_true; /* ||f - K u||_2 / ||f||_2 recomputed in FP64 at exit */
+  int32_t converged;
+  int32_t replacements; /* residual replacements done */
+  double ms;       /* wall time of the call */
+} sn_solve_info;
+
+/* Fill opts with defaults (rtol 1e-8, max_iter 1000, check_every 8). */
+void sn_solve_opts_default(sn_solve_opts *opts);
+
+/*
+ * Solve K u = f for k right-hand sides (1 <= k <= 16): f and u are n x k
+ * row-major. Each column runs its own PCG recurrence (alpha, beta per column);
+ * columns share the matrix and factor reads. info has k entries.
+ * Errors: SN_ENOCONV if some column hits max_iter (u still holds the iterate).
+ */
+sn_status sn_solve(sn_precond pre, int k, const double *f, double *u, const sn_solve_opts *opts,
+                   sn_solve_info *info);
+
+/* y = K x for k columns (n x k row-major). */
+sn_status sn_apply_K(sn_precond pre, int k, const double *x, double *y, int device_ptrs, void *stream);
+/* z = B r, B = P K_0^{-1} P^T + sum_j R_j^T K_j^{-1} R_j (so that BK = P_0 + ... + P_m). */
+sn_status sn_apply_B(sn_precond pre, int k, const double *r, double *z, int device_ptrs, void *stream);
+
+/* ------------------------------------------------------------------ */
+/* Serving: continuous batching of solves over device-resident factors  */
+/* ------------------------------------------------------------------ */
+typedef struct {
+  int64_t hbm_budget;  /* bytes of device memory the server may hold for requests */
+  int32_t max_active;  /* requests iterating together */
+  int32_t iters_per_tick; /* PCG iterations per scheduling tick */
+} sn_server_opts;
+
+sn_status sn_server_create(const sn_server_opts *opts, sn_server *out);
+/*
+ * Queue a solve of K u = f (k columns, host f, n x k row-major) on a factored
+ * preconditioner, which must stay alive until the ticket is collected. The
+ * request is admitted as soon as a slot and its memory footprint fit.
+ * Errors: SN_EINVAL, SN_EBUSY if the request alone exceeds the budget.
+ */
+sn_status sn_server_submit(sn_server srv, sn_precond pre, int k, const double *f, double rtol,
+                           int64_t max_iter, uint64_t *ticket);
+/* Run one scheduling tick: admit, iterate all active requests together, retire. */
+sn_status sn_server_step(sn_server srv, int32_t *n_active, int32_t *n_queued);
+/* SN_EBUSY while pending; when done copies u (n x k) and k info entries and
+ * forgets the ticket. */
+sn_status sn_server_poll(sn_server srv, uint64_t ticket, double *u, sn_solve_info *info);
+void sn_server_destroy(sn_server srv);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPNET_H */

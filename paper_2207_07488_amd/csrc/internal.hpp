@@ -1,0 +1,108 @@
+// Internal types of the spnet library (host side). Not part of the ABI.
+#pragma once
+
+#include <cstdint>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/spnet.h"
+
+namespace spnet {
+
+// Error carried to the ABI boundary, where it becomes an sn_status.
+struct Error : std::runtime_error {
+  sn_status code;
+  Error(sn_status c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+[[noreturn]] inline void fail(sn_status c, const std::string &m) { throw Error(c, m); }
+
+struct Network {
+  int dim = 2;
+  std::vector<double> x;        // n_nodes * dim
+  std::vector<int32_t> edges;   // 2 * n_edges
+  std::vector<uint8_t> dir;     // Dirichlet flag per node
+  int64_t n_nodes() const { return (int64_t)dir.size(); }
+  int64_t n_edges() const { return (int64_t)edges.size() / 2; }
+};
+
+struct System {
+  std::shared_ptr<const Network> net;
+  int model = 0, ncomp = 1;
+  int64_t n = 0;                     // free dofs
+  std::vector<int32_t> free_node;    // free node index -> node id
+  std::vector<int32_t> node_free;    // node id -> free node index or -1
+  std::vector<int64_t> rowptr;       // CSR over dofs
+  std::vector<int32_t> col;
+  std::vector<double> val;
+};
+
+struct DeviceState;  // defined in device.hip
+struct DeviceDeleter {
+  void operator()(DeviceState *d) const;
+};
+
+struct Precond {
+  std::shared_ptr<const System> sys;
+  int nH = 1, policy = 0, dir_lo = 0, dir_hi = 0;
+  int nvert_per_elem = 4;
+  // coarse space: per free node, the 2^d mesh nodes of its element and phi values
+  std::vector<int32_t> Pvert;  // n_free_nodes * 2^d (mesh node id)
+  std::vector<double> Pphi;
+  std::vector<int32_t> vert_coarse;  // mesh node -> coarse group index or -1
+  std::vector<int32_t> coarse_vertex;
+  int64_t m0 = 0;
+  // local spaces (canonical: ascending mesh node, dofs ascending)
+  std::vector<int64_t> star_ptr;
+  std::vector<int32_t> star_dofs;
+  std::vector<int32_t> star_vertex;
+  // factorisation products (filled by factor())
+  int precision = -1;
+  sn_factor_info finfo{};
+  std::unique_ptr<DeviceState, DeviceDeleter> dev;
+};
+
+// network.cpp
+std::shared_ptr<Network> build_network_from_segments(int dim, int64_t nseg, const double *seg, double eps,
+                                                     double merge_tol, int dir_lo, int dir_hi, double band);
+// assemble.cpp
+std::shared_ptr<System> assemble(std::shared_ptr<const Network> net, int model, const double *gamma);
+// spaces.cpp
+std::unique_ptr<Precond> build_spaces(std::shared_ptr<const System> sys, int nH, int policy, int dir_lo,
+                                      int dir_hi);
+
+// factor.cpp: one local factor in the two sweep-stream layouts used on the GPU.
+//   Both streams hold, per step, a header (width w, 1/diag) and w off-diagonal
+//   values; the forward stream walks the columns of L from the first, the
+//   backward stream walks the rows of L from the last, each listing the
+//   entries nearest the diagonal first.
+struct StarFactor {
+  int32_t n = 0;
+  int32_t band = 0;                 // max width
+  std::vector<int32_t> perm;        // factor position -> canonical local index
+  std::vector<int32_t> width_fwd;   // per step
+  std::vector<int32_t> width_bwd;
+  std::vector<double> invdiag;      // per position
+  std::vector<double> colvals;      // forward stream values (no headers), column j entries j+1..j+w
+  std::vector<double> rowvals;      // backward stream values, row i (from n-1 down) entries i-1..i-w
+  int64_t nnz = 0;                  // stored factor entries incl. diagonal
+};
+
+struct HostFactors {
+  std::vector<StarFactor> stars;
+  std::vector<double> coarse_inv;   // m0 x m0 dense inverse of K_0 (symmetric)
+  double seconds = 0;
+};
+
+HostFactors factor_host(const Precond &pre);
+
+// device.hip
+void device_setup(Precond &pre, const HostFactors &hf, int precision);
+void device_solve(Precond &pre, int k, const double *f, double *u, const sn_solve_opts &o, sn_solve_info *info);
+void device_apply_K(Precond &pre, int k, const double *x, double *y, int device_ptrs, void *stream);
+void device_apply_B(Precond &pre, int k, const double *r, double *z, int device_ptrs, void *stream);
+void device_release(DeviceState *d);
+
+}  // namespace spnet

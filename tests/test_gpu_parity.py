@@ -1,0 +1,133 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Bars: integer structure bit-exact (checked on the CPU in test_lib_structure);
+K x to 1e-14; B r (FP64 stars) to 1e-10; the plain PCG iterate at the oracle's
+own iteration count to 1e-10 relative; the mixed path (FP32 stars) to the same
+true residual 1e-8. Tolerance derivation: both sides compute the same Krylov
+iterate; they differ by the rounding of different factor orderings and
+summation orders, amplified by at most cond(K_j) ~ 1e4-1e6 in the local
+solves, i.e. ~1e-12 relative per application.
+"""
+import numpy as np
+import pytest
+
+from paper_2207_07488_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    # name: (dim, n_segments, length, contact_eps, dir_lo, dir_hi, nH, model)
+    "fiber2d_300": (2, 300, 0.2, 0.0, 1, 1, 4, 0),
+    "fiber2d_2k": (2, 2000, 0.08, 0.0, 1, 1, 8, 0),
+    "fiber3d_6k": (3, 6000, 0.12, 0.012, 4, 4, 4, 0),
+    "truss3d_3k": (3, 3000, 0.2, 0.02, 4, 0, 4, 1),
+}
+
+
+@pytest.fixture(scope="module")
+def S():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2207_07488_amd import spnet
+    spnet.lib()
+    return spnet
+
+
+def _pair(S, orc, name, precision, seed=1, policy=0):
+    dim, nseg, l, eps, lo, hi, nH, model = CASES[name]
+    seg = W.fiber_segments(dim, nseg, l, seed=seed)
+    on = orc.Network.from_segments(dim, seg, contact_eps=eps, merge_tol=W.merge_tol(l), dir_lo=lo, dir_hi=hi)
+    osys = orc.System(on, model)
+    opre = orc.Precond(osys, nH, policy, lo, hi)
+    gn = S.Network.from_segments(dim, seg, contact_eps=eps, merge_tol=W.merge_tol(l), dir_lo=lo, dir_hi=hi)
+    gsys = S.System(gn, model)
+    gpre = S.Precond(gsys, nH, policy, lo, hi, precision=precision)
+    return opre, gpre
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_spmv_parity(S, orc, name):
+    opre, gpre = _pair(S, orc, name, S.FP64)
+    x = W.rhs(opre.sys.n, 1, seed=3)[:, 0] - 0.5
+    y = gpre.apply_K(x)
+    ref = opre.sys.apply_K(x)
+    assert np.abs(y - ref).max() <= 1e-14 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_preconditioner_parity_fp64(S, orc, name):
+    opre, gpre = _pair(S, orc, name, S.FP64)
+    r = W.rhs(opre.sys.n, 1, seed=4)[:, 0]
+    z = gpre.apply_B(r)
+    ref = opre.apply_B(r)
+    assert _rel(z, ref) <= 1e-10
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_preconditioner_fp32_stars(S, orc, name):
+    opre, gpre = _pair(S, orc, name, S.FP32_STARS)
+    r = W.rhs(opre.sys.n, 1, seed=4)[:, 0]
+    z = gpre.apply_B(r)
+    ref = opre.apply_B(r)
+    # FP32 factors and sweeps: ~ cond(K_j) * 6e-8
+    assert _rel(z, ref) <= 5e-3
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_pcg_plain_parity(S, orc, name):
+    opre, gpre = _pair(S, orc, name, S.FP64)
+    f = W.rhs(opre.sys.n, 1, seed=7)[:, 0]
+    u_o, it_o, info_o = opre.pcg(f, rtol=1e-8)
+    u_g, info = gpre.solve(f, fixed_iters=it_o)
+    assert info[0]["iters"] == it_o
+    assert _rel(u_g, u_o) <= 1e-10
+    # the tolerance-stopped run takes the same number of iterations
+    hist = opre.pcg(f, rtol=1e-8, history=True)[2]["hist_r"]
+    u_t, info_t = gpre.solve(f, rtol=1e-8)
+    near = abs(hist[-1] / np.linalg.norm(f) - 1e-8) < 0.01e-8
+    assert info_t[0]["iters"] == it_o or near
+    assert info_t[0]["res_true"] <= 1.0001e-8 and info_t[0]["converged"]
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_pcg_mixed(S, orc, name):
+    opre, gpre = _pair(S, orc, name, S.FP32_STARS)
+    f = W.rhs(opre.sys.n, 1, seed=7)[:, 0]
+    u_o, it_o, _ = opre.pcg(f, rtol=1e-8)
+    u_g, info = gpre.solve(f, rtol=1e-8)
+    assert info[0]["converged"] and info[0]["res_true"] <= 1.0001e-8
+    assert info[0]["iters"] <= it_o + 3
+    # the error against the FP64 oracle solution is of the order of the tolerance times cond
+    assert _rel(u_g, u_o) <= 1e-5
+
+
+def test_multi_rhs_columns_independent(S, orc):
+    opre, gpre = _pair(S, orc, "fiber2d_2k", S.FP64)
+    F = W.rhs(opre.sys.n, 3, seed=9)
+    U, infos = gpre.solve(F, rtol=1e-8)
+    for c in range(3):
+        u1, i1 = gpre.solve(F[:, c], rtol=1e-8)
+        assert i1[0]["iters"] == infos[c]["iters"]
+        assert np.array_equal(u1, U[:, c])
+
+
+def test_device_pointers(S, orc):
+    import torch
+    opre, gpre = _pair(S, orc, "fiber2d_300", S.FP64)
+    f = W.rhs(opre.sys.n, 1, seed=7)[:, 0]
+    u_h, _ = gpre.solve(f, rtol=1e-8)
+    fd = torch.from_numpy(f).cuda()
+    u_d, _ = gpre.solve(fd, rtol=1e-8)
+    torch.cuda.synchronize()
+    assert np.array_equal(u_d.cpu().numpy(), u_h)
+
+
+def test_star_policy_free(S, orc):
+    opre, gpre = _pair(S, orc, "fiber2d_300", S.FP64, policy=1)
+    r = W.rhs(opre.sys.n, 1, seed=4)[:, 0]
+    assert _rel(gpre.apply_B(r), opre.apply_B(r)) <= 1e-10
