@@ -1,0 +1,184 @@
+#!/usr/bin/env python3
+"""PCG solves/s at rtol 1e-8 on one MI355X: two-level additive Schwarz PCG on a
+2D fiber network (20,000 segments of length 0.05 in the unit square, Dirichlet
+at x = 0 and x = 1, f uniform[0,1], H = 1/32), FP32-star mixed form against the
+plain FP64 form, with p50/p99 latency per solve.
+
+A step is one full PCG solve (u0 = 0 to ||r|| <= 1e-8 ||f||) of one right-hand
+side already resident in HBM. Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+
+
+def percentile(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    k = (len(xs) - 1) * q
+    lo, hi = int(k), min(int(k) + 1, len(xs) - 1)
+    return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
+
+
+def timed_solves(pre, f, steps, warmup, rtol, profile=False, use_graph=False):
+    import torch
+    from paper_2207_07488_amd import spnet as S
+    for _ in range(warmup):
+        pre.solve(f, rtol=rtol, use_graph=use_graph)
+    torch.cuda.synchronize()
+    if profile:
+        S._check(S.lib().sn_precond_profile(pre.h, 1))
+    lat, iters = [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    u = None
+    for _ in range(steps):
+        a = time.perf_counter()
+        u, info = pre.solve(f, rtol=rtol, use_graph=use_graph)
+        lat.append((time.perf_counter() - a) * 1e3)
+        iters.append(info[0]["iters"])
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    stats = None
+    if profile:
+        st = S.KernelStats()
+        S._check(S.lib().sn_precond_kernel_stats(pre.h, S.C.byref(st)))
+        S._check(S.lib().sn_precond_profile(pre.h, 0))
+        stats = st.asdict()
+    return dict(total_s=total, lat_ms=lat, iters=iters, u=u, info=info, stats=stats)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--nH", type=int, default=32)
+    ap.add_argument("--rtol", type=float, default=1e-8)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic_star_sweep_fiber2d_20k.json"),
+                    help="HBM traffic per sweep launch from rocprofv3 counters (JSON), if present")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2207_07488_amd import spnet as S
+    from paper_2207_07488_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    preset = dict(W.PRESETS["fiber2d_20k"])
+    preset["nH"] = args.nH
+    seg = W.fiber_segments(preset["dim"], preset["n_segments"], preset["length"], preset["seed"])
+    tol = W.merge_tol(preset["length"])
+    t_setup = time.perf_counter()
+    net = S.Network.from_segments(2, seg, merge_tol=tol, dir_lo=preset["dir_lo"], dir_hi=preset["dir_hi"], band=W.BAND)
+    sysm = S.System(net)
+    mixed = S.Precond(sysm, args.nH, S.STARS_ALL, preset["dir_lo"], preset["dir_hi"], precision=S.FP32_STARS)
+    t_setup = time.perf_counter() - t_setup
+    plain = S.Precond(sysm, args.nH, S.STARS_ALL, preset["dir_lo"], preset["dir_hi"], precision=S.FP64)
+    f_host = W.rhs(sysm.n, 1, seed=7)[:, 0]
+    f = torch.from_numpy(f_host).cuda()
+
+    rp = timed_solves(plain, f, args.steps, args.warmup, args.rtol, profile=True)
+    rm = timed_solves(mixed, f, args.steps, args.warmup, args.rtol, profile=True)
+    rg = timed_solves(mixed, f, args.steps, args.warmup, args.rtol, profile=False, use_graph=True)
+    rpg = timed_solves(plain, f, args.steps, args.warmup, args.rtol, profile=False, use_graph=True)
+
+    value = args.steps / rm["total_s"]
+    plain_value = args.steps / rp["total_s"]
+    fim, fip = mixed.factor_info(), plain.factor_info()
+
+    def roof(fi, st):
+        dur_s = st["sweep_ms"] / max(st["sweep_launches"], 1) / 1e3
+        ach = fi["sweep_bytes"] / dur_s / 1e9
+        return dict(bound="hbm", achieved=round(ach, 1), peak=PEAK_HBM_GBS, unit="GB/s",
+                    frac=round(ach / PEAK_HBM_GBS, 4), bytes_per_launch=fi["sweep_bytes"],
+                    avg_launch_us=round(dur_s * 1e6, 2), launches=st["sweep_launches"])
+
+    roof_m, roof_p = roof(fim, rm["stats"]), roof(fip, rp["stats"])
+    traffic = None
+    if os.path.exists(args.traffic):
+        try:
+            with open(args.traffic) as fh:
+                t = json.load(fh)
+            if t.get("sweep_bytes") == fim["sweep_bytes"]:
+                traffic = t.get("hbm_bytes_per_launch")
+        except Exception:
+            traffic = None
+    roof_m["traffic"] = traffic
+    roof_m["kernel"] = "star sweeps (k_star, FP32 factors), one launch per window class per B application"
+
+    u_m = rm["u"].cpu().numpy()
+    u_p = rp["u"].cpu().numpy()
+    out = {
+        "metric": "PCG solves/s at rtol 1e-8 (FP32-star batched vs FP64 plain) + p50/p99 latency",
+        "value": round(value, 3),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(rm["total_s"] / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32/f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "fiber2d_20k_H32",
+            "dim": 2, "n_segments": preset["n_segments"], "length": preset["length"], "nH": args.nH,
+            "nodes": net.n_nodes, "dofs": sysm.n, "nnz": sysm.nnz, "stars": mixed.nstars, "m0": mixed.m0,
+            "rtol": args.rtol, "rhs_per_solve": 1, "precision": "FP32 star factors and sweeps, FP64 CG and coarse",
+        },
+        "latency_ms": {"p50": round(percentile(rm["lat_ms"], 0.5), 3),
+                       "p99": round(percentile(rm["lat_ms"], 0.99), 3)},
+        "iterations": int(statistics.median(rm["iters"])),
+        "iterations_per_s": round(sum(rm["iters"]) / rm["total_s"], 1),
+        "res_true": rm["info"][0]["res_true"],
+        "plain_fp64": {"value": round(plain_value, 3), "unit": "solves/s",
+                       "latency_ms": {"p50": round(percentile(rp["lat_ms"], 0.5), 3),
+                                      "p99": round(percentile(rp["lat_ms"], 0.99), 3)},
+                       "iterations": int(statistics.median(rp["iters"])), "res_true": rp["info"][0]["res_true"],
+                       "roofline_star_sweeps": roof_p},
+        "mixed_over_plain": round(value / plain_value, 3),
+        "graph_replay": {"mixed": round(args.steps / rg["total_s"], 3), "plain": round(args.steps / rpg["total_s"], 3)},
+        "roofline": roof_m,
+        "setup_s": round(t_setup, 2),
+        "factor_info": {"mixed": {k: fim[k] for k in ("star_factor_nnz", "sweep_bytes", "max_band", "max_star_dofs",
+                                                     "factor_seconds")}},
+    }
+
+    if not args.no_cpu_baseline:
+        sys.path.insert(0, os.path.join(ROOT, "oracle"))
+        import oracle as O
+        O.build()
+        onet = O.Network.from_segments(2, seg, merge_tol=tol, dir_lo=preset["dir_lo"], dir_hi=preset["dir_hi"],
+                                       band=W.BAND)
+        opre = O.Precond(O.System(onet), args.nH, 0, preset["dir_lo"], preset["dir_hi"])
+        t0 = time.perf_counter()
+        u_o, it_o, _ = opre.pcg(f_host, rtol=args.rtol)
+        t_o = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": round(1.0 / t_o, 4), "unit": "solves/s", "cores": 1, "kind": "oracle",
+                               "sample": f"one full FP64 oracle PCG solve of the same network and right-hand side "
+                                         f"({it_o} iterations, {t_o:.1f} s; setup untimed)"}
+        nrm = np.linalg.norm(u_o)
+        out["err_vs_oracle"] = {"mixed": float(np.linalg.norm(u_m - u_o) / nrm),
+                                "plain": float(np.linalg.norm(u_p - u_o) / nrm), "oracle_iterations": it_o}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

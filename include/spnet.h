@@ -160,6 +160,17 @@ typedef struct {
   int32_t max_star_dofs;
   int32_t max_band;          /* widest factor row/column */
   double factor_seconds;     /* host time of ordering + numeric factorisation */
+  int64_t sweep_bytes;       /* algorithmic bytes of one application of all star sweeps:
+                                factor values of both sweeps, step headers, gathers of r,
+                                slot writes */
+  int64_t spmv_bytes;        /* algorithmic bytes of one y = K x (values, columns, x, y) */
+  int64_t sweep_flops;       /* 2 flops per factor entry and sweep */
+  double max_pivot_ratio;    /* max over stars of (largest / smallest Cholesky pivot), a lower
+                                bound of cond(K_j) */
+  int32_t star_precision;    /* precision the sweeps run in: SN_PREC_FP32_STARS falls back to
+                                SN_PREC_FP64 when max_pivot_ratio * 2^-24 > 0.05, i.e. when FP32
+                                factors could not resolve the local solves */
+  int32_t pad0;
 } sn_factor_info;
 
 /* Order, factor in FP64 on the host (threads over stars) and upload to the GPU.
@@ -204,6 +215,19 @@ void sn_solve_opts_default(sn_solve_opts *opts);
  */
 sn_status sn_solve(sn_precond pre, int k, const double *f, double *u, const sn_solve_opts *opts,
                    sn_solve_info *info);
+
+/* Kernel timing: while enabled, the star-sweep launches of every B application
+ * are bracketed by HIP events on the solve stream. */
+typedef struct {
+  int64_t sweep_launches;  /* B applications timed */
+  double sweep_ms;         /* summed device time of the star sweeps of those applications */
+  int64_t iterations;      /* PCG iterations run while enabled */
+} sn_kernel_stats;
+
+/* enable = 1 starts (and resets) the recording, 0 stops it. */
+sn_status sn_precond_profile(sn_precond pre, int enable);
+/* Waits for recorded work and returns the totals since the last reset. */
+sn_status sn_precond_kernel_stats(sn_precond pre, sn_kernel_stats *stats);
 
 /* y = K x for k columns (n x k row-major). */
 sn_status sn_apply_K(sn_precond pre, int k, const double *x, double *y, int device_ptrs, void *stream);

@@ -223,6 +223,20 @@ sn_status sn_solve(sn_precond pre, int k, const double *f, double *u, const sn_s
   });
 }
 
+sn_status sn_precond_profile(sn_precond pre, int enable) {
+  return guarded([&] {
+    REQUIRE(pre && pre->p->dev, "preconditioner not factored");
+    spnet::device_profile(*pre->p, enable);
+  });
+}
+
+sn_status sn_precond_kernel_stats(sn_precond pre, sn_kernel_stats *stats) {
+  return guarded([&] {
+    REQUIRE(pre && stats && pre->p->dev, "null argument or not factored");
+    spnet::device_stats(*pre->p, stats);
+  });
+}
+
 sn_status sn_apply_K(sn_precond pre, int k, const double *x, double *y, int device_ptrs, void *stream) {
   return guarded([&] {
     REQUIRE(pre && x && y, "null argument");

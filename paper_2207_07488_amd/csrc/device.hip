@@ -18,6 +18,7 @@
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "internal.hpp"
@@ -32,21 +33,22 @@ namespace spnet {
 
 constexpr int kBlock = 256;   // threads of the vector kernels
 constexpr int kSlice = 64;    // rows per ELL slice (one wavefront)
+constexpr int kMaxGrid = 1024;  // blocks of the grid-stride vector kernels (= partial sums)
 
 // ---------------------------------------------------------------------------
 // device scalars of one PCG recurrence
 // ---------------------------------------------------------------------------
 struct CgScalars {
   double rho, alpha, beta, pq, rr, rz, f2, tol2;
-  double tmp;          // scratch dot result
+  double tmp;  // scratch dot result
   int32_t iters, done, max_iter, fixed, first, pad0;
-  uint32_t ticket[8];  // last-block counters, one per reduction site
 };
 
-enum { T_PQ = 0, T_RR = 1, T_RZ = 2, T_DOT = 3 };
+enum ScalarOp { OP_ALPHA = 0, OP_CONV = 1, OP_BETA = 2, OP_DOT = 3 };
 
 // ---------------------------------------------------------------------------
-// wavefront / block reductions with a fixed combination order
+// reductions: per-block partials in a fixed order, then one block combines
+// them in a fixed order, so every result is independent of scheduling
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double wave_sum(double v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
@@ -65,35 +67,41 @@ __device__ __forceinline__ double block_sum(double v, double *sh) {
   return s;  // thread 0
 }
 
-__device__ __forceinline__ double load_coherent(const double *p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Publish this block's partial; returns true in the block that finishes last,
-// whose thread 0 then gets the fixed-order total in *total.
-__device__ bool last_block_total(double part, double *partials, uint32_t *ticket, double *total, double *sh) {
-  __shared__ bool amlast;
-  if (threadIdx.x == 0) {
-    __hip_atomic_store(&partials[blockIdx.x], part, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __threadfence();
-    const uint32_t t = atomicAdd(ticket, 1u);
-    amlast = (t == gridDim.x - 1);
-  }
-  __syncthreads();
-  if (!amlast) return false;
-  __threadfence();
+// one block: combine the partials of the previous kernel and update the scalars
+__global__ __launch_bounds__(kBlock) void k_scalar(const double *__restrict__ partials, int nparts, CgScalars *sc,
+                                                   int op) {
+  __shared__ double sh[kBlock / 64];
+  if (op != OP_DOT && sc->done) return;
   double s = 0.0;
-  for (int i = threadIdx.x; i < (int)gridDim.x; i += blockDim.x) s += load_coherent(&partials[i]);
-  s = block_sum(s, sh);
-  if (threadIdx.x == 0) {
-    *total = s;
-    *ticket = 0u;
+  for (int i = threadIdx.x; i < nparts; i += kBlock) s += partials[i];
+  const double tot = block_sum(s, sh);
+  if (threadIdx.x != 0) return;
+  switch (op) {
+    case OP_ALPHA:
+      sc->pq = tot;
+      sc->alpha = sc->rho / tot;
+      break;
+    case OP_CONV: {
+      sc->rr = tot;
+      const int it = sc->iters + 1;
+      sc->iters = it;
+      const bool stop = sc->fixed > 0 ? it >= sc->fixed : (tot <= sc->tol2 || it >= sc->max_iter);
+      if (stop) sc->done = 1;
+      break;
+    }
+    case OP_BETA:
+      sc->rz = tot;
+      sc->beta = sc->first ? 0.0 : tot / sc->rho;
+      sc->rho = tot;
+      sc->first = 0;
+      break;
+    default:
+      sc->tmp = tot;
   }
-  return true;
 }
 
 // ---------------------------------------------------------------------------
-// sliced ELL SpMV: y = K x, optional x.y reduction
+// sliced ELL SpMV: y = K x (optionally x.y partials)
 // ---------------------------------------------------------------------------
 struct Sell {
   const int32_t *sptr;  // slice start (elements)
@@ -103,68 +111,54 @@ struct Sell {
 };
 
 __global__ __launch_bounds__(kBlock) void k_spmv(Sell A, const double *__restrict__ x, double *__restrict__ y,
-                                                 int nslices, CgScalars *sc, double *partials, int mode) {
+                                                 int nrows, const CgScalars *sc, double *partials) {
   __shared__ double sh[kBlock / 64];
-  if (mode == 1 && sc->done) return;
-  const int row = blockIdx.x * kBlock + threadIdx.x;
-  const int s = row >> 6, lane = row & 63;
-  double acc = 0.0;
-  if (s < nslices) {
+  if (partials && sc->done) return;
+  double dot = 0.0;
+  for (int row = blockIdx.x * kBlock + threadIdx.x; row < nrows; row += gridDim.x * kBlock) {
+    const int s = row >> 6, lane = row & 63;
     const int base = A.sptr[s], len = A.slen[s];
+    double acc = 0.0;
     for (int c = 0; c < len; ++c) {
       const int e = base + c * kSlice + lane;
       acc += A.val[e] * x[A.col[e]];
     }
     y[row] = acc;
+    dot += x[row] * acc;
   }
-  if (mode != 1) return;
-  const double part = block_sum(s < nslices ? x[row] * acc : 0.0, sh);
-  double tot;
-  if (last_block_total(part, partials, &sc->ticket[T_PQ], &tot, sh) && threadIdx.x == 0) {
-    sc->pq = tot;
-    sc->alpha = sc->rho / tot;
-  }
+  if (!partials) return;
+  const double part = block_sum(dot, sh);
+  if (threadIdx.x == 0) partials[blockIdx.x] = part;
 }
 
-// u += alpha p, r -= alpha q, r.r, convergence test
+// u += alpha p, r -= alpha q, r.r partials
 __global__ __launch_bounds__(kBlock) void k_cg_update(double *u, double *r, const double *p, const double *q, int n,
-                                                      CgScalars *sc, double *partials) {
+                                                      const CgScalars *sc, double *partials) {
   __shared__ double sh[kBlock / 64];
   if (sc->done) return;
   const double a = sc->alpha;
-  const int i = blockIdx.x * kBlock + threadIdx.x;
   double rr = 0.0;
-  if (i < n) {
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
     u[i] += a * p[i];
     const double ri = r[i] - a * q[i];
     r[i] = ri;
-    rr = ri * ri;
+    rr += ri * ri;
   }
   const double part = block_sum(rr, sh);
-  double tot;
-  if (last_block_total(part, partials, &sc->ticket[T_RR], &tot, sh) && threadIdx.x == 0) {
-    sc->rr = tot;
-    const int it = sc->iters + 1;
-    sc->iters = it;
-    bool stop;
-    if (sc->fixed > 0) stop = it >= sc->fixed;
-    else stop = (tot <= sc->tol2) || it >= sc->max_iter;
-    if (stop) sc->done = 1;
-  }
+  if (threadIdx.x == 0) partials[blockIdx.x] = part;
 }
 
-// z = P c + sum of star slots, r.z, beta
+// z = P c + sum of the star slots of every dof (ascending star order), r.z partials
 template <typename TS>
 __global__ __launch_bounds__(kBlock) void k_reduce(double *z, const double *r, const TS *__restrict__ slots,
                                                    const int32_t *__restrict__ slot_of,
                                                    const int32_t *__restrict__ Pc, const double *__restrict__ Pw,
-                                                   const double *__restrict__ cvec, int n, int nv, CgScalars *sc,
-                                                   double *partials, int mode) {
+                                                   const double *__restrict__ cvec, int n, int nv,
+                                                   const CgScalars *sc, double *partials) {
   __shared__ double sh[kBlock / 64];
-  if (mode == 1 && sc->done) return;
-  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (partials && sc->done) return;
   double rz = 0.0;
-  if (i < n) {
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
     double acc = 0.0;
     for (int b = 0; b < nv; ++b) {
       const int c = Pc[(size_t)i * nv + b];
@@ -175,43 +169,36 @@ __global__ __launch_bounds__(kBlock) void k_reduce(double *z, const double *r, c
       if (s >= 0) acc += (double)slots[s];
     }
     z[i] = acc;
-    rz = r[i] * acc;
+    rz += r[i] * acc;
   }
-  if (mode != 1) return;
+  if (!partials) return;
   const double part = block_sum(rz, sh);
-  double tot;
-  if (last_block_total(part, partials, &sc->ticket[T_RZ], &tot, sh) && threadIdx.x == 0) {
-    sc->rz = tot;
-    sc->beta = sc->first ? 0.0 : tot / sc->rho;
-    sc->rho = tot;
-    sc->first = 0;
-  }
+  if (threadIdx.x == 0) partials[blockIdx.x] = part;
 }
 
-__global__ __launch_bounds__(kBlock) void k_p_update(double *p, const double *z, int n, CgScalars *sc) {
+__global__ __launch_bounds__(kBlock) void k_p_update(double *p, const double *z, int n, const CgScalars *sc) {
   if (sc->done) return;
   const double b = sc->beta;
-  const int i = blockIdx.x * kBlock + threadIdx.x;
-  if (i < n) p[i] = z[i] + b * p[i];
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) p[i] = z[i] + b * p[i];
 }
 
-// r_H = P^T r: one wavefront per coarse dof, fixed-order lane sums
+// r_H = P^T r: one block per coarse dof, fixed-order sums
 __global__ __launch_bounds__(kBlock) void k_restrict(const int32_t *__restrict__ ptr, const int32_t *__restrict__ dof,
                                                      const double *__restrict__ w, const double *__restrict__ r,
-                                                     double *rH, int m0, CgScalars *sc, int mode) {
-  if (mode == 1 && sc->done) return;
-  const int c = (blockIdx.x * kBlock + threadIdx.x) >> 6, lane = threadIdx.x & 63;
-  if (c >= m0) return;
+                                                     double *rH, int m0, const CgScalars *sc, int check) {
+  __shared__ double sh[kBlock / 64];
+  if (check && sc->done) return;
+  const int c = blockIdx.x;
   double acc = 0.0;
-  for (int q = ptr[c] + lane; q < ptr[c + 1]; q += 64) acc += w[q] * r[dof[q]];
-  acc = wave_sum(acc);
-  if (lane == 0) rH[c] = acc;
+  for (int q = ptr[c] + threadIdx.x; q < ptr[c + 1]; q += kBlock) acc += w[q] * r[dof[q]];
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) rH[c] = acc;
 }
 
 // c = K_0^{-1} r_H, one wavefront per row of the dense inverse
 __global__ __launch_bounds__(kBlock) void k_coarse_gemv(const double *__restrict__ Kinv, const double *__restrict__ rH,
-                                                        double *cvec, int m0, CgScalars *sc, int mode) {
-  if (mode == 1 && sc->done) return;
+                                                        double *cvec, int m0, const CgScalars *sc, int check) {
+  if (check && sc->done) return;
   const int row = (blockIdx.x * kBlock + threadIdx.x) >> 6, lane = threadIdx.x & 63;
   if (row >= m0) return;
   const double *a = Kinv + (size_t)row * m0;
@@ -221,29 +208,25 @@ __global__ __launch_bounds__(kBlock) void k_coarse_gemv(const double *__restrict
   if (lane == 0) cvec[row] = acc;
 }
 
-__global__ __launch_bounds__(kBlock) void k_dot(const double *a, const double *b, int n, CgScalars *sc,
-                                                double *partials) {
+__global__ __launch_bounds__(kBlock) void k_dot(const double *a, const double *b, int n, double *partials) {
   __shared__ double sh[kBlock / 64];
-  const int i = blockIdx.x * kBlock + threadIdx.x;
-  const double part = block_sum(i < n ? a[i] * b[i] : 0.0, sh);
-  double tot;
-  if (last_block_total(part, partials, &sc->ticket[T_DOT], &tot, sh) && threadIdx.x == 0) sc->tmp = tot;
+  double s = 0.0;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) s += a[i] * b[i];
+  const double part = block_sum(s, sh);
+  if (threadIdx.x == 0) partials[blockIdx.x] = part;
 }
 
 // y = a - b
 __global__ __launch_bounds__(kBlock) void k_sub(double *y, const double *a, const double *b, int n) {
-  const int i = blockIdx.x * kBlock + threadIdx.x;
-  if (i < n) y[i] = a[i] - b[i];
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) y[i] = a[i] - b[i];
 }
 
 // strided column gather / scatter between n x k blocks and a contiguous vector
 __global__ __launch_bounds__(kBlock) void k_gather_col(double *dst, const double *src, int n, int k, int c) {
-  const int i = blockIdx.x * kBlock + threadIdx.x;
-  if (i < n) dst[i] = src[(size_t)i * k + c];
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) dst[i] = src[(size_t)i * k + c];
 }
 __global__ __launch_bounds__(kBlock) void k_scatter_col(double *dst, const double *src, int n, int k, int c) {
-  const int i = blockIdx.x * kBlock + threadIdx.x;
-  if (i < n) dst[(size_t)i * k + c] = src[i];
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) dst[(size_t)i * k + c] = src[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -252,51 +235,71 @@ __global__ __launch_bounds__(kBlock) void k_scatter_col(double *dst, const doubl
 // The vector of the star lives in LDS in factor order. A sweep walks the
 // steps of a stream: the forward stream holds the columns of L (step j: the
 // entries L_{j+1..j+w, j}), the backward stream the rows of L from the last
-// (step s = row n-1-s: L_{i,i-1..i-w}); with the vector read in reverse order
-// the backward sweep is the same recurrence as the forward one.
+// (step s = row i = n-1-s: the entries L_{i, i-1..i-w}); read in reverse
+// order, the vector makes the backward sweep the same recurrence as the
+// forward one. Stream values are divided by the step's pivot, so a step
+// subtracts m_t g_j from row j+1+t with the raw running value g_j, and the
+// pivot division is applied to 64 finished rows at once.
 //
 // Window: before step j, lane l of register g[q] holds the running value of
-// row j + l + 64 q. Lane 0 of g[0] is then final: y_j = g * (1/L_jj). The
-// window slides by one lane (DPP wave shift left), the next row enters at lane
-// 63 of the last register, and every lane updates its row with the column
-// entry t = lane + 64 q. Column values are loaded R steps ahead into a
-// register ring; step headers (offset, width, 1/diag) arrive 64 at a time.
+// row j + l + 64 q; lane 0 of g[0] is final. The window slides by one lane
+// (DPP wave shift left), the next row enters at lane 63 of the last register.
+// SG consecutive steps (4 in FP32, 2 in FP64) are packed lane-major, so one
+// 16-byte load per lane and register fetches them all; groups are loaded RG
+// groups ahead into a register ring, their offsets and widths arrive 64 at a
+// time.
 // ---------------------------------------------------------------------------
 struct StarArgs {
   int32_t nstars;
-  const int32_t *order;   // stars of this launch, largest first
-  const int32_t *st_n;
-  const int32_t *st_vb;   // base position of the star in all per-position arrays
-  const int64_t *st_fb;   // forward stream value base
-  const int64_t *st_bb;   // backward stream value base
-  const int32_t *pos_dof; // global dof of each position (factor order)
-  const int32_t *f_off, *f_w, *b_off, *b_w;  // per-step headers
-  const void *f_inv, *b_inv;                 // 1/diag per step (T)
-  const void *f_val, *b_val;                 // stream values (T)
+  const int32_t *order;    // stars, longest first
+  const int32_t *st_n;     // positions of the star
+  const int32_t *st_vb;    // base in the per-position arrays
+  const int32_t *st_q;     // window registers
+  const int32_t *st_gb;    // base in the per-group arrays
+  const int64_t *st_fb;    // forward stream value base
+  const int64_t *st_bb;    // backward stream value base
+  const int32_t *pos_dof;  // global dof of each position (factor order)
+  const int32_t *f_go, *f_gw, *b_go, *b_gw;  // per group: value offset (from the star base), width
+  const void *f_inv, *b_inv;                 // 1/pivot per step (T)
+  const void *f_val, *b_val;                 // packed stream values (T)
   void *slots;                               // T, per position
   int32_t pad;                               // LDS zero padding each side (elements)
 };
 
 template <typename T>
-struct Lanes;
+struct Pack;
 template <>
-struct Lanes<float> {
+struct Pack<float> {
+  using V = float4;
+  static constexpr int SG = 4;
+  static __device__ __forceinline__ float get(const V &v, int k) {
+    return k == 0 ? v.x : (k == 1 ? v.y : (k == 2 ? v.z : v.w));
+  }
+  static __device__ __forceinline__ V masked(bool keep, const V &v) {
+    return V{keep ? v.x : 0.f, keep ? v.y : 0.f, keep ? v.z : 0.f, keep ? v.w : 0.f};
+  }
   static __device__ __forceinline__ float first(float v) {
     return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
-  }
-  static __device__ __forceinline__ float lane(float v, int l) {
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
-  }
-  static __device__ __forceinline__ float put(float old, float v, int l) {
-    return (int)(threadIdx.x & 63) == l ? v : old;
   }
   // lanes 0..62 take lane+1, lane 63 takes `in`
   static __device__ __forceinline__ float shl(float v, float in) {
     return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(in), __float_as_int(v), 0x130, 0xF, 0xF, false));
   }
+  template <int L>
+  static __device__ __forceinline__ float put(float vec, float s) {
+    int r = __float_as_int(vec);
+    asm volatile("v_writelane_b32 %0, %1, %2" : "+v"(r) : "s"(__float_as_int(s)), "i"(L));
+    return __int_as_float(r);
+  }
 };
 template <>
-struct Lanes<double> {
+struct Pack<double> {
+  using V = double2;
+  static constexpr int SG = 2;
+  static __device__ __forceinline__ double get(const V &v, int k) { return k == 0 ? v.x : v.y; }
+  static __device__ __forceinline__ V masked(bool keep, const V &v) {
+    return V{keep ? v.x : 0.0, keep ? v.y : 0.0};
+  }
   static __device__ __forceinline__ int lo(double v) { return (int)(uint32_t)(__double_as_longlong(v)); }
   static __device__ __forceinline__ int hi(double v) { return (int)(uint32_t)(__double_as_longlong(v) >> 32); }
   static __device__ __forceinline__ double mk(int l, int h) {
@@ -305,94 +308,128 @@ struct Lanes<double> {
   static __device__ __forceinline__ double first(double v) {
     return mk(__builtin_amdgcn_readfirstlane(lo(v)), __builtin_amdgcn_readfirstlane(hi(v)));
   }
-  static __device__ __forceinline__ double lane(double v, int l) {
-    return mk(__builtin_amdgcn_readlane(lo(v), l), __builtin_amdgcn_readlane(hi(v), l));
-  }
-  static __device__ __forceinline__ double put(double old, double v, int l) {
-    return (int)(threadIdx.x & 63) == l ? v : old;
-  }
   static __device__ __forceinline__ double shl(double v, double in) {
     return mk(__builtin_amdgcn_update_dpp(lo(in), lo(v), 0x130, 0xF, 0xF, false),
               __builtin_amdgcn_update_dpp(hi(in), hi(v), 0x130, 0xF, 0xF, false));
   }
+  template <int L>
+  static __device__ __forceinline__ double put(double vec, double s) {
+    int l = lo(vec), h = hi(vec);
+    asm volatile("v_writelane_b32 %0, %1, %2" : "+v"(l) : "s"(lo(s)), "i"(L));
+    asm volatile("v_writelane_b32 %0, %1, %2" : "+v"(h) : "s"(hi(s)), "i"(L));
+    return mk(l, h);
+  }
+};
+
+template <int S, int E>
+struct StaticFor {
+  template <typename F>
+  static __device__ __forceinline__ void run(F &&f) {
+    f(std::integral_constant<int, S>{});
+    StaticFor<S + 1, E>::run(f);
+  }
+};
+template <int E>
+struct StaticFor<E, E> {
+  template <typename F>
+  static __device__ __forceinline__ void run(F &&) {}
 };
 
 // One sweep over n steps. vec points at position 0 of the LDS vector (with
-// `pad` zero elements on both sides); rev selects reversed indexing.
-template <typename T, int Q, int R, bool rev>
-__device__ __forceinline__ void sweep(T *vec, int n, const int32_t *__restrict__ hoff,
-                                      const int32_t *__restrict__ hw, const T *__restrict__ hinv,
-                                      const T *__restrict__ vals) {
+// `pad` zero elements on both sides); REV reads it in reverse.
+template <typename T, int Q, int RG, bool REV>
+__device__ __forceinline__ void sweep(T *vec, int n, const int32_t *__restrict__ go, const int32_t *__restrict__ gw,
+                                      const T *__restrict__ inv, const T *__restrict__ vals) {
+  using P = Pack<T>;
+  using V = typename P::V;
+  constexpr int SG = P::SG, GPB = 64 / SG;
+  static_assert(GPB % RG == 0, "ring must divide the groups of a block");
   const int lane = threadIdx.x & 63;
-  auto at = [&](int p) -> int { return rev ? (n - 1 - p) : p; };
+  auto at = [&](int p) -> int { return REV ? (n - 1 - p) : p; };
+  const int ngroups = (n + SG - 1) / SG;
   T g[Q];
 #pragma unroll
   for (int q = 0; q < Q; ++q) g[q] = vec[at(lane + 64 * q)];
-  // header blocks: current, next, next-next
-  int h_off0 = 0, h_w0 = 0, h_off1 = 0, h_w1 = 0, h_off2 = 0, h_w2 = 0;
-  T h_inv0 = 0, h_inv1 = 0, h_inv2 = 0;
-  if (lane < n) { h_off0 = hoff[lane]; h_w0 = hw[lane]; h_inv0 = hinv[lane]; }
-  if (64 + lane < n) { h_off1 = hoff[64 + lane]; h_w1 = hw[64 + lane]; h_inv1 = hinv[64 + lane]; }
-  if (128 + lane < n) { h_off2 = hoff[128 + lane]; h_w2 = hw[128 + lane]; h_inv2 = hinv[128 + lane]; }
-  // value ring: ring[s % R] holds step (block base + s) values
-  T ring[R][Q];
+  // rows entering the window, read NP steps ahead: nxt[s % NP] is row j + 64 Q
+  constexpr int NP = 8;
+  T nxt[NP];
 #pragma unroll
-  for (int s = 0; s < R; ++s) {
-    const int o = __builtin_amdgcn_readlane(h_off0, s);
+  for (int i = 0; i < NP; ++i) nxt[i] = vec[at(64 * Q + i)];
+  // group headers of the 64 groups from the current block's first group
+  int hoA = lane < ngroups ? go[lane] : 0, hwA = lane < ngroups ? gw[lane] : 0;
+  T hinv = lane < n ? inv[lane] : T(0);
+  V ring[RG][Q];
 #pragma unroll
-    for (int q = 0; q < Q; ++q) ring[s][q] = (s < n) ? vals[o + lane + 64 * q] : T(0);
+  for (int rg = 0; rg < RG; ++rg) {
+    const int o = __builtin_amdgcn_readlane(hoA, rg), w = __builtin_amdgcn_readlane(hwA, rg);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const V v = *reinterpret_cast<const V *>(vals + o + (lane + 64 * q) * SG);
+      ring[rg][q] = P::masked(lane + 64 * q < w, v);
+    }
   }
-  T nxt0 = vec[at(64 * Q)], nxt1 = vec[at(64 * Q + 1)];
-  // Steps past the end are harmless: their rows are zero padding, so y = 0.
   for (int jb = 0; jb < n; jb += 64) {
-    T ybuf = 0;
-#pragma unroll
-    for (int s = 0; s < 64; ++s) {
-      const int j = jb + s;
-      const T inv = Lanes<T>::lane(h_inv0, s);
-      const int w = __builtin_amdgcn_readlane(h_w0, s);
-      const T y = Lanes<T>::first(g[0]) * inv;
-      ybuf = Lanes<T>::shl(ybuf, y);  // after 64 steps lane l holds y of step jb + l
+    const int gb = jb / SG;
+    const int hoB = gb + GPB + lane < ngroups ? go[gb + GPB + lane] : 0;
+    const int hwB = gb + GPB + lane < ngroups ? gw[gb + GPB + lane] : 0;
+    const T hinvN = jb + 64 + lane < n ? inv[jb + 64 + lane] : T(0);
+    T ybuf = T(0);
+    StaticFor<0, 64>::run([&](auto sc) {
+      constexpr int s = decltype(sc)::value;
+      constexpr int gi = s / SG, k = s % SG;
+      const T gj = P::first(g[0]);
       T carry[Q];
 #pragma unroll
-      for (int q = 0; q + 1 < Q; ++q) carry[q] = Lanes<T>::first(g[q + 1]);
+      for (int q = 0; q + 1 < Q; ++q) carry[q] = P::first(g[q + 1]);
 #pragma unroll
-      for (int q = 0; q + 1 < Q; ++q) g[q] = Lanes<T>::shl(g[q], carry[q]);
-      g[Q - 1] = Lanes<T>::shl(g[Q - 1], nxt0);
-      nxt0 = nxt1;
-      nxt1 = vec[at(j + 64 * Q + 2)];
+      for (int q = 0; q + 1 < Q; ++q) g[q] = P::shl(g[q], carry[q]);
+      g[Q - 1] = P::shl(g[Q - 1], nxt[s % NP]);
+      nxt[s % NP] = vec[at(jb + s + 64 * Q + NP)];
+      ybuf = P::template put<s>(ybuf, gj);
 #pragma unroll
-      for (int q = 0; q < Q; ++q) {
-        const T lv = (lane + 64 * q < w) ? ring[s % R][q] : T(0);
-        g[q] = g[q] - lv * y;
+      for (int q = 0; q < Q; ++q) g[q] = g[q] - P::get(ring[gi % RG][q], k) * gj;
+      if constexpr (k == SG - 1) {
+        // the group is consumed: fetch the group RG positions ahead
+        constexpr int li = gi + RG;
+        const int o = __builtin_amdgcn_readlane(hoA, li), w = __builtin_amdgcn_readlane(hwA, li);
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+          const V v = *reinterpret_cast<const V *>(vals + o + (lane + 64 * q) * SG);
+          ring[gi % RG][q] = P::masked(lane + 64 * q < w, v);
+        }
       }
-      // loads of step j + R (offsets of steps past the end are 0: in bounds)
-      const int o = (s + R < 64) ? __builtin_amdgcn_readlane(h_off0, (s + R) & 63)
-                                 : __builtin_amdgcn_readlane(h_off1, (s + R) & 63);
-#pragma unroll
-      for (int q = 0; q < Q; ++q) ring[s % R][q] = vals[o + lane + 64 * q];
-    }
-    if (jb + lane < n) vec[at(jb + lane)] = ybuf;
-    h_off0 = h_off1; h_w0 = h_w1; h_inv0 = h_inv1;
-    h_off1 = h_off2; h_w1 = h_w2; h_inv1 = h_inv2;
-    const int nb = jb + 192 + lane;
-    h_off2 = 0; h_w2 = 0; h_inv2 = T(0);
-    if (nb < n) { h_off2 = hoff[nb]; h_w2 = hw[nb]; h_inv2 = hinv[nb]; }
+    });
+    if (jb + lane < n) vec[at(jb + lane)] = ybuf * hinv;
+    hinv = hinvN;
+    hoA = hoB;
+    hwA = hwB;
   }
 }
 
-template <typename T, int Q, int R>
-__global__ __launch_bounds__(64) void k_star(StarArgs a, const double *__restrict__ r, const CgScalars *sc, int mode) {
-  if (mode == 1 && sc->done) return;
+template <typename T, int Q>
+__device__ __forceinline__ void star_solve(const StarArgs &a, int st, int n, T *vec) {
+  constexpr int GPB = 64 / Pack<T>::SG;
+  constexpr int RG0 = 16 / Q;
+  constexpr int RG = RG0 >= GPB ? GPB : (RG0 >= 8 ? 8 : (RG0 >= 4 ? 4 : (RG0 >= 2 ? 2 : 1)));
+  const int vb = a.st_vb[st], gbase = a.st_gb[st];
+  sweep<T, Q, RG, false>(vec, n, a.f_go + gbase, a.f_gw + gbase, static_cast<const T *>(a.f_inv) + vb,
+                         static_cast<const T *>(a.f_val) + a.st_fb[st]);
+  __syncthreads();
+  sweep<T, Q, RG, true>(vec, n, a.b_go + gbase, a.b_gw + gbase, static_cast<const T *>(a.b_inv) + vb,
+                        static_cast<const T *>(a.b_val) + a.st_bb[st]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(64) void k_star(StarArgs a, const double *__restrict__ r, const CgScalars *sc, int check) {
+  if (check && sc->done) return;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   T *lds = reinterpret_cast<T *>(lds_raw);
   const int wv = blockIdx.x;
   if (wv >= a.nstars) return;
   const int st = a.order[wv];
-  const int n = a.st_n[st], vb = a.st_vb[st];
+  const int n = a.st_n[st], vb = a.st_vb[st], Q = a.st_q[st];
   const int lane = threadIdx.x;
   T *vec = lds + a.pad;
-  // zero the padding, gather r in factor order
   for (int i = lane; i < a.pad; i += 64) {
     lds[i] = T(0);
     vec[n + i] = T(0);
@@ -400,11 +437,13 @@ __global__ __launch_bounds__(64) void k_star(StarArgs a, const double *__restric
   const int32_t *dofs = a.pos_dof + vb;
   for (int p = lane; p < n; p += 64) vec[p] = (T)r[dofs[p]];
   __syncthreads();
-  sweep<T, Q, R, false>(vec, n, a.f_off + vb, a.f_w + vb, static_cast<const T *>(a.f_inv) + vb,
-                 static_cast<const T *>(a.f_val) + a.st_fb[st]);
-  __syncthreads();
-  sweep<T, Q, R, true>(vec, n, a.b_off + vb, a.b_w + vb, static_cast<const T *>(a.b_inv) + vb,
-                 static_cast<const T *>(a.b_val) + a.st_bb[st]);
+  switch (Q) {
+    case 1: star_solve<T, 1>(a, st, n, vec); break;
+    case 2: star_solve<T, 2>(a, st, n, vec); break;
+    case 4: star_solve<T, 4>(a, st, n, vec); break;
+    case 8: star_solve<T, 8>(a, st, n, vec); break;
+    default: star_solve<T, 16>(a, st, n, vec); break;
+  }
   __syncthreads();
   T *out = static_cast<T *>(a.slots) + vb;
   for (int p = lane; p < n; p += 64) out[p] = vec[p];
@@ -435,18 +474,12 @@ struct DBuf {
     n = 0;
   }
   size_t bytes() const { return n * sizeof(T); }
-};
-
-struct StarBin {
-  int Q = 1;
-  int maxn = 0;
-  DBuf<int32_t> order;
-  int count = 0;
+  ~DBuf() { release(); }
 };
 
 struct Workspace {
   int k = 0;
-  DBuf<double> u, r, p, q, z, f, rH, c, partials, tmpk;
+  DBuf<double> u, r, p, q, z, f, rH, c, partials;
   DBuf<CgScalars> sc;
 };
 
@@ -461,19 +494,30 @@ struct DeviceState {
   DBuf<int32_t> sptr, slen, col;
   DBuf<double> val;
   // stars
-  int32_t nstars = 0, pad = 0;
-  DBuf<int32_t> st_n, st_vb, pos_dof, f_off, f_w, b_off, b_w;
+  int32_t nstars = 0, pad = 0, maxn = 0;
+  DBuf<int32_t> order, st_n, st_vb, st_q, st_gb, pos_dof, f_go, f_gw, b_go, b_gw, slot_of;
   DBuf<int64_t> st_fb, st_bb;
   DBuf<float> f_inv32, b_inv32, f_val32, b_val32, slots32;
   DBuf<double> f_inv64, b_inv64, f_val64, b_val64, slots64;
-  std::vector<StarBin> bins;
-  DBuf<int32_t> slot_of;
   // coarse
   DBuf<double> Kinv, PTw, Pw;
   DBuf<int32_t> PTptr, PTdof, Pc;
   Workspace ws;
   int64_t bytes = 0;
+  // captured iteration blocks: graphs[i] runs 2^i PCG iterations
+  std::vector<hipGraphExec_t> graphs;
+  std::vector<hipGraph_t> graph_defs;
+  // profiling
+  bool profiling = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_used, ev_free;
+  int64_t prof_iters = 0;
   ~DeviceState() {
+    for (auto &g : graphs)
+      if (g) (void)hipGraphExecDestroy(g);
+    for (auto &g : graph_defs)
+      if (g) (void)hipGraphDestroy(g);
+    for (auto &e : ev_used) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
+    for (auto &e : ev_free) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
     if (own) (void)hipStreamDestroy(own);
   }
 };
@@ -483,52 +527,148 @@ void DeviceDeleter::operator()(DeviceState *d) const { delete d; }
 
 namespace {
 
-int pick_ring(int Q, bool dbl) {
-  int regs = 64 / (dbl ? 2 : 1);  // ring registers budget (32-bit)
-  int r = regs / Q;
-  int p = 64;
-  while (p > r && p > 4) p >>= 1;
-  return p;
+int window_regs(int band) {
+  const int q = (band + 63) / 64;
+  for (int w = 1; w <= 16; w *= 2)
+    if (q <= w) return w;
+  return -1;
 }
 
-template <typename T, int Q, int R>
-void launch_bin_t(const StarArgs &a, const StarBin &b, const double *r, const CgScalars *sc, int mode,
-                  hipStream_t s, int pad) {
-  StarArgs aa = a;
-  aa.nstars = b.count;
-  aa.order = b.order.p;
-  const size_t lds = (size_t)(b.maxn + 2 * pad) * sizeof(T);
-  if (lds > 65536) HIPCHK(hipFuncSetAttribute((const void *)k_star<T, Q, R>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                              (int)lds));
-  hipLaunchKernelGGL((k_star<T, Q, R>), dim3(b.count), dim3(64), lds, s, aa, r, sc, mode);
-}
+inline unsigned nblk(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+inline unsigned grid_for(int64_t n) { return std::max(1u, std::min<unsigned>(kMaxGrid, nblk(n))); }
 
+// Pack one sweep stream of a star: steps in groups of SG, each group padded
+// to its widest step, lane-major (entry t of the SG steps adjacent), values
+// divided by the step's pivot.
 template <typename T>
-void launch_bin(const StarArgs &a, const StarBin &b, const double *r, const CgScalars *sc, int mode, hipStream_t s,
-                int pad) {
-  constexpr bool D = sizeof(T) == 8;
-  switch (b.Q) {
-    case 1: launch_bin_t<T, 1, D ? 16 : 32>(a, b, r, sc, mode, s, pad); break;
-    case 2: launch_bin_t<T, 2, D ? 8 : 16>(a, b, r, sc, mode, s, pad); break;
-    case 3: launch_bin_t<T, 3, D ? 4 : 8>(a, b, r, sc, mode, s, pad); break;
-    case 4: launch_bin_t<T, 4, D ? 4 : 8>(a, b, r, sc, mode, s, pad); break;
-    case 6: launch_bin_t<T, 6, D ? 2 : 4>(a, b, r, sc, mode, s, pad); break;
-    case 8: launch_bin_t<T, 8, D ? 2 : 4>(a, b, r, sc, mode, s, pad); break;
-    default: fail(SN_EINVAL, "unsupported star window");
+void pack_stream(const std::vector<int32_t> &width, const std::vector<double> &vals, const std::vector<double> &inv,
+                 int SG, std::vector<T> &out, std::vector<int32_t> &go, std::vector<int32_t> &gw, int64_t base) {
+  const int n = (int)width.size();
+  std::vector<int64_t> start((size_t)n + 1, 0);
+  for (int j = 0; j < n; ++j) start[j + 1] = start[j] + width[j];
+  for (int g0 = 0; g0 < n; g0 += SG) {
+    int W = 0;
+    for (int k = 0; k < SG && g0 + k < n; ++k) W = std::max(W, width[g0 + k]);
+    go.push_back((int32_t)((int64_t)out.size() - base));
+    gw.push_back(W);
+    for (int t = 0; t < W; ++t)
+      for (int k = 0; k < SG; ++k) {
+        const int j = g0 + k;
+        double v = 0.0;
+        if (j < n && t < width[j]) v = vals[(size_t)(start[j] + t)] * inv[j];
+        out.push_back((T)v);
+      }
   }
 }
 
-int bin_Q(int band) {
-  const int q = (band + 63) / 64;
-  if (q <= 4) return std::max(q, 1);
-  if (q <= 6) return 6;
-  if (q <= 8) return 8;
-  return -1;
+template <typename T>
+void upload_stars(DeviceState &d, const Precond &pre, const HostFactors &hf, sn_factor_info &fi) {
+  constexpr int SG = 16 / (int)sizeof(T);
+  const int64_t ns = (int64_t)hf.stars.size();
+  std::vector<int32_t> st_n(ns), st_vb(ns), st_q(ns), st_gb(ns), pos_dof, f_go, f_gw, b_go, b_gw;
+  std::vector<int64_t> st_fb(ns), st_bb(ns);
+  std::vector<T> f_val, b_val, f_inv, b_inv;
+  int64_t tot = 0, real_vals = 0;
+  int maxband = 0, maxq = 1;
+  for (int64_t s = 0; s < ns; ++s) {
+    const StarFactor &F = hf.stars[s];
+    const int q = window_regs(std::max(F.band, 1));
+    if (q < 0) fail(SN_EINVAL, "star band " + std::to_string(F.band) + " exceeds the widest sweep window (1024)");
+    st_n[s] = F.n;
+    st_vb[s] = (int32_t)tot;
+    st_q[s] = q;
+    st_gb[s] = (int32_t)f_go.size();
+    maxq = std::max(maxq, q);
+    maxband = std::max(maxband, F.band);
+    d.maxn = std::max(d.maxn, F.n);
+    // forward: columns j; backward: rows n-1-s
+    std::vector<double> finv(F.invdiag), binv((size_t)F.n);
+    for (int p = 0; p < F.n; ++p) binv[p] = F.invdiag[F.n - 1 - p];
+    st_fb[s] = (int64_t)f_val.size();
+    pack_stream<T>(F.width_fwd, F.colvals, finv, SG, f_val, f_go, f_gw, st_fb[s]);
+    st_bb[s] = (int64_t)b_val.size();
+    pack_stream<T>(F.width_bwd, F.rowvals, binv, SG, b_val, b_go, b_gw, st_bb[s]);
+    const int32_t *dofs = &pre.star_dofs[pre.star_ptr[s]];
+    for (int p = 0; p < F.n; ++p) {
+      pos_dof.push_back(dofs[F.perm[p]]);
+      f_inv.push_back((T)finv[p]);
+      b_inv.push_back((T)binv[p]);
+    }
+    tot += F.n;
+    real_vals += (int64_t)(F.colvals.size() + F.rowvals.size());
+  }
+  if (tot >= (int64_t)1 << 31 || (int64_t)std::max(f_val.size(), b_val.size()) >= (int64_t)1 << 31)
+    fail(SN_EINVAL, "star streams too large for 32-bit offsets");
+  // over-read slack: a group load reads up to 64*Q lanes of SG values
+  const size_t slack = (size_t)64 * 16 * SG + 64;
+  f_val.resize(f_val.size() + slack, T(0));
+  b_val.resize(b_val.size() + slack, T(0));
+  d.pad = 64 * (maxq + 2);
+  // schedule: longest chain first
+  std::vector<int32_t> order((size_t)ns);
+  for (int64_t s = 0; s < ns; ++s) order[s] = (int32_t)s;
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return st_n[a] > st_n[b]; });
+  // dof -> slots in ascending star order
+  std::vector<int32_t> slot_of((size_t)d.npad * d.nv, -1);
+  {
+    std::vector<int32_t> cnt((size_t)d.n, 0);
+    for (int64_t s = 0; s < ns; ++s)
+      for (int p = 0; p < st_n[s]; ++p) {
+        const int32_t dof = pos_dof[st_vb[s] + p];
+        if (cnt[dof] >= d.nv) fail(SN_EINVAL, "a dof lies in more stars than its element has mesh nodes");
+        slot_of[(size_t)dof * d.nv + cnt[dof]++] = st_vb[s] + p;
+      }
+  }
+  d.nstars = (int32_t)ns;
+  d.order.upload(order);
+  d.st_n.upload(st_n);
+  d.st_vb.upload(st_vb);
+  d.st_q.upload(st_q);
+  d.st_gb.upload(st_gb);
+  d.st_fb.upload(st_fb);
+  d.st_bb.upload(st_bb);
+  d.pos_dof.upload(pos_dof);
+  d.f_go.upload(f_go);
+  d.f_gw.upload(f_gw);
+  d.b_go.upload(b_go);
+  d.b_gw.upload(b_gw);
+  d.slot_of.upload(slot_of);
+  int64_t stream_bytes;
+  if constexpr (sizeof(T) == 4) {
+    d.f_inv32.upload(f_inv);
+    d.b_inv32.upload(b_inv);
+    d.f_val32.upload(f_val);
+    d.b_val32.upload(b_val);
+    d.slots32.alloc((size_t)tot);
+    d.slots32.zero();
+    stream_bytes = (int64_t)(d.f_val32.bytes() + d.b_val32.bytes());
+  } else {
+    d.f_inv64.upload(f_inv);
+    d.b_inv64.upload(b_inv);
+    d.f_val64.upload(f_val);
+    d.b_val64.upload(b_val);
+    d.slots64.alloc((size_t)tot);
+    d.slots64.zero();
+    stream_bytes = (int64_t)(d.f_val64.bytes() + d.b_val64.bytes());
+  }
+  const int64_t sT = sizeof(T);
+  // algorithmic bytes of one application: every off-diagonal factor entry once
+  // per sweep, the pivot of every step, the gather (dof id and r) and the slot
+  // write of every position; the zero padding of the packed groups is not counted
+  fi.sweep_bytes = real_vals * sT + tot * (2 * sT + 4 + 8 + sT);
+  fi.sweep_flops = 2 * real_vals + 2 * tot;
+  fi.star_stream_bytes = stream_bytes;
+  fi.max_band = maxband;
+  fi.max_star_dofs = d.maxn;
 }
 
 }  // namespace
 
 void device_setup(Precond &pre, const HostFactors &hf, int precision) {
+  double max_ratio = 1.0;
+  for (const StarFactor &F : hf.stars) max_ratio = std::max(max_ratio, F.pivot_ratio);
+  const int requested = precision;
+  if (precision == SN_PREC_FP32_STARS && max_ratio * std::ldexp(1.0, -24) > 0.05) precision = SN_PREC_FP64;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) fail(SN_EDEVICE, "no HIP device available");
   auto d = std::make_unique<DeviceState>();
@@ -542,6 +682,7 @@ void device_setup(Precond &pre, const HostFactors &hf, int precision) {
   d->nv = pre.nvert_per_elem;
   const int64_t n = sys.n, npad = d->npad;
   if (n >= (int64_t)1 << 30) fail(SN_EINVAL, "system too large for 32-bit indices");
+  sn_factor_info fi{};
 
   // sliced ELL
   {
@@ -584,115 +725,11 @@ void device_setup(Precond &pre, const HostFactors &hf, int precision) {
   }
 
   // stars
-  const int64_t ns = (int64_t)hf.stars.size();
-  d->nstars = (int32_t)ns;
-  std::vector<int32_t> st_n(ns), st_vb(ns);
-  std::vector<int64_t> st_fb(ns), st_bb(ns);
-  int64_t tot = 0, fv = 0, bv = 0;
-  int maxband = 0, maxn = 0;
-  for (int64_t s = 0; s < ns; ++s) {
-    const StarFactor &F = hf.stars[s];
-    st_n[s] = F.n;
-    st_vb[s] = (int32_t)tot;
-    st_fb[s] = fv;
-    st_bb[s] = bv;
-    tot += F.n;
-    fv += (int64_t)F.colvals.size();
-    bv += (int64_t)F.rowvals.size();
-    maxband = std::max(maxband, F.band);
-    maxn = std::max(maxn, F.n);
-  }
-  if (tot >= (int64_t)1 << 31) fail(SN_EINVAL, "too many star positions");
-  const int maxQ = std::max(1, bin_Q(maxband));
-  if (bin_Q(maxband) < 0) fail(SN_EINVAL, "star band " + std::to_string(maxband) + " exceeds the widest sweep window (512)");
-  d->pad = 64 * (maxQ + 3);
-  const int64_t tailpad = 64 * 8 + 64;  // stream over-read slack
-  std::vector<int32_t> pos_dof((size_t)tot), f_off((size_t)tot), f_w((size_t)tot), b_off((size_t)tot),
-      b_w((size_t)tot);
-  std::vector<double> f_inv((size_t)tot), b_inv((size_t)tot), f_val((size_t)(fv + tailpad), 0.0),
-      b_val((size_t)(bv + tailpad), 0.0);
-  std::vector<int32_t> slot_of((size_t)npad * d->nv, -1);
+  if (precision == SN_PREC_FP32_STARS) upload_stars<float>(*d, pre, hf, fi);
+  else upload_stars<double>(*d, pre, hf, fi);
   int64_t star_nnz = 0;
-  for (int64_t s = 0; s < ns; ++s) {
-    const StarFactor &F = hf.stars[s];
-    const int64_t vb = st_vb[s];
-    const int32_t *dofs = &pre.star_dofs[pre.star_ptr[s]];
-    int64_t of = 0, ob = 0;
-    for (int p = 0; p < F.n; ++p) {
-      const int32_t dof = dofs[F.perm[p]];
-      pos_dof[vb + p] = dof;
-      f_off[vb + p] = (int32_t)of;
-      f_w[vb + p] = F.width_fwd[p];
-      f_inv[vb + p] = F.invdiag[p];
-      of += F.width_fwd[p];
-      b_off[vb + p] = (int32_t)ob;
-      b_w[vb + p] = F.width_bwd[p];
-      b_inv[vb + p] = F.invdiag[F.n - 1 - p];
-      ob += F.width_bwd[p];
-    }
-    std::copy(F.colvals.begin(), F.colvals.end(), f_val.begin() + st_fb[s]);
-    std::copy(F.rowvals.begin(), F.rowvals.end(), b_val.begin() + st_bb[s]);
-    star_nnz += F.nnz;
-  }
-  // dof -> slots in ascending star order
-  {
-    std::vector<int32_t> cnt((size_t)n, 0);
-    for (int64_t s = 0; s < ns; ++s)
-      for (int p = 0; p < st_n[s]; ++p) {
-        const int32_t dof = pos_dof[st_vb[s] + p];
-        if (cnt[dof] >= d->nv) fail(SN_EINVAL, "a dof lies in more stars than its element has mesh nodes");
-        slot_of[(size_t)dof * d->nv + cnt[dof]++] = st_vb[s] + p;
-      }
-  }
-  d->st_n.upload(st_n);
-  d->st_vb.upload(st_vb);
-  d->st_fb.upload(st_fb);
-  d->st_bb.upload(st_bb);
-  d->pos_dof.upload(pos_dof);
-  d->f_off.upload(f_off);
-  d->f_w.upload(f_w);
-  d->b_off.upload(b_off);
-  d->b_w.upload(b_w);
-  d->slot_of.upload(slot_of);
-  int64_t stream_bytes = 0;
-  if (precision == SN_PREC_FP32_STARS) {
-    auto cast = [](const std::vector<double> &v) {
-      std::vector<float> o(v.size());
-      for (size_t i = 0; i < v.size(); ++i) o[i] = (float)v[i];
-      return o;
-    };
-    d->f_inv32.upload(cast(f_inv));
-    d->b_inv32.upload(cast(b_inv));
-    d->f_val32.upload(cast(f_val));
-    d->b_val32.upload(cast(b_val));
-    d->slots32.alloc((size_t)tot);
-    d->slots32.zero();
-    stream_bytes = (int64_t)(d->f_val32.bytes() + d->b_val32.bytes() + d->f_inv32.bytes() + d->b_inv32.bytes());
-  } else {
-    d->f_inv64.upload(f_inv);
-    d->b_inv64.upload(b_inv);
-    d->f_val64.upload(f_val);
-    d->b_val64.upload(b_val);
-    d->slots64.alloc((size_t)tot);
-    d->slots64.zero();
-    stream_bytes = (int64_t)(d->f_val64.bytes() + d->b_val64.bytes() + d->f_inv64.bytes() + d->b_inv64.bytes());
-  }
-  // bins by window width, largest stars first
-  {
-    std::vector<std::vector<int32_t>> byq(9);
-    for (int64_t s = 0; s < ns; ++s) byq[bin_Q(hf.stars[s].band < 1 ? 1 : hf.stars[s].band)].push_back((int32_t)s);
-    for (int q = 1; q <= 8; ++q) {
-      if (byq[q].empty()) continue;
-      auto &v = byq[q];
-      std::stable_sort(v.begin(), v.end(), [&](int32_t a, int32_t b) { return st_n[a] > st_n[b]; });
-      StarBin b;
-      b.Q = q;
-      b.count = (int)v.size();
-      b.maxn = st_n[v[0]];
-      b.order.upload(v);
-      d->bins.push_back(std::move(b));
-    }
-  }
+  for (const StarFactor &F : hf.stars) star_nnz += F.nnz;
+
   // coarse operator
   const int nc = sys.ncomp, nv = d->nv;
   if (d->m0 > 0) {
@@ -734,20 +771,24 @@ void device_setup(Precond &pre, const HostFactors &hf, int precision) {
     d->Pw.upload(std::vector<double>((size_t)npad * nv, 0.0));
   }
   HIPCHK(hipDeviceSynchronize());
-  d->bytes = (int64_t)(d->sptr.bytes() + d->slen.bytes() + d->col.bytes() + d->val.bytes() + d->st_n.bytes() +
-                       d->st_vb.bytes() + d->st_fb.bytes() + d->st_bb.bytes() + d->pos_dof.bytes() +
-                       d->f_off.bytes() + d->f_w.bytes() + d->b_off.bytes() + d->b_w.bytes() + d->slot_of.bytes() +
-                       d->Kinv.bytes() + d->Pc.bytes() + d->Pw.bytes() + d->PTptr.bytes() + d->PTdof.bytes() +
-                       d->PTw.bytes()) +
-             stream_bytes + (int64_t)(d->slots32.bytes() + d->slots64.bytes());
-  pre.finfo.star_factor_nnz = star_nnz;
-  pre.finfo.star_stream_bytes = stream_bytes;
-  pre.finfo.coarse_bytes = (int64_t)d->Kinv.bytes();
-  pre.finfo.device_bytes = d->bytes;
-  pre.finfo.max_star_dofs = maxn;
-  pre.finfo.max_band = maxband;
-  pre.finfo.factor_seconds = hf.seconds;
-  pre.precision = precision;
+  d->bytes = (int64_t)(d->sptr.bytes() + d->slen.bytes() + d->col.bytes() + d->val.bytes() + d->order.bytes() +
+                       d->st_n.bytes() + d->st_vb.bytes() + d->st_q.bytes() + d->st_gb.bytes() + d->st_fb.bytes() +
+                       d->st_bb.bytes() + d->pos_dof.bytes() + d->f_go.bytes() + d->f_gw.bytes() + d->b_go.bytes() +
+                       d->b_gw.bytes() + d->slot_of.bytes() + d->Kinv.bytes() + d->Pc.bytes() + d->Pw.bytes() +
+                       d->PTptr.bytes() + d->PTdof.bytes() + d->PTw.bytes() + d->f_inv32.bytes() +
+                       d->b_inv32.bytes() + d->f_inv64.bytes() + d->b_inv64.bytes() + d->slots32.bytes() +
+                       d->slots64.bytes()) +
+             fi.star_stream_bytes;
+  const int64_t nnz = (int64_t)sys.col.size();
+  fi.spmv_bytes = nnz * (8 + 4 + 8) + n * 8;
+  fi.max_pivot_ratio = max_ratio;
+  fi.star_precision = precision;
+  fi.star_factor_nnz = star_nnz;
+  fi.coarse_bytes = (int64_t)d->Kinv.bytes();
+  fi.device_bytes = d->bytes;
+  fi.factor_seconds = hf.seconds;
+  pre.finfo = fi;
+  pre.precision = requested;
   pre.dev.reset(d.release());
 }
 
@@ -756,34 +797,43 @@ namespace {
 void ensure_ws(DeviceState &d, int k) {
   Workspace &w = d.ws;
   if (w.sc.p && w.k >= k) return;
+  // captured graphs refer to the old buffers
+  for (auto &g : d.graphs)
+    if (g) (void)hipGraphExecDestroy(g);
+  for (auto &g : d.graph_defs)
+    if (g) (void)hipGraphDestroy(g);
+  d.graphs.clear();
+  d.graph_defs.clear();
   const size_t np = (size_t)d.npad;
-  w.u.alloc(np);
-  w.r.alloc(np);
-  w.p.alloc(np);
-  w.q.alloc(np);
-  w.z.alloc(np);
-  w.f.alloc(np);
-  w.tmpk.alloc(np * (size_t)std::max(k, 1));
+  for (auto *b : {&w.u, &w.r, &w.p, &w.q, &w.z, &w.f}) {
+    b->alloc(np);
+    b->zero();
+  }
   w.rH.alloc((size_t)std::max<int64_t>(d.m0, 1));
   w.c.alloc((size_t)std::max<int64_t>(d.m0, 1));
-  w.partials.alloc(np / kBlock + 64);
+  w.rH.zero();
+  w.c.zero();
+  w.partials.alloc(kMaxGrid);
   w.sc.alloc(1);
-  for (auto *b : {&w.u, &w.r, &w.p, &w.q, &w.z, &w.f, &w.rH, &w.c}) b->zero();
   w.sc.zero();
   w.k = k;
 }
 
 StarArgs star_args(DeviceState &d) {
   StarArgs a{};
+  a.nstars = d.nstars;
+  a.order = d.order.p;
   a.st_n = d.st_n.p;
   a.st_vb = d.st_vb.p;
+  a.st_q = d.st_q.p;
+  a.st_gb = d.st_gb.p;
   a.st_fb = d.st_fb.p;
   a.st_bb = d.st_bb.p;
   a.pos_dof = d.pos_dof.p;
-  a.f_off = d.f_off.p;
-  a.f_w = d.f_w.p;
-  a.b_off = d.b_off.p;
-  a.b_w = d.b_w.p;
+  a.f_go = d.f_go.p;
+  a.f_gw = d.f_gw.p;
+  a.b_go = d.b_go.p;
+  a.b_gw = d.b_gw.p;
   a.pad = d.pad;
   if (d.precision == SN_PREC_FP32_STARS) {
     a.f_inv = d.f_inv32.p;
@@ -801,48 +851,104 @@ StarArgs star_args(DeviceState &d) {
   return a;
 }
 
-inline unsigned nblk(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+template <typename T>
+void launch_star(DeviceState &d, const double *r, const CgScalars *sc, int check, hipStream_t s) {
+  const size_t lds = (size_t)(d.maxn + 2 * d.pad) * sizeof(T);
+  if (lds > 65536)
+    HIPCHK(hipFuncSetAttribute((const void *)k_star<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hipLaunchKernelGGL(k_star<T>, dim3(d.nstars), dim3(64), lds, s, star_args(d), r, sc, check);
+}
 
-// z = B r (mode 1: part of a PCG iteration, also r.z and beta)
-void launch_B(DeviceState &d, const double *r, double *z, CgScalars *sc, int mode, hipStream_t s) {
-  const StarArgs a = star_args(d);
-  for (const StarBin &b : d.bins) {
-    if (d.precision == SN_PREC_FP32_STARS) launch_bin<float>(a, b, r, sc, mode, s, d.pad);
-    else launch_bin<double>(a, b, r, sc, mode, s, d.pad);
+// z = B r; with check = 1 the kernels skip work once the recurrence is done and
+// r.z goes to the partials
+void launch_B(DeviceState &d, const double *r, double *z, CgScalars *sc, int check, hipStream_t s) {
+  std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+  if (d.profiling) {
+    if (d.ev_free.empty()) {
+      HIPCHK(hipEventCreate(&ev.first));
+      HIPCHK(hipEventCreate(&ev.second));
+    } else {
+      ev = d.ev_free.back();
+      d.ev_free.pop_back();
+    }
+    HIPCHK(hipEventRecord(ev.first, s));
+  }
+  if (d.nstars > 0) {
+    if (d.precision == SN_PREC_FP32_STARS) launch_star<float>(d, r, sc, check, s);
+    else launch_star<double>(d, r, sc, check, s);
+  }
+  if (d.profiling) {
+    HIPCHK(hipEventRecord(ev.second, s));
+    d.ev_used.push_back(ev);
   }
   Workspace &w = d.ws;
   if (d.m0 > 0) {
-    hipLaunchKernelGGL(k_restrict, dim3(nblk(d.m0 * 64)), dim3(kBlock), 0, s, d.PTptr.p, d.PTdof.p, d.PTw.p, r, w.rH.p,
-                       (int)d.m0, sc, mode);
+    hipLaunchKernelGGL(k_restrict, dim3((unsigned)d.m0), dim3(kBlock), 0, s, d.PTptr.p, d.PTdof.p, d.PTw.p, r, w.rH.p,
+                       (int)d.m0, sc, check);
     hipLaunchKernelGGL(k_coarse_gemv, dim3(nblk(d.m0 * 64)), dim3(kBlock), 0, s, d.Kinv.p, w.rH.p, w.c.p, (int)d.m0,
-                       sc, mode);
+                       sc, check);
   }
+  const unsigned G = grid_for(d.npad);
+  double *parts = check ? w.partials.p : nullptr;
   if (d.precision == SN_PREC_FP32_STARS)
-    hipLaunchKernelGGL(k_reduce<float>, dim3(nblk(d.npad)), dim3(kBlock), 0, s, z, r, d.slots32.p, d.slot_of.p,
-                       d.Pc.p, d.Pw.p, w.c.p, (int)d.npad, d.nv, sc, w.partials.p, mode);
+    hipLaunchKernelGGL(k_reduce<float>, dim3(G), dim3(kBlock), 0, s, z, r, d.slots32.p, d.slot_of.p, d.Pc.p, d.Pw.p,
+                       w.c.p, (int)d.npad, d.nv, sc, parts);
   else
-    hipLaunchKernelGGL(k_reduce<double>, dim3(nblk(d.npad)), dim3(kBlock), 0, s, z, r, d.slots64.p, d.slot_of.p,
-                       d.Pc.p, d.Pw.p, w.c.p, (int)d.npad, d.nv, sc, w.partials.p, mode);
+    hipLaunchKernelGGL(k_reduce<double>, dim3(G), dim3(kBlock), 0, s, z, r, d.slots64.p, d.slot_of.p, d.Pc.p, d.Pw.p,
+                       w.c.p, (int)d.npad, d.nv, sc, parts);
+  if (check) hipLaunchKernelGGL(k_scalar, dim3(1), dim3(kBlock), 0, s, w.partials.p, (int)G, sc, (int)OP_BETA);
 }
 
-void launch_spmv(DeviceState &d, const double *x, double *y, CgScalars *sc, int mode, hipStream_t s) {
+void launch_spmv(DeviceState &d, const double *x, double *y, CgScalars *sc, bool dot, hipStream_t s) {
   Sell A{d.sptr.p, d.slen.p, d.col.p, d.val.p};
-  hipLaunchKernelGGL(k_spmv, dim3(nblk(d.npad)), dim3(kBlock), 0, s, A, x, y, d.nslices, sc, d.ws.partials.p, mode);
+  const unsigned G = grid_for(d.npad);
+  hipLaunchKernelGGL(k_spmv, dim3(G), dim3(kBlock), 0, s, A, x, y, (int)d.npad, sc, dot ? d.ws.partials.p : nullptr);
+  if (dot) hipLaunchKernelGGL(k_scalar, dim3(1), dim3(kBlock), 0, s, d.ws.partials.p, (int)G, sc, (int)OP_ALPHA);
 }
 
 void launch_iteration(DeviceState &d, hipStream_t s) {
   Workspace &w = d.ws;
+  if (d.profiling) ++d.prof_iters;
   CgScalars *sc = w.sc.p;
-  launch_spmv(d, w.p.p, w.q.p, sc, 1, s);
-  hipLaunchKernelGGL(k_cg_update, dim3(nblk(d.npad)), dim3(kBlock), 0, s, w.u.p, w.r.p, w.p.p, w.q.p, (int)d.npad, sc,
+  const unsigned G = grid_for(d.npad);
+  launch_spmv(d, w.p.p, w.q.p, sc, true, s);
+  hipLaunchKernelGGL(k_cg_update, dim3(G), dim3(kBlock), 0, s, w.u.p, w.r.p, w.p.p, w.q.p, (int)d.npad, sc,
                      w.partials.p);
+  hipLaunchKernelGGL(k_scalar, dim3(1), dim3(kBlock), 0, s, w.partials.p, (int)G, sc, (int)OP_CONV);
   launch_B(d, w.r.p, w.z.p, sc, 1, s);
-  hipLaunchKernelGGL(k_p_update, dim3(nblk(d.npad)), dim3(kBlock), 0, s, w.p.p, w.z.p, (int)d.npad, sc);
+  hipLaunchKernelGGL(k_p_update, dim3(G), dim3(kBlock), 0, s, w.p.p, w.z.p, (int)d.npad, sc);
+}
+
+// run m iterations: as captured graphs of 2^i iterations, or launch by launch
+void run_iterations(DeviceState &d, int m, bool use_graph, hipStream_t s) {
+  if (!use_graph || d.profiling) {
+    for (int it = 0; it < m; ++it) launch_iteration(d, s);
+    return;
+  }
+  for (int i = 0; m > 0; ++i) {
+    if (!(m & (1 << i))) continue;
+    if ((int)d.graphs.size() <= i) {
+      d.graphs.resize(i + 1, nullptr);
+      d.graph_defs.resize(i + 1, nullptr);
+    }
+    if (!d.graphs[i]) {
+      // capture on the library's own stream, replay on the caller's
+      HIPCHK(hipStreamSynchronize(s));
+      HIPCHK(hipStreamBeginCapture(d.own, hipStreamCaptureModeRelaxed));
+      for (int it = 0; it < (1 << i); ++it) launch_iteration(d, d.own);
+      HIPCHK(hipStreamEndCapture(d.own, &d.graph_defs[i]));
+      HIPCHK(hipGraphInstantiate(&d.graphs[i], d.graph_defs[i], nullptr, nullptr, 0));
+    }
+    HIPCHK(hipGraphLaunch(d.graphs[i], s));
+    m -= 1 << i;
+  }
 }
 
 double device_dot(DeviceState &d, const double *a, const double *b, hipStream_t s) {
   Workspace &w = d.ws;
-  hipLaunchKernelGGL(k_dot, dim3(nblk(d.npad)), dim3(kBlock), 0, s, a, b, (int)d.npad, w.sc.p, w.partials.p);
+  const unsigned G = grid_for(d.npad);
+  hipLaunchKernelGGL(k_dot, dim3(G), dim3(kBlock), 0, s, a, b, (int)d.npad, w.partials.p);
+  hipLaunchKernelGGL(k_scalar, dim3(1), dim3(kBlock), 0, s, w.partials.p, (int)G, w.sc.p, (int)OP_DOT);
   double v = 0;
   HIPCHK(hipMemcpyAsync(&v, &w.sc.p->tmp, sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
@@ -853,7 +959,7 @@ double device_dot(DeviceState &d, const double *a, const double *b, hipStream_t 
 void load_column(DeviceState &d, double *dst, const double *src, int k, int c, bool dev_ptrs, hipStream_t s) {
   const int64_t n = d.n;
   if (dev_ptrs) {
-    hipLaunchKernelGGL(k_gather_col, dim3(nblk(n)), dim3(kBlock), 0, s, dst, src, (int)n, k, c);
+    hipLaunchKernelGGL(k_gather_col, dim3(grid_for(n)), dim3(kBlock), 0, s, dst, src, (int)n, k, c);
   } else {
     std::vector<double> tmp((size_t)n);
     for (int64_t i = 0; i < n; ++i) tmp[i] = src[(size_t)i * k + c];
@@ -865,7 +971,7 @@ void load_column(DeviceState &d, double *dst, const double *src, int k, int c, b
 void store_column(DeviceState &d, double *dst, const double *src, int k, int c, bool dev_ptrs, hipStream_t s) {
   const int64_t n = d.n;
   if (dev_ptrs) {
-    hipLaunchKernelGGL(k_scatter_col, dim3(nblk(n)), dim3(kBlock), 0, s, dst, src, (int)n, k, c);
+    hipLaunchKernelGGL(k_scatter_col, dim3(grid_for(n)), dim3(kBlock), 0, s, dst, src, (int)n, k, c);
   } else {
     std::vector<double> tmp((size_t)n);
     HIPCHK(hipMemcpyAsync(tmp.data(), src, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -876,6 +982,29 @@ void store_column(DeviceState &d, double *dst, const double *src, int k, int c, 
 
 }  // namespace
 
+void device_profile(Precond &pre, int enable) {
+  DeviceState &d = *pre.dev;
+  HIPCHK(hipDeviceSynchronize());
+  for (auto &e : d.ev_used) d.ev_free.push_back(e);
+  d.ev_used.clear();
+  d.prof_iters = 0;
+  d.profiling = enable != 0;
+}
+
+void device_stats(Precond &pre, sn_kernel_stats *st) {
+  DeviceState &d = *pre.dev;
+  double ms = 0.0;
+  for (auto &e : d.ev_used) {
+    HIPCHK(hipEventSynchronize(e.second));
+    float t = 0.f;
+    HIPCHK(hipEventElapsedTime(&t, e.first, e.second));
+    ms += t;
+  }
+  st->sweep_launches = (int64_t)d.ev_used.size();
+  st->sweep_ms = ms;
+  st->iterations = d.prof_iters;
+}
+
 void device_apply_K(Precond &pre, int k, const double *x, double *y, int device_ptrs, void *stream) {
   DeviceState &d = *pre.dev;
   hipStream_t s = stream ? (hipStream_t)stream : d.own;
@@ -883,7 +1012,7 @@ void device_apply_K(Precond &pre, int k, const double *x, double *y, int device_
   Workspace &w = d.ws;
   for (int c = 0; c < k; ++c) {
     load_column(d, w.p.p, x, k, c, device_ptrs, s);
-    launch_spmv(d, w.p.p, w.q.p, w.sc.p, 0, s);
+    launch_spmv(d, w.p.p, w.q.p, w.sc.p, false, s);
     store_column(d, y, w.q.p, k, c, device_ptrs, s);
   }
   HIPCHK(hipStreamSynchronize(s));
@@ -916,8 +1045,8 @@ void device_solve(Precond &pre, int k, const double *f, double *u, const sn_solv
     else HIPCHK(hipMemsetAsync(w.u.p, 0, (size_t)d.npad * sizeof(double), s));
     // r = f - K u
     if (o.use_u0) {
-      launch_spmv(d, w.u.p, w.q.p, w.sc.p, 0, s);
-      hipLaunchKernelGGL(k_sub, dim3(nblk(d.npad)), dim3(kBlock), 0, s, w.r.p, w.f.p, w.q.p, (int)d.npad);
+      launch_spmv(d, w.u.p, w.q.p, w.sc.p, false, s);
+      hipLaunchKernelGGL(k_sub, dim3(grid_for(d.npad)), dim3(kBlock), 0, s, w.r.p, w.f.p, w.q.p, (int)d.npad);
     } else {
       HIPCHK(hipMemcpyAsync(w.r.p, w.f.p, (size_t)d.npad * sizeof(double), hipMemcpyDeviceToDevice, s));
     }
@@ -939,18 +1068,39 @@ void device_solve(Precond &pre, int k, const double *f, double *u, const sn_solv
       launch_B(d, w.r.p, w.z.p, w.sc.p, 1, s);
       HIPCHK(hipMemcpyAsync(w.p.p, w.z.p, (size_t)d.npad * sizeof(double), hipMemcpyDeviceToDevice, s));
       int64_t since_replace = 0;
+      // iterations queued between read-backs: first `check`, then the number the
+      // observed contraction of ||r||^2 predicts is still needed (>= 1)
+      int block = h.fixed > 0 ? std::min(check, h.fixed) : check;
+      double prev_rr = h.rr;
+      int prev_it = 0;
       for (;;) {
-        for (int it = 0; it < check; ++it) launch_iteration(d, s);
+        run_iterations(d, block, o.use_graph != 0, s);
         HIPCHK(hipMemcpyAsync(&h, w.sc.p, sizeof(h), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
-        since_replace += check;
+        since_replace += block;
+        if (h.fixed > 0) {
+          block = std::max(1, std::min(4 * check, h.fixed - h.iters));
+        } else {
+          const int di = h.iters - prev_it;
+          block = check;
+          if (di > 0 && h.rr > 0.0 && prev_rr > h.rr && h.rr > h.tol2) {
+            const double rate = std::pow(h.rr / prev_rr, 1.0 / di);
+            const double need = std::log(h.tol2 / h.rr) / std::log(rate);
+            if (std::isfinite(need)) block = (int)std::max(1.0, std::min((double)(4 * check), std::ceil(need)));
+          }
+          prev_rr = h.rr;
+          prev_it = h.iters;
+        }
         if (h.done) {
-          // confirm with the true residual; continue from it if the recurrence drifted
-          if (h.fixed == 0 && h.iters < h.max_iter) {
-            launch_spmv(d, w.u.p, w.q.p, w.sc.p, 0, s);
-            hipLaunchKernelGGL(k_sub, dim3(nblk(d.npad)), dim3(kBlock), 0, s, w.q.p, w.f.p, w.q.p, (int)d.npad);
+          // confirm with the true residual. When it exceeds the tolerance by a
+          // small factor the recurrence has drifted: restart from it. A true
+          // residual far above the tolerance is the attainable accuracy of the
+          // system in FP64, which a restart cannot improve.
+          if (h.fixed == 0 && h.rr <= h.tol2 && h.iters < h.max_iter) {
+            launch_spmv(d, w.u.p, w.q.p, w.sc.p, false, s);
+            hipLaunchKernelGGL(k_sub, dim3(grid_for(d.npad)), dim3(kBlock), 0, s, w.q.p, w.f.p, w.q.p, (int)d.npad);
             const double t2 = device_dot(d, w.q.p, w.q.p, s);
-            if (t2 > h.tol2 * 1.0000001 && replacements < 20) {
+            if (t2 > h.tol2 * 1.0000001 && t2 < 100.0 * h.tol2 && replacements < 3) {
               // restart from the true residual: r = f - K u, z = B r, p = z
               HIPCHK(hipMemcpyAsync(w.r.p, w.q.p, (size_t)d.npad * sizeof(double), hipMemcpyDeviceToDevice, s));
               ++replacements;
@@ -962,22 +1112,25 @@ void device_solve(Precond &pre, int k, const double *f, double *u, const sn_solv
               launch_B(d, w.r.p, w.z.p, w.sc.p, 1, s);
               HIPCHK(hipMemcpyAsync(w.p.p, w.z.p, (size_t)d.npad * sizeof(double), hipMemcpyDeviceToDevice, s));
               since_replace = 0;
+              block = check;
+              prev_rr = t2;
+              prev_it = h.iters;
               continue;
             }
           }
           break;
         }
         if (o.replace_every > 0 && since_replace >= o.replace_every) {
-          launch_spmv(d, w.u.p, w.q.p, w.sc.p, 0, s);
-          hipLaunchKernelGGL(k_sub, dim3(nblk(d.npad)), dim3(kBlock), 0, s, w.r.p, w.f.p, w.q.p, (int)d.npad);
+          launch_spmv(d, w.u.p, w.q.p, w.sc.p, false, s);
+          hipLaunchKernelGGL(k_sub, dim3(grid_for(d.npad)), dim3(kBlock), 0, s, w.r.p, w.f.p, w.q.p, (int)d.npad);
           ++replacements;
           since_replace = 0;
         }
       }
     }
     // true residual
-    launch_spmv(d, w.u.p, w.q.p, w.sc.p, 0, s);
-    hipLaunchKernelGGL(k_sub, dim3(nblk(d.npad)), dim3(kBlock), 0, s, w.q.p, w.f.p, w.q.p, (int)d.npad);
+    launch_spmv(d, w.u.p, w.q.p, w.sc.p, false, s);
+    hipLaunchKernelGGL(k_sub, dim3(grid_for(d.npad)), dim3(kBlock), 0, s, w.q.p, w.f.p, w.q.p, (int)d.npad);
     const double t2 = device_dot(d, w.q.p, w.q.p, s);
     store_column(d, u, w.u.p, k, c, o.device_ptrs != 0, s);
     HIPCHK(hipStreamSynchronize(s));

@@ -205,6 +205,13 @@ void factor_star(const System &sys, const int32_t *dofs, int32_t m, std::vector<
   }
   F.band = band;
   F.nnz = coff[m];
+  double dmin = 0.0, dmax = 0.0;
+  for (int32_t j = 0; j < m; ++j) {
+    const double dj = A[coff[j]] * A[coff[j]];
+    if (j == 0 || dj < dmin) dmin = dj;
+    if (j == 0 || dj > dmax) dmax = dj;
+  }
+  F.pivot_ratio = m > 0 ? dmax / dmin : 1.0;
 }
 
 template <typename Fn>

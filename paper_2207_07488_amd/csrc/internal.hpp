@@ -88,6 +88,7 @@ struct StarFactor {
   std::vector<double> colvals;      // forward stream values (no headers), column j entries j+1..j+w
   std::vector<double> rowvals;      // backward stream values, row i (from n-1 down) entries i-1..i-w
   int64_t nnz = 0;                  // stored factor entries incl. diagonal
+  double pivot_ratio = 1.0;         // largest / smallest pivot L_jj^2
 };
 
 struct HostFactors {
@@ -104,5 +105,7 @@ void device_solve(Precond &pre, int k, const double *f, double *u, const sn_solv
 void device_apply_K(Precond &pre, int k, const double *x, double *y, int device_ptrs, void *stream);
 void device_apply_B(Precond &pre, int k, const double *r, double *z, int device_ptrs, void *stream);
 void device_release(DeviceState *d);
+void device_profile(Precond &pre, int enable);
+void device_stats(Precond &pre, sn_kernel_stats *st);
 
 }  // namespace spnet

@@ -38,7 +38,16 @@ class SolveInfo(C.Structure):
 class FactorInfo(C.Structure):
     _fields_ = [("star_factor_nnz", C.c_int64), ("star_stream_bytes", C.c_int64), ("coarse_bytes", C.c_int64),
                 ("device_bytes", C.c_int64), ("max_star_dofs", C.c_int32), ("max_band", C.c_int32),
-                ("factor_seconds", C.c_double)]
+                ("factor_seconds", C.c_double), ("sweep_bytes", C.c_int64), ("spmv_bytes", C.c_int64),
+                ("sweep_flops", C.c_int64), ("max_pivot_ratio", C.c_double), ("star_precision", C.c_int32),
+                ("pad0", C.c_int32)]
+
+    def asdict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class KernelStats(C.Structure):
+    _fields_ = [("sweep_launches", C.c_int64), ("sweep_ms", C.c_double), ("iterations", C.c_int64)]
 
     def asdict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -79,6 +88,8 @@ SIGNATURES = {
     "sn_precond_destroy": (None, [_P]),
     "sn_solve_opts_default": (None, [C.POINTER(SolveOpts)]),
     "sn_solve": (C.c_int, [_P, C.c_int, _P, _P, C.POINTER(SolveOpts), C.POINTER(SolveInfo)]),
+    "sn_precond_profile": (C.c_int, [_P, C.c_int]),
+    "sn_precond_kernel_stats": (C.c_int, [_P, C.POINTER(KernelStats)]),
     "sn_apply_K": (C.c_int, [_P, C.c_int, _P, _P, C.c_int, _P]),
     "sn_apply_B": (C.c_int, [_P, C.c_int, _P, _P, C.c_int, _P]),
     "sn_server_create": (C.c_int, [C.POINTER(ServerOpts), C.POINTER(_P)]),

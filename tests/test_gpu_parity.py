@@ -1,12 +1,14 @@
 """GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
 
 Bars: integer structure bit-exact (checked on the CPU in test_lib_structure);
-K x to 1e-14; B r (FP64 stars) to 1e-10; the plain PCG iterate at the oracle's
-own iteration count to 1e-10 relative; the mixed path (FP32 stars) to the same
-true residual 1e-8. Tolerance derivation: both sides compute the same Krylov
+K x to 1e-14; B r (FP64 stars) and the plain PCG iterate at the oracle's own
+iteration count to tol = max(1e-10, 10 * 2^-52 * kappa), kappa the largest
+condition number of the local and coarse matrices; the mixed path (FP32 stars)
+to the same true residual 1e-8. Derivation: both sides compute the same Krylov
 iterate; they differ by the rounding of different factor orderings and
-summation orders, amplified by at most cond(K_j) ~ 1e4-1e6 in the local
-solves, i.e. ~1e-12 relative per application.
+summation orders, which a direct solve amplifies by at most cond(K_j). For the
+heat model kappa ~ 1e4-1e5, so the bar is 1e-10; the truss model's 1e-6
+isotropic term gives kappa ~ 1e10 and a bar near 2e-5.
 """
 import numpy as np
 import pytest
@@ -20,8 +22,29 @@ CASES = {
     "fiber2d_300": (2, 300, 0.2, 0.0, 1, 1, 4, 0),
     "fiber2d_2k": (2, 2000, 0.08, 0.0, 1, 1, 8, 0),
     "fiber3d_6k": (3, 6000, 0.12, 0.012, 4, 4, 4, 0),
-    "truss3d_3k": (3, 3000, 0.2, 0.02, 4, 0, 4, 1),
+    "truss3d_1500": (3, 1500, 0.25, 0.025, 4, 0, 4, 1),
 }
+_KAPPA = {}
+
+
+def _tol(orc, name, opre):
+    """max(1e-10, 10 u kappa) with kappa from dense eigenvalues of every local matrix
+    and of K_0 (computed once per case)."""
+    if CASES[name][7] == 0:
+        return 1e-10
+    if name not in _KAPPA:
+        import scipy.sparse as sp
+        rp, ci, v = opre.sys.csr()
+        K = sp.csr_matrix((v, ci, rp), shape=(opre.sys.n, opre.sys.n))
+        spp, sd, _ = opre.stars()
+        kap = 1.0
+        for j in range(opre.nstars):
+            d = sd[spp[j]:spp[j + 1]]
+            ev = np.linalg.eigvalsh(K[d][:, d].toarray())
+            kap = max(kap, ev[-1] / ev[0])
+        ev = np.linalg.eigvalsh(opre.K0_dense())
+        _KAPPA[name] = max(kap, ev[-1] / ev[0])
+    return max(1e-10, 10 * 2.0 ** -52 * _KAPPA[name])
 
 
 @pytest.fixture(scope="module")
@@ -65,7 +88,7 @@ def test_preconditioner_parity_fp64(S, orc, name):
     r = W.rhs(opre.sys.n, 1, seed=4)[:, 0]
     z = gpre.apply_B(r)
     ref = opre.apply_B(r)
-    assert _rel(z, ref) <= 1e-10
+    assert _rel(z, ref) <= _tol(orc, name, opre)
 
 
 @pytest.mark.parametrize("name", list(CASES))
@@ -74,8 +97,14 @@ def test_preconditioner_fp32_stars(S, orc, name):
     r = W.rhs(opre.sys.n, 1, seed=4)[:, 0]
     z = gpre.apply_B(r)
     ref = opre.apply_B(r)
-    # FP32 factors and sweeps: ~ cond(K_j) * 6e-8
-    assert _rel(z, ref) <= 5e-3
+    fi = gpre.factor_info()
+    if fi["star_precision"] == S.FP64:
+        # FP32 could not resolve these local solves: the library kept FP64 factors
+        assert fi["max_pivot_ratio"] * 2.0 ** -24 > 0.05
+        assert _rel(z, ref) <= _tol(orc, name, opre)
+    else:
+        # FP32 factors and sweeps: ~ cond(K_j) * 6e-8
+        assert _rel(z, ref) <= 5e-3
 
 
 @pytest.mark.parametrize("name", list(CASES))
@@ -85,25 +114,27 @@ def test_pcg_plain_parity(S, orc, name):
     u_o, it_o, info_o = opre.pcg(f, rtol=1e-8)
     u_g, info = gpre.solve(f, fixed_iters=it_o)
     assert info[0]["iters"] == it_o
-    assert _rel(u_g, u_o) <= 1e-10
+    assert _rel(u_g, u_o) <= _tol(orc, name, opre)
     # the tolerance-stopped run takes the same number of iterations
     hist = opre.pcg(f, rtol=1e-8, history=True)[2]["hist_r"]
     u_t, info_t = gpre.solve(f, rtol=1e-8)
     near = abs(hist[-1] / np.linalg.norm(f) - 1e-8) < 0.01e-8
     assert info_t[0]["iters"] == it_o or near
-    assert info_t[0]["res_true"] <= 1.0001e-8 and info_t[0]["converged"]
+    # the true residual reaches the tolerance, or the oracle's own attainable
+    # accuracy where FP64 cannot get there (truss model)
+    assert info_t[0]["res_true"] <= max(1.0001e-8, 2 * info_o["true_res"]) and info_t[0]["converged"]
 
 
 @pytest.mark.parametrize("name", list(CASES))
 def test_pcg_mixed(S, orc, name):
     opre, gpre = _pair(S, orc, name, S.FP32_STARS)
     f = W.rhs(opre.sys.n, 1, seed=7)[:, 0]
-    u_o, it_o, _ = opre.pcg(f, rtol=1e-8)
+    u_o, it_o, info_o = opre.pcg(f, rtol=1e-8)
     u_g, info = gpre.solve(f, rtol=1e-8)
-    assert info[0]["converged"] and info[0]["res_true"] <= 1.0001e-8
+    assert info[0]["converged"] and info[0]["res_true"] <= max(1.0001e-8, 2 * info_o["true_res"])
     assert info[0]["iters"] <= it_o + 3
     # the error against the FP64 oracle solution is of the order of the tolerance times cond
-    assert _rel(u_g, u_o) <= 1e-5
+    assert _rel(u_g, u_o) <= max(1e-5, _tol(orc, name, opre))
 
 
 def test_multi_rhs_columns_independent(S, orc):
@@ -131,3 +162,16 @@ def test_star_policy_free(S, orc):
     opre, gpre = _pair(S, orc, "fiber2d_300", S.FP64, policy=1)
     r = W.rhs(opre.sys.n, 1, seed=4)[:, 0]
     assert _rel(gpre.apply_B(r), opre.apply_B(r)) <= 1e-10
+
+
+def test_graph_replay_matches_eager(S, orc):
+    """Iteration blocks replayed from captured HIP graphs give the eager result,
+    bit for bit, on every replay (with eager work in between)."""
+    opre, gpre = _pair(S, orc, "fiber2d_2k", S.FP32_STARS)
+    f = W.rhs(opre.sys.n, 1, seed=7)[:, 0]
+    u_e, i_e = gpre.solve(f, rtol=1e-8)
+    for rep in range(3):
+        u_g, i_g = gpre.solve(f, rtol=1e-8, use_graph=True)
+        assert i_g[0]["iters"] == i_e[0]["iters"]
+        assert np.array_equal(u_g, u_e), rep
+        gpre.apply_B(f)  # eager work between replays
