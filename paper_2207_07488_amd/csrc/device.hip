@@ -9,8 +9,9 @@
 //   coarse      r_H = P^T r, c = K_0^{-1} r_H (dense inverse)
 //   reduce      z = P c + sum of the star slots of every dof, r.z   -> beta
 //   p_update    p = z + beta p
-// Dot products are reduced per block and then in a fixed order by the last
-// block to finish, so results do not depend on scheduling.
+// Dot products are reduced per block in a fixed order and the partials are
+// combined in a fixed order by a one-block kernel, so results do not depend on
+// scheduling. The star sweeps live in star_kernel.hpp.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -21,28 +22,14 @@
 #include <type_traits>
 #include <vector>
 
-#include "internal.hpp"
+#include "device_common.hpp"
 
 namespace spnet {
 
-#define HIPCHK(x)                                                                                \
-  do {                                                                                           \
-    hipError_t e_ = (x);                                                                         \
-    if (e_ != hipSuccess) fail(SN_EDEVICE, std::string(#x) + ": " + hipGetErrorString(e_));      \
-  } while (0)
 
 constexpr int kBlock = 256;   // threads of the vector kernels
 constexpr int kSlice = 64;    // rows per ELL slice (one wavefront)
 constexpr int kMaxGrid = 1024;  // blocks of the grid-stride vector kernels (= partial sums)
-
-// ---------------------------------------------------------------------------
-// device scalars of one PCG recurrence
-// ---------------------------------------------------------------------------
-struct CgScalars {
-  double rho, alpha, beta, pq, rr, rz, f2, tol2;
-  double tmp;  // scratch dot result
-  int32_t iters, done, max_iter, fixed, first, pad0;
-};
 
 enum ScalarOp { OP_ALPHA = 0, OP_CONV = 1, OP_BETA = 2, OP_DOT = 3 };
 
@@ -230,226 +217,6 @@ __global__ __launch_bounds__(kBlock) void k_scatter_col(double *dst, const doubl
 }
 
 // ---------------------------------------------------------------------------
-// Star sweeps. One wavefront solves L_j L_j^T z = r[S_j] for one star.
-//
-// The vector of the star lives in LDS in factor order. A sweep walks the
-// steps of a stream: the forward stream holds the columns of L (step j: the
-// entries L_{j+1..j+w, j}), the backward stream the rows of L from the last
-// (step s = row i = n-1-s: the entries L_{i, i-1..i-w}); read in reverse
-// order, the vector makes the backward sweep the same recurrence as the
-// forward one. Stream values are divided by the step's pivot, so a step
-// subtracts m_t g_j from row j+1+t with the raw running value g_j, and the
-// pivot division is applied to 64 finished rows at once.
-//
-// Window: before step j, lane l of register g[q] holds the running value of
-// row j + l + 64 q; lane 0 of g[0] is final. The window slides by one lane
-// (DPP wave shift left), the next row enters at lane 63 of the last register.
-// SG consecutive steps (4 in FP32, 2 in FP64) are packed lane-major, so one
-// 16-byte load per lane and register fetches them all; groups are loaded RG
-// groups ahead into a register ring, their offsets and widths arrive 64 at a
-// time.
-// ---------------------------------------------------------------------------
-struct StarArgs {
-  int32_t nstars;
-  const int32_t *order;    // stars, longest first
-  const int32_t *st_n;     // positions of the star
-  const int32_t *st_vb;    // base in the per-position arrays
-  const int32_t *st_q;     // window registers
-  const int32_t *st_gb;    // base in the per-group arrays
-  const int64_t *st_fb;    // forward stream value base
-  const int64_t *st_bb;    // backward stream value base
-  const int32_t *pos_dof;  // global dof of each position (factor order)
-  const int32_t *f_go, *f_gw, *b_go, *b_gw;  // per group: value offset (from the star base), width
-  const void *f_inv, *b_inv;                 // 1/pivot per step (T)
-  const void *f_val, *b_val;                 // packed stream values (T)
-  void *slots;                               // T, per position
-  int32_t pad;                               // LDS zero padding each side (elements)
-};
-
-template <typename T>
-struct Pack;
-template <>
-struct Pack<float> {
-  using V = float4;
-  static constexpr int SG = 4;
-  static __device__ __forceinline__ float get(const V &v, int k) {
-    return k == 0 ? v.x : (k == 1 ? v.y : (k == 2 ? v.z : v.w));
-  }
-  static __device__ __forceinline__ V masked(bool keep, const V &v) {
-    return V{keep ? v.x : 0.f, keep ? v.y : 0.f, keep ? v.z : 0.f, keep ? v.w : 0.f};
-  }
-  static __device__ __forceinline__ float first(float v) {
-    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
-  }
-  // lanes 0..62 take lane+1, lane 63 takes `in`
-  static __device__ __forceinline__ float shl(float v, float in) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(in), __float_as_int(v), 0x130, 0xF, 0xF, false));
-  }
-  template <int L>
-  static __device__ __forceinline__ float put(float vec, float s) {
-    int r = __float_as_int(vec);
-    asm volatile("v_writelane_b32 %0, %1, %2" : "+v"(r) : "s"(__float_as_int(s)), "i"(L));
-    return __int_as_float(r);
-  }
-};
-template <>
-struct Pack<double> {
-  using V = double2;
-  static constexpr int SG = 2;
-  static __device__ __forceinline__ double get(const V &v, int k) { return k == 0 ? v.x : v.y; }
-  static __device__ __forceinline__ V masked(bool keep, const V &v) {
-    return V{keep ? v.x : 0.0, keep ? v.y : 0.0};
-  }
-  static __device__ __forceinline__ int lo(double v) { return (int)(uint32_t)(__double_as_longlong(v)); }
-  static __device__ __forceinline__ int hi(double v) { return (int)(uint32_t)(__double_as_longlong(v) >> 32); }
-  static __device__ __forceinline__ double mk(int l, int h) {
-    return __longlong_as_double(((long long)(uint32_t)h << 32) | (long long)(uint32_t)l);
-  }
-  static __device__ __forceinline__ double first(double v) {
-    return mk(__builtin_amdgcn_readfirstlane(lo(v)), __builtin_amdgcn_readfirstlane(hi(v)));
-  }
-  static __device__ __forceinline__ double shl(double v, double in) {
-    return mk(__builtin_amdgcn_update_dpp(lo(in), lo(v), 0x130, 0xF, 0xF, false),
-              __builtin_amdgcn_update_dpp(hi(in), hi(v), 0x130, 0xF, 0xF, false));
-  }
-  template <int L>
-  static __device__ __forceinline__ double put(double vec, double s) {
-    int l = lo(vec), h = hi(vec);
-    asm volatile("v_writelane_b32 %0, %1, %2" : "+v"(l) : "s"(lo(s)), "i"(L));
-    asm volatile("v_writelane_b32 %0, %1, %2" : "+v"(h) : "s"(hi(s)), "i"(L));
-    return mk(l, h);
-  }
-};
-
-template <int S, int E>
-struct StaticFor {
-  template <typename F>
-  static __device__ __forceinline__ void run(F &&f) {
-    f(std::integral_constant<int, S>{});
-    StaticFor<S + 1, E>::run(f);
-  }
-};
-template <int E>
-struct StaticFor<E, E> {
-  template <typename F>
-  static __device__ __forceinline__ void run(F &&) {}
-};
-
-// One sweep over n steps. vec points at position 0 of the LDS vector (with
-// `pad` zero elements on both sides); REV reads it in reverse.
-template <typename T, int Q, int RG, bool REV>
-__device__ __forceinline__ void sweep(T *vec, int n, const int32_t *__restrict__ go, const int32_t *__restrict__ gw,
-                                      const T *__restrict__ inv, const T *__restrict__ vals) {
-  using P = Pack<T>;
-  using V = typename P::V;
-  constexpr int SG = P::SG, GPB = 64 / SG;
-  static_assert(GPB % RG == 0, "ring must divide the groups of a block");
-  const int lane = threadIdx.x & 63;
-  auto at = [&](int p) -> int { return REV ? (n - 1 - p) : p; };
-  const int ngroups = (n + SG - 1) / SG;
-  T g[Q];
-#pragma unroll
-  for (int q = 0; q < Q; ++q) g[q] = vec[at(lane + 64 * q)];
-  // rows entering the window, read NP steps ahead: nxt[s % NP] is row j + 64 Q
-  constexpr int NP = 8;
-  T nxt[NP];
-#pragma unroll
-  for (int i = 0; i < NP; ++i) nxt[i] = vec[at(64 * Q + i)];
-  // group headers of the 64 groups from the current block's first group
-  int hoA = lane < ngroups ? go[lane] : 0, hwA = lane < ngroups ? gw[lane] : 0;
-  T hinv = lane < n ? inv[lane] : T(0);
-  V ring[RG][Q];
-#pragma unroll
-  for (int rg = 0; rg < RG; ++rg) {
-    const int o = __builtin_amdgcn_readlane(hoA, rg), w = __builtin_amdgcn_readlane(hwA, rg);
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      const V v = *reinterpret_cast<const V *>(vals + o + (lane + 64 * q) * SG);
-      ring[rg][q] = P::masked(lane + 64 * q < w, v);
-    }
-  }
-  for (int jb = 0; jb < n; jb += 64) {
-    const int gb = jb / SG;
-    const int hoB = gb + GPB + lane < ngroups ? go[gb + GPB + lane] : 0;
-    const int hwB = gb + GPB + lane < ngroups ? gw[gb + GPB + lane] : 0;
-    const T hinvN = jb + 64 + lane < n ? inv[jb + 64 + lane] : T(0);
-    T ybuf = T(0);
-    StaticFor<0, 64>::run([&](auto sc) {
-      constexpr int s = decltype(sc)::value;
-      constexpr int gi = s / SG, k = s % SG;
-      const T gj = P::first(g[0]);
-      T carry[Q];
-#pragma unroll
-      for (int q = 0; q + 1 < Q; ++q) carry[q] = P::first(g[q + 1]);
-#pragma unroll
-      for (int q = 0; q + 1 < Q; ++q) g[q] = P::shl(g[q], carry[q]);
-      g[Q - 1] = P::shl(g[Q - 1], nxt[s % NP]);
-      nxt[s % NP] = vec[at(jb + s + 64 * Q + NP)];
-      ybuf = P::template put<s>(ybuf, gj);
-#pragma unroll
-      for (int q = 0; q < Q; ++q) g[q] = g[q] - P::get(ring[gi % RG][q], k) * gj;
-      if constexpr (k == SG - 1) {
-        // the group is consumed: fetch the group RG positions ahead
-        constexpr int li = gi + RG;
-        const int o = __builtin_amdgcn_readlane(hoA, li), w = __builtin_amdgcn_readlane(hwA, li);
-#pragma unroll
-        for (int q = 0; q < Q; ++q) {
-          const V v = *reinterpret_cast<const V *>(vals + o + (lane + 64 * q) * SG);
-          ring[gi % RG][q] = P::masked(lane + 64 * q < w, v);
-        }
-      }
-    });
-    if (jb + lane < n) vec[at(jb + lane)] = ybuf * hinv;
-    hinv = hinvN;
-    hoA = hoB;
-    hwA = hwB;
-  }
-}
-
-template <typename T, int Q>
-__device__ __forceinline__ void star_solve(const StarArgs &a, int st, int n, T *vec) {
-  constexpr int GPB = 64 / Pack<T>::SG;
-  constexpr int RG0 = 16 / Q;
-  constexpr int RG = RG0 >= GPB ? GPB : (RG0 >= 8 ? 8 : (RG0 >= 4 ? 4 : (RG0 >= 2 ? 2 : 1)));
-  const int vb = a.st_vb[st], gbase = a.st_gb[st];
-  sweep<T, Q, RG, false>(vec, n, a.f_go + gbase, a.f_gw + gbase, static_cast<const T *>(a.f_inv) + vb,
-                         static_cast<const T *>(a.f_val) + a.st_fb[st]);
-  __syncthreads();
-  sweep<T, Q, RG, true>(vec, n, a.b_go + gbase, a.b_gw + gbase, static_cast<const T *>(a.b_inv) + vb,
-                        static_cast<const T *>(a.b_val) + a.st_bb[st]);
-}
-
-template <typename T>
-__global__ __launch_bounds__(64) void k_star(StarArgs a, const double *__restrict__ r, const CgScalars *sc, int check) {
-  if (check && sc->done) return;
-  extern __shared__ __align__(16) unsigned char lds_raw[];
-  T *lds = reinterpret_cast<T *>(lds_raw);
-  const int wv = blockIdx.x;
-  if (wv >= a.nstars) return;
-  const int st = a.order[wv];
-  const int n = a.st_n[st], vb = a.st_vb[st], Q = a.st_q[st];
-  const int lane = threadIdx.x;
-  T *vec = lds + a.pad;
-  for (int i = lane; i < a.pad; i += 64) {
-    lds[i] = T(0);
-    vec[n + i] = T(0);
-  }
-  const int32_t *dofs = a.pos_dof + vb;
-  for (int p = lane; p < n; p += 64) vec[p] = (T)r[dofs[p]];
-  __syncthreads();
-  switch (Q) {
-    case 1: star_solve<T, 1>(a, st, n, vec); break;
-    case 2: star_solve<T, 2>(a, st, n, vec); break;
-    case 4: star_solve<T, 4>(a, st, n, vec); break;
-    case 8: star_solve<T, 8>(a, st, n, vec); break;
-    default: star_solve<T, 16>(a, st, n, vec); break;
-  }
-  __syncthreads();
-  T *out = static_cast<T *>(a.slots) + vb;
-  for (int p = lane; p < n; p += 64) out[p] = vec[p];
-}
-
-// ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
 template <typename T>
@@ -495,7 +262,11 @@ struct DeviceState {
   DBuf<double> val;
   // stars
   int32_t nstars = 0, pad = 0, maxn = 0;
-  DBuf<int32_t> order, st_n, st_vb, st_q, st_gb, pos_dof, f_go, f_gw, b_go, b_gw, slot_of;
+  int32_t n_narrow = 0, n_wide = 0, maxn_narrow = 0, maxn_wide = 0;
+  hipStream_t aux = nullptr;       // wide stars run beside the narrow ones
+  hipEvent_t fork = nullptr, join = nullptr;
+  DBuf<int32_t> order_narrow, order_wide, st_n, st_vb, st_q, st_gb, pos_dof, slot_of;
+  DBuf<uint32_t> f_hdr, b_hdr;
   DBuf<int64_t> st_fb, st_bb;
   DBuf<float> f_inv32, b_inv32, f_val32, b_val32, slots32;
   DBuf<double> f_inv64, b_inv64, f_val64, b_val64, slots64;
@@ -518,6 +289,9 @@ struct DeviceState {
       if (g) (void)hipGraphDestroy(g);
     for (auto &e : ev_used) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
     for (auto &e : ev_free) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
+    if (fork) (void)hipEventDestroy(fork);
+    if (join) (void)hipEventDestroy(join);
+    if (aux) (void)hipStreamDestroy(aux);
     if (own) (void)hipStreamDestroy(own);
   }
 };
@@ -537,35 +311,50 @@ int window_regs(int band) {
 inline unsigned nblk(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 inline unsigned grid_for(int64_t n) { return std::max(1u, std::min<unsigned>(kMaxGrid, nblk(n))); }
 
-// Pack one sweep stream of a star: steps in groups of SG, each group padded
-// to its widest step, lane-major (entry t of the SG steps adjacent), values
-// divided by the step's pivot.
+// Pack one sweep stream of a star: steps in groups of SG (the first step of
+// every group a multiple of SG), values divided by the step's pivot. Lane l
+// and window register q read slot u = ((l - j0 - 1) mod 64) + 64 q of the group
+// with first step j0 (mod 64); slot u holds, for k = 0..SG-1, entry
+// t = 64 q + ((u mod 64 - k) mod 64) of step j0 + k (zero past the step's width).
+// The group stores slots 0..W-1, W one past the last non-zero slot.
 template <typename T>
 void pack_stream(const std::vector<int32_t> &width, const std::vector<double> &vals, const std::vector<double> &inv,
-                 int SG, std::vector<T> &out, std::vector<int32_t> &go, std::vector<int32_t> &gw, int64_t base) {
+                 int SG, int Q, std::vector<T> &out, std::vector<uint32_t> &hdr, int64_t base) {
   const int n = (int)width.size();
   std::vector<int64_t> start((size_t)n + 1, 0);
   for (int j = 0; j < n; ++j) start[j + 1] = start[j] + width[j];
-  for (int g0 = 0; g0 < n; g0 += SG) {
+  auto entry = [&](int j, int slot, int k) -> double {
+    const int jj = j + k;
+    if (jj >= n) return 0.0;
+    const int q = slot / 64, u = slot % 64;
+    const int t = 64 * q + ((u - k) & 63);
+    if (t >= width[jj]) return 0.0;
+    return vals[(size_t)(start[jj] + t)] * inv[jj];
+  };
+  for (int j0 = 0; j0 < n; j0 += SG) {
     int W = 0;
-    for (int k = 0; k < SG && g0 + k < n; ++k) W = std::max(W, width[g0 + k]);
-    go.push_back((int32_t)((int64_t)out.size() - base));
-    gw.push_back(W);
-    for (int t = 0; t < W; ++t)
-      for (int k = 0; k < SG; ++k) {
-        const int j = g0 + k;
-        double v = 0.0;
-        if (j < n && t < width[j]) v = vals[(size_t)(start[j] + t)] * inv[j];
-        out.push_back((T)v);
-      }
+    for (int slot = 0; slot < 64 * Q; ++slot)
+      for (int k = 0; k < SG; ++k)
+        if (entry(j0, slot, k) != 0.0) W = slot + 1;
+    const int64_t off = ((int64_t)out.size() - base) / SG;  // 16-byte units (groups are whole slots)
+    if (off >= (1 << 21) || W >= (1 << 11)) fail(SN_EINVAL, "star stream too large for the packed group headers");
+    hdr.push_back((uint32_t)W << 21 | (uint32_t)off);
+    for (int slot = 0; slot < W; ++slot)
+      for (int k = 0; k < SG; ++k) out.push_back((T)entry(j0, slot, k));
   }
+  // zero headers past the end: the sweep reads whole blocks of headers ahead
+  const int GPB = 64 / SG;
+  const size_t ng = (size_t)(n + SG - 1) / SG;
+  const size_t padded = (ng + GPB - 1) / GPB * GPB + 3 * GPB;
+  hdr.resize(hdr.size() + (padded - ng), 0u);
 }
 
 template <typename T>
 void upload_stars(DeviceState &d, const Precond &pre, const HostFactors &hf, sn_factor_info &fi) {
   constexpr int SG = 16 / (int)sizeof(T);
   const int64_t ns = (int64_t)hf.stars.size();
-  std::vector<int32_t> st_n(ns), st_vb(ns), st_q(ns), st_gb(ns), pos_dof, f_go, f_gw, b_go, b_gw;
+  std::vector<int32_t> st_n(ns), st_vb(ns), st_q(ns), st_gb(ns), pos_dof;
+  std::vector<uint32_t> f_hdr, b_hdr;
   std::vector<int64_t> st_fb(ns), st_bb(ns);
   std::vector<T> f_val, b_val, f_inv, b_inv;
   int64_t tot = 0, real_vals = 0;
@@ -577,7 +366,7 @@ void upload_stars(DeviceState &d, const Precond &pre, const HostFactors &hf, sn_
     st_n[s] = F.n;
     st_vb[s] = (int32_t)tot;
     st_q[s] = q;
-    st_gb[s] = (int32_t)f_go.size();
+    st_gb[s] = (int32_t)f_hdr.size();
     maxq = std::max(maxq, q);
     maxband = std::max(maxband, F.band);
     d.maxn = std::max(d.maxn, F.n);
@@ -585,9 +374,10 @@ void upload_stars(DeviceState &d, const Precond &pre, const HostFactors &hf, sn_
     std::vector<double> finv(F.invdiag), binv((size_t)F.n);
     for (int p = 0; p < F.n; ++p) binv[p] = F.invdiag[F.n - 1 - p];
     st_fb[s] = (int64_t)f_val.size();
-    pack_stream<T>(F.width_fwd, F.colvals, finv, SG, f_val, f_go, f_gw, st_fb[s]);
+    pack_stream<T>(F.width_fwd, F.colvals, finv, SG, q, f_val, f_hdr, st_fb[s]);
     st_bb[s] = (int64_t)b_val.size();
-    pack_stream<T>(F.width_bwd, F.rowvals, binv, SG, b_val, b_go, b_gw, st_bb[s]);
+    pack_stream<T>(F.width_bwd, F.rowvals, binv, SG, q, b_val, b_hdr, st_bb[s]);
+    if (f_hdr.size() != b_hdr.size()) fail(SN_EINVAL, "internal: header arrays out of step");
     const int32_t *dofs = &pre.star_dofs[pre.star_ptr[s]];
     for (int p = 0; p < F.n; ++p) {
       pos_dof.push_back(dofs[F.perm[p]]);
@@ -604,10 +394,16 @@ void upload_stars(DeviceState &d, const Precond &pre, const HostFactors &hf, sn_
   f_val.resize(f_val.size() + slack, T(0));
   b_val.resize(b_val.size() + slack, T(0));
   d.pad = 64 * (maxq + 2);
-  // schedule: longest chain first
-  std::vector<int32_t> order((size_t)ns);
-  for (int64_t s = 0; s < ns; ++s) order[s] = (int32_t)s;
-  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return st_n[a] > st_n[b]; });
+  // schedule: longest chain first, narrow and wide windows in separate kernels
+  std::vector<int32_t> narrow, wide;
+  for (int64_t s = 0; s < ns; ++s) (st_q[s] <= 2 ? narrow : wide).push_back((int32_t)s);
+  auto by_len = [&](int32_t a, int32_t b) { return st_n[a] > st_n[b]; };
+  std::stable_sort(narrow.begin(), narrow.end(), by_len);
+  std::stable_sort(wide.begin(), wide.end(), by_len);
+  d.n_narrow = (int32_t)narrow.size();
+  d.n_wide = (int32_t)wide.size();
+  d.maxn_narrow = narrow.empty() ? 0 : st_n[narrow[0]];
+  d.maxn_wide = wide.empty() ? 0 : st_n[wide[0]];
   // dof -> slots in ascending star order
   std::vector<int32_t> slot_of((size_t)d.npad * d.nv, -1);
   {
@@ -620,7 +416,8 @@ void upload_stars(DeviceState &d, const Precond &pre, const HostFactors &hf, sn_
       }
   }
   d.nstars = (int32_t)ns;
-  d.order.upload(order);
+  d.order_narrow.upload(narrow);
+  d.order_wide.upload(wide);
   d.st_n.upload(st_n);
   d.st_vb.upload(st_vb);
   d.st_q.upload(st_q);
@@ -628,10 +425,8 @@ void upload_stars(DeviceState &d, const Precond &pre, const HostFactors &hf, sn_
   d.st_fb.upload(st_fb);
   d.st_bb.upload(st_bb);
   d.pos_dof.upload(pos_dof);
-  d.f_go.upload(f_go);
-  d.f_gw.upload(f_gw);
-  d.b_go.upload(b_go);
-  d.b_gw.upload(b_gw);
+  d.f_hdr.upload(f_hdr);
+  d.b_hdr.upload(b_hdr);
   d.slot_of.upload(slot_of);
   int64_t stream_bytes;
   if constexpr (sizeof(T) == 4) {
@@ -674,6 +469,9 @@ void device_setup(Precond &pre, const HostFactors &hf, int precision) {
   auto d = std::make_unique<DeviceState>();
   HIPCHK(hipGetDevice(&d->device));
   HIPCHK(hipStreamCreateWithFlags(&d->own, hipStreamNonBlocking));
+  HIPCHK(hipStreamCreateWithFlags(&d->aux, hipStreamNonBlocking));
+  HIPCHK(hipEventCreateWithFlags(&d->fork, hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&d->join, hipEventDisableTiming));
   const System &sys = *pre.sys;
   d->precision = precision;
   d->n = sys.n;
@@ -771,10 +569,11 @@ void device_setup(Precond &pre, const HostFactors &hf, int precision) {
     d->Pw.upload(std::vector<double>((size_t)npad * nv, 0.0));
   }
   HIPCHK(hipDeviceSynchronize());
-  d->bytes = (int64_t)(d->sptr.bytes() + d->slen.bytes() + d->col.bytes() + d->val.bytes() + d->order.bytes() +
+  d->bytes = (int64_t)(d->sptr.bytes() + d->slen.bytes() + d->col.bytes() + d->val.bytes() + d->order_narrow.bytes() +
+                       d->order_wide.bytes() +
                        d->st_n.bytes() + d->st_vb.bytes() + d->st_q.bytes() + d->st_gb.bytes() + d->st_fb.bytes() +
-                       d->st_bb.bytes() + d->pos_dof.bytes() + d->f_go.bytes() + d->f_gw.bytes() + d->b_go.bytes() +
-                       d->b_gw.bytes() + d->slot_of.bytes() + d->Kinv.bytes() + d->Pc.bytes() + d->Pw.bytes() +
+                       d->st_bb.bytes() + d->pos_dof.bytes() + d->f_hdr.bytes() + d->b_hdr.bytes() +
+                       d->slot_of.bytes() + d->Kinv.bytes() + d->Pc.bytes() + d->Pw.bytes() +
                        d->PTptr.bytes() + d->PTdof.bytes() + d->PTw.bytes() + d->f_inv32.bytes() +
                        d->b_inv32.bytes() + d->f_inv64.bytes() + d->b_inv64.bytes() + d->slots32.bytes() +
                        d->slots64.bytes()) +
@@ -821,8 +620,8 @@ void ensure_ws(DeviceState &d, int k) {
 
 StarArgs star_args(DeviceState &d) {
   StarArgs a{};
-  a.nstars = d.nstars;
-  a.order = d.order.p;
+  a.nstars = d.n_narrow;
+  a.order = d.order_narrow.p;
   a.st_n = d.st_n.p;
   a.st_vb = d.st_vb.p;
   a.st_q = d.st_q.p;
@@ -830,10 +629,8 @@ StarArgs star_args(DeviceState &d) {
   a.st_fb = d.st_fb.p;
   a.st_bb = d.st_bb.p;
   a.pos_dof = d.pos_dof.p;
-  a.f_go = d.f_go.p;
-  a.f_gw = d.f_gw.p;
-  a.b_go = d.b_go.p;
-  a.b_gw = d.b_gw.p;
+  a.f_hdr = d.f_hdr.p;
+  a.b_hdr = d.b_hdr.p;
   a.pad = d.pad;
   if (d.precision == SN_PREC_FP32_STARS) {
     a.f_inv = d.f_inv32.p;
@@ -851,13 +648,6 @@ StarArgs star_args(DeviceState &d) {
   return a;
 }
 
-template <typename T>
-void launch_star(DeviceState &d, const double *r, const CgScalars *sc, int check, hipStream_t s) {
-  const size_t lds = (size_t)(d.maxn + 2 * d.pad) * sizeof(T);
-  if (lds > 65536)
-    HIPCHK(hipFuncSetAttribute((const void *)k_star<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  hipLaunchKernelGGL(k_star<T>, dim3(d.nstars), dim3(64), lds, s, star_args(d), r, sc, check);
-}
 
 // z = B r; with check = 1 the kernels skip work once the recurrence is done and
 // r.z goes to the partials
@@ -874,8 +664,27 @@ void launch_B(DeviceState &d, const double *r, double *z, CgScalars *sc, int che
     HIPCHK(hipEventRecord(ev.first, s));
   }
   if (d.nstars > 0) {
-    if (d.precision == SN_PREC_FP32_STARS) launch_star<float>(d, r, sc, check, s);
-    else launch_star<double>(d, r, sc, check, s);
+    StarArgs a = star_args(d);
+    StarArgs aw = a;
+    aw.nstars = d.n_wide;
+    aw.order = d.order_wide.p;
+    const bool f32 = d.precision == SN_PREC_FP32_STARS;
+    if (d.n_wide > 0 && d.n_narrow > 0) {
+      // fork: the wide stars run on the auxiliary stream beside the narrow ones
+      HIPCHK(hipEventRecord(d.fork, s));
+      HIPCHK(hipStreamWaitEvent(d.aux, d.fork, 0));
+      if (f32) launch_star_fp32(aw, true, d.maxn_wide, r, sc, check, d.aux);
+      else launch_star_fp64(aw, true, d.maxn_wide, r, sc, check, d.aux);
+      HIPCHK(hipEventRecord(d.join, d.aux));
+    } else if (d.n_wide > 0) {
+      if (f32) launch_star_fp32(aw, true, d.maxn_wide, r, sc, check, s);
+      else launch_star_fp64(aw, true, d.maxn_wide, r, sc, check, s);
+    }
+    if (d.n_narrow > 0) {
+      if (f32) launch_star_fp32(a, false, d.maxn_narrow, r, sc, check, s);
+      else launch_star_fp64(a, false, d.maxn_narrow, r, sc, check, s);
+    }
+    if (d.n_wide > 0 && d.n_narrow > 0) HIPCHK(hipStreamWaitEvent(s, d.join, 0));
   }
   if (d.profiling) {
     HIPCHK(hipEventRecord(ev.second, s));
