@@ -59,6 +59,18 @@ def timed_solves(pre, f, steps, warmup, rtol, profile=False, use_graph=False):
     return dict(total_s=total, lat_ms=lat, iters=iters, u=u, info=info, stats=stats)
 
 
+def copy_probe(mib):
+    import torch
+    n = mib * (1 << 20) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8, "launches": 5}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -69,7 +81,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic_star_sweep_fiber2d_20k.json"),
                     help="HBM traffic per sweep launch from rocprofv3 counters (JSON), if present")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB (5 times) and exit: the reference "
+                         "kernel that scales the FETCH_SIZE / WRITE_SIZE counters to bytes")
     args = ap.parse_args()
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
@@ -120,7 +138,8 @@ def main():
         except Exception:
             traffic = None
     roof_m["traffic"] = traffic
-    roof_m["kernel"] = "star sweeps (k_star, FP32 factors), one launch per window class per B application"
+    roof_m["kernel"] = ("star sweeps, FP32 factors: k_star narrow (1-2 window registers) and wide (4-16) kernels, "
+                        "timed together per application of B")
 
     u_m = rm["u"].cpu().numpy()
     u_p = rp["u"].cpu().numpy()
