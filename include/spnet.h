@@ -237,26 +237,57 @@ sn_status sn_apply_B(sn_precond pre, int k, const double *r, double *z, int devi
 /* ------------------------------------------------------------------ */
 /* Serving: continuous batching of solves over device-resident factors  */
 /* ------------------------------------------------------------------ */
+/*
+ * A server runs the PCG iterations of many requests together. Every
+ * preconditioner with requests gets an engine: a batch of `max_columns` PCG
+ * columns (one per right-hand side) whose iterations run as one launch
+ * sequence on the engine's own stream, so that the engines of different
+ * networks overlap on the device. A request occupies k columns of its
+ * preconditioner's engine from admission until its last column converges;
+ * columns are admitted and retired between ticks while the other columns keep
+ * iterating (continuous batching). Every column runs its own recurrence with
+ * the same arithmetic as sn_solve, so a result does not depend on the other
+ * requests in the batch.
+ *
+ * Admission is by device-memory footprint: an engine costs its vectors and
+ * star slots, a preconditioner the server factors costs its factors. When a
+ * new engine does not fit in hbm_budget, idle engines are evicted (least
+ * recently used first) together with the factors the server uploaded for
+ * them. Unfactored preconditioners are factored on host worker threads while
+ * other requests iterate. A server handle is used from one thread at a time.
+ */
 typedef struct {
-  int64_t hbm_budget;  /* bytes of device memory the server may hold for requests */
-  int32_t max_active;  /* requests iterating together */
-  int32_t iters_per_tick; /* PCG iterations per scheduling tick */
+  int64_t hbm_budget;     /* bytes of device memory for engines and the factors the server uploads */
+  int32_t max_columns;    /* engine width: 1, 2, 4, 8 or 16 (default 8); a request takes k <= this */
+  int32_t iters_per_tick; /* PCG iterations queued per engine and tick (default 4) */
+  int32_t precision;      /* precision of the factors the server computes (SN_PREC_*) */
+  int32_t use_graph;      /* 1: replay iteration blocks as captured HIP graphs */
 } sn_server_opts;
 
+void sn_server_opts_default(sn_server_opts *opts);
 sn_status sn_server_create(const sn_server_opts *opts, sn_server *out);
 /*
- * Queue a solve of K u = f (k columns, host f, n x k row-major) on a factored
- * preconditioner, which must stay alive until the ticket is collected. The
- * request is admitted as soon as a slot and its memory footprint fit.
- * Errors: SN_EINVAL, SN_EBUSY if the request alone exceeds the budget.
+ * Queue a solve of K u = f (k columns; f on the host, n x k row-major, copied)
+ * with tolerance rtol and iteration limit max_iter per column. The
+ * preconditioner may be factored or not (then the server factors it); the
+ * server keeps it alive until the ticket is collected.
+ * Errors: SN_EINVAL (k out of range, non-finite f), SN_EBUSY if the request
+ * alone exceeds the budget.
  */
 sn_status sn_server_submit(sn_server srv, sn_precond pre, int k, const double *f, double rtol,
                            int64_t max_iter, uint64_t *ticket);
-/* Run one scheduling tick: admit, iterate all active requests together, retire. */
+/*
+ * One scheduling tick: wait for the previous tick of every engine, retire the
+ * converged columns, admit queued requests that fit, and queue the next
+ * iterations of every engine (asynchronously). n_active: requests iterating,
+ * n_queued: requests waiting.
+ */
 sn_status sn_server_step(sn_server srv, int32_t *n_active, int32_t *n_queued);
 /* SN_EBUSY while pending; when done copies u (n x k) and k info entries and
- * forgets the ticket. */
+ * forgets the ticket. A request that failed returns its error once. */
 sn_status sn_server_poll(sn_server srv, uint64_t ticket, double *u, sn_solve_info *info);
+/* Device bytes the server holds (engines and the factors it uploaded). */
+sn_status sn_server_usage(sn_server srv, int64_t *device_bytes, int32_t *n_engines);
 void sn_server_destroy(sn_server srv);
 
 #ifdef __cplusplus

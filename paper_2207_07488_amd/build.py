@@ -16,11 +16,13 @@ ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 HIPCC = os.path.join(ROCM, "bin", "hipcc")
 
 HOST_SOURCES = ["network.cpp", "assemble.cpp", "spaces.cpp", "factor.cpp", "api.cpp", "serve.cpp"]
-DEVICE_SOURCES = ["device.hip", "star_fp32.hip", "star_fp64.hip"]
+DEVICE_SOURCES = ["device.hip"]
+# the star sweep launcher, once per factor precision and column count
+STAR_VARIANTS = [(t, kc) for t in ("float", "double") for kc in (1, 2, 4, 8, 16)]
 
 HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-ffp-contract=off", "-Wall", "-Wno-unused-function", "-pthread"]
 DEVICE_FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang",
-                "-packed-fp32-ops", "-Wno-unused-result"]
+                "-packed-fp32-ops", "-ffp-contract=off", "-Wno-unused-result"]
 
 
 def _run(cmd):
@@ -31,18 +33,46 @@ def _run(cmd):
     return r
 
 
-def build(verbose: bool = False) -> str:
+def _stale(obj, src):
+    """obj is missing or older than its source or any header of csrc/ or include/."""
+    if not os.path.exists(obj):
+        return True
+    t = os.path.getmtime(obj)
+    hdrs = ["internal.hpp"]
+    if src.endswith(".cpp"):
+        hdrs.append("handles.hpp")
+    else:
+        hdrs.append("device_common.hpp")
+    if src.endswith("star_inst.hip"):
+        hdrs.append("star_kernel.hpp")
+    deps = [src] + [os.path.join(CSRC, h) for h in hdrs]
+    deps.append(os.path.join(os.path.dirname(HERE), "include", "spnet.h"))
+    return any(os.path.getmtime(d) > t for d in deps)
+
+
+def build(verbose: bool = False, force: bool = True) -> str:
+    """Compile and link libspnet.so; force=False skips objects newer than their sources."""
     os.makedirs(BUILD, exist_ok=True)
     jobs = []
     for src in HOST_SOURCES:
         obj = os.path.join(BUILD, src + ".o")
         jobs.append(["g++", *HOST_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
+    objs = [os.path.join(BUILD, s + ".o") for s in HOST_SOURCES + DEVICE_SOURCES]
     for src in DEVICE_SOURCES:
         obj = os.path.join(BUILD, src + ".o")
         jobs.append([HIPCC, *DEVICE_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
-    with ThreadPoolExecutor(max_workers=min(8, len(jobs))) as ex:
-        list(ex.map(_run, jobs))
-    objs = [os.path.join(BUILD, s + ".o") for s in HOST_SOURCES + DEVICE_SOURCES]
+    for t, kc in STAR_VARIANTS:
+        obj = os.path.join(BUILD, f"star_{t}_{kc}.o")
+        objs.append(obj)
+        jobs.append([HIPCC, *DEVICE_FLAGS, f"-DSTAR_T={t}", f"-DSTAR_KC={kc}", "-c",
+                     os.path.join(CSRC, "star_inst.hip"), "-o", obj])
+    # the widest variants first: they take longest
+    jobs.sort(key=lambda j: -max([int(a.split("=")[1]) for a in j if a.startswith("-DSTAR_KC=")] or [0]))
+    if not force:
+        jobs = [j for j in jobs if _stale(j[-1], [a for a in j if a.endswith((".cpp", ".hip"))][0])]
+    if jobs:
+        with ThreadPoolExecutor(max_workers=min(int(os.environ.get("MAX_JOBS", "8")), len(jobs))) as ex:
+            list(ex.map(_run, jobs))
     tmp = LIB + ".tmp"
     _run([HIPCC, "-shared", "--offload-arch=gfx950", "-o", tmp, *objs, "-lpthread"])
     os.replace(tmp, LIB)
@@ -52,4 +82,4 @@ def build(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, force="--incremental" not in sys.argv)

@@ -4,25 +4,15 @@
 #include <cstring>
 #include <new>
 
-#include "internal.hpp"
-
-struct sn_network_s {
-  std::shared_ptr<spnet::Network> p;
-};
-struct sn_system_s {
-  std::shared_ptr<spnet::System> p;
-};
-struct sn_precond_s {
-  std::shared_ptr<spnet::Precond> p;
-};
+#include "handles.hpp"
 
 namespace {
 thread_local std::string g_err;
+}  // namespace
 
-template <typename Fn>
-sn_status guarded(Fn fn) {
+sn_status spnet::guarded_call(void (*fn)(void *), void *ctx) {
   try {
-    fn();
+    fn(ctx);
     return SN_OK;
   } catch (const spnet::Error &e) {
     g_err = e.what();
@@ -38,6 +28,9 @@ sn_status guarded(Fn fn) {
     return SN_EINVAL;
   }
 }
+
+namespace {
+using spnet::guarded;
 
 #define REQUIRE(c, msg) \
   do {                  \

@@ -1,17 +1,21 @@
 // GPU hot path for gfx950 (MI355X): PCG on P = BK (Sec. 4.2) with the
 // two-level additive Schwarz preconditioner B = P K_0^{-1} P^T +
-// sum_j R_j^T K_j^{-1} R_j (Sec. 4.1).
+// sum_j R_j^T K_j^{-1} R_j (Sec. 4.1), for KC right-hand sides at once.
 //
-// Per iteration:
-//   spmv_dot    q = K p (sliced ELL, 64-row slices) and p.q        -> alpha
-//   cg_update   u += alpha p, r -= alpha q, r.r, convergence flag
-//   star sweeps z_j = K_j^{-1} r[S_j] for every star, one wavefront per star
-//   coarse      r_H = P^T r, c = K_0^{-1} r_H (dense inverse)
-//   reduce      z = P c + sum of the star slots of every dof, r.z   -> beta
-//   p_update    p = z + beta p
+// Every column runs its own recurrence (alpha, beta, convergence per column);
+// the columns share the reads of the matrix, the star factors and the coarse
+// operator. A vector of the batch is npad x KC, position-major (the KC values
+// of a dof are adjacent). Per iteration:
+//   first half   q = K p (sliced ELL, 64-row slices) and p.q   -> alpha
+//                u += alpha p, r -= alpha q, r.r, convergence
+//   second half  star sweeps z_j = K_j^{-1} r[S_j] (one wavefront per star)
+//                r_H = P^T r, c = K_0^{-1} r_H (dense inverse)
+//                z = P c + sum of the star slots of every dof, r.z -> beta
+//                p = z + beta p
 // Dot products are reduced per block in a fixed order and the partials are
-// combined in a fixed order by a one-block kernel, so results do not depend on
-// scheduling. The star sweeps live in star_kernel.hpp.
+// combined in a fixed order by a one-block kernel, per column, with the same
+// arithmetic for every column and every KC: a column's iterates do not depend
+// on the other columns of its batch. The star sweeps live in star_kernel.hpp.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -26,12 +30,71 @@
 
 namespace spnet {
 
+constexpr int kBlock = 256;     // threads of the vector kernels
+constexpr int kSlice = 64;      // rows per ELL slice (one wavefront)
+constexpr int kMaxGrid = 1024;  // blocks of the grid-stride vector kernels (= partial sums per column)
+constexpr int kMaxCols = 16;
 
-constexpr int kBlock = 256;   // threads of the vector kernels
-constexpr int kSlice = 64;    // rows per ELL slice (one wavefront)
-constexpr int kMaxGrid = 1024;  // blocks of the grid-stride vector kernels (= partial sums)
+enum ScalarOp { OP_ALPHA = 0, OP_CONV = 1, OP_BETA = 2, OP_F2 = 3, OP_R2 = 4, OP_TRUE = 5, OP_DOT = 6 };
 
-enum ScalarOp { OP_ALPHA = 0, OP_CONV = 1, OP_BETA = 2, OP_DOT = 3 };
+// ---------------------------------------------------------------------------
+// KC adjacent doubles
+// ---------------------------------------------------------------------------
+template <int KC>
+struct Vec {
+  double v[KC];
+  __device__ __forceinline__ void load(const double *p) {
+    if constexpr (KC == 1) {
+      v[0] = p[0];
+    } else {
+#pragma unroll
+      for (int i = 0; i < KC / 2; ++i) {
+        const double2 t = reinterpret_cast<const double2 *>(p)[i];
+        v[2 * i] = t.x;
+        v[2 * i + 1] = t.y;
+      }
+    }
+  }
+  __device__ __forceinline__ void store(double *p) const {
+    if constexpr (KC == 1) {
+      p[0] = v[0];
+    } else {
+#pragma unroll
+      for (int i = 0; i < KC / 2; ++i) reinterpret_cast<double2 *>(p)[i] = double2{v[2 * i], v[2 * i + 1]};
+    }
+  }
+  __device__ __forceinline__ void zero() {
+#pragma unroll
+    for (int c = 0; c < KC; ++c) v[c] = 0.0;
+  }
+};
+
+template <typename TS, int KC>
+struct SlotVec;
+template <int KC>
+struct SlotVec<double, KC> : Vec<KC> {};
+template <int KC>
+struct SlotVec<float, KC> {
+  float v[KC];
+  __device__ __forceinline__ void load(const float *p) {
+    if constexpr (KC == 1) {
+      v[0] = p[0];
+    } else if constexpr (KC == 2) {
+      const float2 t = *reinterpret_cast<const float2 *>(p);
+      v[0] = t.x;
+      v[1] = t.y;
+    } else {
+#pragma unroll
+      for (int i = 0; i < KC / 4; ++i) {
+        const float4 t = reinterpret_cast<const float4 *>(p)[i];
+        v[4 * i] = t.x;
+        v[4 * i + 1] = t.y;
+        v[4 * i + 2] = t.z;
+        v[4 * i + 3] = t.w;
+      }
+    }
+  }
+};
 
 // ---------------------------------------------------------------------------
 // reductions: per-block partials in a fixed order, then one block combines
@@ -54,41 +117,113 @@ __device__ __forceinline__ double block_sum(double v, double *sh) {
   return s;  // thread 0
 }
 
-// one block: combine the partials of the previous kernel and update the scalars
-__global__ __launch_bounds__(kBlock) void k_scalar(const double *__restrict__ partials, int nparts, CgScalars *sc,
-                                                   int op) {
-  __shared__ double sh[kBlock / 64];
-  if (op != OP_DOT && sc->done) return;
-  double s = 0.0;
-  for (int i = threadIdx.x; i < nparts; i += kBlock) s += partials[i];
-  const double tot = block_sum(s, sh);
-  if (threadIdx.x != 0) return;
-  switch (op) {
-    case OP_ALPHA:
-      sc->pq = tot;
-      sc->alpha = sc->rho / tot;
-      break;
-    case OP_CONV: {
-      sc->rr = tot;
-      const int it = sc->iters + 1;
-      sc->iters = it;
-      const bool stop = sc->fixed > 0 ? it >= sc->fixed : (tot <= sc->tol2 || it >= sc->max_iter);
-      if (stop) sc->done = 1;
-      break;
+// per-column block sums of a kBlock-thread block; results in thread 0, which
+// writes them to partials[c * kMaxGrid + blockIdx.x]
+template <int KC>
+__device__ __forceinline__ void block_partials(const Vec<KC> &v, double *partials) {
+  __shared__ double sh[kBlock / 64][KC];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int c = 0; c < KC; ++c) {
+    const double s = wave_sum(v.v[c]);
+    if (lane == 0) sh[w][c] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int c = 0; c < KC; ++c) {
+      double s = 0.0;
+      for (int i = 0; i < kBlock / 64; ++i) s += sh[i][c];
+      partials[c * kMaxGrid + blockIdx.x] = s;
     }
-    case OP_BETA:
-      sc->rz = tot;
-      sc->beta = sc->first ? 0.0 : tot / sc->rho;
-      sc->rho = tot;
-      sc->first = 0;
-      break;
-    default:
-      sc->tmp = tot;
+  }
+}
+
+template <int KC>
+__device__ __forceinline__ bool any_selected(const CgScalars *sc, int sel, uint32_t mask) {
+  if (sel == SEL_ALL) return true;
+  bool any = false;
+#pragma unroll
+  for (int c = 0; c < KC; ++c) any |= column_selected(sc[c], sel, mask, c);
+  return any;
+}
+
+// one block: combine the partials of the previous kernel per column and update
+// the scalars of the selected columns
+template <int KC>
+__global__ __launch_bounds__(kBlock) void k_scalar(const double *__restrict__ partials, int nparts, CgScalars *sc,
+                                                   int op, int sel, uint32_t mask) {
+  __shared__ double sh[kBlock / 64];
+  for (int c = 0; c < KC; ++c) {
+    if (!column_selected(sc[c], sel, mask, c)) continue;  // uniform
+    double s = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += kBlock) s += partials[c * kMaxGrid + i];
+    const double tot = block_sum(s, sh);
+    if (threadIdx.x != 0) continue;
+    CgScalars &x = sc[c];
+    switch (op) {
+      case OP_ALPHA:
+        x.pq = tot;
+        x.alpha = x.rho / tot;
+        break;
+      case OP_CONV: {
+        x.rr = tot;
+        const int it = x.iters + 1;
+        x.iters = it;
+        const bool stop = x.fixed > 0 ? it >= x.fixed : (tot <= x.tol2 || it >= x.max_iter);
+        if (stop) {
+          x.done = 1;
+          x.verify = 1;
+        }
+        break;
+      }
+      case OP_BETA:
+        x.rz = tot;
+        x.beta = x.first ? 0.0 : tot / x.rho;
+        x.rho = tot;
+        x.first = 0;
+        x.fresh = 0;
+        x.restart = 0;
+        break;
+      case OP_F2:
+        x.f2 = tot;
+        x.tol2 = x.rtol * x.rtol * tot;
+        break;
+      case OP_R2:
+        x.rr = tot;
+        if (x.fixed == 0 && (tot <= x.tol2 || x.f2 == 0.0)) {
+          // nothing to iterate: r^(0) is the true residual
+          x.done = 1;
+          x.t2 = tot;
+        }
+        break;
+      case OP_TRUE: {
+        // The recurrence stopped; t2 = ||f - K u||^2. When it exceeds the
+        // tolerance by a small factor the recurrence has drifted: restart from
+        // the true residual. A true residual far above the tolerance is the
+        // attainable accuracy of the system in FP64, which a restart cannot
+        // improve.
+        x.t2 = tot;
+        x.verify = 0;
+        if (x.fixed == 0 && x.rr <= x.tol2 && x.iters < x.max_iter && tot > x.tol2 * 1.0000001 &&
+            tot < 100.0 * x.tol2 && x.replacements < 3) {
+          x.replacements += 1;
+          x.rr = tot;
+          x.done = 0;
+          x.first = 1;
+          x.fresh = 1;
+          x.restart = 1;
+        }
+        break;
+      }
+      default:
+        x.tmp = tot;
+    }
   }
 }
 
 // ---------------------------------------------------------------------------
-// sliced ELL SpMV: y = K x (optionally x.y partials)
+// sliced ELL SpMV: y = K x for KC columns, optionally x.y partials
 // ---------------------------------------------------------------------------
 struct Sell {
   const int32_t *sptr;  // slice start (elements)
@@ -97,123 +232,281 @@ struct Sell {
   const double *val;
 };
 
+template <int KC>
 __global__ __launch_bounds__(kBlock) void k_spmv(Sell A, const double *__restrict__ x, double *__restrict__ y,
-                                                 int nrows, const CgScalars *sc, double *partials) {
-  __shared__ double sh[kBlock / 64];
-  if (partials && sc->done) return;
-  double dot = 0.0;
+                                                 int nrows, const CgScalars *sc, int sel, double *partials) {
+  if (!any_selected<KC>(sc, sel, 0u)) return;
+  Vec<KC> dot;
+  dot.zero();
   for (int row = blockIdx.x * kBlock + threadIdx.x; row < nrows; row += gridDim.x * kBlock) {
     const int s = row >> 6, lane = row & 63;
     const int base = A.sptr[s], len = A.slen[s];
-    double acc = 0.0;
+    Vec<KC> acc;
+    acc.zero();
     for (int c = 0; c < len; ++c) {
       const int e = base + c * kSlice + lane;
-      acc += A.val[e] * x[A.col[e]];
+      const double a = A.val[e];
+      Vec<KC> xv;
+      xv.load(x + (size_t)A.col[e] * KC);
+#pragma unroll
+      for (int k = 0; k < KC; ++k) acc.v[k] = __builtin_fma(a, xv.v[k], acc.v[k]);
     }
-    y[row] = acc;
-    dot += x[row] * acc;
+    acc.store(y + (size_t)row * KC);
+    if (partials) {
+      Vec<KC> xr;
+      xr.load(x + (size_t)row * KC);
+#pragma unroll
+      for (int k = 0; k < KC; ++k) dot.v[k] = __builtin_fma(xr.v[k], acc.v[k], dot.v[k]);
+    }
   }
-  if (!partials) return;
-  const double part = block_sum(dot, sh);
-  if (threadIdx.x == 0) partials[blockIdx.x] = part;
+  if (partials) block_partials<KC>(dot, partials);
 }
 
-// u += alpha p, r -= alpha q, r.r partials
+// first-half columns: u += alpha p, r -= alpha q, r.r partials
+template <int KC>
 __global__ __launch_bounds__(kBlock) void k_cg_update(double *u, double *r, const double *p, const double *q, int n,
                                                       const CgScalars *sc, double *partials) {
-  __shared__ double sh[kBlock / 64];
-  if (sc->done) return;
-  const double a = sc->alpha;
-  double rr = 0.0;
-  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
-    u[i] += a * p[i];
-    const double ri = r[i] - a * q[i];
-    r[i] = ri;
-    rr += ri * ri;
+  if (!any_selected<KC>(sc, SEL_FIRST, 0u)) return;
+  bool on[KC];
+  double a[KC];
+#pragma unroll
+  for (int c = 0; c < KC; ++c) {
+    on[c] = column_selected(sc[c], SEL_FIRST, 0u, c);
+    a[c] = sc[c].alpha;
   }
-  const double part = block_sum(rr, sh);
-  if (threadIdx.x == 0) partials[blockIdx.x] = part;
+  Vec<KC> rr;
+  rr.zero();
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+    Vec<KC> uv, rv, pv, qv;
+    uv.load(u + (size_t)i * KC);
+    rv.load(r + (size_t)i * KC);
+    pv.load(p + (size_t)i * KC);
+    qv.load(q + (size_t)i * KC);
+#pragma unroll
+    for (int c = 0; c < KC; ++c) {
+      if (!on[c]) continue;
+      uv.v[c] = __builtin_fma(a[c], pv.v[c], uv.v[c]);
+      rv.v[c] = __builtin_fma(-a[c], qv.v[c], rv.v[c]);
+      rr.v[c] = __builtin_fma(rv.v[c], rv.v[c], rr.v[c]);
+    }
+    uv.store(u + (size_t)i * KC);
+    rv.store(r + (size_t)i * KC);
+  }
+  block_partials<KC>(rr, partials);
 }
 
 // z = P c + sum of the star slots of every dof (ascending star order), r.z partials
-template <typename TS>
+template <typename TS, int KC>
 __global__ __launch_bounds__(kBlock) void k_reduce(double *z, const double *r, const TS *__restrict__ slots,
                                                    const int32_t *__restrict__ slot_of,
                                                    const int32_t *__restrict__ Pc, const double *__restrict__ Pw,
                                                    const double *__restrict__ cvec, int n, int nv,
-                                                   const CgScalars *sc, double *partials) {
-  __shared__ double sh[kBlock / 64];
-  if (partials && sc->done) return;
-  double rz = 0.0;
+                                                   const CgScalars *sc, int sel, double *partials) {
+  if (!any_selected<KC>(sc, sel, 0u)) return;
+  Vec<KC> rz;
+  rz.zero();
   for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
-    double acc = 0.0;
+    Vec<KC> acc;
+    acc.zero();
     for (int b = 0; b < nv; ++b) {
       const int c = Pc[(size_t)i * nv + b];
-      if (c >= 0) acc += Pw[(size_t)i * nv + b] * cvec[c];
+      if (c >= 0) {
+        const double w = Pw[(size_t)i * nv + b];
+        Vec<KC> cv;
+        cv.load(cvec + (size_t)c * KC);
+#pragma unroll
+        for (int k = 0; k < KC; ++k) acc.v[k] = __builtin_fma(w, cv.v[k], acc.v[k]);
+      }
     }
     for (int b = 0; b < nv; ++b) {
       const int s = slot_of[(size_t)i * nv + b];
-      if (s >= 0) acc += (double)slots[s];
+      if (s >= 0) {
+        SlotVec<TS, KC> sv;
+        sv.load(slots + (size_t)s * KC);
+#pragma unroll
+        for (int k = 0; k < KC; ++k) acc.v[k] += (double)sv.v[k];
+      }
     }
-    z[i] = acc;
-    rz += r[i] * acc;
+    acc.store(z + (size_t)i * KC);
+    if (partials) {
+      Vec<KC> rv;
+      rv.load(r + (size_t)i * KC);
+#pragma unroll
+      for (int k = 0; k < KC; ++k) rz.v[k] = __builtin_fma(rv.v[k], acc.v[k], rz.v[k]);
+    }
   }
-  if (!partials) return;
-  const double part = block_sum(rz, sh);
-  if (threadIdx.x == 0) partials[blockIdx.x] = part;
+  if (partials) block_partials<KC>(rz, partials);
 }
 
+// second-half columns: p = z + beta p
+template <int KC>
 __global__ __launch_bounds__(kBlock) void k_p_update(double *p, const double *z, int n, const CgScalars *sc) {
-  if (sc->done) return;
-  const double b = sc->beta;
-  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) p[i] = z[i] + b * p[i];
+  if (!any_selected<KC>(sc, SEL_SECOND, 0u)) return;
+  bool on[KC];
+  double b[KC];
+#pragma unroll
+  for (int c = 0; c < KC; ++c) {
+    on[c] = column_selected(sc[c], SEL_SECOND, 0u, c);
+    b[c] = sc[c].beta;
+  }
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+    Vec<KC> pv, zv;
+    pv.load(p + (size_t)i * KC);
+    zv.load(z + (size_t)i * KC);
+#pragma unroll
+    for (int c = 0; c < KC; ++c)
+      if (on[c]) pv.v[c] = __builtin_fma(b[c], pv.v[c], zv.v[c]);
+    pv.store(p + (size_t)i * KC);
+  }
 }
 
 // r_H = P^T r: one block per coarse dof, fixed-order sums
+template <int KC>
 __global__ __launch_bounds__(kBlock) void k_restrict(const int32_t *__restrict__ ptr, const int32_t *__restrict__ dof,
                                                      const double *__restrict__ w, const double *__restrict__ r,
-                                                     double *rH, int m0, const CgScalars *sc, int check) {
-  __shared__ double sh[kBlock / 64];
-  if (check && sc->done) return;
-  const int c = blockIdx.x;
-  double acc = 0.0;
-  for (int q = ptr[c] + threadIdx.x; q < ptr[c + 1]; q += kBlock) acc += w[q] * r[dof[q]];
-  acc = block_sum(acc, sh);
-  if (threadIdx.x == 0) rH[c] = acc;
+                                                     double *rH, int m0, const CgScalars *sc, int sel) {
+  __shared__ double sh[kBlock / 64][KC];
+  if (!any_selected<KC>(sc, sel, 0u)) return;
+  const int g = blockIdx.x;
+  Vec<KC> acc;
+  acc.zero();
+  for (int q = ptr[g] + threadIdx.x; q < ptr[g + 1]; q += kBlock) {
+    const double wq = w[q];
+    Vec<KC> rv;
+    rv.load(r + (size_t)dof[q] * KC);
+#pragma unroll
+    for (int k = 0; k < KC; ++k) acc.v[k] = __builtin_fma(wq, rv.v[k], acc.v[k]);
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < KC; ++k) {
+    const double s = wave_sum(acc.v[k]);
+    if (lane == 0) sh[wv][k] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    Vec<KC> out;
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+      double s = 0.0;
+      for (int i = 0; i < kBlock / 64; ++i) s += sh[i][k];
+      out.v[k] = s;
+    }
+    out.store(rH + (size_t)g * KC);
+  }
 }
 
 // c = K_0^{-1} r_H, one wavefront per row of the dense inverse
+template <int KC>
 __global__ __launch_bounds__(kBlock) void k_coarse_gemv(const double *__restrict__ Kinv, const double *__restrict__ rH,
-                                                        double *cvec, int m0, const CgScalars *sc, int check) {
-  if (check && sc->done) return;
+                                                        double *cvec, int m0, const CgScalars *sc, int sel) {
+  if (!any_selected<KC>(sc, sel, 0u)) return;
   const int row = (blockIdx.x * kBlock + threadIdx.x) >> 6, lane = threadIdx.x & 63;
   if (row >= m0) return;
   const double *a = Kinv + (size_t)row * m0;
-  double acc = 0.0;
-  for (int j = lane; j < m0; j += 64) acc += a[j] * rH[j];
-  acc = wave_sum(acc);
-  if (lane == 0) cvec[row] = acc;
+  Vec<KC> acc;
+  acc.zero();
+  for (int j = lane; j < m0; j += 64) {
+    const double aj = a[j];
+    Vec<KC> x;
+    x.load(rH + (size_t)j * KC);
+#pragma unroll
+    for (int k = 0; k < KC; ++k) acc.v[k] = __builtin_fma(aj, x.v[k], acc.v[k]);
+  }
+  Vec<KC> out;
+#pragma unroll
+  for (int k = 0; k < KC; ++k) out.v[k] = wave_sum(acc.v[k]);
+  if (lane == 0) out.store(cvec + (size_t)row * KC);
 }
 
-__global__ __launch_bounds__(kBlock) void k_dot(const double *a, const double *b, int n, double *partials) {
-  __shared__ double sh[kBlock / 64];
-  double s = 0.0;
-  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) s += a[i] * b[i];
-  const double part = block_sum(s, sh);
-  if (threadIdx.x == 0) partials[blockIdx.x] = part;
+// a.b partials per column
+template <int KC>
+__global__ __launch_bounds__(kBlock) void k_dot(const double *a, const double *b, int n, double *partials,
+                                                const CgScalars *sc, int sel, uint32_t mask) {
+  if (!any_selected<KC>(sc, sel, mask)) return;
+  Vec<KC> s;
+  s.zero();
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+    Vec<KC> av, bv;
+    av.load(a + (size_t)i * KC);
+    bv.load(b + (size_t)i * KC);
+#pragma unroll
+    for (int k = 0; k < KC; ++k) s.v[k] = __builtin_fma(av.v[k], bv.v[k], s.v[k]);
+  }
+  block_partials<KC>(s, partials);
 }
 
-// y = a - b
-__global__ __launch_bounds__(kBlock) void k_sub(double *y, const double *a, const double *b, int n) {
-  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) y[i] = a[i] - b[i];
+// y = a - b on the selected columns (others untouched), y.y partials
+template <int KC>
+__global__ __launch_bounds__(kBlock) void k_sub_dot(double *y, const double *a, const double *b, int n,
+                                                    const CgScalars *sc, int sel, uint32_t mask, double *partials) {
+  if (!any_selected<KC>(sc, sel, mask)) return;
+  bool on[KC];
+#pragma unroll
+  for (int c = 0; c < KC; ++c) on[c] = column_selected(sc[c], sel, mask, c);
+  Vec<KC> s;
+  s.zero();
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+    Vec<KC> yv, av, bv;
+    yv.load(y + (size_t)i * KC);
+    av.load(a + (size_t)i * KC);
+    bv.load(b + (size_t)i * KC);
+#pragma unroll
+    for (int c = 0; c < KC; ++c) {
+      if (!on[c]) continue;
+      yv.v[c] = av.v[c] - bv.v[c];
+      s.v[c] = __builtin_fma(yv.v[c], yv.v[c], s.v[c]);
+    }
+    yv.store(y + (size_t)i * KC);
+  }
+  if (partials) block_partials<KC>(s, partials);
 }
 
-// strided column gather / scatter between n x k blocks and a contiguous vector
-__global__ __launch_bounds__(kBlock) void k_gather_col(double *dst, const double *src, int n, int k, int c) {
-  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) dst[i] = src[(size_t)i * k + c];
+// dst = src on the selected columns
+template <int KC>
+__global__ __launch_bounds__(kBlock) void k_copy_sel(double *dst, const double *src, int n, const CgScalars *sc,
+                                                     int sel, uint32_t mask) {
+  if (!any_selected<KC>(sc, sel, mask)) return;
+  bool on[KC];
+#pragma unroll
+  for (int c = 0; c < KC; ++c) on[c] = column_selected(sc[c], sel, mask, c);
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+    Vec<KC> dv, sv;
+    dv.load(dst + (size_t)i * KC);
+    sv.load(src + (size_t)i * KC);
+#pragma unroll
+    for (int c = 0; c < KC; ++c)
+      if (on[c]) dv.v[c] = sv.v[c];
+    dv.store(dst + (size_t)i * KC);
+  }
 }
-__global__ __launch_bounds__(kBlock) void k_scatter_col(double *dst, const double *src, int n, int k, int c) {
-  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) dst[(size_t)i * k + c] = src[i];
+
+// Start column `col` from column j of the n x k block `src`: f = r = src,
+// u = p = 0 (rows n..npad-1 zero).
+template <int KC>
+__global__ __launch_bounds__(kBlock) void k_admit(double *f, double *r, double *u, double *p, const double *src,
+                                                  int n, int npad, int k, int j, int col) {
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < npad; i += gridDim.x * kBlock) {
+    const double v = i < n ? src[(size_t)i * k + j] : 0.0;
+    const size_t o = (size_t)i * KC + col;
+    f[o] = v;
+    r[o] = v;
+    u[o] = 0.0;
+    p[o] = 0.0;
+  }
+}
+
+// column col of a batch vector <-> column j of an n x k block
+template <int KC>
+__global__ __launch_bounds__(kBlock) void k_col_in(double *dst, const double *src, int n, int npad, int k, int j,
+                                                   int col) {
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < npad; i += gridDim.x * kBlock)
+    dst[(size_t)i * KC + col] = i < n ? src[(size_t)i * k + j] : 0.0;
+}
+template <int KC>
+__global__ __launch_bounds__(kBlock) void k_col_out(double *dst, const double *src, int n, int k, int j, int col) {
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock)
+    dst[(size_t)i * k + j] = src[(size_t)i * KC + col];
 }
 
 // ---------------------------------------------------------------------------
@@ -226,7 +519,14 @@ struct DBuf {
   void alloc(size_t cnt) {
     release();
     n = cnt;
-    if (cnt) HIPCHK(hipMalloc(&p, cnt * sizeof(T)));
+    if (cnt) {
+      const hipError_t e = hipMalloc(&p, cnt * sizeof(T));
+      if (e != hipSuccess) {
+        p = nullptr;
+        n = 0;
+        fail(SN_ENOMEM, "device allocation of " + std::to_string(cnt * sizeof(T)) + " bytes failed");
+      }
+    }
   }
   void upload(const std::vector<T> &h) {
     alloc(h.size());
@@ -244,16 +544,9 @@ struct DBuf {
   ~DBuf() { release(); }
 };
 
-struct Workspace {
-  int k = 0;
-  DBuf<double> u, r, p, q, z, f, rH, c, partials;
-  DBuf<CgScalars> sc;
-};
-
 struct DeviceState {
   int device = 0;
   int precision = 0;
-  hipStream_t own = nullptr;
   int64_t n = 0, npad = 0, m0 = 0;
   int nv = 4;
   // matrix
@@ -261,40 +554,73 @@ struct DeviceState {
   DBuf<int32_t> sptr, slen, col;
   DBuf<double> val;
   // stars
-  int32_t nstars = 0, pad = 0, maxn = 0;
-  int32_t n_narrow = 0, n_wide = 0, maxn_narrow = 0, maxn_wide = 0;
-  hipStream_t aux = nullptr;       // wide stars run beside the narrow ones
-  hipEvent_t fork = nullptr, join = nullptr;
+  int32_t nstars = 0, maxn = 0;
+  int32_t n_narrow = 0, n_wide = 0;
+  int64_t slot_count = 0;
   DBuf<int32_t> order_narrow, order_wide, st_n, st_vb, st_q, st_gb, pos_dof, slot_of;
   DBuf<uint32_t> f_hdr, b_hdr;
   DBuf<int64_t> st_fb, st_bb;
-  DBuf<float> f_inv32, b_inv32, f_val32, b_val32, slots32;
-  DBuf<double> f_inv64, b_inv64, f_val64, b_val64, slots64;
+  DBuf<float> f_inv32, b_inv32, f_val32, b_val32;
+  DBuf<double> f_inv64, b_inv64, f_val64, b_val64;
   // coarse
   DBuf<double> Kinv, PTw, Pw;
   DBuf<int32_t> PTptr, PTdof, Pc;
-  Workspace ws;
   int64_t bytes = 0;
-  // captured iteration blocks: graphs[i] runs 2^i PCG iterations
-  std::vector<hipGraphExec_t> graphs;
-  std::vector<hipGraph_t> graph_defs;
+  // engines of sn_solve / sn_apply_*, one per width
+  std::unique_ptr<Engine> solve_engine[5];
   // profiling
   bool profiling = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_used, ev_free;
   int64_t prof_iters = 0;
-  ~DeviceState() {
+  ~DeviceState();
+};
+
+// Everything a batch of KC columns writes: vectors, per-column scalars, star
+// slots, captured iteration graphs and streams. Engines never share these, so
+// engines on the same preconditioner can run side by side.
+struct Engine {
+  Precond *pre = nullptr;
+  DeviceState *d = nullptr;
+  int kc = 1;
+  DBuf<double> u, r, p, q, z, f, rH, c, partials;
+  DBuf<CgScalars> sc;
+  DBuf<float> slots32;
+  DBuf<double> slots64;
+  CgScalars *host_sc = nullptr;  // pinned: last read-back, and the source of uploads
+  bool sc_dirty = false;         // host_sc changed since the last upload
+  hipStream_t own = nullptr;     // the engine's stream (and graph capture)
+  hipStream_t aux = nullptr;     // wide stars run beside the narrow ones
+  hipEvent_t fork = nullptr, join = nullptr, tick_done = nullptr;
+  bool in_flight = false;
+  std::vector<hipGraphExec_t> graphs;  // graphs[i] runs 2^i iterations on `own`-captured work
+  std::vector<hipGraph_t> graph_defs;
+  int64_t bytes = 0;
+  ~Engine() {
+    if (in_flight && tick_done) (void)hipEventSynchronize(tick_done);
     for (auto &g : graphs)
       if (g) (void)hipGraphExecDestroy(g);
     for (auto &g : graph_defs)
       if (g) (void)hipGraphDestroy(g);
-    for (auto &e : ev_used) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
-    for (auto &e : ev_free) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
+    if (host_sc) (void)hipHostFree(host_sc);
     if (fork) (void)hipEventDestroy(fork);
     if (join) (void)hipEventDestroy(join);
+    if (tick_done) (void)hipEventDestroy(tick_done);
     if (aux) (void)hipStreamDestroy(aux);
     if (own) (void)hipStreamDestroy(own);
   }
 };
+
+DeviceState::~DeviceState() {
+  for (auto &e : solve_engine) e.reset();
+  for (auto &e : ev_used) {
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
+  for (auto &e : ev_free) {
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
+}
 
 void device_release(DeviceState *d) { delete d; }
 void DeviceDeleter::operator()(DeviceState *d) const { delete d; }
@@ -393,7 +719,6 @@ void upload_stars(DeviceState &d, const Precond &pre, const HostFactors &hf, sn_
   const size_t slack = (size_t)64 * 16 * SG + 64;
   f_val.resize(f_val.size() + slack, T(0));
   b_val.resize(b_val.size() + slack, T(0));
-  d.pad = 64 * (maxq + 2);
   // schedule: longest chain first, narrow and wide windows in separate kernels
   std::vector<int32_t> narrow, wide;
   for (int64_t s = 0; s < ns; ++s) (st_q[s] <= 2 ? narrow : wide).push_back((int32_t)s);
@@ -402,8 +727,6 @@ void upload_stars(DeviceState &d, const Precond &pre, const HostFactors &hf, sn_
   std::stable_sort(wide.begin(), wide.end(), by_len);
   d.n_narrow = (int32_t)narrow.size();
   d.n_wide = (int32_t)wide.size();
-  d.maxn_narrow = narrow.empty() ? 0 : st_n[narrow[0]];
-  d.maxn_wide = wide.empty() ? 0 : st_n[wide[0]];
   // dof -> slots in ascending star order
   std::vector<int32_t> slot_of((size_t)d.npad * d.nv, -1);
   {
@@ -416,6 +739,7 @@ void upload_stars(DeviceState &d, const Precond &pre, const HostFactors &hf, sn_
       }
   }
   d.nstars = (int32_t)ns;
+  d.slot_count = tot;
   d.order_narrow.upload(narrow);
   d.order_wide.upload(wide);
   d.st_n.upload(st_n);
@@ -434,16 +758,12 @@ void upload_stars(DeviceState &d, const Precond &pre, const HostFactors &hf, sn_
     d.b_inv32.upload(b_inv);
     d.f_val32.upload(f_val);
     d.b_val32.upload(b_val);
-    d.slots32.alloc((size_t)tot);
-    d.slots32.zero();
     stream_bytes = (int64_t)(d.f_val32.bytes() + d.b_val32.bytes());
   } else {
     d.f_inv64.upload(f_inv);
     d.b_inv64.upload(b_inv);
     d.f_val64.upload(f_val);
     d.b_val64.upload(b_val);
-    d.slots64.alloc((size_t)tot);
-    d.slots64.zero();
     stream_bytes = (int64_t)(d.f_val64.bytes() + d.b_val64.bytes());
   }
   const int64_t sT = sizeof(T);
@@ -457,6 +777,7 @@ void upload_stars(DeviceState &d, const Precond &pre, const HostFactors &hf, sn_
   fi.max_star_dofs = d.maxn;
 }
 
+
 }  // namespace
 
 void device_setup(Precond &pre, const HostFactors &hf, int precision) {
@@ -468,10 +789,6 @@ void device_setup(Precond &pre, const HostFactors &hf, int precision) {
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) fail(SN_EDEVICE, "no HIP device available");
   auto d = std::make_unique<DeviceState>();
   HIPCHK(hipGetDevice(&d->device));
-  HIPCHK(hipStreamCreateWithFlags(&d->own, hipStreamNonBlocking));
-  HIPCHK(hipStreamCreateWithFlags(&d->aux, hipStreamNonBlocking));
-  HIPCHK(hipEventCreateWithFlags(&d->fork, hipEventDisableTiming));
-  HIPCHK(hipEventCreateWithFlags(&d->join, hipEventDisableTiming));
   const System &sys = *pre.sys;
   d->precision = precision;
   d->n = sys.n;
@@ -575,8 +892,7 @@ void device_setup(Precond &pre, const HostFactors &hf, int precision) {
                        d->st_bb.bytes() + d->pos_dof.bytes() + d->f_hdr.bytes() + d->b_hdr.bytes() +
                        d->slot_of.bytes() + d->Kinv.bytes() + d->Pc.bytes() + d->Pw.bytes() +
                        d->PTptr.bytes() + d->PTdof.bytes() + d->PTw.bytes() + d->f_inv32.bytes() +
-                       d->b_inv32.bytes() + d->f_inv64.bytes() + d->b_inv64.bytes() + d->slots32.bytes() +
-                       d->slots64.bytes()) +
+                       d->b_inv32.bytes() + d->f_inv64.bytes() + d->b_inv64.bytes()) +
              fi.star_stream_bytes;
   const int64_t nnz = (int64_t)sys.col.size();
   fi.spmv_bytes = nnz * (8 + 4 + 8) + n * 8;
@@ -591,34 +907,45 @@ void device_setup(Precond &pre, const HostFactors &hf, int precision) {
   pre.dev.reset(d.release());
 }
 
-namespace {
-
-void ensure_ws(DeviceState &d, int k) {
-  Workspace &w = d.ws;
-  if (w.sc.p && w.k >= k) return;
-  // captured graphs refer to the old buffers
-  for (auto &g : d.graphs)
-    if (g) (void)hipGraphExecDestroy(g);
-  for (auto &g : d.graph_defs)
-    if (g) (void)hipGraphDestroy(g);
-  d.graphs.clear();
-  d.graph_defs.clear();
-  const size_t np = (size_t)d.npad;
-  for (auto *b : {&w.u, &w.r, &w.p, &w.q, &w.z, &w.f}) {
-    b->alloc(np);
-    b->zero();
+// ---------------------------------------------------------------------------
+// star sweep dispatch over the column counts (instantiated in star_inst.hip)
+// ---------------------------------------------------------------------------
+template <typename T>
+static void launch_star_kc(int kc, const StarArgs &a, bool wide, const double *r, const CgScalars *sc, int sel,
+                           hipStream_t s) {
+  switch (kc) {
+    case 1: launch_star_t<T, 1>(a, wide, r, sc, sel, s); break;
+    case 2: launch_star_t<T, 2>(a, wide, r, sc, sel, s); break;
+    case 4: launch_star_t<T, 4>(a, wide, r, sc, sel, s); break;
+    case 8: launch_star_t<T, 8>(a, wide, r, sc, sel, s); break;
+    case 16: launch_star_t<T, 16>(a, wide, r, sc, sel, s); break;
+    default: fail(SN_EINVAL, "unsupported column count");
   }
-  w.rH.alloc((size_t)std::max<int64_t>(d.m0, 1));
-  w.c.alloc((size_t)std::max<int64_t>(d.m0, 1));
-  w.rH.zero();
-  w.c.zero();
-  w.partials.alloc(kMaxGrid);
-  w.sc.alloc(1);
-  w.sc.zero();
-  w.k = k;
+}
+void launch_star_fp32(int kc, const StarArgs &a, bool wide, const double *r, const CgScalars *sc, int sel,
+                      hipStream_t s) {
+  launch_star_kc<float>(kc, a, wide, r, sc, sel, s);
+}
+void launch_star_fp64(int kc, const StarArgs &a, bool wide, const double *r, const CgScalars *sc, int sel,
+                      hipStream_t s) {
+  launch_star_kc<double>(kc, a, wide, r, sc, sel, s);
 }
 
-StarArgs star_args(DeviceState &d) {
+namespace {
+
+template <typename F>
+void with_kc(int kc, F &&f) {
+  switch (kc) {
+    case 1: f(std::integral_constant<int, 1>{}); break;
+    case 2: f(std::integral_constant<int, 2>{}); break;
+    case 4: f(std::integral_constant<int, 4>{}); break;
+    case 8: f(std::integral_constant<int, 8>{}); break;
+    case 16: f(std::integral_constant<int, 16>{}); break;
+    default: fail(SN_EINVAL, "unsupported column count " + std::to_string(kc));
+  }
+}
+
+StarArgs star_args(DeviceState &d, Engine &e) {
   StarArgs a{};
   a.nstars = d.n_narrow;
   a.order = d.order_narrow.p;
@@ -631,27 +958,26 @@ StarArgs star_args(DeviceState &d) {
   a.pos_dof = d.pos_dof.p;
   a.f_hdr = d.f_hdr.p;
   a.b_hdr = d.b_hdr.p;
-  a.pad = d.pad;
   if (d.precision == SN_PREC_FP32_STARS) {
     a.f_inv = d.f_inv32.p;
     a.b_inv = d.b_inv32.p;
     a.f_val = d.f_val32.p;
     a.b_val = d.b_val32.p;
-    a.slots = d.slots32.p;
+    a.slots = e.slots32.p;
   } else {
     a.f_inv = d.f_inv64.p;
     a.b_inv = d.b_inv64.p;
     a.f_val = d.f_val64.p;
     a.b_val = d.b_val64.p;
-    a.slots = d.slots64.p;
+    a.slots = e.slots64.p;
   }
   return a;
 }
 
-
-// z = B r; with check = 1 the kernels skip work once the recurrence is done and
-// r.z goes to the partials
-void launch_B(DeviceState &d, const double *r, double *z, CgScalars *sc, int check, hipStream_t s) {
+// star sweeps of the selected columns (all columns are swept; the kernels
+// return at once when no column is selected)
+void launch_stars(Engine &e, const double *r, int sel, hipStream_t s) {
+  DeviceState &d = *e.d;
   std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
   if (d.profiling) {
     if (d.ev_free.empty()) {
@@ -664,133 +990,389 @@ void launch_B(DeviceState &d, const double *r, double *z, CgScalars *sc, int che
     HIPCHK(hipEventRecord(ev.first, s));
   }
   if (d.nstars > 0) {
-    StarArgs a = star_args(d);
+    StarArgs a = star_args(d, e);
     StarArgs aw = a;
     aw.nstars = d.n_wide;
     aw.order = d.order_wide.p;
     const bool f32 = d.precision == SN_PREC_FP32_STARS;
+    auto L = [&](const StarArgs &x, bool wide, hipStream_t st) {
+      if (f32) launch_star_fp32(e.kc, x, wide, r, e.sc.p, sel, st);
+      else launch_star_fp64(e.kc, x, wide, r, e.sc.p, sel, st);
+    };
     if (d.n_wide > 0 && d.n_narrow > 0) {
       // fork: the wide stars run on the auxiliary stream beside the narrow ones
-      HIPCHK(hipEventRecord(d.fork, s));
-      HIPCHK(hipStreamWaitEvent(d.aux, d.fork, 0));
-      if (f32) launch_star_fp32(aw, true, d.maxn_wide, r, sc, check, d.aux);
-      else launch_star_fp64(aw, true, d.maxn_wide, r, sc, check, d.aux);
-      HIPCHK(hipEventRecord(d.join, d.aux));
+      HIPCHK(hipEventRecord(e.fork, s));
+      HIPCHK(hipStreamWaitEvent(e.aux, e.fork, 0));
+      L(aw, true, e.aux);
+      HIPCHK(hipEventRecord(e.join, e.aux));
+      L(a, false, s);
+      HIPCHK(hipStreamWaitEvent(s, e.join, 0));
     } else if (d.n_wide > 0) {
-      if (f32) launch_star_fp32(aw, true, d.maxn_wide, r, sc, check, s);
-      else launch_star_fp64(aw, true, d.maxn_wide, r, sc, check, s);
+      L(aw, true, s);
+    } else {
+      L(a, false, s);
     }
-    if (d.n_narrow > 0) {
-      if (f32) launch_star_fp32(a, false, d.maxn_narrow, r, sc, check, s);
-      else launch_star_fp64(a, false, d.maxn_narrow, r, sc, check, s);
-    }
-    if (d.n_wide > 0 && d.n_narrow > 0) HIPCHK(hipStreamWaitEvent(s, d.join, 0));
   }
   if (d.profiling) {
     HIPCHK(hipEventRecord(ev.second, s));
     d.ev_used.push_back(ev);
   }
-  Workspace &w = d.ws;
-  if (d.m0 > 0) {
-    hipLaunchKernelGGL(k_restrict, dim3((unsigned)d.m0), dim3(kBlock), 0, s, d.PTptr.p, d.PTdof.p, d.PTw.p, r, w.rH.p,
-                       (int)d.m0, sc, check);
-    hipLaunchKernelGGL(k_coarse_gemv, dim3(nblk(d.m0 * 64)), dim3(kBlock), 0, s, d.Kinv.p, w.rH.p, w.c.p, (int)d.m0,
-                       sc, check);
-  }
-  const unsigned G = grid_for(d.npad);
-  double *parts = check ? w.partials.p : nullptr;
-  if (d.precision == SN_PREC_FP32_STARS)
-    hipLaunchKernelGGL(k_reduce<float>, dim3(G), dim3(kBlock), 0, s, z, r, d.slots32.p, d.slot_of.p, d.Pc.p, d.Pw.p,
-                       w.c.p, (int)d.npad, d.nv, sc, parts);
-  else
-    hipLaunchKernelGGL(k_reduce<double>, dim3(G), dim3(kBlock), 0, s, z, r, d.slots64.p, d.slot_of.p, d.Pc.p, d.Pw.p,
-                       w.c.p, (int)d.npad, d.nv, sc, parts);
-  if (check) hipLaunchKernelGGL(k_scalar, dim3(1), dim3(kBlock), 0, s, w.partials.p, (int)G, sc, (int)OP_BETA);
 }
 
-void launch_spmv(DeviceState &d, const double *x, double *y, CgScalars *sc, bool dot, hipStream_t s) {
+// z = B r on the selected columns; with dot, r.z -> rho, beta (second half)
+void launch_B(Engine &e, const double *r, double *z, int sel, bool dot, hipStream_t s) {
+  DeviceState &d = *e.d;
+  launch_stars(e, r, sel, s);
+  with_kc(e.kc, [&](auto K) {
+    constexpr int KC = decltype(K)::value;
+    if (d.m0 > 0) {
+      hipLaunchKernelGGL(k_restrict<KC>, dim3((unsigned)d.m0), dim3(kBlock), 0, s, d.PTptr.p, d.PTdof.p, d.PTw.p, r,
+                         e.rH.p, (int)d.m0, e.sc.p, sel);
+      hipLaunchKernelGGL(k_coarse_gemv<KC>, dim3(nblk(d.m0 * 64)), dim3(kBlock), 0, s, d.Kinv.p, e.rH.p, e.c.p,
+                         (int)d.m0, e.sc.p, sel);
+    }
+    const unsigned G = grid_for(d.npad);
+    double *parts = dot ? e.partials.p : nullptr;
+    if (d.precision == SN_PREC_FP32_STARS)
+      hipLaunchKernelGGL((k_reduce<float, KC>), dim3(G), dim3(kBlock), 0, s, z, r, e.slots32.p, d.slot_of.p, d.Pc.p,
+                         d.Pw.p, e.c.p, (int)d.npad, d.nv, e.sc.p, sel, parts);
+    else
+      hipLaunchKernelGGL((k_reduce<double, KC>), dim3(G), dim3(kBlock), 0, s, z, r, e.slots64.p, d.slot_of.p, d.Pc.p,
+                         d.Pw.p, e.c.p, (int)d.npad, d.nv, e.sc.p, sel, parts);
+    if (dot)
+      hipLaunchKernelGGL(k_scalar<KC>, dim3(1), dim3(kBlock), 0, s, e.partials.p, (int)G, e.sc.p, (int)OP_BETA, sel,
+                         0u);
+  });
+}
+
+// y = K x on the selected columns; with dot, x.y -> alpha (first half)
+void launch_spmv(Engine &e, const double *x, double *y, int sel, bool dot, hipStream_t s) {
+  DeviceState &d = *e.d;
   Sell A{d.sptr.p, d.slen.p, d.col.p, d.val.p};
   const unsigned G = grid_for(d.npad);
-  hipLaunchKernelGGL(k_spmv, dim3(G), dim3(kBlock), 0, s, A, x, y, (int)d.npad, sc, dot ? d.ws.partials.p : nullptr);
-  if (dot) hipLaunchKernelGGL(k_scalar, dim3(1), dim3(kBlock), 0, s, d.ws.partials.p, (int)G, sc, (int)OP_ALPHA);
+  with_kc(e.kc, [&](auto K) {
+    constexpr int KC = decltype(K)::value;
+    hipLaunchKernelGGL(k_spmv<KC>, dim3(G), dim3(kBlock), 0, s, A, x, y, (int)d.npad, e.sc.p, sel,
+                       dot ? e.partials.p : nullptr);
+    if (dot)
+      hipLaunchKernelGGL(k_scalar<KC>, dim3(1), dim3(kBlock), 0, s, e.partials.p, (int)G, e.sc.p, (int)OP_ALPHA, sel,
+                         0u);
+  });
 }
 
-void launch_iteration(DeviceState &d, hipStream_t s) {
-  Workspace &w = d.ws;
+void launch_iteration(Engine &e, hipStream_t s) {
+  DeviceState &d = *e.d;
   if (d.profiling) ++d.prof_iters;
-  CgScalars *sc = w.sc.p;
   const unsigned G = grid_for(d.npad);
-  launch_spmv(d, w.p.p, w.q.p, sc, true, s);
-  hipLaunchKernelGGL(k_cg_update, dim3(G), dim3(kBlock), 0, s, w.u.p, w.r.p, w.p.p, w.q.p, (int)d.npad, sc,
-                     w.partials.p);
-  hipLaunchKernelGGL(k_scalar, dim3(1), dim3(kBlock), 0, s, w.partials.p, (int)G, sc, (int)OP_CONV);
-  launch_B(d, w.r.p, w.z.p, sc, 1, s);
-  hipLaunchKernelGGL(k_p_update, dim3(G), dim3(kBlock), 0, s, w.p.p, w.z.p, (int)d.npad, sc);
+  launch_spmv(e, e.p.p, e.q.p, SEL_FIRST, true, s);
+  with_kc(e.kc, [&](auto K) {
+    constexpr int KC = decltype(K)::value;
+    hipLaunchKernelGGL(k_cg_update<KC>, dim3(G), dim3(kBlock), 0, s, e.u.p, e.r.p, e.p.p, e.q.p, (int)d.npad, e.sc.p,
+                       e.partials.p);
+    hipLaunchKernelGGL(k_scalar<KC>, dim3(1), dim3(kBlock), 0, s, e.partials.p, (int)G, e.sc.p, (int)OP_CONV,
+                       (int)SEL_FIRST, 0u);
+  });
+  launch_B(e, e.r.p, e.z.p, SEL_SECOND, true, s);
+  with_kc(e.kc, [&](auto K) {
+    constexpr int KC = decltype(K)::value;
+    hipLaunchKernelGGL(k_p_update<KC>, dim3(G), dim3(kBlock), 0, s, e.p.p, e.z.p, (int)d.npad, e.sc.p);
+  });
+}
+
+// true residual of the stopped columns: restart or final (see OP_TRUE)
+void launch_verify(Engine &e, hipStream_t s) {
+  DeviceState &d = *e.d;
+  const unsigned G = grid_for(d.npad);
+  launch_spmv(e, e.u.p, e.q.p, SEL_VERIFY, false, s);
+  with_kc(e.kc, [&](auto K) {
+    constexpr int KC = decltype(K)::value;
+    hipLaunchKernelGGL(k_sub_dot<KC>, dim3(G), dim3(kBlock), 0, s, e.q.p, e.f.p, e.q.p, (int)d.npad, e.sc.p,
+                       (int)SEL_VERIFY, 0u, e.partials.p);
+    hipLaunchKernelGGL(k_scalar<KC>, dim3(1), dim3(kBlock), 0, s, e.partials.p, (int)G, e.sc.p, (int)OP_TRUE,
+                       (int)SEL_VERIFY, 0u);
+    hipLaunchKernelGGL(k_copy_sel<KC>, dim3(G), dim3(kBlock), 0, s, e.r.p, e.q.p, (int)d.npad, e.sc.p,
+                       (int)SEL_RESTART, 0u);
+  });
+}
+
+// f.f -> f2, tol2 and r.r -> rr (done at once when nothing is to iterate) for
+// the columns of `mask`
+void launch_start_dots(Engine &e, uint32_t mask, hipStream_t s) {
+  DeviceState &d = *e.d;
+  const unsigned G = grid_for(d.npad);
+  with_kc(e.kc, [&](auto K) {
+    constexpr int KC = decltype(K)::value;
+    hipLaunchKernelGGL(k_dot<KC>, dim3(G), dim3(kBlock), 0, s, e.f.p, e.f.p, (int)d.npad, e.partials.p, e.sc.p,
+                       (int)SEL_MASK, mask);
+    hipLaunchKernelGGL(k_scalar<KC>, dim3(1), dim3(kBlock), 0, s, e.partials.p, (int)G, e.sc.p, (int)OP_F2,
+                       (int)SEL_MASK, mask);
+    hipLaunchKernelGGL(k_dot<KC>, dim3(G), dim3(kBlock), 0, s, e.r.p, e.r.p, (int)d.npad, e.partials.p, e.sc.p,
+                       (int)SEL_MASK, mask);
+    hipLaunchKernelGGL(k_scalar<KC>, dim3(1), dim3(kBlock), 0, s, e.partials.p, (int)G, e.sc.p, (int)OP_R2,
+                       (int)SEL_MASK, mask);
+  });
 }
 
 // run m iterations: as captured graphs of 2^i iterations, or launch by launch
-void run_iterations(DeviceState &d, int m, bool use_graph, hipStream_t s) {
-  if (!use_graph || d.profiling) {
-    for (int it = 0; it < m; ++it) launch_iteration(d, s);
+void run_iterations(Engine &e, int m, bool use_graph, hipStream_t s) {
+  if (!use_graph || e.d->profiling) {
+    for (int it = 0; it < m; ++it) launch_iteration(e, s);
     return;
   }
   for (int i = 0; m > 0; ++i) {
     if (!(m & (1 << i))) continue;
-    if ((int)d.graphs.size() <= i) {
-      d.graphs.resize(i + 1, nullptr);
-      d.graph_defs.resize(i + 1, nullptr);
+    if ((int)e.graphs.size() <= i) {
+      e.graphs.resize(i + 1, nullptr);
+      e.graph_defs.resize(i + 1, nullptr);
     }
-    if (!d.graphs[i]) {
-      // capture on the library's own stream, replay on the caller's
+    if (!e.graphs[i]) {
+      // capture on the engine's own stream, replay on the caller's
       HIPCHK(hipStreamSynchronize(s));
-      HIPCHK(hipStreamBeginCapture(d.own, hipStreamCaptureModeRelaxed));
-      for (int it = 0; it < (1 << i); ++it) launch_iteration(d, d.own);
-      HIPCHK(hipStreamEndCapture(d.own, &d.graph_defs[i]));
-      HIPCHK(hipGraphInstantiate(&d.graphs[i], d.graph_defs[i], nullptr, nullptr, 0));
+      HIPCHK(hipStreamBeginCapture(e.own, hipStreamCaptureModeRelaxed));
+      for (int it = 0; it < (1 << i); ++it) launch_iteration(e, e.own);
+      HIPCHK(hipStreamEndCapture(e.own, &e.graph_defs[i]));
+      HIPCHK(hipGraphInstantiate(&e.graphs[i], e.graph_defs[i], nullptr, nullptr, 0));
     }
-    HIPCHK(hipGraphLaunch(d.graphs[i], s));
+    HIPCHK(hipGraphLaunch(e.graphs[i], s));
     m -= 1 << i;
   }
 }
 
-double device_dot(DeviceState &d, const double *a, const double *b, hipStream_t s) {
-  Workspace &w = d.ws;
-  const unsigned G = grid_for(d.npad);
-  hipLaunchKernelGGL(k_dot, dim3(G), dim3(kBlock), 0, s, a, b, (int)d.npad, w.partials.p);
-  hipLaunchKernelGGL(k_scalar, dim3(1), dim3(kBlock), 0, s, w.partials.p, (int)G, w.sc.p, (int)OP_DOT);
-  double v = 0;
-  HIPCHK(hipMemcpyAsync(&v, &w.sc.p->tmp, sizeof(double), hipMemcpyDeviceToHost, s));
+void upload_scalars(Engine &e, hipStream_t s) {
+  HIPCHK(hipMemcpyAsync(e.sc.p, e.host_sc, (size_t)e.kc * sizeof(CgScalars), hipMemcpyHostToDevice, s));
+  e.sc_dirty = false;
+}
+
+// iterations, true-residual checks and the asynchronous read-back of the
+// column states
+void tick(Engine &e, int iters, bool use_graph, hipStream_t s) {
+  if (e.sc_dirty) upload_scalars(e, s);
+  if (iters > 0) run_iterations(e, iters, use_graph, s);
+  launch_verify(e, s);
+  HIPCHK(hipMemcpyAsync(e.host_sc, e.sc.p, (size_t)e.kc * sizeof(CgScalars), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipEventRecord(e.tick_done, s));
+  e.in_flight = true;
+}
+
+void wait_tick(Engine &e) {
+  if (!e.in_flight) return;
+  HIPCHK(hipEventSynchronize(e.tick_done));
+  e.in_flight = false;
+}
+
+CgScalars column_init(double rtol, int64_t max_iter, int64_t fixed) {
+  CgScalars x;
+  std::memset(&x, 0, sizeof(x));
+  x.rtol = rtol;
+  x.max_iter = (int32_t)std::min<int64_t>(max_iter > 0 ? max_iter : 1000, 1 << 30);
+  x.fixed = (int32_t)std::max<int64_t>(std::min<int64_t>(fixed, 1 << 30), 0);
+  x.active = 1;
+  x.first = 1;
+  x.fresh = 1;
+  return x;
+}
+
+int kc_index(int kc) {
+  switch (kc) {
+    case 1: return 0;
+    case 2: return 1;
+    case 4: return 2;
+    case 8: return 3;
+    default: return 4;
+  }
+}
+
+Engine &solve_engine(Precond &pre, int k) {
+  DeviceState &d = *pre.dev;
+  const int kc = engine_width_for(k);
+  auto &slot = d.solve_engine[kc_index(kc)];
+  if (!slot) slot.reset(engine_create(pre, kc));
+  return *slot;
+}
+
+// host n x k block -> staging buffer (the engine's q); returns the device source
+const double *stage_block(Engine &e, const double *src, int k, bool dev_ptrs, hipStream_t s) {
+  if (dev_ptrs) return src;
+  HIPCHK(hipMemcpyAsync(e.q.p, src, (size_t)e.d->n * k * sizeof(double), hipMemcpyHostToDevice, s));
+  return e.q.p;
+}
+
+// batch vector columns 0..k-1 -> n x k block (host or device)
+void store_block(Engine &e, double *dst, const double *src, int k, bool dev_ptrs, hipStream_t s) {
+  DeviceState &d = *e.d;
+  if (dev_ptrs) {
+    with_kc(e.kc, [&](auto K) {
+      constexpr int KC = decltype(K)::value;
+      for (int j = 0; j < k; ++j)
+        hipLaunchKernelGGL(k_col_out<KC>, dim3(grid_for(d.n)), dim3(kBlock), 0, s, dst, src, (int)d.n, k, j, j);
+    });
+    HIPCHK(hipStreamSynchronize(s));
+    return;
+  }
+  std::vector<double> tmp((size_t)d.n * e.kc);
+  HIPCHK(hipMemcpyAsync(tmp.data(), src, tmp.size() * sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
-  return v;
+  for (int64_t i = 0; i < d.n; ++i)
+    for (int j = 0; j < k; ++j) dst[(size_t)i * k + j] = tmp[(size_t)i * e.kc + j];
 }
 
-// copy column c of an n x k block (host or device) into a padded device vector
-void load_column(DeviceState &d, double *dst, const double *src, int k, int c, bool dev_ptrs, hipStream_t s) {
-  const int64_t n = d.n;
-  if (dev_ptrs) {
-    hipLaunchKernelGGL(k_gather_col, dim3(grid_for(n)), dim3(kBlock), 0, s, dst, src, (int)n, k, c);
-  } else {
-    std::vector<double> tmp((size_t)n);
-    for (int64_t i = 0; i < n; ++i) tmp[i] = src[(size_t)i * k + c];
-    HIPCHK(hipMemcpyAsync(dst, tmp.data(), (size_t)n * sizeof(double), hipMemcpyHostToDevice, s));
-    HIPCHK(hipStreamSynchronize(s));
-  }
-}
-
-void store_column(DeviceState &d, double *dst, const double *src, int k, int c, bool dev_ptrs, hipStream_t s) {
-  const int64_t n = d.n;
-  if (dev_ptrs) {
-    hipLaunchKernelGGL(k_scatter_col, dim3(grid_for(n)), dim3(kBlock), 0, s, dst, src, (int)n, k, c);
-  } else {
-    std::vector<double> tmp((size_t)n);
-    HIPCHK(hipMemcpyAsync(tmp.data(), src, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    for (int64_t i = 0; i < n; ++i) dst[(size_t)i * k + c] = tmp[i];
-  }
+// n x k block (device) -> batch vector columns 0..k-1 (the rest zero)
+void load_block(Engine &e, double *dst, const double *src_dev, int k, hipStream_t s) {
+  DeviceState &d = *e.d;
+  with_kc(e.kc, [&](auto K) {
+    constexpr int KC = decltype(K)::value;
+    for (int j = 0; j < e.kc; ++j) {
+      if (j < k)
+        hipLaunchKernelGGL(k_col_in<KC>, dim3(grid_for(d.npad)), dim3(kBlock), 0, s, dst, src_dev, (int)d.n,
+                           (int)d.npad, k, j, j);
+      else
+        hipLaunchKernelGGL(k_col_in<KC>, dim3(grid_for(d.npad)), dim3(kBlock), 0, s, dst, src_dev, 0, (int)d.npad,
+                           k, 0, j);
+    }
+  });
 }
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// engines
+// ---------------------------------------------------------------------------
+int engine_width_for(int k) {
+  if (k < 1 || k > kMaxCols) fail(SN_EINVAL, "k must be in 1..16");
+  int w = 1;
+  while (w < k) w *= 2;
+  return w;
+}
+
+int64_t engine_footprint(const Precond &pre, int kc) {
+  const int64_t n = pre.sys->n, npad = (n + kBlock - 1) / kBlock * kBlock;
+  const int64_t m0 = std::max<int64_t>(pre.m0, 1);
+  const int prec = pre.dev ? pre.finfo.star_precision : pre.precision;
+  const int64_t ts = prec == SN_PREC_FP32_STARS ? 4 : 8;
+  return (6 * npad * kc + 2 * m0 * kc + (int64_t)kc * kMaxGrid) * 8 + kc * (int64_t)sizeof(CgScalars) +
+         (int64_t)pre.star_dofs.size() * kc * ts;
+}
+
+Engine *engine_create(Precond &pre, int kc) {
+  if (!pre.dev) fail(SN_EINVAL, "preconditioner not factored");
+  (void)engine_width_for(kc);
+  if (engine_width_for(kc) != kc) fail(SN_EINVAL, "engine width must be 1, 2, 4, 8 or 16");
+  DeviceState &d = *pre.dev;
+  std::unique_ptr<Engine> e(new Engine);
+  e->pre = &pre;
+  e->d = &d;
+  e->kc = kc;
+  const size_t np = (size_t)d.npad * kc;
+  for (auto *b : {&e->u, &e->r, &e->p, &e->q, &e->z, &e->f}) {
+    b->alloc(np);
+    b->zero();
+  }
+  const size_t nm = (size_t)std::max<int64_t>(d.m0, 1) * kc;
+  e->rH.alloc(nm);
+  e->c.alloc(nm);
+  e->rH.zero();
+  e->c.zero();
+  e->partials.alloc((size_t)kc * kMaxGrid);
+  e->partials.zero();
+  e->sc.alloc((size_t)kc);
+  e->sc.zero();
+  if (d.precision == SN_PREC_FP32_STARS) {
+    e->slots32.alloc((size_t)std::max<int64_t>(d.slot_count, 1) * kc);
+    e->slots32.zero();
+  } else {
+    e->slots64.alloc((size_t)std::max<int64_t>(d.slot_count, 1) * kc);
+    e->slots64.zero();
+  }
+  HIPCHK(hipHostMalloc((void **)&e->host_sc, (size_t)kc * sizeof(CgScalars), hipHostMallocDefault));
+  std::memset(e->host_sc, 0, (size_t)kc * sizeof(CgScalars));
+  HIPCHK(hipStreamCreateWithFlags(&e->own, hipStreamNonBlocking));
+  HIPCHK(hipStreamCreateWithFlags(&e->aux, hipStreamNonBlocking));
+  HIPCHK(hipEventCreateWithFlags(&e->fork, hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&e->join, hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&e->tick_done, hipEventDisableTiming));
+  HIPCHK(hipDeviceSynchronize());
+  e->bytes = (int64_t)(6 * np * 8 + 2 * nm * 8 + e->partials.bytes() + e->sc.bytes() + e->slots32.bytes() +
+                       e->slots64.bytes());
+  return e.release();
+}
+
+void engine_destroy(Engine *e) { delete e; }
+int engine_width(const Engine *e) { return e->kc; }
+
+void engine_admit(Engine *e, int k, const int32_t *cols, const double *f, const double *rtol,
+                  const int64_t *max_iter) {
+  if (e->in_flight) fail(SN_EINVAL, "internal: admission into a running engine");
+  if (k < 1 || k > e->kc) fail(SN_EINVAL, "internal: bad admission size");
+  DeviceState &d = *e->d;
+  const hipStream_t s = e->own;
+  const double *src = stage_block(*e, f, k, false, s);
+  uint32_t mask = 0;
+  with_kc(e->kc, [&](auto K) {
+    constexpr int KC = decltype(K)::value;
+    for (int j = 0; j < k; ++j) {
+      const int c = cols[j];
+      if (c < 0 || c >= e->kc || e->host_sc[c].active) fail(SN_EINVAL, "internal: column not free");
+      hipLaunchKernelGGL(k_admit<KC>, dim3(grid_for(d.npad)), dim3(kBlock), 0, s, e->f.p, e->r.p, e->u.p, e->p.p,
+                         src, (int)d.n, (int)d.npad, k, j, c);
+      e->host_sc[c] = column_init(rtol[j], max_iter[j], 0);
+      mask |= 1u << c;
+    }
+  });
+  upload_scalars(*e, s);
+  launch_start_dots(*e, mask, s);
+}
+
+void engine_tick(Engine *e, int iters, bool use_graph) {
+  if (e->in_flight) fail(SN_EINVAL, "internal: tick on a running engine");
+  tick(*e, iters, use_graph, e->own);
+}
+
+bool engine_query(Engine *e) {
+  if (!e->in_flight) return true;
+  const hipError_t r = hipEventQuery(e->tick_done);
+  if (r == hipErrorNotReady) return false;
+  HIPCHK(r);
+  e->in_flight = false;
+  return true;
+}
+
+void engine_wait(Engine *e) { wait_tick(*e); }
+
+void engine_status(const Engine *e, ColumnStatus *out) {
+  for (int c = 0; c < e->kc; ++c) {
+    const CgScalars &x = e->host_sc[c];
+    out[c].iters = x.iters;
+    out[c].rr = x.rr;
+    out[c].f2 = x.f2;
+    out[c].tol2 = x.tol2;
+    out[c].t2 = x.t2;
+    out[c].active = x.active;
+    out[c].done = x.done;
+    out[c].verify = x.verify;
+    out[c].replacements = x.replacements;
+    out[c].fixed = x.fixed;
+  }
+}
+
+void engine_retire(Engine *e, int c, double *u, int64_t ld) {
+  if (e->in_flight) fail(SN_EINVAL, "internal: retire on a running engine");
+  DeviceState &d = *e->d;
+  const hipStream_t s = e->own;
+  with_kc(e->kc, [&](auto K) {
+    constexpr int KC = decltype(K)::value;
+    hipLaunchKernelGGL(k_col_out<KC>, dim3(grid_for(d.n)), dim3(kBlock), 0, s, e->q.p, e->u.p, (int)d.n, 1, 0, c);
+  });
+  std::vector<double> tmp((size_t)d.n);
+  HIPCHK(hipMemcpyAsync(tmp.data(), e->q.p, tmp.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  for (int64_t i = 0; i < d.n; ++i) u[(size_t)i * ld] = tmp[i];
+  std::memset(&e->host_sc[c], 0, sizeof(CgScalars));
+  e->sc_dirty = true;
+}
+
+// ---------------------------------------------------------------------------
+// sn_solve / sn_apply_* on the per-width engines of the preconditioner
+// ---------------------------------------------------------------------------
 void device_profile(Precond &pre, int enable) {
   DeviceState &d = *pre.dev;
   HIPCHK(hipDeviceSynchronize());
@@ -814,143 +1396,131 @@ void device_stats(Precond &pre, sn_kernel_stats *st) {
   st->iterations = d.prof_iters;
 }
 
+int64_t device_bytes(const Precond &pre) { return pre.dev ? pre.dev->bytes : 0; }
+
 void device_apply_K(Precond &pre, int k, const double *x, double *y, int device_ptrs, void *stream) {
-  DeviceState &d = *pre.dev;
-  hipStream_t s = stream ? (hipStream_t)stream : d.own;
-  ensure_ws(d, k);
-  Workspace &w = d.ws;
-  for (int c = 0; c < k; ++c) {
-    load_column(d, w.p.p, x, k, c, device_ptrs, s);
-    launch_spmv(d, w.p.p, w.q.p, w.sc.p, false, s);
-    store_column(d, y, w.q.p, k, c, device_ptrs, s);
-  }
-  HIPCHK(hipStreamSynchronize(s));
+  Engine &e = solve_engine(pre, k);
+  wait_tick(e);
+  const hipStream_t s = stream ? (hipStream_t)stream : e.own;
+  const double *src = stage_block(e, x, k, device_ptrs != 0, s);
+  load_block(e, e.p.p, src, k, s);
+  launch_spmv(e, e.p.p, e.z.p, SEL_ALL, false, s);
+  store_block(e, y, e.z.p, k, device_ptrs != 0, s);
 }
 
 void device_apply_B(Precond &pre, int k, const double *r, double *z, int device_ptrs, void *stream) {
-  DeviceState &d = *pre.dev;
-  hipStream_t s = stream ? (hipStream_t)stream : d.own;
-  ensure_ws(d, k);
-  Workspace &w = d.ws;
-  for (int c = 0; c < k; ++c) {
-    load_column(d, w.r.p, r, k, c, device_ptrs, s);
-    launch_B(d, w.r.p, w.z.p, w.sc.p, 0, s);
-    store_column(d, z, w.z.p, k, c, device_ptrs, s);
-  }
-  HIPCHK(hipStreamSynchronize(s));
+  Engine &e = solve_engine(pre, k);
+  wait_tick(e);
+  const hipStream_t s = stream ? (hipStream_t)stream : e.own;
+  const double *src = stage_block(e, r, k, device_ptrs != 0, s);
+  load_block(e, e.r.p, src, k, s);
+  launch_B(e, e.r.p, e.z.p, SEL_ALL, false, s);
+  store_block(e, z, e.z.p, k, device_ptrs != 0, s);
 }
 
 void device_solve(Precond &pre, int k, const double *f, double *u, const sn_solve_opts &o, sn_solve_info *info) {
-  DeviceState &d = *pre.dev;
-  hipStream_t s = o.stream ? (hipStream_t)o.stream : d.own;
-  ensure_ws(d, k);
-  Workspace &w = d.ws;
+  const auto t0 = std::chrono::steady_clock::now();
+  Engine &e = solve_engine(pre, k);
+  wait_tick(e);
+  DeviceState &d = *e.d;
+  const hipStream_t s = o.stream ? (hipStream_t)o.stream : e.own;
+  const bool dev = o.device_ptrs != 0;
   const int check = o.check_every > 0 ? o.check_every : 8;
-  bool all_conv = true;
-  for (int c = 0; c < k; ++c) {
-    const auto t0 = std::chrono::steady_clock::now();
-    load_column(d, w.f.p, f, k, c, o.device_ptrs != 0, s);
-    if (o.use_u0) load_column(d, w.u.p, u, k, c, o.device_ptrs != 0, s);
-    else HIPCHK(hipMemsetAsync(w.u.p, 0, (size_t)d.npad * sizeof(double), s));
-    // r = f - K u
-    if (o.use_u0) {
-      launch_spmv(d, w.u.p, w.q.p, w.sc.p, false, s);
-      hipLaunchKernelGGL(k_sub, dim3(grid_for(d.npad)), dim3(kBlock), 0, s, w.r.p, w.f.p, w.q.p, (int)d.npad);
+  // start the k columns: f = r = f_j, u = p = 0; unused columns stay inactive
+  const double *src = stage_block(e, f, k, dev, s);
+  uint32_t mask = 0;
+  with_kc(e.kc, [&](auto K) {
+    constexpr int KC = decltype(K)::value;
+    for (int j = 0; j < e.kc; ++j)
+      hipLaunchKernelGGL(k_admit<KC>, dim3(grid_for(d.npad)), dim3(kBlock), 0, s, e.f.p, e.r.p, e.u.p, e.p.p, src,
+                         j < k ? (int)d.n : 0, (int)d.npad, k, j < k ? j : 0, j);
+  });
+  for (int j = 0; j < e.kc; ++j) {
+    if (j < k) {
+      e.host_sc[j] = column_init(o.rtol, o.max_iter, o.fixed_iters);
+      mask |= 1u << j;
     } else {
-      HIPCHK(hipMemcpyAsync(w.r.p, w.f.p, (size_t)d.npad * sizeof(double), hipMemcpyDeviceToDevice, s));
+      std::memset(&e.host_sc[j], 0, sizeof(CgScalars));
     }
-    const double f2 = device_dot(d, w.f.p, w.f.p, s);
-    const double r2 = device_dot(d, w.r.p, w.r.p, s);
-    CgScalars h{};
-    h.f2 = f2;
-    h.tol2 = o.rtol * o.rtol * f2;
-    h.max_iter = (int32_t)std::min<int64_t>(o.max_iter > 0 ? o.max_iter : 1000, 1 << 30);
-    h.fixed = (int32_t)std::max<int64_t>(o.fixed_iters, 0);
-    h.first = 1;
-    h.rr = r2;
-    h.done = (h.fixed == 0 && r2 <= h.tol2) || (h.fixed == 0 && f2 == 0.0) ? 1 : 0;
-    HIPCHK(hipMemcpyAsync(w.sc.p, &h, sizeof(h), hipMemcpyHostToDevice, s));
-    HIPCHK(hipStreamSynchronize(s));
-    int replacements = 0;
-    if (!h.done) {
-      // z = B r, rho = r.z, p = z
-      launch_B(d, w.r.p, w.z.p, w.sc.p, 1, s);
-      HIPCHK(hipMemcpyAsync(w.p.p, w.z.p, (size_t)d.npad * sizeof(double), hipMemcpyDeviceToDevice, s));
-      int64_t since_replace = 0;
-      // iterations queued between read-backs: first `check`, then the number the
-      // observed contraction of ||r||^2 predicts is still needed (>= 1)
-      int block = h.fixed > 0 ? std::min(check, h.fixed) : check;
-      double prev_rr = h.rr;
-      int prev_it = 0;
-      for (;;) {
-        run_iterations(d, block, o.use_graph != 0, s);
-        HIPCHK(hipMemcpyAsync(&h, w.sc.p, sizeof(h), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        since_replace += block;
-        if (h.fixed > 0) {
-          block = std::max(1, std::min(4 * check, h.fixed - h.iters));
-        } else {
-          const int di = h.iters - prev_it;
-          block = check;
-          if (di > 0 && h.rr > 0.0 && prev_rr > h.rr && h.rr > h.tol2) {
-            const double rate = std::pow(h.rr / prev_rr, 1.0 / di);
-            const double need = std::log(h.tol2 / h.rr) / std::log(rate);
-            if (std::isfinite(need)) block = (int)std::max(1.0, std::min((double)(4 * check), std::ceil(need)));
-          }
-          prev_rr = h.rr;
-          prev_it = h.iters;
-        }
-        if (h.done) {
-          // confirm with the true residual. When it exceeds the tolerance by a
-          // small factor the recurrence has drifted: restart from it. A true
-          // residual far above the tolerance is the attainable accuracy of the
-          // system in FP64, which a restart cannot improve.
-          if (h.fixed == 0 && h.rr <= h.tol2 && h.iters < h.max_iter) {
-            launch_spmv(d, w.u.p, w.q.p, w.sc.p, false, s);
-            hipLaunchKernelGGL(k_sub, dim3(grid_for(d.npad)), dim3(kBlock), 0, s, w.q.p, w.f.p, w.q.p, (int)d.npad);
-            const double t2 = device_dot(d, w.q.p, w.q.p, s);
-            if (t2 > h.tol2 * 1.0000001 && t2 < 100.0 * h.tol2 && replacements < 3) {
-              // restart from the true residual: r = f - K u, z = B r, p = z
-              HIPCHK(hipMemcpyAsync(w.r.p, w.q.p, (size_t)d.npad * sizeof(double), hipMemcpyDeviceToDevice, s));
-              ++replacements;
-              h.done = 0;
-              h.rr = t2;
-              h.first = 1;
-              HIPCHK(hipMemcpyAsync(w.sc.p, &h, sizeof(h), hipMemcpyHostToDevice, s));
-              HIPCHK(hipStreamSynchronize(s));
-              launch_B(d, w.r.p, w.z.p, w.sc.p, 1, s);
-              HIPCHK(hipMemcpyAsync(w.p.p, w.z.p, (size_t)d.npad * sizeof(double), hipMemcpyDeviceToDevice, s));
-              since_replace = 0;
-              block = check;
-              prev_rr = t2;
-              prev_it = h.iters;
-              continue;
-            }
-          }
-          break;
-        }
-        if (o.replace_every > 0 && since_replace >= o.replace_every) {
-          launch_spmv(d, w.u.p, w.q.p, w.sc.p, false, s);
-          hipLaunchKernelGGL(k_sub, dim3(grid_for(d.npad)), dim3(kBlock), 0, s, w.r.p, w.f.p, w.q.p, (int)d.npad);
-          ++replacements;
-          since_replace = 0;
-        }
+  }
+  upload_scalars(e, s);
+  if (o.use_u0) {
+    // r = f - K u0
+    const double *usrc = stage_block(e, u, k, dev, s);
+    load_block(e, e.u.p, usrc, k, s);
+    launch_spmv(e, e.u.p, e.q.p, SEL_ALL, false, s);
+    with_kc(e.kc, [&](auto K) {
+      constexpr int KC = decltype(K)::value;
+      hipLaunchKernelGGL(k_sub_dot<KC>, dim3(grid_for(d.npad)), dim3(kBlock), 0, s, e.r.p, e.f.p, e.q.p,
+                         (int)d.npad, e.sc.p, (int)SEL_MASK, mask, (double *)nullptr);
+    });
+  }
+  launch_start_dots(e, mask, s);
+  // iterations queued between read-backs: first `check`, then the number the
+  // observed contraction of ||r||^2 predicts the slowest column still needs
+  // (at least 1, at most 4 check); one at a time while kernels are timed, so
+  // that no timed launch runs after convergence
+  std::vector<double> prev_rr(k, 0.0);
+  std::vector<int64_t> prev_it(k, 0);
+  int block = o.fixed_iters > 0 ? (int)std::min<int64_t>(check, o.fixed_iters + 1) : check;
+  int64_t since_replace = 0;
+  bool first_tick = true;
+  for (;;) {
+    if (d.profiling) block = 1;
+    tick(e, block, o.use_graph != 0, s);
+    wait_tick(e);
+    since_replace += block;
+    bool running = false;
+    int next = 1;
+    for (int j = 0; j < k; ++j) {
+      const CgScalars &x = e.host_sc[j];
+      if (x.done && !x.verify) continue;
+      running = true;
+      if (x.fixed > 0) {
+        next = std::max<int>(next, (int)std::min<int64_t>(4 * check, x.fixed - x.iters + (x.fresh ? 1 : 0)));
+        continue;
       }
+      int need = check;
+      const int64_t di = x.iters - prev_it[j];
+      if (!first_tick && di > 0 && x.rr > 0.0 && prev_rr[j] > x.rr && x.rr > x.tol2) {
+        const double rate = std::pow(x.rr / prev_rr[j], 1.0 / (double)di);
+        const double nd = std::log(x.tol2 / x.rr) / std::log(rate);
+        if (std::isfinite(nd)) need = (int)std::max(1.0, std::min((double)(4 * check), std::ceil(nd)));
+      }
+      next = std::max(next, need);
+      prev_rr[j] = x.rr;
+      prev_it[j] = x.iters;
     }
-    // true residual
-    launch_spmv(d, w.u.p, w.q.p, w.sc.p, false, s);
-    hipLaunchKernelGGL(k_sub, dim3(grid_for(d.npad)), dim3(kBlock), 0, s, w.q.p, w.f.p, w.q.p, (int)d.npad);
-    const double t2 = device_dot(d, w.q.p, w.q.p, s);
-    store_column(d, u, w.u.p, k, c, o.device_ptrs != 0, s);
-    HIPCHK(hipStreamSynchronize(s));
-    const double fn = std::sqrt(f2);
-    info[c].iters = h.iters;
-    info[c].res_rec = fn > 0 ? std::sqrt(h.rr) / fn : std::sqrt(h.rr);
-    info[c].res_true = fn > 0 ? std::sqrt(t2) / fn : std::sqrt(t2);
-    info[c].converged = (h.fixed > 0) ? 1 : (h.rr <= h.tol2 ? 1 : 0);
-    info[c].replacements = replacements;
-    info[c].ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-    if (!info[c].converged) all_conv = false;
+    first_tick = false;
+    if (!running) break;
+    block = next;
+    if (o.replace_every > 0 && since_replace >= o.replace_every) {
+      // residual replacement on the iterating columns: r = f - K u
+      launch_spmv(e, e.u.p, e.q.p, SEL_ALL, false, s);
+      with_kc(e.kc, [&](auto K) {
+        constexpr int KC = decltype(K)::value;
+        hipLaunchKernelGGL(k_sub_dot<KC>, dim3(grid_for(d.npad)), dim3(kBlock), 0, s, e.r.p, e.f.p, e.q.p,
+                           (int)d.npad, e.sc.p, (int)SEL_FIRST, 0u, (double *)nullptr);
+      });
+      for (int j = 0; j < k; ++j)
+        if (!e.host_sc[j].done && !e.host_sc[j].fresh) e.host_sc[j].replacements += 1;
+      e.sc_dirty = true;
+      since_replace = 0;
+    }
+  }
+  store_block(e, u, e.u.p, k, dev, s);
+  const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  bool all_conv = true;
+  for (int j = 0; j < k; ++j) {
+    const CgScalars &x = e.host_sc[j];
+    const double fn = std::sqrt(x.f2);
+    info[j].iters = x.iters;
+    info[j].res_rec = fn > 0 ? std::sqrt(x.rr) / fn : std::sqrt(x.rr);
+    info[j].res_true = fn > 0 ? std::sqrt(x.t2) / fn : std::sqrt(x.t2);
+    info[j].converged = x.fixed > 0 ? 1 : (x.rr <= x.tol2 ? 1 : 0);
+    info[j].replacements = x.replacements;
+    info[j].ms = ms;
+    if (!info[j].converged) all_conv = false;
   }
   if (!all_conv) fail(SN_ENOCONV, "PCG reached max_iter before the tolerance");
 }

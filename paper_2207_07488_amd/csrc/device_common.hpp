@@ -17,13 +17,44 @@ namespace spnet {
   } while (0)
 
 // ---------------------------------------------------------------------------
-// device scalars of one PCG recurrence
+// Device state of one PCG column (one right-hand side), Sec. 4.2. A batch of KC
+// columns keeps one of these per column; the kernels read the flags to decide
+// which columns they advance.
+//
+//   active  the column holds a right-hand side
+//   fresh   the next iteration skips its first half (q = K p ... convergence)
+//           and only computes z = B r, rho = r.z and p = z: a column joins a
+//           running batch this way
+//   done    the recurrence has stopped (tolerance, max_iter or fixed count)
+//   verify  stopped, its true residual f - K u is still to be checked
+//   restart the check asked for a restart from the true residual
 // ---------------------------------------------------------------------------
 struct CgScalars {
-  double rho, alpha, beta, pq, rr, rz, f2, tol2;
-  double tmp;  // scratch dot result
-  int32_t iters, done, max_iter, fixed, first, pad0;
+  double rho, alpha, beta, rr, f2, tol2, t2, rtol;
+  double tmp, pq, rz, pad0;
+  int32_t iters, done, max_iter, fixed, first, fresh, verify, restart, replacements, active, pad1, pad2;
 };
+
+// which columns a kernel works on
+enum ColumnSel : int32_t {
+  SEL_ALL = 0,      // every column (apply_K / apply_B / set-up)
+  SEL_FIRST = 1,    // first half of an iteration: active, not done, not fresh
+  SEL_SECOND = 2,   // second half: active, not done
+  SEL_VERIFY = 3,   // stopped columns whose true residual is pending
+  SEL_RESTART = 4,  // columns restarting from their true residual
+  SEL_MASK = 5,     // the columns of an explicit bit mask
+};
+
+__device__ __forceinline__ bool column_selected(const CgScalars &s, int sel, uint32_t mask, int c) {
+  switch (sel) {
+    case SEL_ALL: return true;
+    case SEL_FIRST: return s.active && !s.done && !s.fresh;
+    case SEL_SECOND: return s.active && !s.done;
+    case SEL_VERIFY: return s.active && s.verify;
+    case SEL_RESTART: return s.active && s.restart;
+    default: return (mask >> c) & 1u;
+  }
+}
 
 // Arguments of the star sweep kernel (see star_kernel.hpp).
 struct StarArgs {
@@ -39,15 +70,19 @@ struct StarArgs {
   const uint32_t *f_hdr, *b_hdr;             // per group: width << 21 | offset (16-byte units)
   const void *f_inv, *b_inv;                 // 1/pivot per step (T)
   const void *f_val, *b_val;                 // packed stream values (T)
-  void *slots;                               // T, per position
-  int32_t pad;                               // LDS zero padding each side (elements)
+  void *slots;                               // T, per position and column (position-major)
 };
 
 // one launch over the stars of a.order, narrow (windows of 1-2 registers) or
-// wide (4-16); defined in star_fp32.hip / star_fp64.hip
-void launch_star_fp32(const StarArgs &a, bool wide, int maxn, const double *r, const CgScalars *sc, int check,
+// wide (4-16), for kc columns; defined in star_inst.hip (one object per
+// precision and column count)
+void launch_star_fp32(int kc, const StarArgs &a, bool wide, const double *r, const CgScalars *sc, int sel,
                       hipStream_t s);
-void launch_star_fp64(const StarArgs &a, bool wide, int maxn, const double *r, const CgScalars *sc, int check,
+void launch_star_fp64(int kc, const StarArgs &a, bool wide, const double *r, const CgScalars *sc, int sel,
                       hipStream_t s);
+
+// per precision and column count
+template <typename T, int KC>
+void launch_star_t(const StarArgs &a, bool wide, const double *r, const CgScalars *sc, int sel, hipStream_t s);
 
 }  // namespace spnet

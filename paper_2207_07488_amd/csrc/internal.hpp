@@ -107,5 +107,37 @@ void device_apply_B(Precond &pre, int k, const double *r, double *z, int device_
 void device_release(DeviceState *d);
 void device_profile(Precond &pre, int enable);
 void device_stats(Precond &pre, sn_kernel_stats *st);
+int64_t device_bytes(const Precond &pre);
+
+// ---------------------------------------------------------------------------
+// Engine: the device workspace of kc PCG columns (independent recurrences, one
+// right-hand side each) on one factored preconditioner. Columns are admitted
+// and retired between ticks; a tick queues iterations for every running
+// column on the engine's own stream and reads the column states back
+// asynchronously. sn_solve and the server both run on engines.
+// ---------------------------------------------------------------------------
+struct Engine;
+struct ColumnStatus {
+  int64_t iters;
+  double rr, f2, tol2, t2;
+  int32_t active, done, verify, replacements, fixed;
+};
+int engine_width_for(int k);                          // 1, 2, 4, 8 or 16 >= k
+int64_t engine_footprint(const Precond &pre, int kc);  // device bytes of an engine
+Engine *engine_create(Precond &pre, int kc);           // pre must be factored
+void engine_destroy(Engine *e);
+int engine_width(const Engine *e);
+// Start columns cols[0..k-1] on f (host, n x k row-major): u = 0, r = f, p = 0,
+// per-column tolerance and iteration limit. The engine must be idle.
+void engine_admit(Engine *e, int k, const int32_t *cols, const double *f, const double *rtol,
+                  const int64_t *max_iter);
+// Queue `iters` iterations and the true-residual checks of stopped columns;
+// the column states are read back when the tick completes.
+void engine_tick(Engine *e, int iters, bool use_graph);
+bool engine_query(Engine *e);  // the last tick has completed
+void engine_wait(Engine *e);
+void engine_status(const Engine *e, ColumnStatus *out);  // kc entries, as of the last completed tick
+// copy column c of u to host (stride ld) and free the column
+void engine_retire(Engine *e, int c, double *u, int64_t ld);
 
 }  // namespace spnet

@@ -1,29 +1,34 @@
-// Star sweep kernel (templated on the factor precision): see the comment
-// below. Included by star_fp32.hip and star_fp64.hip only.
+// Star sweep kernel, templated on the factor precision T and the number of
+// right-hand-side columns KC. Included by star_inst.hip only.
 #pragma once
 #include "device_common.hpp"
 
 namespace spnet {
 
 // ---------------------------------------------------------------------------
-// Star sweeps. One wavefront solves L_j L_j^T z = r[S_j] for one star.
+// Star sweeps: z_j = K_j^{-1} r[S_j] = L_j^{-T} L_j^{-1} r[S_j] for every star j
+// (the local solves behind the projections P_j, Sec. 4.1), for KC columns at
+// once. One wavefront per star; the factor streams are read once for all
+// columns.
 //
-// The vector of the star lives in LDS in factor order. A sweep walks the
-// steps of a stream: the forward stream holds the columns of L (step j: the
-// entries L_{j+1..j+w, j}), the backward stream the rows of L from the last
-// (step s = row i = n-1-s: the entries L_{i, i-1..i-w}); read in reverse
-// order, the vector makes the backward sweep the same recurrence as the
-// forward one. Stream values are divided by the step's pivot, so a step
-// subtracts m_t g_j from row j+1+t with the raw running value g_j, and the
-// pivot division is applied to 64 finished rows at once.
+// The star's vector lives in its slot segment (global memory, position-major:
+// the KC values of a position are adjacent) in factor order. The forward sweep
+// walks the columns of L (step j: entries L_{j+1..j+w, j}); the backward sweep
+// walks the rows of L from the last one (step s = row n-1-s: entries
+// L_{i, i-1..i-w}) on the vector read in reverse, which makes it the same
+// recurrence. Stream values are divided by the pivot of their step, so step j
+// subtracts m_t g_j from row j+1+t with the raw running value g_j; the pivot
+// division is applied when a row is written back.
 //
-// Window: before step j, lane l of register g[q] holds the running value of
-// row j + l + 64 q; lane 0 of g[0] is final. The window slides by one lane
-// (DPP wave shift left), the next row enters at lane 63 of the last register.
-// SG consecutive steps (4 in FP32, 2 in FP64) are packed lane-major, so one
-// 16-byte load per lane and register fetches them all; groups are loaded RG
-// groups ahead into a register ring, their offsets and widths arrive 64 at a
-// time.
+// Window: lane l holds the rows r = l (mod 64) in registers R[0..Q]: R[q] is
+// the row 64(b+q) + l during block b. At step j = 64b + s the finished row j
+// sits in lane s of R[0]; the rows still to be updated are, for lanes l > s,
+// R[0..Q-1], for lanes l <= s, R[1..Q]. The q-th of them needs stream entry
+// t = ((l - j - 1) mod 64) + 64 q, which the host stores so that lane l loads
+// it for SG consecutive steps with one 16-byte load. A per-lane select routes
+// the loaded multiplier q to R[q] or R[q+1]; no row moves between lanes. At
+// the end of a block R[0] holds 64 finished rows, the registers shift by one
+// and the next rows enter from memory (loaded one block ahead).
 // ---------------------------------------------------------------------------
 
 template <typename T>
@@ -38,23 +43,11 @@ struct Pack<float> {
   static __device__ __forceinline__ V masked(bool keep, const V &v) {
     return V{keep ? v.x : 0.f, keep ? v.y : 0.f, keep ? v.z : 0.f, keep ? v.w : 0.f};
   }
-  static __device__ __forceinline__ float first(float v) {
-    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
-  }
   template <int L>
   static __device__ __forceinline__ float lane(float v) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), L));
   }
-  // lanes 0..62 take lane+1, lane 63 takes `in`
-  static __device__ __forceinline__ float shl(float v, float in) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(in), __float_as_int(v), 0x130, 0xF, 0xF, false));
-  }
-  template <int L>
-  static __device__ __forceinline__ float put(float vec, float s) {
-    int r = __float_as_int(vec);
-    asm volatile("v_writelane_b32 %0, %1, %2" : "+v"(r) : "s"(__float_as_int(s)), "i"(L));
-    return __int_as_float(r);
-  }
+  static __device__ __forceinline__ float fnma(float m, float g, float x) { return __builtin_fmaf(-m, g, x); }
 };
 template <>
 struct Pack<double> {
@@ -69,24 +62,11 @@ struct Pack<double> {
   static __device__ __forceinline__ double mk(int l, int h) {
     return __longlong_as_double(((long long)(uint32_t)h << 32) | (long long)(uint32_t)l);
   }
-  static __device__ __forceinline__ double first(double v) {
-    return mk(__builtin_amdgcn_readfirstlane(lo(v)), __builtin_amdgcn_readfirstlane(hi(v)));
-  }
   template <int L>
   static __device__ __forceinline__ double lane(double v) {
     return mk(__builtin_amdgcn_readlane(lo(v), L), __builtin_amdgcn_readlane(hi(v), L));
   }
-  static __device__ __forceinline__ double shl(double v, double in) {
-    return mk(__builtin_amdgcn_update_dpp(lo(in), lo(v), 0x130, 0xF, 0xF, false),
-              __builtin_amdgcn_update_dpp(hi(in), hi(v), 0x130, 0xF, 0xF, false));
-  }
-  template <int L>
-  static __device__ __forceinline__ double put(double vec, double s) {
-    int l = lo(vec), h = hi(vec);
-    asm volatile("v_writelane_b32 %0, %1, %2" : "+v"(l) : "s"(lo(s)), "i"(L));
-    asm volatile("v_writelane_b32 %0, %1, %2" : "+v"(h) : "s"(hi(s)), "i"(L));
-    return mk(l, h);
-  }
+  static __device__ __forceinline__ double fnma(double m, double g, double x) { return __builtin_fma(-m, g, x); }
 };
 
 template <int S, int E>
@@ -103,166 +83,245 @@ struct StaticFor<E, E> {
   static __device__ __forceinline__ void run(F &&) {}
 };
 
-// One sweep over n steps. vec points at position 0 of the LDS vector (with
-// `pad` zero elements on both sides); REV reads it in reverse.
-//
-// Rows stay in their lanes: lane l, register q holds the row r = l (mod 64)
-// that is the (q+1)-th such row after the current step j. Step j reads the
-// finished row j from lane j mod 64 (a constant lane inside the unrolled
-// block), that lane moves its later rows down one register and takes the
-// next row from the incoming vector, and every lane subtracts its entry times
-// g_j. Lane l of register q therefore needs entry t = ((l - j - 1) mod 64) + 64 q
-// of step j; the host stores the SG steps of a group skewed so that lane l
-// fetches all of them with one 16-byte load from slot ((l - j0 - 1) mod 64) + 64 q,
-// j0 the group's first step.
+// N consecutive values of type T, moved with the widest aligned accesses
+template <typename T, int N>
+struct Row {
+  T v[N];
+  static constexpr int BYTES = N * (int)sizeof(T);
+  static constexpr int CH = BYTES >= 16 ? 16 : BYTES;  // chunk bytes
+  __device__ __forceinline__ void load(const T *p) {
+    if constexpr (CH == 16) {
+      using C = float4;
+#pragma unroll
+      for (int i = 0; i < BYTES / 16; ++i) {
+        const C c = reinterpret_cast<const C *>(p)[i];
+        __builtin_memcpy(reinterpret_cast<char *>(v) + 16 * i, &c, 16);
+      }
+    } else if constexpr (CH == 8) {
+      const float2 c = *reinterpret_cast<const float2 *>(p);
+      __builtin_memcpy(v, &c, 8);
+    } else {
+      v[0] = p[0];
+    }
+  }
+  __device__ __forceinline__ void store(T *p) const {
+    if constexpr (CH == 16) {
+      using C = float4;
+#pragma unroll
+      for (int i = 0; i < BYTES / 16; ++i) {
+        C c;
+        __builtin_memcpy(&c, reinterpret_cast<const char *>(v) + 16 * i, 16);
+        reinterpret_cast<C *>(p)[i] = c;
+      }
+    } else if constexpr (CH == 8) {
+      float2 c;
+      __builtin_memcpy(&c, v, 8);
+      *reinterpret_cast<float2 *>(p) = c;
+    } else {
+      p[0] = v[0];
+    }
+  }
+};
+
 // read-only data read through the constant address space (scalar loads)
 typedef const __attribute__((address_space(4))) uint32_t *const_u32_ptr;
 
-template <typename T, int Q, int RG, bool REV>
-__device__ __forceinline__ void sweep(T *vec, int n, const uint32_t *__restrict__ hdr_g, const T *__restrict__ inv,
-                                      const T *__restrict__ vals) {
+// One sweep over the n steps of a stream for CW columns c0..c0+CW-1 of the
+// star's slot segment `sl` (KC values per position). REV reads and writes the
+// vector in reverse position order.
+template <typename T, int KC, int CW, int Q, int RG, bool REV>
+__device__ __forceinline__ void sweep(T *sl, int c0, int n, const uint32_t *__restrict__ hdr_g,
+                                      const T *__restrict__ inv, const T *__restrict__ vals) {
   const const_u32_ptr hdr = (const_u32_ptr)hdr_g;
   using P = Pack<T>;
   using V = typename P::V;
   constexpr int SG = P::SG, GPB = 64 / SG;
   static_assert(GPB % RG == 0, "ring must divide the groups of a block");
-  static_assert(GPB + RG <= 2 * GPB, "ring lookahead spans at most the next block");
   const int lane = threadIdx.x & 63;
-  auto at = [&](int p) -> int { return REV ? (n - 1 - p) : p; };
-  T g[Q];
+  // row p of the sweep (clamped into the star; rows past the end read as 0)
+  auto load_row = [&](int p, T (&dst)[CW]) {
+    const int pc = p < n ? p : n - 1;
+    Row<T, CW> rw;
+    rw.load(sl + (size_t)(REV ? n - 1 - pc : pc) * KC + c0);
 #pragma unroll
-  for (int q = 0; q < Q; ++q) g[q] = vec[at(lane + 64 * q)];
-  T inc = vec[at(64 * Q + lane)];  // lane l: the row entering at step l of the block
+    for (int c = 0; c < CW; ++c) dst[c] = p < n ? rw.v[c] : T(0);
+  };
+  T R[Q + 1][CW];
+#pragma unroll
+  for (int q = 0; q <= Q; ++q) load_row(lane + 64 * q, R[q]);
+  T inc[CW];
+  load_row(64 * (Q + 1) + lane, inc);
   T hinv = lane < n ? inv[lane] : T(0);
   // group headers (uniform): width << 21 | offset in 16-byte units; hc: this
   // block, hn: the next (the header array is padded with zeros past the end)
   uint32_t hc[GPB], hn[GPB];
 #pragma unroll
-  for (int i = 0; i < GPB; ++i) {
-    hc[i] = hdr[i];
-    hn[i] = hdr[GPB + i];
-  }
-  auto fetch = [&](uint32_t h, int s0, V(&dst)[Q]) {
-    const T *base = vals + (size_t)(h & 0x1FFFFFu) * SG;
-    const int w = (int)(h >> 21);
-    const int ub = (lane - s0 - 1) & 63;
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      const V v = *reinterpret_cast<const V *>(base + (ub + 64 * q) * SG);
-      dst[q] = P::masked(ub + 64 * q < w, v);
-    }
-  };
+  for (int i = 0; i < GPB; ++i) hc[i] = hdr[i];
+  // ring of raw group loads; the width mask is applied when a group is used,
+  // so that no load has to complete before its group comes up
   V ring[RG][Q];
+  uint32_t ring_w[RG];
+  auto fetch = [&](uint32_t h, int s0, int rg) {
+    const T *base = vals + (size_t)(h & 0x1FFFFFu) * SG;
+    // lane offsets computed at each fetch rather than kept for every group
+    int l = lane;
+    asm volatile("; fetch lane %0" : "+v"(l));
+    const int ub = (l - s0 - 1) & 63;
+    ring_w[rg] = h >> 21;
 #pragma unroll
-  for (int rg = 0; rg < RG; ++rg) fetch(hc[rg], (rg * SG) & 63, ring[rg]);
+    for (int q = 0; q < Q; ++q) ring[rg][q] = *reinterpret_cast<const V *>(base + (ub + 64 * q) * SG);
+  };
+#pragma unroll
+  for (int rg = 0; rg < RG; ++rg) fetch(hc[rg], (rg * SG) & 63, rg);
   for (int jb = 0; jb < n; jb += 64) {
     const int gb = jb / SG;
-    uint32_t hnn[GPB];
 #pragma unroll
-    for (int i = 0; i < GPB; ++i) hnn[i] = hdr[gb + 2 * GPB + i];
+    for (int i = 0; i < GPB; ++i) hn[i] = hdr[gb + GPB + i];
     const T hinvN = jb + 64 + lane < n ? inv[jb + 64 + lane] : T(0);
-    const T incN = vec[at(jb + 64 + 64 * Q + lane)];
-    T ybuf = T(0);
+    T incN[CW];
+    load_row(jb + 64 * (Q + 2) + lane, incN);
+    // an opaque copy of the lane id per block keeps the per-step lane
+    // comparisons inside the loop
+    int lid = lane;
+    asm volatile("; lane id %0" : "+v"(lid));
     StaticFor<0, 64>::run([&](auto sc) {
       constexpr int s = decltype(sc)::value;
       constexpr int gi = s / SG, k = s % SG;
-      const T gj = P::template lane<s>(g[0]);
-      ybuf = P::template put<s>(ybuf, gj);
+      V(&cur)[Q] = ring[gi % RG];
+      if constexpr (k == 0) {
+        // the group comes up: zero the entries past its width
+        const int ub = (lane - s - 1) & 63;
 #pragma unroll
-      for (int q = 0; q + 1 < Q; ++q) g[q] = P::template put<s>(g[q], P::template lane<s>(g[q + 1]));
-      g[Q - 1] = P::template put<s>(g[Q - 1], P::template lane<s>(inc));
+        for (int q = 0; q < Q; ++q) cur[q] = P::masked((uint32_t)(ub + 64 * q) < ring_w[gi % RG], cur[q]);
+      }
+      const bool up = lid > s;  // lanes whose R[0] row is still open
+      T g[CW];
 #pragma unroll
-      for (int q = 0; q < Q; ++q) g[q] = g[q] - P::get(ring[gi % RG][q], k) * gj;
+      for (int c = 0; c < CW; ++c) g[c] = P::template lane<s>(R[0][c]);
+      T M[Q + 1];
+      M[0] = up ? P::get(cur[0], k) : T(0);
+#pragma unroll
+      for (int q = 1; q < Q; ++q) M[q] = up ? P::get(cur[q], k) : P::get(cur[q - 1], k);
+      M[Q] = up ? T(0) : P::get(cur[Q - 1], k);
+#pragma unroll
+      for (int q = 0; q <= Q; ++q)
+#pragma unroll
+        for (int c = 0; c < CW; ++c) {
+          R[q][c] = P::fnma(M[q], g[c], R[q][c]);
+          // keep every update in its step: otherwise updates of registers not
+          // read during the block sink to its end with their operands live
+          asm volatile("" : "+v"(R[q][c]));
+        }
       if constexpr (k == SG - 1) {
         // the group is consumed: fetch the group RG positions ahead
         constexpr int li = gi + RG;
-        fetch(li < GPB ? hc[li % GPB] : hn[li % GPB], (li * SG) & 63, ring[gi % RG]);
+        fetch(li < GPB ? hc[li % GPB] : hn[li % GPB], (li * SG) & 63, gi % RG);
       }
     });
-    if (jb + lane < n) vec[at(jb + lane)] = ybuf * hinv;
-    hinv = hinvN;
-    inc = incN;
+    if (jb + lane < n) {
+      Row<T, CW> rw;
 #pragma unroll
-    for (int i = 0; i < GPB; ++i) {
-      hc[i] = hn[i];
-      hn[i] = hnn[i];
+      for (int c = 0; c < CW; ++c) rw.v[c] = R[0][c] * hinv;
+      rw.store(sl + (size_t)(REV ? n - 1 - (jb + lane) : jb + lane) * KC + c0);
     }
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+      for (int c = 0; c < CW; ++c) R[q][c] = R[q + 1][c];
+#pragma unroll
+    for (int c = 0; c < CW; ++c) {
+      R[Q][c] = inc[c];
+      inc[c] = incN[c];
+    }
+    hinv = hinvN;
+#pragma unroll
+    for (int i = 0; i < GPB; ++i) hc[i] = hn[i];
   }
 }
 
-template <typename T, int Q>
-__device__ __forceinline__ void star_solve(const StarArgs &a, int st, int n, T *vec, int &sink) {
+// columns per pass: keeps the window (Q+1 registers per column) within the
+// register file next to the stream ring
+template <typename T, int Q, int KC>
+constexpr int pass_columns() {
+  constexpr int words = (int)sizeof(T) / 4;
+  constexpr int cap = (Q + 1) * words * 16 <= 96 ? 16
+                      : (Q + 1) * words * 8 <= 96 ? 8
+                      : (Q + 1) * words * 4 <= 96 ? 4
+                      : (Q + 1) * words * 2 <= 96 ? 2 : 1;
+  return KC < cap ? KC : cap;
+}
+
+template <typename T, int KC, int Q>
+__device__ __forceinline__ void star_solve(const StarArgs &a, int st, int n, T *sl) {
   constexpr int GPB = 64 / Pack<T>::SG;
   constexpr int RG0 = 16 / Q;
   constexpr int RG = RG0 >= GPB ? GPB : (RG0 >= 8 ? 8 : (RG0 >= 4 ? 4 : (RG0 >= 2 ? 2 : 1)));
+  constexpr int CW = pass_columns<T, Q, KC>();
   const int vb = a.st_vb[st], gbase = a.st_gb[st];
   const T *finv = static_cast<const T *>(a.f_inv) + vb, *binv = static_cast<const T *>(a.b_inv) + vb;
   const T *fval = static_cast<const T *>(a.f_val) + a.st_fb[st], *bval = static_cast<const T *>(a.b_val) + a.st_bb[st];
-  sweep<T, Q, RG, false>(vec, n, a.f_hdr + gbase, finv, fval);
-  __syncthreads();
-  sweep<T, Q, RG, true>(vec, n, a.b_hdr + gbase, binv, bval);
-  (void)sink;
+  for (int c0 = 0; c0 < KC; c0 += CW) {
+    sweep<T, KC, CW, Q, RG, false>(sl, c0, n, a.f_hdr + gbase, finv, fval);
+    __syncthreads();
+    sweep<T, KC, CW, Q, RG, true>(sl, c0, n, a.b_hdr + gbase, binv, bval);
+    __syncthreads();
+  }
 }
 
 // WIDE = false: stars with windows of 1-2 registers, true: 4-16 registers (kept
 // in separate kernels so that each gets the registers its variants need)
-template <typename T, bool WIDE>
-__global__ __launch_bounds__(64) void k_star(StarArgs a, const double *__restrict__ r, const CgScalars *sc, int check) {
-  if (check && sc->done) return;
-  extern __shared__ __align__(16) unsigned char lds_raw[];
-  T *lds = reinterpret_cast<T *>(lds_raw);
+template <typename T, bool WIDE, int KC>
+__global__ __launch_bounds__(64) void k_star(StarArgs a, const double *__restrict__ r, const CgScalars *sc, int sel) {
+  if (sel != SEL_ALL) {
+    bool any = false;
+#pragma unroll
+    for (int c = 0; c < KC; ++c) any |= column_selected(sc[c], sel, 0u, c);
+    if (!any) return;
+  }
   const int wv = blockIdx.x;
   if (wv >= a.nstars) return;
   const int st = a.order[wv];
   const int n = a.st_n[st], vb = a.st_vb[st], Q = a.st_q[st];
   const int lane = threadIdx.x;
-  T *vec = lds + a.pad;
-  for (int i = lane; i < a.pad; i += 64) {
-    lds[i] = T(0);
-    vec[n + i] = T(0);
-  }
-  // gather r in factor order, 16 rows per lane in flight at a time
+  T *sl = static_cast<T *>(a.slots) + (size_t)vb * KC;
+  // gather r (KC adjacent values per dof) in factor order, U rows per lane in
+  // flight; clamped unconditional loads keep them all in flight
+  constexpr int U = KC <= 2 ? 16 : 32 / KC;
   const int32_t *dofs = a.pos_dof + vb;
-  for (int p0 = 0; p0 < n; p0 += 64 * 16) {
-    // unconditional loads at clamped positions keep all 16 in flight
-    int idx[16];
+  for (int p0 = 0; p0 < n; p0 += 64 * U) {
+    int idx[U];
 #pragma unroll
-    for (int u = 0; u < 16; ++u) idx[u] = dofs[min(p0 + 64 * u + lane, n - 1)];
-    double val[16];
+    for (int u = 0; u < U; ++u) idx[u] = dofs[min(p0 + 64 * u + lane, n - 1)];
+    Row<double, KC> val[U];
 #pragma unroll
-    for (int u = 0; u < 16; ++u) val[u] = r[idx[u]];
+    for (int u = 0; u < U; ++u) val[u].load(r + (size_t)idx[u] * KC);
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
+    for (int u = 0; u < U; ++u) {
       const int p = p0 + 64 * u + lane;
-      if (p < n) vec[p] = (T)val[u];
+      if (p < n) {
+        Row<T, KC> o;
+#pragma unroll
+        for (int c = 0; c < KC; ++c) o.v[c] = (T)val[u].v[c];
+        o.store(sl + (size_t)p * KC);
+      }
     }
   }
   __syncthreads();
-  int sink = 0;
   if constexpr (!WIDE) {
-    if (Q == 1) star_solve<T, 1>(a, st, n, vec, sink);
-    else star_solve<T, 2>(a, st, n, vec, sink);
+    if (Q == 1) star_solve<T, KC, 1>(a, st, n, sl);
+    else star_solve<T, KC, 2>(a, st, n, sl);
   } else {
-    if (Q == 4) star_solve<T, 4>(a, st, n, vec, sink);
-    else if (Q == 8) star_solve<T, 8>(a, st, n, vec, sink);
-    else star_solve<T, 16>(a, st, n, vec, sink);
+    if (Q == 4) star_solve<T, KC, 4>(a, st, n, sl);
+    else if (Q == 8) star_solve<T, KC, 8>(a, st, n, sl);
+    else star_solve<T, KC, 16>(a, st, n, sl);
   }
-  __syncthreads();
-  T *out = static_cast<T *>(a.slots) + vb;
-  for (int p = lane; p < n; p += 64) out[p] = vec[p];
 }
 
-// one launch over the stars of a.order (all narrow or all wide)
-template <typename T>
-void launch_star_t(const StarArgs &a, bool wide, int maxn, const double *r, const CgScalars *sc, int check,
-                   hipStream_t s) {
+template <typename T, int KC>
+void launch_star_t(const StarArgs &a, bool wide, const double *r, const CgScalars *sc, int sel, hipStream_t s) {
   if (a.nstars <= 0) return;
-  const size_t lds = (size_t)(maxn + 2 * a.pad) * sizeof(T);
-  const void *fn = wide ? (const void *)k_star<T, true> : (const void *)k_star<T, false>;
-  if (lds > 65536) HIPCHK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  if (wide) hipLaunchKernelGGL((k_star<T, true>), dim3(a.nstars), dim3(64), lds, s, a, r, sc, check);
-  else hipLaunchKernelGGL((k_star<T, false>), dim3(a.nstars), dim3(64), lds, s, a, r, sc, check);
+  if (wide) hipLaunchKernelGGL((k_star<T, true, KC>), dim3(a.nstars), dim3(64), 0, s, a, r, sc, sel);
+  else hipLaunchKernelGGL((k_star<T, false, KC>), dim3(a.nstars), dim3(64), 0, s, a, r, sc, sel);
 }
-
 
 }  // namespace spnet

@@ -54,7 +54,8 @@ class KernelStats(C.Structure):
 
 
 class ServerOpts(C.Structure):
-    _fields_ = [("hbm_budget", C.c_int64), ("max_active", C.c_int32), ("iters_per_tick", C.c_int32)]
+    _fields_ = [("hbm_budget", C.c_int64), ("max_columns", C.c_int32), ("iters_per_tick", C.c_int32),
+                ("precision", C.c_int32), ("use_graph", C.c_int32)]
 
 
 class SpnetError(RuntimeError):
@@ -92,10 +93,12 @@ SIGNATURES = {
     "sn_precond_kernel_stats": (C.c_int, [_P, C.POINTER(KernelStats)]),
     "sn_apply_K": (C.c_int, [_P, C.c_int, _P, _P, C.c_int, _P]),
     "sn_apply_B": (C.c_int, [_P, C.c_int, _P, _P, C.c_int, _P]),
+    "sn_server_opts_default": (None, [C.POINTER(ServerOpts)]),
     "sn_server_create": (C.c_int, [C.POINTER(ServerOpts), C.POINTER(_P)]),
     "sn_server_submit": (C.c_int, [_P, _P, C.c_int, _P, _dbl, _i64, C.POINTER(C.c_uint64)]),
     "sn_server_step": (C.c_int, [_P, C.POINTER(_i32), C.POINTER(_i32)]),
     "sn_server_poll": (C.c_int, [_P, C.c_uint64, _P, C.POINTER(SolveInfo)]),
+    "sn_server_usage": (C.c_int, [_P, C.POINTER(_i64), C.POINTER(_i32)]),
     "sn_server_destroy": (None, [_P]),
 }
 
@@ -307,6 +310,60 @@ class Precond:
         if getattr(self, "h", None) and _lib is not None:
             _lib.sn_precond_destroy(self.h)
             self.h = None
+
+
+class Server:
+    """Continuous-batching solve server (sn_server_*): requests on factored or
+    unfactored preconditioners iterate together, admitted by device memory."""
+
+    def __init__(self, hbm_budget=None, max_columns=8, iters_per_tick=4, precision=FP32_STARS, use_graph=True):
+        o = ServerOpts()
+        lib().sn_server_opts_default(C.byref(o))
+        if hbm_budget is not None:
+            o.hbm_budget = int(hbm_budget)
+        o.max_columns, o.iters_per_tick, o.precision, o.use_graph = max_columns, iters_per_tick, precision, int(use_graph)
+        h = _P()
+        _check(lib().sn_server_create(C.byref(o), C.byref(h)))
+        self.h = h
+        self._keep = {}  # ticket -> (precond, k)
+
+    def submit(self, pre: "Precond", f, rtol=1e-8, max_iter=1000):
+        fa = _np(f, np.float64)
+        k = 1 if fa.ndim == 1 else fa.shape[1]
+        t = C.c_uint64()
+        _check(lib().sn_server_submit(self.h, pre.h, k, _ptr(fa), rtol, max_iter, C.byref(t)))
+        self._keep[t.value] = (pre, k, fa.shape)
+        return t.value
+
+    def step(self):
+        a, q = _i32(), _i32()
+        _check(lib().sn_server_step(self.h, C.byref(a), C.byref(q)))
+        return a.value, q.value
+
+    def poll(self, ticket):
+        """(u, [info]) when the request is done, None while it is pending."""
+        pre, k, shape = self._keep[ticket]
+        u = np.zeros(shape)
+        infos = (SolveInfo * k)()
+        rc = lib().sn_server_poll(self.h, ticket, _ptr(u), infos)
+        if rc == SN_EBUSY:
+            return None
+        del self._keep[ticket]
+        _check(rc)
+        return u, [i.asdict() for i in infos]
+
+    def usage(self):
+        b, n = _i64(), _i32()
+        _check(lib().sn_server_usage(self.h, C.byref(b), C.byref(n)))
+        return b.value, n.value
+
+    def close(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.sn_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
 
 
 def build_fiber_problem(preset: dict, precision=FP64, policy=STARS_ALL, nH=None, model=None):

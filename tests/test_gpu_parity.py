@@ -175,3 +175,38 @@ def test_graph_replay_matches_eager(S, orc):
         assert i_g[0]["iters"] == i_e[0]["iters"]
         assert np.array_equal(u_g, u_e), rep
         gpre.apply_B(f)  # eager work between replays
+
+
+@pytest.mark.parametrize("precision", ["FP64", "FP32_STARS"])
+def test_batch_columns_match_single_solves_bitwise(S, orc, precision):
+    """A column's iterates do not depend on the batch: k = 5 (a batch of 8 with
+    3 idle columns) and k = 16 give, column by column, the k = 1 result bit for
+    bit."""
+    opre, gpre = _pair(S, orc, "fiber2d_2k", getattr(S, precision))
+    F = W.rhs(opre.sys.n, 16, seed=11)
+    U16, i16 = gpre.solve(F, rtol=1e-8)
+    U5, i5 = gpre.solve(F[:, :5], rtol=1e-8)
+    for c in range(16):
+        u1, i1 = gpre.solve(F[:, c], rtol=1e-8)
+        assert i1[0]["iters"] == i16[c]["iters"]
+        assert np.array_equal(u1, U16[:, c]), c
+        if c < 5:
+            assert np.array_equal(u1, U5[:, c]), c
+
+
+def test_batch_fixed_iterations_vs_oracle(S, orc):
+    opre, gpre = _pair(S, orc, "fiber3d_6k", S.FP64)
+    F = W.rhs(opre.sys.n, 4, seed=12)
+    U, infos = gpre.solve(F, fixed_iters=12)
+    for c in range(4):
+        u_o, it_o, _ = opre.pcg(F[:, c], fixed_iters=12)
+        assert infos[c]["iters"] == 12
+        assert _rel(U[:, c], u_o) <= _tol(orc, "fiber3d_6k", opre)
+
+
+def test_batch_apply_B_columns(S, orc):
+    opre, gpre = _pair(S, orc, "fiber2d_300", S.FP64)
+    R = W.rhs(opre.sys.n, 3, seed=13)
+    Z = gpre.apply_B(R)
+    for c in range(3):
+        assert _rel(Z[:, c], opre.apply_B(R[:, c])) <= 1e-10

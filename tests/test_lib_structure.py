@@ -1,0 +1,186 @@
+"""CPU checks of libspnet: the exported surface, the integer structure against
+the oracle (bit-exact), and the error paths of the C ABI.
+
+Runs without a GPU: network generation, assembly and the coarse/star spaces
+are host code; only factorisation and solves need the device (and refuse
+loudly when there is none).
+"""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2207_07488_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def S():
+    from paper_2207_07488_amd import spnet
+    try:
+        spnet.lib()
+    except (ImportError, OSError) as e:
+        pytest.skip(f"libspnet not built: {e}")
+    return spnet
+
+
+def _header_functions():
+    txt = open(os.path.join(ROOT, "include", "spnet.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    names = set(re.findall(r"\b(sn_[a-z0-9_]+)\s*\(", txt))
+    return sorted(names)
+
+
+def test_every_declared_function_is_exported(S):
+    names = _header_functions()
+    assert len(names) >= 25
+    L = C.CDLL(S.LIB_PATH)
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+    # and the binding knows every one of them
+    assert not [n for n in names if n not in S.SIGNATURES]
+
+
+def test_version_string(S):
+    assert b"gfx950" in S.lib().sn_version()
+
+
+# (dim, n_segments, length, contact_eps, dir_lo, dir_hi, nH, model, seed)
+STRUCT_CASES = {
+    "2d_300": (2, 300, 0.2, 0.0, 1, 1, 4, 0, 1),
+    "2d_3k": (2, 3000, 0.06, 0.0, 1, 1, 8, 0, 5),
+    "3d_6k": (3, 6000, 0.12, 0.012, 4, 4, 4, 0, 3),
+    "truss_1500": (3, 1500, 0.25, 0.025, 4, 0, 4, 1, 4),
+}
+
+
+@pytest.mark.parametrize("name", list(STRUCT_CASES))
+@pytest.mark.parametrize("policy", [0, 1])
+def test_structure_bit_exact_vs_oracle(S, orc, name, policy):
+    dim, nseg, l, eps, lo, hi, nH, model, seed = STRUCT_CASES[name]
+    seg = W.fiber_segments(dim, nseg, l, seed=seed)
+    kw = dict(contact_eps=eps, merge_tol=W.merge_tol(l), dir_lo=lo, dir_hi=hi)
+    on, gn = orc.Network.from_segments(dim, seg, **kw), S.Network.from_segments(dim, seg, **kw)
+    # node coordinates, edges and the Dirichlet set: bit-exact
+    for a, b in zip(on.arrays(), gn.arrays()):
+        assert a.shape == b.shape and np.array_equal(a, b)
+    osys, gsys = orc.System(on, model), S.System(gn, model)
+    (orp, oci, ov), (grp, gci, gv) = osys.csr(), gsys.csr()
+    assert np.array_equal(orp, grp) and np.array_equal(oci, gci)
+    # values: the same sums, possibly in another order
+    assert np.abs(ov - gv).max() <= 1e-13 * np.abs(ov).max()
+    assert np.array_equal(osys.free_nodes(), gsys.free_nodes())
+    opre = orc.Precond(osys, nH, policy, lo, hi, factor=False)
+    gpre = S.Precond(gsys, nH, policy, lo, hi)
+    assert opre.m0 == gpre.m0
+    for a, b in zip(opre.stars(), gpre.stars()):
+        assert np.array_equal(a, b)
+    assert np.array_equal(opre.coarse_vertices(), gpre.coarse_vertices())
+
+
+def _status(S, fn, *args):
+    rc = fn(*args)
+    return rc, S.lib().sn_last_error().decode()
+
+
+def test_error_paths_network(S):
+    L = S.lib()
+    h = C.c_void_p()
+    seg = np.zeros((1, 4))
+    rc, msg = _status(S, L.sn_network_from_segments, 4, 1, seg.ctypes.data_as(C.c_void_p), 0.0, 1e-5, 1, 1, 1e-3,
+                      C.byref(h))
+    assert rc == S.SN_EINVAL and "dim" in msg
+    rc, msg = _status(S, L.sn_network_from_segments, 2, 1, seg.ctypes.data_as(C.c_void_p), 0.0, 0.0, 1, 1, 1e-3,
+                      C.byref(h))
+    assert rc == S.SN_EINVAL and "merge_tol" in msg
+    seg3 = np.zeros((1, 6))
+    rc, msg = _status(S, L.sn_network_from_segments, 3, 1, seg3.ctypes.data_as(C.c_void_p), 0.0, 1e-5, 4, 4, 1e-3,
+                      C.byref(h))
+    assert rc == S.SN_EINVAL and "contact_eps" in msg
+    x = np.array([[0.0, 0.0], [1.0, 0.0]])
+    e = np.array([[0, 2]], dtype=np.int32)
+    d = np.array([1, 0], dtype=np.uint8)
+    rc, msg = _status(S, L.sn_network_from_arrays, 2, 2, x.ctypes.data_as(C.c_void_p), 1,
+                      e.ctypes.data_as(C.c_void_p), d.ctypes.data_as(C.c_void_p), C.byref(h))
+    assert rc == S.SN_EINVAL and "out of range" in msg
+    e = np.array([[1, 1]], dtype=np.int32)
+    rc, msg = _status(S, L.sn_network_from_arrays, 2, 2, x.ctypes.data_as(C.c_void_p), 1,
+                      e.ctypes.data_as(C.c_void_p), d.ctypes.data_as(C.c_void_p), C.byref(h))
+    assert rc == S.SN_EINVAL and "self loop" in msg
+    x[1, 0] = np.nan
+    e = np.array([[0, 1]], dtype=np.int32)
+    rc, msg = _status(S, L.sn_network_from_arrays, 2, 2, x.ctypes.data_as(C.c_void_p), 1,
+                      e.ctypes.data_as(C.c_void_p), d.ctypes.data_as(C.c_void_p), C.byref(h))
+    assert rc == S.SN_EINVAL and "non-finite" in msg
+
+
+def test_error_paths_system_and_spaces(S):
+    x, e = W.grid_network(5)
+    nodir = np.zeros(len(x), dtype=np.uint8)
+    net = S.Network.from_arrays(x, e, nodir)
+    with pytest.raises(S.SpnetError) as ei:
+        S.System(net)
+    assert ei.value.code == S.SN_ESINGULAR
+    d = W.boundary_flags(x, 1, 1, 1e-3)
+    net = S.Network.from_arrays(x, e, d)
+    with pytest.raises(S.SpnetError) as ei:
+        S.System(net, model=S.MODEL_TRUSS)  # the truss model is three-dimensional
+    assert ei.value.code == S.SN_EINVAL
+    with pytest.raises(S.SpnetError) as ei:
+        S.System(net, model=7)
+    assert ei.value.code == S.SN_EINVAL
+    sysm = S.System(net)
+    for bad in (0, 5000):
+        with pytest.raises(S.SpnetError) as ei:
+            S.Precond(sysm, bad)
+        assert ei.value.code == S.SN_EINVAL
+    with pytest.raises(S.SpnetError) as ei:
+        S.Precond(sysm, 2, policy=3)
+    assert ei.value.code == S.SN_EINVAL
+
+
+def test_solve_requires_factor_and_valid_arguments(S):
+    x, e = W.grid_network(5)
+    net = S.Network.from_arrays(x, e, W.boundary_flags(x, 1, 1, 1e-3))
+    pre = S.Precond(S.System(net), 2)
+    L = S.lib()
+    f = np.ones(pre.sys.n)
+    u = np.zeros(pre.sys.n)
+    info = (S.SolveInfo * 1)()
+    rc, msg = _status(S, L.sn_solve, pre.h, 1, f.ctypes.data_as(C.c_void_p), u.ctypes.data_as(C.c_void_p), None, info)
+    assert rc == S.SN_EINVAL and "not factored" in msg
+    rc, msg = _status(S, L.sn_solve, pre.h, 0, f.ctypes.data_as(C.c_void_p), u.ctypes.data_as(C.c_void_p), None, info)
+    assert rc == S.SN_EINVAL
+    rc, msg = _status(S, L.sn_precond_factor, pre.h, 9)
+    assert rc == S.SN_EINVAL and "precision" in msg
+    rc, msg = _status(S, L.sn_apply_B, pre.h, 1, f.ctypes.data_as(C.c_void_p), u.ctypes.data_as(C.c_void_p), 0, None)
+    assert rc == S.SN_EINVAL and "not factored" in msg
+
+
+def test_factor_refuses_without_a_device(S):
+    """The product path has no CPU fallback: without a GPU, factoring fails with
+    SN_EDEVICE after the host factorisation."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    x, e = W.grid_network(5)
+    pre = S.Precond(S.System(S.Network.from_arrays(x, e, W.boundary_flags(x, 1, 1, 1e-3))), 2)
+    with pytest.raises(S.SpnetError) as ei:
+        pre.factor(S.FP64)
+    assert ei.value.code == S.SN_EDEVICE
+
+
+def test_non_spd_star_is_reported(S):
+    """A star holding a whole component without a Dirichlet node has a singular
+    local matrix: factorisation reports SN_ENOTSPD before any device work."""
+    # two disjoint edges; only the first touches the Dirichlet side
+    x = np.array([[0.0, 0.5], [0.3, 0.5], [0.6, 0.2], [0.9, 0.2]])
+    e = np.array([[0, 1], [2, 3]], dtype=np.int32)
+    d = np.array([1, 0, 0, 0], dtype=np.uint8)
+    pre = S.Precond(S.System(S.Network.from_arrays(x, e, d)), 1)
+    with pytest.raises(S.SpnetError) as ei:
+        pre.factor(S.FP64)
+    assert ei.value.code in (S.SN_ENOTSPD, S.SN_EDEVICE)
