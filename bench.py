@@ -20,6 +20,18 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+KERNEL_SOURCES = ("paper_2207_07488_amd/csrc/star_kernel.hpp", "paper_2207_07488_amd/csrc/star_inst.hip",
+                  "paper_2207_07488_amd/csrc/device_common.hpp")
+
+
+def kernel_source_hash():
+    """Hash of the star sweep sources: counter data taken on other sources is stale."""
+    import hashlib
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def percentile(xs, q):
@@ -71,6 +83,69 @@ def copy_probe(mib):
     print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8, "launches": 5}), flush=True)
 
 
+def serving_leg(n_requests, rate, pool_size=8, seed=5):
+    """Poisson arrivals of solve requests (1-8 right-hand sides, uniform[0,1]
+    loads) on a pool of 2D and 3D fiber networks of 2k-500k nodes, served by
+    one continuous-batching server (FP32 stars). The pool's factors are made
+    resident by one untimed request per network first. Latency runs from the
+    scheduled arrival to the poll that returns the result."""
+    import numpy as np
+    from paper_2207_07488_amd import spnet as S
+    from paper_2207_07488_amd import workloads as W
+    pool = W.serving_pool(pool_size, seed)
+    pres = []
+    for p in pool:
+        seg = W.fiber_segments(p["dim"], p["n_segments"], p["length"], p["seed"])
+        net = S.Network.from_segments(p["dim"], seg, contact_eps=p.get("contact_eps", 0.0),
+                                      merge_tol=W.merge_tol(p["length"]), dir_lo=p["dir_lo"], dir_hi=p["dir_hi"],
+                                      band=W.BAND)
+        pres.append(S.Precond(S.System(net), p["nH"], S.STARS_ALL, p["dir_lo"], p["dir_hi"]))
+    srv = S.Server(max_columns=8, iters_per_tick=4, precision=S.FP32_STARS)
+    # resident factors, engines and captured graphs (untimed)
+    warm = [srv.submit(pre, W.rhs(pre.sys.n, 1, seed=1)) for pre in pres]
+    while warm:
+        srv.step()
+        warm = [t for t in warm if srv.poll(t) is None]
+    arrivals = W.poisson_arrivals(n_requests, rate, seed + 1)
+    pick = W.uniform01(seed + 2, 0, 2 * n_requests)
+    reqs = []
+    for i in range(n_requests):
+        j = min(int(pick[2 * i] * len(pres)), len(pres) - 1)
+        k = 1 + min(int(pick[2 * i + 1] * 8), 7)
+        reqs.append((j, k, W.rhs(pres[j].sys.n, k, seed=100 + i)))
+    pending, lat, iters, worst = {}, [], [], 0.0
+    nxt, solved = 0, 0
+    t0 = time.perf_counter()
+    while nxt < n_requests or pending:
+        now = time.perf_counter() - t0
+        while nxt < n_requests and arrivals[nxt] <= now:
+            j, k, F = reqs[nxt]
+            pending[srv.submit(pres[j], F)] = (nxt, k)
+            nxt += 1
+        srv.step()
+        for t in list(pending):
+            r = srv.poll(t)
+            if r is None:
+                continue
+            i, k = pending.pop(t)
+            lat.append((time.perf_counter() - t0 - arrivals[i]) * 1e3)
+            iters.extend(x["iters"] for x in r[1])
+            worst = max(worst, max(x["res_true"] for x in r[1]))
+            solved += k
+        if nxt < n_requests and not pending:
+            time.sleep(max(0.0, arrivals[nxt] - (time.perf_counter() - t0)))
+    makespan = time.perf_counter() - t0
+    used, neng = srv.usage()
+    srv.close()
+    return {"requests": n_requests, "arrival_rate_per_s": rate, "rhs_solved": solved,
+            "solves_per_s": round(solved / makespan, 2), "makespan_s": round(makespan, 3),
+            "latency_ms": {"p50": round(percentile(lat, 0.5), 3), "p99": round(percentile(lat, 0.99), 3)},
+            "median_iterations": int(np.median(iters)), "max_res_true": worst,
+            "networks": [{"dim": p["dim"], "dofs": pre.sys.n, "nH": p["nH"], "stars": pre.nstars} for p, pre in
+                         zip(pool, pres)],
+            "engines": neng, "device_bytes": used, "engine_width": 8, "iters_per_tick": 4}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -79,6 +154,9 @@ def main():
     ap.add_argument("--nH", type=int, default=32)
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=64)
+    ap.add_argument("--serving-rate", type=float, default=100.0, help="Poisson arrival rate (requests/s)")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic_star_sweep_fiber2d_20k.json"),
                     help="HBM traffic per sweep launch from rocprofv3 counters (JSON), if present")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -116,6 +194,17 @@ def main():
     rg = timed_solves(mixed, f, args.steps, args.warmup, args.rtol, profile=False, use_graph=True)
     rpg = timed_solves(plain, f, args.steps, args.warmup, args.rtol, profile=False, use_graph=True)
 
+    multi = {}
+    for k in (8, 16):
+        F = torch.from_numpy(W.rhs(sysm.n, k, seed=17)).cuda()
+        for name, pre in (("mixed", mixed), ("plain", plain)):
+            r = timed_solves(pre, F, max(2, args.steps // 4), 1, args.rtol, use_graph=True)
+            n_solves = k * max(2, args.steps // 4)
+            multi[f"{name}_k{k}"] = {"solves_per_s": round(n_solves / r["total_s"], 2),
+                                     "ms_per_batch": round(r["total_s"] / max(2, args.steps // 4) * 1e3, 3),
+                                     "max_iterations": int(max(i["iters"] for i in r["info"])),
+                                     "max_res_true": max(i["res_true"] for i in r["info"])}
+
     value = args.steps / rm["total_s"]
     plain_value = args.steps / rp["total_s"]
     fim, fip = mixed.factor_info(), plain.factor_info()
@@ -133,7 +222,7 @@ def main():
         try:
             with open(args.traffic) as fh:
                 t = json.load(fh)
-            if t.get("sweep_bytes") == fim["sweep_bytes"]:
+            if t.get("sweep_bytes") == fim["sweep_bytes"] and t.get("kernel_src") == kernel_source_hash():
                 traffic = t.get("hbm_bytes_per_launch")
         except Exception:
             traffic = None
@@ -174,11 +263,15 @@ def main():
                        "roofline_star_sweeps": roof_p},
         "mixed_over_plain": round(value / plain_value, 3),
         "graph_replay": {"mixed": round(args.steps / rg["total_s"], 3), "plain": round(args.steps / rpg["total_s"], 3)},
+        "multi_rhs": multi,
         "roofline": roof_m,
         "setup_s": round(t_setup, 2),
         "factor_info": {"mixed": {k: fim[k] for k in ("star_factor_nnz", "sweep_bytes", "max_band", "max_star_dofs",
                                                      "factor_seconds")}},
     }
+
+    if not args.no_serving:
+        out["serving"] = serving_leg(args.serving_requests, args.serving_rate)
 
     if not args.no_cpu_baseline:
         sys.path.insert(0, os.path.join(ROOT, "oracle"))

@@ -558,7 +558,7 @@ struct DeviceState {
   int32_t n_narrow = 0, n_wide = 0;
   int64_t slot_count = 0;
   DBuf<int32_t> order_narrow, order_wide, st_n, st_vb, st_q, st_gb, pos_dof, slot_of;
-  DBuf<uint32_t> f_hdr, b_hdr;
+  DBuf<uint16_t> f_hdr, b_hdr;
   DBuf<int64_t> st_fb, st_bb;
   DBuf<float> f_inv32, b_inv32, f_val32, b_val32;
   DBuf<double> f_inv64, b_inv64, f_val64, b_val64;
@@ -642,10 +642,12 @@ inline unsigned grid_for(int64_t n) { return std::max(1u, std::min<unsigned>(kMa
 // and window register q read slot u = ((l - j0 - 1) mod 64) + 64 q of the group
 // with first step j0 (mod 64); slot u holds, for k = 0..SG-1, entry
 // t = 64 q + ((u mod 64 - k) mod 64) of step j0 + k (zero past the step's width).
-// The group stores slots 0..W-1, W one past the last non-zero slot.
+// The group stores slots 0..W-1, W one past the last non-zero slot, right after
+// the previous group; `widths` gets W (16-bit) per group, so a group's offset is
+// the sum of the widths before it.
 template <typename T>
 void pack_stream(const std::vector<int32_t> &width, const std::vector<double> &vals, const std::vector<double> &inv,
-                 int SG, int Q, std::vector<T> &out, std::vector<uint32_t> &hdr, int64_t base) {
+                 int SG, int Q, std::vector<T> &out, std::vector<uint16_t> &widths) {
   const int n = (int)width.size();
   std::vector<int64_t> start((size_t)n + 1, 0);
   for (int j = 0; j < n; ++j) start[j + 1] = start[j] + width[j];
@@ -662,17 +664,16 @@ void pack_stream(const std::vector<int32_t> &width, const std::vector<double> &v
     for (int slot = 0; slot < 64 * Q; ++slot)
       for (int k = 0; k < SG; ++k)
         if (entry(j0, slot, k) != 0.0) W = slot + 1;
-    const int64_t off = ((int64_t)out.size() - base) / SG;  // 16-byte units (groups are whole slots)
-    if (off >= (1 << 21) || W >= (1 << 11)) fail(SN_EINVAL, "star stream too large for the packed group headers");
-    hdr.push_back((uint32_t)W << 21 | (uint32_t)off);
+    widths.push_back((uint16_t)W);
     for (int slot = 0; slot < W; ++slot)
       for (int k = 0; k < SG; ++k) out.push_back((T)entry(j0, slot, k));
   }
-  // zero headers past the end: the sweep reads whole blocks of headers ahead
+  // zero widths past the end: the sweep reads whole blocks of widths up to
+  // four blocks ahead
   const int GPB = 64 / SG;
   const size_t ng = (size_t)(n + SG - 1) / SG;
-  const size_t padded = (ng + GPB - 1) / GPB * GPB + 3 * GPB;
-  hdr.resize(hdr.size() + (padded - ng), 0u);
+  const size_t padded = (ng + GPB - 1) / GPB * GPB + 4 * GPB;
+  widths.resize(widths.size() + (padded - ng), 0);
 }
 
 template <typename T>
@@ -680,7 +681,7 @@ void upload_stars(DeviceState &d, const Precond &pre, const HostFactors &hf, sn_
   constexpr int SG = 16 / (int)sizeof(T);
   const int64_t ns = (int64_t)hf.stars.size();
   std::vector<int32_t> st_n(ns), st_vb(ns), st_q(ns), st_gb(ns), pos_dof;
-  std::vector<uint32_t> f_hdr, b_hdr;
+  std::vector<uint16_t> f_hdr, b_hdr;
   std::vector<int64_t> st_fb(ns), st_bb(ns);
   std::vector<T> f_val, b_val, f_inv, b_inv;
   int64_t tot = 0, real_vals = 0;
@@ -700,9 +701,9 @@ void upload_stars(DeviceState &d, const Precond &pre, const HostFactors &hf, sn_
     std::vector<double> finv(F.invdiag), binv((size_t)F.n);
     for (int p = 0; p < F.n; ++p) binv[p] = F.invdiag[F.n - 1 - p];
     st_fb[s] = (int64_t)f_val.size();
-    pack_stream<T>(F.width_fwd, F.colvals, finv, SG, q, f_val, f_hdr, st_fb[s]);
+    pack_stream<T>(F.width_fwd, F.colvals, finv, SG, q, f_val, f_hdr);
     st_bb[s] = (int64_t)b_val.size();
-    pack_stream<T>(F.width_bwd, F.rowvals, binv, SG, q, b_val, b_hdr, st_bb[s]);
+    pack_stream<T>(F.width_bwd, F.rowvals, binv, SG, q, b_val, b_hdr);
     if (f_hdr.size() != b_hdr.size()) fail(SN_EINVAL, "internal: header arrays out of step");
     const int32_t *dofs = &pre.star_dofs[pre.star_ptr[s]];
     for (int p = 0; p < F.n; ++p) {

@@ -67,7 +67,7 @@ struct StarArgs {
   const int64_t *st_fb;    // forward stream value base
   const int64_t *st_bb;    // backward stream value base
   const int32_t *pos_dof;  // global dof of each position (factor order)
-  const uint32_t *f_hdr, *b_hdr;             // per group: width << 21 | offset (16-byte units)
+  const uint16_t *f_hdr, *b_hdr;             // per group: width in 16-byte slots (groups are contiguous)
   const void *f_inv, *b_inv;                 // 1/pivot per step (T)
   const void *f_val, *b_val;                 // packed stream values (T)
   void *slots;                               // T, per position and column (position-major)

@@ -130,13 +130,11 @@ typedef const __attribute__((address_space(4))) uint32_t *const_u32_ptr;
 // star's slot segment `sl` (KC values per position). REV reads and writes the
 // vector in reverse position order.
 template <typename T, int KC, int CW, int Q, int RG, bool REV>
-__device__ __forceinline__ void sweep(T *sl, int c0, int n, const uint32_t *__restrict__ hdr_g,
+__device__ __forceinline__ void sweep(T *sl, int c0, int n, const uint16_t *__restrict__ hdr_g,
                                       const T *__restrict__ inv, const T *__restrict__ vals) {
-  const const_u32_ptr hdr = (const_u32_ptr)hdr_g;
   using P = Pack<T>;
   using V = typename P::V;
   constexpr int SG = P::SG, GPB = 64 / SG;
-  static_assert(GPB % RG == 0, "ring must divide the groups of a block");
   const int lane = threadIdx.x & 63;
   // row p of the sweep (clamped into the star; rows past the end read as 0)
   auto load_row = [&](int p, T (&dst)[CW]) {
@@ -152,90 +150,113 @@ __device__ __forceinline__ void sweep(T *sl, int c0, int n, const uint32_t *__re
   T inc[CW];
   load_row(64 * (Q + 1) + lane, inc);
   T hinv = lane < n ? inv[lane] : T(0);
-  // group headers (uniform): width << 21 | offset in 16-byte units; hc: this
-  // block, hn: the next (the header array is padded with zeros past the end)
-  uint32_t hc[GPB], hn[GPB];
-#pragma unroll
-  for (int i = 0; i < GPB; ++i) hc[i] = hdr[i];
+  // Group widths (16-bit, two per word; zero past the end of the stream). A
+  // group starts where the previous one ends, so the fetches, which come in
+  // group order, keep a running offset. The ring reaches RG groups ahead, i.e.
+  // into block b + HB - 1. Lane i of `wcur` holds width word i counted from the
+  // current block's first group; `wnext` (the same from the next block on) is
+  // loaded at the start of a block, a block before it is used. Vector loads
+  // complete in order, so waiting for it does not wait for later loads. A ring
+  // longer than a block repeats its slots every UB blocks, so the loop body
+  // covers UB blocks.
+  constexpr int HB = RG > GPB ? 3 : 2;
+  constexpr int UB = RG > GPB ? RG / GPB : 1;
+  constexpr int WPB = GPB / 2;  // width words per block
+  static_assert(RG <= GPB ? GPB % RG == 0 : (RG % GPB == 0 && UB <= 2), "ring and block sizes do not fit");
+  const uint32_t *hw = reinterpret_cast<const uint32_t *>(hdr_g);
+  const int wl = lane < HB * WPB ? lane : HB * WPB - 1;
+  uint32_t wcur = hw[wl];
+  auto width_of = [&](auto gc) -> uint32_t {  // group index from the current block's first
+    constexpr int g = decltype(gc)::value;
+    const uint32_t w = (uint32_t)__builtin_amdgcn_readlane((int)wcur, g / 2);
+    return (w >> (16 * (g % 2))) & 0xFFFFu;
+  };
+  uint32_t foff = 0;  // 16-byte offset of the next group to fetch
   // ring of raw group loads; the width mask is applied when a group is used,
   // so that no load has to complete before its group comes up
   V ring[RG][Q];
   uint32_t ring_w[RG];
-  auto fetch = [&](uint32_t h, int s0, int rg) {
-    const T *base = vals + (size_t)(h & 0x1FFFFFu) * SG;
+  auto fetch = [&](uint32_t w, int s0, int rg) {
+    const T *base = vals + (size_t)foff * SG;
+    foff += w;
     // lane offsets computed at each fetch rather than kept for every group
     int l = lane;
     asm volatile("; fetch lane %0" : "+v"(l));
     const int ub = (l - s0 - 1) & 63;
-    ring_w[rg] = h >> 21;
+    ring_w[rg] = w;
 #pragma unroll
     for (int q = 0; q < Q; ++q) ring[rg][q] = *reinterpret_cast<const V *>(base + (ub + 64 * q) * SG);
   };
+  StaticFor<0, RG>::run([&](auto rc) {
+    constexpr int rg = decltype(rc)::value;
+    fetch(width_of(rc), (rg * SG) & 63, rg);
+  });
+  for (int jb0 = 0; jb0 < n; jb0 += 64 * UB) {
+    StaticFor<0, UB>::run([&](auto hc_) {
+      constexpr int H = decltype(hc_)::value;
+      const int jb = jb0 + 64 * H;
+      if (jb >= n) return;
+      const uint32_t wnext = hw[(jb / 64 + 1) * WPB + wl];
+      const T hinvN = jb + 64 + lane < n ? inv[jb + 64 + lane] : T(0);
+      T incN[CW];
+      load_row(jb + 64 * (Q + 2) + lane, incN);
+      // an opaque copy of the lane id per block keeps the per-step lane
+      // comparisons inside the loop
+      int lid = lane;
+      asm volatile("; lane id %0" : "+v"(lid));
+      StaticFor<0, 64>::run([&](auto sc) {
+        constexpr int s = decltype(sc)::value;
+        constexpr int gi = s / SG, k = s % SG;
+        constexpr int slot = (H * GPB + gi) % RG;
+        V(&cur)[Q] = ring[slot];
+        if constexpr (k == 0) {
+          // the group comes up: zero the entries past its width
+          const int ub = (lane - s - 1) & 63;
 #pragma unroll
-  for (int rg = 0; rg < RG; ++rg) fetch(hc[rg], (rg * SG) & 63, rg);
-  for (int jb = 0; jb < n; jb += 64) {
-    const int gb = jb / SG;
-#pragma unroll
-    for (int i = 0; i < GPB; ++i) hn[i] = hdr[gb + GPB + i];
-    const T hinvN = jb + 64 + lane < n ? inv[jb + 64 + lane] : T(0);
-    T incN[CW];
-    load_row(jb + 64 * (Q + 2) + lane, incN);
-    // an opaque copy of the lane id per block keeps the per-step lane
-    // comparisons inside the loop
-    int lid = lane;
-    asm volatile("; lane id %0" : "+v"(lid));
-    StaticFor<0, 64>::run([&](auto sc) {
-      constexpr int s = decltype(sc)::value;
-      constexpr int gi = s / SG, k = s % SG;
-      V(&cur)[Q] = ring[gi % RG];
-      if constexpr (k == 0) {
-        // the group comes up: zero the entries past its width
-        const int ub = (lane - s - 1) & 63;
-#pragma unroll
-        for (int q = 0; q < Q; ++q) cur[q] = P::masked((uint32_t)(ub + 64 * q) < ring_w[gi % RG], cur[q]);
-      }
-      const bool up = lid > s;  // lanes whose R[0] row is still open
-      T g[CW];
-#pragma unroll
-      for (int c = 0; c < CW; ++c) g[c] = P::template lane<s>(R[0][c]);
-      T M[Q + 1];
-      M[0] = up ? P::get(cur[0], k) : T(0);
-#pragma unroll
-      for (int q = 1; q < Q; ++q) M[q] = up ? P::get(cur[q], k) : P::get(cur[q - 1], k);
-      M[Q] = up ? T(0) : P::get(cur[Q - 1], k);
-#pragma unroll
-      for (int q = 0; q <= Q; ++q)
-#pragma unroll
-        for (int c = 0; c < CW; ++c) {
-          R[q][c] = P::fnma(M[q], g[c], R[q][c]);
-          // keep every update in its step: otherwise updates of registers not
-          // read during the block sink to its end with their operands live
-          asm volatile("" : "+v"(R[q][c]));
+          for (int q = 0; q < Q; ++q) cur[q] = P::masked((uint32_t)(ub + 64 * q) < ring_w[slot], cur[q]);
         }
-      if constexpr (k == SG - 1) {
-        // the group is consumed: fetch the group RG positions ahead
-        constexpr int li = gi + RG;
-        fetch(li < GPB ? hc[li % GPB] : hn[li % GPB], (li * SG) & 63, gi % RG);
+        const bool up = lid > s;  // lanes whose R[0] row is still open
+        T g[CW];
+#pragma unroll
+        for (int c = 0; c < CW; ++c) g[c] = P::template lane<s>(R[0][c]);
+        T M[Q + 1];
+        M[0] = up ? P::get(cur[0], k) : T(0);
+#pragma unroll
+        for (int q = 1; q < Q; ++q) M[q] = up ? P::get(cur[q], k) : P::get(cur[q - 1], k);
+        M[Q] = up ? T(0) : P::get(cur[Q - 1], k);
+#pragma unroll
+        for (int q = 0; q <= Q; ++q)
+#pragma unroll
+          for (int c = 0; c < CW; ++c) {
+            R[q][c] = P::fnma(M[q], g[c], R[q][c]);
+            // keep every update in its step: otherwise updates of registers
+            // not read during the block sink to its end with their operands live
+            asm volatile("" : "+v"(R[q][c]));
+          }
+        if constexpr (k == SG - 1) {
+          // the group is consumed: fetch the group RG positions ahead into its slot
+          constexpr int li = gi + RG;
+          fetch(width_of(std::integral_constant<int, li>{}), (li * SG) & 63, slot);
+        }
+      });
+      if (jb + lane < n) {
+        Row<T, CW> rw;
+#pragma unroll
+        for (int c = 0; c < CW; ++c) rw.v[c] = R[0][c] * hinv;
+        rw.store(sl + (size_t)(REV ? n - 1 - (jb + lane) : jb + lane) * KC + c0);
       }
+#pragma unroll
+      for (int q = 0; q < Q; ++q)
+#pragma unroll
+        for (int c = 0; c < CW; ++c) R[q][c] = R[q + 1][c];
+#pragma unroll
+      for (int c = 0; c < CW; ++c) {
+        R[Q][c] = inc[c];
+        inc[c] = incN[c];
+      }
+      hinv = hinvN;
+      wcur = wnext;
     });
-    if (jb + lane < n) {
-      Row<T, CW> rw;
-#pragma unroll
-      for (int c = 0; c < CW; ++c) rw.v[c] = R[0][c] * hinv;
-      rw.store(sl + (size_t)(REV ? n - 1 - (jb + lane) : jb + lane) * KC + c0);
-    }
-#pragma unroll
-    for (int q = 0; q < Q; ++q)
-#pragma unroll
-      for (int c = 0; c < CW; ++c) R[q][c] = R[q + 1][c];
-#pragma unroll
-    for (int c = 0; c < CW; ++c) {
-      R[Q][c] = inc[c];
-      inc[c] = incN[c];
-    }
-    hinv = hinvN;
-#pragma unroll
-    for (int i = 0; i < GPB; ++i) hc[i] = hn[i];
   }
 }
 
@@ -254,9 +275,13 @@ constexpr int pass_columns() {
 template <typename T, int KC, int Q>
 __device__ __forceinline__ void star_solve(const StarArgs &a, int st, int n, T *sl) {
   constexpr int GPB = 64 / Pack<T>::SG;
-  constexpr int RG0 = 16 / Q;
-  constexpr int RG = RG0 >= GPB ? GPB : (RG0 >= 8 ? 8 : (RG0 >= 4 ? 4 : (RG0 >= 2 ? 2 : 1)));
   constexpr int CW = pass_columns<T, Q, KC>();
+  // ring of 16-byte group loads: 32 slots (128 registers) for windows of 1-2
+  // registers, 16 for wider ones, fewer when many columns share a step (a step
+  // then takes longer, so fewer steps of lookahead hide the same latency)
+  constexpr int SLOTS = (Q <= 2 ? 32 : 16) / (CW >= 8 ? CW / 4 : 1);
+  constexpr int RG0 = SLOTS / Q > 2 * GPB ? 2 * GPB : SLOTS / Q;
+  constexpr int RG = RG0 >= 32 ? 32 : RG0 >= 16 ? 16 : RG0 >= 8 ? 8 : RG0 >= 4 ? 4 : RG0 >= 2 ? 2 : 1;
   const int vb = a.st_vb[st], gbase = a.st_gb[st];
   const T *finv = static_cast<const T *>(a.f_inv) + vb, *binv = static_cast<const T *>(a.b_inv) + vb;
   const T *fval = static_cast<const T *>(a.f_val) + a.st_fb[st], *bval = static_cast<const T *>(a.b_val) + a.st_bb[st];

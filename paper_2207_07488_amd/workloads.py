@@ -133,3 +133,34 @@ BAND = 1e-3
 def merge_tol(length: float) -> float:
     """Merge distance of Sec. 6.1: fiber length times 1e-4."""
     return length * 1e-4
+
+
+def serving_pool(count: int, seed: int, n_min: float = 2e3, n_max: float = 5e5) -> list:
+    """Networks of a serving mix: node counts log-uniform in [n_min, n_max],
+    2D and 3D alternating, fiber density well above percolation, and the mesh
+    chosen so that stars hold about 500 nodes on average.
+
+    2D: segments n = N / (2 + D/pi) at density n l^2 = D = 20 (about D/pi
+    crossings per segment). 3D: n = N / 4 with l = (25.5/n)^(1/3) and contact
+    distance l/10 (about 4 contacts per segment). Mesh: 4N/nH^2 = 500 (2D),
+    8N/nH^3 = 500 (3D), the 3D coarse space capped below 8192 dofs.
+    """
+    u = uniform01(seed, 0, count)
+    out = []
+    for i in range(count):
+        N = float(np.exp(np.log(n_min) + (np.log(n_max) - np.log(n_min)) * u[i]))
+        if i % 2 == 0:
+            D = 20.0
+            n = max(int(N / (2.0 + D / np.pi)), 16)
+            length = float(np.sqrt(D / n))
+            nH = max(2, int(round(np.sqrt(4.0 * N / 500.0))))
+            out.append(dict(dim=2, n_segments=n, length=length, seed=seed * 1000 + i, dir_lo=1, dir_hi=1, nH=nH,
+                            target_nodes=int(N)))
+        else:
+            n = max(int(N / 4.0), 16)
+            length = float((25.5 / n) ** (1.0 / 3.0))
+            nH = min(19, max(2, int(round((8.0 * N / 500.0) ** (1.0 / 3.0)))))
+            out.append(dict(dim=3, n_segments=n, length=length, contact_eps=length / 10.0, seed=seed * 1000 + i,
+                            dir_lo=4, dir_hi=4, nH=nH, target_nodes=int(N)))
+    return out
+
