@@ -155,6 +155,7 @@ def main():
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-h-sweep", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=64)
     ap.add_argument("--serving-rate", type=float, default=100.0, help="Poisson arrival rate (requests/s)")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic_star_sweep_fiber2d_20k.json"),
@@ -204,6 +205,21 @@ def main():
                                      "ms_per_batch": round(r["total_s"] / max(2, args.steps // 4) * 1e3, 3),
                                      "max_iterations": int(max(i["iters"] for i in r["info"])),
                                      "max_res_true": max(i["res_true"] for i in r["info"])}
+
+    # the mesh-size sweep of the same network (H = 1/16, 1/32, 1/64)
+    h_sweep = {}
+    if not args.no_h_sweep:
+        for nH in (16, 32, 64):
+            row = {}
+            for name, prec in (("mixed", S.FP32_STARS), ("plain", S.FP64)):
+                pre = S.Precond(sysm, nH, S.STARS_ALL, preset["dir_lo"], preset["dir_hi"], precision=prec)
+                r = timed_solves(pre, f, max(3, args.steps // 4), 1, args.rtol, use_graph=True)
+                row[name] = {"solves_per_s": round(max(3, args.steps // 4) / r["total_s"], 2),
+                             "iterations": int(r["iters"][-1]), "res_true": r["info"][0]["res_true"]}
+                row["stars"], row["m0"] = pre.nstars, pre.m0
+                row["max_star_dofs"] = pre.factor_info()["max_star_dofs"]
+                del pre
+            h_sweep[f"H=1/{nH}"] = row
 
     value = args.steps / rm["total_s"]
     plain_value = args.steps / rp["total_s"]
@@ -264,6 +280,7 @@ def main():
         "mixed_over_plain": round(value / plain_value, 3),
         "graph_replay": {"mixed": round(args.steps / rg["total_s"], 3), "plain": round(args.steps / rpg["total_s"], 3)},
         "multi_rhs": multi,
+        "h_sweep": h_sweep,
         "roofline": roof_m,
         "setup_s": round(t_setup, 2),
         "factor_info": {"mixed": {k: fim[k] for k in ("star_factor_nnz", "sweep_bytes", "max_band", "max_star_dofs",

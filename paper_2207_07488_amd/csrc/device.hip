@@ -557,6 +557,7 @@ struct DeviceState {
   int32_t nstars = 0, maxn = 0;
   int32_t n_narrow = 0, n_wide = 0;
   int64_t slot_count = 0;
+  int64_t f_zero = 0, b_zero = 0;
   DBuf<int32_t> order_narrow, order_wide, st_n, st_vb, st_q, st_gb, pos_dof, slot_of;
   DBuf<uint16_t> f_hdr, b_hdr;
   DBuf<int64_t> st_fb, st_bb;
@@ -590,7 +591,8 @@ struct Engine {
   bool sc_dirty = false;         // host_sc changed since the last upload
   hipStream_t own = nullptr;     // the engine's stream (and graph capture)
   hipStream_t aux = nullptr;     // wide stars run beside the narrow ones
-  hipEvent_t fork = nullptr, join = nullptr, tick_done = nullptr;
+  hipStream_t aux2 = nullptr;    // the coarse solve runs beside the star sweeps
+  hipEvent_t fork = nullptr, join = nullptr, fork2 = nullptr, join2 = nullptr, tick_done = nullptr;
   bool in_flight = false;
   std::vector<hipGraphExec_t> graphs;  // graphs[i] runs 2^i iterations on `own`-captured work
   std::vector<hipGraph_t> graph_defs;
@@ -604,7 +606,10 @@ struct Engine {
     if (host_sc) (void)hipHostFree(host_sc);
     if (fork) (void)hipEventDestroy(fork);
     if (join) (void)hipEventDestroy(join);
+    if (fork2) (void)hipEventDestroy(fork2);
+    if (join2) (void)hipEventDestroy(join2);
     if (tick_done) (void)hipEventDestroy(tick_done);
+    if (aux2) (void)hipStreamDestroy(aux2);
     if (aux) (void)hipStreamDestroy(aux);
     if (own) (void)hipStreamDestroy(own);
   }
@@ -716,8 +721,11 @@ void upload_stars(DeviceState &d, const Precond &pre, const HostFactors &hf, sn_
   }
   if (tot >= (int64_t)1 << 31 || (int64_t)std::max(f_val.size(), b_val.size()) >= (int64_t)1 << 31)
     fail(SN_EINVAL, "star streams too large for 32-bit offsets");
-  // over-read slack: a group load reads up to 64*Q lanes of SG values
+  // zero region: lanes past a group's width load from here (64*Q lanes of SG
+  // values, Q <= 16)
   const size_t slack = (size_t)64 * 16 * SG + 64;
+  d.f_zero = (int64_t)f_val.size();
+  d.b_zero = (int64_t)b_val.size();
   f_val.resize(f_val.size() + slack, T(0));
   b_val.resize(b_val.size() + slack, T(0));
   // schedule: longest chain first, narrow and wide windows in separate kernels
@@ -959,6 +967,8 @@ StarArgs star_args(DeviceState &d, Engine &e) {
   a.pos_dof = d.pos_dof.p;
   a.f_hdr = d.f_hdr.p;
   a.b_hdr = d.b_hdr.p;
+  a.f_zero = d.f_zero;
+  a.b_zero = d.b_zero;
   if (d.precision == SN_PREC_FP32_STARS) {
     a.f_inv = d.f_inv32.p;
     a.b_inv = d.b_inv32.p;
@@ -1023,15 +1033,24 @@ void launch_stars(Engine &e, const double *r, int sel, hipStream_t s) {
 // z = B r on the selected columns; with dot, r.z -> rho, beta (second half)
 void launch_B(Engine &e, const double *r, double *z, int sel, bool dot, hipStream_t s) {
   DeviceState &d = *e.d;
+  if (d.m0 > 0) {
+    // the coarse solve is independent of the local solves (the preconditioner
+    // is additive): it runs on its own stream beside the star sweeps
+    HIPCHK(hipEventRecord(e.fork2, s));
+    HIPCHK(hipStreamWaitEvent(e.aux2, e.fork2, 0));
+    with_kc(e.kc, [&](auto K) {
+      constexpr int KC = decltype(K)::value;
+      hipLaunchKernelGGL(k_restrict<KC>, dim3((unsigned)d.m0), dim3(kBlock), 0, e.aux2, d.PTptr.p, d.PTdof.p,
+                         d.PTw.p, r, e.rH.p, (int)d.m0, e.sc.p, sel);
+      hipLaunchKernelGGL(k_coarse_gemv<KC>, dim3(nblk(d.m0 * 64)), dim3(kBlock), 0, e.aux2, d.Kinv.p, e.rH.p, e.c.p,
+                         (int)d.m0, e.sc.p, sel);
+    });
+    HIPCHK(hipEventRecord(e.join2, e.aux2));
+  }
   launch_stars(e, r, sel, s);
+  if (d.m0 > 0) HIPCHK(hipStreamWaitEvent(s, e.join2, 0));
   with_kc(e.kc, [&](auto K) {
     constexpr int KC = decltype(K)::value;
-    if (d.m0 > 0) {
-      hipLaunchKernelGGL(k_restrict<KC>, dim3((unsigned)d.m0), dim3(kBlock), 0, s, d.PTptr.p, d.PTdof.p, d.PTw.p, r,
-                         e.rH.p, (int)d.m0, e.sc.p, sel);
-      hipLaunchKernelGGL(k_coarse_gemv<KC>, dim3(nblk(d.m0 * 64)), dim3(kBlock), 0, s, d.Kinv.p, e.rH.p, e.c.p,
-                         (int)d.m0, e.sc.p, sel);
-    }
     const unsigned G = grid_for(d.npad);
     double *parts = dot ? e.partials.p : nullptr;
     if (d.precision == SN_PREC_FP32_STARS)
@@ -1290,6 +1309,9 @@ Engine *engine_create(Precond &pre, int kc) {
   HIPCHK(hipStreamCreateWithFlags(&e->aux, hipStreamNonBlocking));
   HIPCHK(hipEventCreateWithFlags(&e->fork, hipEventDisableTiming));
   HIPCHK(hipEventCreateWithFlags(&e->join, hipEventDisableTiming));
+  HIPCHK(hipStreamCreateWithFlags(&e->aux2, hipStreamNonBlocking));
+  HIPCHK(hipEventCreateWithFlags(&e->fork2, hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&e->join2, hipEventDisableTiming));
   HIPCHK(hipEventCreateWithFlags(&e->tick_done, hipEventDisableTiming));
   HIPCHK(hipDeviceSynchronize());
   e->bytes = (int64_t)(6 * np * 8 + 2 * nm * 8 + e->partials.bytes() + e->sc.bytes() + e->slots32.bytes() +

@@ -70,6 +70,7 @@ struct StarArgs {
   const uint16_t *f_hdr, *b_hdr;             // per group: width in 16-byte slots (groups are contiguous)
   const void *f_inv, *b_inv;                 // 1/pivot per step (T)
   const void *f_val, *b_val;                 // packed stream values (T)
+  int64_t f_zero, b_zero;                    // element offset of a zero region (16 KB) in f_val / b_val
   void *slots;                               // T, per position and column (position-major)
 };
 

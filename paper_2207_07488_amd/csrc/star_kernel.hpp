@@ -25,7 +25,8 @@ namespace spnet {
 // sits in lane s of R[0]; the rows still to be updated are, for lanes l > s,
 // R[0..Q-1], for lanes l <= s, R[1..Q]. The q-th of them needs stream entry
 // t = ((l - j - 1) mod 64) + 64 q, which the host stores so that lane l loads
-// it for SG consecutive steps with one 16-byte load. A per-lane select routes
+// it for SG consecutive steps with one 16-byte load (lanes past the group's
+// width load zeros from a zero region). A per-lane select routes
 // the loaded multiplier q to R[q] or R[q+1]; no row moves between lanes. At
 // the end of a block R[0] holds 64 finished rows, the registers shift by one
 // and the next rows enter from memory (loaded one block ahead).
@@ -40,9 +41,6 @@ struct Pack<float> {
   static __device__ __forceinline__ float get(const V &v, int k) {
     return k == 0 ? v.x : (k == 1 ? v.y : (k == 2 ? v.z : v.w));
   }
-  static __device__ __forceinline__ V masked(bool keep, const V &v) {
-    return V{keep ? v.x : 0.f, keep ? v.y : 0.f, keep ? v.z : 0.f, keep ? v.w : 0.f};
-  }
   template <int L>
   static __device__ __forceinline__ float lane(float v) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), L));
@@ -54,9 +52,6 @@ struct Pack<double> {
   using V = double2;
   static constexpr int SG = 2;
   static __device__ __forceinline__ double get(const V &v, int k) { return k == 0 ? v.x : v.y; }
-  static __device__ __forceinline__ V masked(bool keep, const V &v) {
-    return V{keep ? v.x : 0.0, keep ? v.y : 0.0};
-  }
   static __device__ __forceinline__ int lo(double v) { return (int)(uint32_t)(__double_as_longlong(v)); }
   static __device__ __forceinline__ int hi(double v) { return (int)(uint32_t)(__double_as_longlong(v) >> 32); }
   static __device__ __forceinline__ double mk(int l, int h) {
@@ -131,7 +126,8 @@ typedef const __attribute__((address_space(4))) uint32_t *const_u32_ptr;
 // vector in reverse position order.
 template <typename T, int KC, int CW, int Q, int RG, bool REV>
 __device__ __forceinline__ void sweep(T *sl, int c0, int n, const uint16_t *__restrict__ hdr_g,
-                                      const T *__restrict__ inv, const T *__restrict__ vals) {
+                                      const T *__restrict__ inv, const T *__restrict__ vals, uint32_t sbase,
+                                      uint32_t zbase) {
   using P = Pack<T>;
   using V = typename P::V;
   constexpr int SG = P::SG, GPB = 64 / SG;
@@ -172,20 +168,22 @@ __device__ __forceinline__ void sweep(T *sl, int c0, int n, const uint16_t *__re
     return (w >> (16 * (g % 2))) & 0xFFFFu;
   };
   uint32_t foff = 0;  // 16-byte offset of the next group to fetch
-  // ring of raw group loads; the width mask is applied when a group is used,
-  // so that no load has to complete before its group comes up
+  // ring of group loads RG groups ahead; lanes past a group's width read the
+  // zero region instead, so a loaded group is used as it is
   V ring[RG][Q];
-  uint32_t ring_w[RG];
   auto fetch = [&](uint32_t w, int s0, int rg) {
-    const T *base = vals + (size_t)foff * SG;
+    const uint32_t gbase = sbase + foff * SG;
     foff += w;
     // lane offsets computed at each fetch rather than kept for every group
     int l = lane;
     asm volatile("; fetch lane %0" : "+v"(l));
-    const int ub = (l - s0 - 1) & 63;
-    ring_w[rg] = w;
+    const uint32_t ub = (uint32_t)((l - s0 - 1) & 63);
 #pragma unroll
-    for (int q = 0; q < Q; ++q) ring[rg][q] = *reinterpret_cast<const V *>(base + (ub + 64 * q) * SG);
+    for (int q = 0; q < Q; ++q) {
+      const uint32_t u = ub + 64u * q;
+      const uint32_t off = (u < w ? gbase : zbase) + u * SG;
+      ring[rg][q] = *reinterpret_cast<const V *>(vals + off);
+    }
   };
   StaticFor<0, RG>::run([&](auto rc) {
     constexpr int rg = decltype(rc)::value;
@@ -208,13 +206,7 @@ __device__ __forceinline__ void sweep(T *sl, int c0, int n, const uint16_t *__re
         constexpr int s = decltype(sc)::value;
         constexpr int gi = s / SG, k = s % SG;
         constexpr int slot = (H * GPB + gi) % RG;
-        V(&cur)[Q] = ring[slot];
-        if constexpr (k == 0) {
-          // the group comes up: zero the entries past its width
-          const int ub = (lane - s - 1) & 63;
-#pragma unroll
-          for (int q = 0; q < Q; ++q) cur[q] = P::masked((uint32_t)(ub + 64 * q) < ring_w[slot], cur[q]);
-        }
+        const V(&cur)[Q] = ring[slot];
         const bool up = lid > s;  // lanes whose R[0] row is still open
         T g[CW];
 #pragma unroll
@@ -284,11 +276,12 @@ __device__ __forceinline__ void star_solve(const StarArgs &a, int st, int n, T *
   constexpr int RG = RG0 >= 32 ? 32 : RG0 >= 16 ? 16 : RG0 >= 8 ? 8 : RG0 >= 4 ? 4 : RG0 >= 2 ? 2 : 1;
   const int vb = a.st_vb[st], gbase = a.st_gb[st];
   const T *finv = static_cast<const T *>(a.f_inv) + vb, *binv = static_cast<const T *>(a.b_inv) + vb;
-  const T *fval = static_cast<const T *>(a.f_val) + a.st_fb[st], *bval = static_cast<const T *>(a.b_val) + a.st_bb[st];
+  const T *fval = static_cast<const T *>(a.f_val), *bval = static_cast<const T *>(a.b_val);
+  const uint32_t fb = (uint32_t)a.st_fb[st], bb = (uint32_t)a.st_bb[st];
   for (int c0 = 0; c0 < KC; c0 += CW) {
-    sweep<T, KC, CW, Q, RG, false>(sl, c0, n, a.f_hdr + gbase, finv, fval);
+    sweep<T, KC, CW, Q, RG, false>(sl, c0, n, a.f_hdr + gbase, finv, fval, fb, (uint32_t)a.f_zero);
     __syncthreads();
-    sweep<T, KC, CW, Q, RG, true>(sl, c0, n, a.b_hdr + gbase, binv, bval);
+    sweep<T, KC, CW, Q, RG, true>(sl, c0, n, a.b_hdr + gbase, binv, bval, bb, (uint32_t)a.b_zero);
     __syncthreads();
   }
 }
