@@ -229,6 +229,15 @@ sn_status sn_precond_profile(sn_precond pre, int enable);
 /* Waits for recorded work and returns the totals since the last reset. */
 sn_status sn_precond_kernel_stats(sn_precond pre, sn_kernel_stats *stats);
 
+/*
+ * Occupancy of the star sweeps chosen for batches of k columns: when the
+ * preconditioner first solves with a batch width, every candidate limit of
+ * resident star wavefronts per SIMD (none, 4, 3, 2, 1) is timed on the device
+ * and the fastest kept. Returns that limit (0 = none) and its sweep time
+ * (microseconds per application of B, all stars).
+ */
+sn_status sn_precond_engine_info(sn_precond pre, int k, int32_t *star_waves_per_simd, double *star_sweep_us);
+
 /* y = K x for k columns (n x k row-major). */
 sn_status sn_apply_K(sn_precond pre, int k, const double *x, double *y, int device_ptrs, void *stream);
 /* z = B r, B = P K_0^{-1} P^T + sum_j R_j^T K_j^{-1} R_j (so that BK = P_0 + ... + P_m). */

@@ -149,17 +149,39 @@ __device__ __forceinline__ bool any_selected(const CgScalars *sc, int sel, uint3
 }
 
 // one block: combine the partials of the previous kernel per column and update
-// the scalars of the selected columns
+// the scalars of the selected columns. Every column is summed like a single
+// one (thread t adds partials t, t+256, ... in order, then a fixed block tree),
+// all columns at once.
 template <int KC>
 __global__ __launch_bounds__(kBlock) void k_scalar(const double *__restrict__ partials, int nparts, CgScalars *sc,
                                                    int op, int sel, uint32_t mask) {
-  __shared__ double sh[kBlock / 64];
+  __shared__ double sh[kBlock / 64][KC];
+  bool on[KC];
+  bool any = false;
+#pragma unroll
   for (int c = 0; c < KC; ++c) {
-    if (!column_selected(sc[c], sel, mask, c)) continue;  // uniform
-    double s = 0.0;
-    for (int i = threadIdx.x; i < nparts; i += kBlock) s += partials[c * kMaxGrid + i];
-    const double tot = block_sum(s, sh);
-    if (threadIdx.x != 0) continue;
+    on[c] = column_selected(sc[c], sel, mask, c);
+    any |= on[c];
+  }
+  if (!any) return;
+  Vec<KC> sum;
+  sum.zero();
+  for (int i = threadIdx.x; i < nparts; i += kBlock)
+#pragma unroll
+    for (int c = 0; c < KC; ++c)
+      if (on[c]) sum.v[c] += partials[c * kMaxGrid + i];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int c = 0; c < KC; ++c) {
+    const double v = wave_sum(sum.v[c]);
+    if (lane == 0) sh[w][c] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  for (int c = 0; c < KC; ++c) {
+    if (!on[c]) continue;
+    double tot = 0.0;
+    for (int i = 0; i < kBlock / 64; ++i) tot += sh[i][c];
     CgScalars &x = sc[c];
     switch (op) {
       case OP_ALPHA:
@@ -360,63 +382,102 @@ __global__ __launch_bounds__(kBlock) void k_p_update(double *p, const double *z,
   }
 }
 
-// r_H = P^T r: one block per coarse dof, fixed-order sums
+// r_H = P^T r: one wavefront per coarse dof (four per block); lane l sums the
+// entries l, l+64, ... of the dof's list, then a fixed wavefront tree
 template <int KC>
 __global__ __launch_bounds__(kBlock) void k_restrict(const int32_t *__restrict__ ptr, const int32_t *__restrict__ dof,
                                                      const double *__restrict__ w, const double *__restrict__ r,
                                                      double *rH, int m0, const CgScalars *sc, int sel) {
-  __shared__ double sh[kBlock / 64][KC];
   if (!any_selected<KC>(sc, sel, 0u)) return;
-  const int g = blockIdx.x;
+  const int g = (blockIdx.x * kBlock + threadIdx.x) >> 6, lane = threadIdx.x & 63;
+  if (g >= m0) return;
   Vec<KC> acc;
   acc.zero();
-  for (int q = ptr[g] + threadIdx.x; q < ptr[g + 1]; q += kBlock) {
+  const int q1 = ptr[g + 1];
+  for (int q = ptr[g] + lane; q < q1; q += 64) {
     const double wq = w[q];
     Vec<KC> rv;
     rv.load(r + (size_t)dof[q] * KC);
 #pragma unroll
     for (int k = 0; k < KC; ++k) acc.v[k] = __builtin_fma(wq, rv.v[k], acc.v[k]);
   }
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-  for (int k = 0; k < KC; ++k) {
-    const double s = wave_sum(acc.v[k]);
-    if (lane == 0) sh[wv][k] = s;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    Vec<KC> out;
-#pragma unroll
-    for (int k = 0; k < KC; ++k) {
-      double s = 0.0;
-      for (int i = 0; i < kBlock / 64; ++i) s += sh[i][k];
-      out.v[k] = s;
-    }
-    out.store(rH + (size_t)g * KC);
-  }
-}
-
-// c = K_0^{-1} r_H, one wavefront per row of the dense inverse
-template <int KC>
-__global__ __launch_bounds__(kBlock) void k_coarse_gemv(const double *__restrict__ Kinv, const double *__restrict__ rH,
-                                                        double *cvec, int m0, const CgScalars *sc, int sel) {
-  if (!any_selected<KC>(sc, sel, 0u)) return;
-  const int row = (blockIdx.x * kBlock + threadIdx.x) >> 6, lane = threadIdx.x & 63;
-  if (row >= m0) return;
-  const double *a = Kinv + (size_t)row * m0;
-  Vec<KC> acc;
-  acc.zero();
-  for (int j = lane; j < m0; j += 64) {
-    const double aj = a[j];
-    Vec<KC> x;
-    x.load(rH + (size_t)j * KC);
-#pragma unroll
-    for (int k = 0; k < KC; ++k) acc.v[k] = __builtin_fma(aj, x.v[k], acc.v[k]);
-  }
   Vec<KC> out;
 #pragma unroll
   for (int k = 0; k < KC; ++k) out.v[k] = wave_sum(acc.v[k]);
-  if (lane == 0) out.store(cvec + (size_t)row * KC);
+  if (lane == 0) out.store(rH + (size_t)g * KC);
+}
+
+// c = K_0^{-1} r_H. A wavefront computes RW rows; lane l takes the columns
+// 2l, 2l+1 of every 128-column chunk (16-byte loads of the row), in chunk
+// order, then a fixed wavefront tree: the same order for every column count.
+// With several columns the chunk of r_H is staged in LDS once per block and
+// shared by its 4 RW rows.
+template <int KC>
+__global__ __launch_bounds__(kBlock) void k_coarse_gemv(const double *__restrict__ Kinv, const double *__restrict__ rH,
+                                                        double *cvec, int m0, const CgScalars *sc, int sel) {
+  constexpr int RW = KC >= 4 ? 4 : 1;  // rows per wavefront
+  constexpr int CH = 128;              // columns per chunk
+  __shared__ double xs[KC > 1 ? CH * KC : 1];
+  if (!any_selected<KC>(sc, sel, 0u)) return;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int row0 = (blockIdx.x * (kBlock / 64) + wv) * RW;
+  Vec<KC> acc[RW];
+#pragma unroll
+  for (int i = 0; i < RW; ++i) acc[i].zero();
+  for (int j0 = 0; j0 < m0; j0 += CH) {
+    if constexpr (KC > 1) {
+      __syncthreads();
+      for (int t = threadIdx.x; t < CH * KC; t += kBlock) {
+        const int j = j0 + t / KC;
+        xs[t] = j < m0 ? rH[(size_t)j0 * KC + t] : 0.0;
+      }
+      __syncthreads();
+    }
+    const int ja = j0 + 2 * lane;
+#pragma unroll
+    for (int i = 0; i < RW; ++i) {
+      const int row = row0 + i;
+      if (row >= m0) break;
+      const double *a = Kinv + (size_t)row * m0;
+      double a0 = 0.0, a1 = 0.0;
+      if (ja + 1 < m0) {
+        if ((m0 & 1) == 0) {
+          const double2 t = *reinterpret_cast<const double2 *>(a + ja);
+          a0 = t.x;
+          a1 = t.y;
+        } else {
+          a0 = a[ja];
+          a1 = a[ja + 1];
+        }
+      } else if (ja < m0) {
+        a0 = a[ja];
+      }
+      Vec<KC> x0, x1;
+      if constexpr (KC > 1) {
+#pragma unroll
+        for (int k = 0; k < KC; ++k) {
+          x0.v[k] = xs[(2 * lane) * KC + k];
+          x1.v[k] = xs[(2 * lane + 1) * KC + k];
+        }
+      } else {
+        x0.v[0] = ja < m0 ? rH[ja] : 0.0;
+        x1.v[0] = ja + 1 < m0 ? rH[ja + 1] : 0.0;
+      }
+#pragma unroll
+      for (int k = 0; k < KC; ++k) {
+        acc[i].v[k] = __builtin_fma(a0, x0.v[k], acc[i].v[k]);
+        acc[i].v[k] = __builtin_fma(a1, x1.v[k], acc[i].v[k]);
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < RW; ++i) {
+    const int row = row0 + i;
+    Vec<KC> out;
+#pragma unroll
+    for (int k = 0; k < KC; ++k) out.v[k] = wave_sum(acc[i].v[k]);
+    if (lane == 0 && row < m0) out.store(cvec + (size_t)row * KC);
+  }
 }
 
 // a.b partials per column
@@ -588,6 +649,10 @@ struct Engine {
   DBuf<float> slots32;
   DBuf<double> slots64;
   CgScalars *host_sc = nullptr;  // pinned: last read-back, and the source of uploads
+  // star sweep occupancy chosen by measurement: waves per SIMD (0: no limit)
+  // and the LDS reservation that enforces it
+  int32_t star_cap = 0, star_lds = 0;
+  double star_us = 0.0;
   bool sc_dirty = false;         // host_sc changed since the last upload
   hipStream_t own = nullptr;     // the engine's stream (and graph capture)
   hipStream_t aux = nullptr;     // wide stars run beside the narrow ones
@@ -969,6 +1034,7 @@ StarArgs star_args(DeviceState &d, Engine &e) {
   a.b_hdr = d.b_hdr.p;
   a.f_zero = d.f_zero;
   a.b_zero = d.b_zero;
+  a.lds_reserve = e.star_lds;
   if (d.precision == SN_PREC_FP32_STARS) {
     a.f_inv = d.f_inv32.p;
     a.b_inv = d.b_inv32.p;
@@ -1040,10 +1106,12 @@ void launch_B(Engine &e, const double *r, double *z, int sel, bool dot, hipStrea
     HIPCHK(hipStreamWaitEvent(e.aux2, e.fork2, 0));
     with_kc(e.kc, [&](auto K) {
       constexpr int KC = decltype(K)::value;
-      hipLaunchKernelGGL(k_restrict<KC>, dim3((unsigned)d.m0), dim3(kBlock), 0, e.aux2, d.PTptr.p, d.PTdof.p,
+      hipLaunchKernelGGL(k_restrict<KC>, dim3(nblk(d.m0 * 64)), dim3(kBlock), 0, e.aux2, d.PTptr.p, d.PTdof.p,
                          d.PTw.p, r, e.rH.p, (int)d.m0, e.sc.p, sel);
-      hipLaunchKernelGGL(k_coarse_gemv<KC>, dim3(nblk(d.m0 * 64)), dim3(kBlock), 0, e.aux2, d.Kinv.p, e.rH.p, e.c.p,
-                         (int)d.m0, e.sc.p, sel);
+      constexpr int RW = KC >= 4 ? 4 : 1;
+      const unsigned gb = (unsigned)((d.m0 + 4 * RW - 1) / (4 * RW));
+      hipLaunchKernelGGL(k_coarse_gemv<KC>, dim3(gb), dim3(kBlock), 0, e.aux2, d.Kinv.p, e.rH.p, e.c.p, (int)d.m0,
+                         e.sc.p, sel);
     });
     HIPCHK(hipEventRecord(e.join2, e.aux2));
   }
@@ -1252,6 +1320,47 @@ void load_block(Engine &e, double *dst, const double *src_dev, int k, hipStream_
   });
 }
 
+// Star sweep occupancy: all stars are resident at once unless registers or an
+// LDS reservation limit them. Few resident waves per SIMD leave the hardware
+// to hand out the remaining (shorter, longest-first ordered) stars as waves
+// finish, which balances uneven stars; many hide more latency. The best limit
+// depends on the star sizes and the column count, so it is measured: every
+// candidate sweeps all stars (zero input) a few times and the fastest wins.
+void tune_stars(Engine &e) {
+  DeviceState &d = *e.d;
+  if (d.nstars == 0) return;
+  const bool prof = d.profiling;
+  d.profiling = false;
+  hipEvent_t t0, t1;
+  HIPCHK(hipEventCreate(&t0));
+  HIPCHK(hipEventCreate(&t1));
+  const int caps[] = {0, 4, 3, 2, 1};
+  double best = 1e30;
+  int best_cap = 0;
+  for (int cap : caps) {
+    e.star_cap = cap;
+    e.star_lds = cap == 0 ? 0 : (160 * 1024 / (4 * cap)) & ~511;
+    for (int w = 0; w < 2; ++w) launch_stars(e, e.r.p, SEL_ALL, e.own);
+    HIPCHK(hipEventRecord(t0, e.own));
+    for (int it = 0; it < 3; ++it) launch_stars(e, e.r.p, SEL_ALL, e.own);
+    HIPCHK(hipEventRecord(t1, e.own));
+    HIPCHK(hipEventSynchronize(t1));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, t0, t1));
+    const double us = 1e3 * ms / 3.0;
+    if (us < 0.98 * best) {
+      best = us;
+      best_cap = cap;
+    }
+  }
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
+  e.star_cap = best_cap;
+  e.star_lds = best_cap == 0 ? 0 : (160 * 1024 / (4 * best_cap)) & ~511;
+  e.star_us = best;
+  d.profiling = prof;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -1316,6 +1425,7 @@ Engine *engine_create(Precond &pre, int kc) {
   HIPCHK(hipDeviceSynchronize());
   e->bytes = (int64_t)(6 * np * 8 + 2 * nm * 8 + e->partials.bytes() + e->sc.bytes() + e->slots32.bytes() +
                        e->slots64.bytes());
+  tune_stars(*e);
   return e.release();
 }
 
@@ -1420,6 +1530,12 @@ void device_stats(Precond &pre, sn_kernel_stats *st) {
 }
 
 int64_t device_bytes(const Precond &pre) { return pre.dev ? pre.dev->bytes : 0; }
+
+void device_engine_info(Precond &pre, int k, int32_t *waves_per_simd, double *sweep_us) {
+  Engine &e = solve_engine(pre, k);
+  if (waves_per_simd) *waves_per_simd = e.star_cap;
+  if (sweep_us) *sweep_us = e.star_us;
+}
 
 void device_apply_K(Precond &pre, int k, const double *x, double *y, int device_ptrs, void *stream) {
   Engine &e = solve_engine(pre, k);

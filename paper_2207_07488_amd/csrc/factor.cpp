@@ -257,69 +257,93 @@ HostFactors factor_host(const Precond &pre) {
     factor_star(sys, &pre.star_dofs[pre.star_ptr[s]], m, where, hf.stars[s], s);
   });
 
-  // coarse matrix K_0 = P^T K P (dense), band Cholesky, explicit inverse
+  // coarse matrix K_0 = P^T K P in band storage, band Cholesky, explicit inverse
   const int64_t m0 = pre.m0;
   const int nc = sys.ncomp, nv = pre.nvert_per_elem;
-  if (m0 > 8192) fail(SN_EINVAL, "coarse space too large for the dense coarse operator (m0 > 8192)");
+  if (m0 > 16384) fail(SN_EINVAL, "coarse space too large for the dense coarse operator (m0 > 16384)");
   if (m0 > 0) {
-    std::vector<double> K0((size_t)m0 * m0, 0.0);
-    for (int64_t i = 0; i < sys.n; ++i) {
-      const int64_t fi = i / nc;
-      const int ci = (int)(i % nc);
-      for (int64_t q = sys.rowptr[i]; q < sys.rowptr[i + 1]; ++q) {
-        const int64_t j = sys.col[q], fj = j / nc;
-        const int cj = (int)(j % nc);
-        for (int a = 0; a < nv; ++a) {
-          const int32_t ga = pre.vert_coarse[pre.Pvert[(size_t)fi * nv + a]];
-          if (ga < 0) continue;
-          const double wa = pre.Pphi[(size_t)fi * nv + a] * sys.val[q];
-          const int64_t A_ = (int64_t)ga * nc + ci;
-          for (int b = 0; b < nv; ++b) {
-            const int32_t gb = pre.vert_coarse[pre.Pvert[(size_t)fj * nv + b]];
-            if (gb < 0) continue;
-            K0[(size_t)A_ * m0 + (int64_t)gb * nc + cj] += wa * pre.Pphi[(size_t)fj * nv + b];
+    // every coupling of K_0: coarse dofs of the elements of the two ends of a
+    // matrix entry; visit(A, B, value)
+    auto couplings = [&](auto visit) {
+      for (int64_t i = 0; i < sys.n; ++i) {
+        const int64_t fi = i / nc;
+        const int ci = (int)(i % nc);
+        for (int64_t q = sys.rowptr[i]; q < sys.rowptr[i + 1]; ++q) {
+          const int64_t j = sys.col[q], fj = j / nc;
+          const int cj = (int)(j % nc);
+          for (int a = 0; a < nv; ++a) {
+            const int32_t ga = pre.vert_coarse[pre.Pvert[(size_t)fi * nv + a]];
+            if (ga < 0) continue;
+            const double wa = pre.Pphi[(size_t)fi * nv + a] * sys.val[q];
+            const int64_t A_ = (int64_t)ga * nc + ci;
+            for (int b = 0; b < nv; ++b) {
+              const int32_t gb = pre.vert_coarse[pre.Pvert[(size_t)fj * nv + b]];
+              if (gb < 0) continue;
+              visit(A_, (int64_t)gb * nc + cj, wa * pre.Pphi[(size_t)fj * nv + b]);
+            }
           }
         }
       }
-    }
-    // band of K_0
+    };
     int64_t bw = 0;
-    for (int64_t i = 0; i < m0; ++i)
-      for (int64_t j = 0; j < i; ++j)
-        if (K0[(size_t)i * m0 + j] != 0.0) {
-          bw = std::max(bw, i - j);
-          break;
-        }
-    // in-place band Cholesky, lower triangle, row-major
+    couplings([&](int64_t A_, int64_t B_, double) { bw = std::max(bw, A_ - B_); });
+    // lower band by columns: Lb[j * W + k] = K_0(j + k, j), k = 0..bw
+    const int64_t W = bw + 1;
+    std::vector<double> Lb((size_t)(m0 * W), 0.0);
+    couplings([&](int64_t A_, int64_t B_, double v) {
+      if (A_ >= B_) Lb[(size_t)(B_ * W + (A_ - B_))] += v;
+    });
+    // right-looking band Cholesky
     for (int64_t j = 0; j < m0; ++j) {
-      double d = K0[(size_t)j * m0 + j];
+      double *cj = &Lb[(size_t)(j * W)];
+      const double d = cj[0];
       if (!(d > 0.0)) fail(SN_ENOTSPD, "coarse matrix P^T K P is not positive definite");
-      d = std::sqrt(d);
-      K0[(size_t)j * m0 + j] = d;
-      const int64_t iend = std::min(m0 - 1, j + bw);
-      for (int64_t i = j + 1; i <= iend; ++i) K0[(size_t)i * m0 + j] /= d;
-      for (int64_t c = j + 1; c <= iend; ++c) {
-        const double lcj = K0[(size_t)c * m0 + j];
-        if (lcj == 0.0) continue;
-        for (int64_t i = c; i <= iend; ++i) K0[(size_t)i * m0 + c] -= K0[(size_t)i * m0 + j] * lcj;
+      const double sd = std::sqrt(d);
+      cj[0] = sd;
+      const int64_t len = std::min(W, m0 - j);
+      for (int64_t k = 1; k < len; ++k) cj[k] /= sd;
+      for (int64_t t = 1; t < len; ++t) {
+        const double l = cj[t];
+        if (l == 0.0) continue;
+        double *cc = &Lb[(size_t)((j + t) * W)];  // column j + t, rows j + t ..
+        for (int64_t k = t; k < len; ++k) cc[k - t] -= cj[k] * l;
       }
     }
-    hf.coarse_inv.assign((size_t)m0 * m0, 0.0);
-    parallel_for(m0, [&](int64_t col) {
-      std::vector<double> y((size_t)m0, 0.0);
-      y[col] = 1.0;
-      for (int64_t i = col; i < m0; ++i) {
-        double s = y[i];
-        const int64_t j0 = std::max<int64_t>(col, i - bw);
-        for (int64_t j = j0; j < i; ++j) s -= K0[(size_t)i * m0 + j] * y[j];
-        y[i] = s / K0[(size_t)i * m0 + i];
+    // K_0^{-1}: columns solved with the band factor, eight at a time so that
+    // one pass over the factor serves eight right-hand sides
+    constexpr int RB = 8;
+    hf.coarse_inv.assign((size_t)(m0 * m0), 0.0);
+    const int64_t nblocks = (m0 + RB - 1) / RB;
+    parallel_for(nblocks, [&](int64_t blk) {
+      const int64_t c0 = blk * RB, nb = std::min<int64_t>(RB, m0 - c0);
+      std::vector<double> y((size_t)(m0 * RB), 0.0);  // row-major: y[i * RB + r]
+      for (int64_t r = 0; r < nb; ++r) y[(size_t)((c0 + r) * RB + r)] = 1.0;
+      // forward: L y = e (column-oriented; rows above c0 stay zero)
+      for (int64_t j = c0; j < m0; ++j) {
+        const double *cj = &Lb[(size_t)(j * W)];
+        double *yj = &y[(size_t)(j * RB)];
+        for (int r = 0; r < RB; ++r) yj[r] /= cj[0];
+        const int64_t len = std::min(W, m0 - j);
+        for (int64_t k = 1; k < len; ++k) {
+          double *yi = &y[(size_t)((j + k) * RB)];
+          const double l = cj[k];
+          for (int r = 0; r < RB; ++r) yi[r] -= l * yj[r];
+        }
       }
+      // backward: L^T x = y
       for (int64_t i = m0 - 1; i >= 0; --i) {
-        y[i] /= K0[(size_t)i * m0 + i];
-        const int64_t j0 = std::max<int64_t>(0, i - bw);
-        for (int64_t j = j0; j < i; ++j) y[j] -= K0[(size_t)i * m0 + j] * y[i];
+        const double *ci = &Lb[(size_t)(i * W)];
+        double *yi = &y[(size_t)(i * RB)];
+        const int64_t len = std::min(W, m0 - i);
+        for (int64_t k = 1; k < len; ++k) {
+          const double *yk = &y[(size_t)((i + k) * RB)];
+          const double l = ci[k];
+          for (int r = 0; r < RB; ++r) yi[r] -= l * yk[r];
+        }
+        for (int r = 0; r < RB; ++r) yi[r] /= ci[0];
       }
-      std::memcpy(&hf.coarse_inv[(size_t)col * m0], y.data(), (size_t)m0 * sizeof(double));
+      for (int64_t r = 0; r < nb; ++r)
+        for (int64_t i = 0; i < m0; ++i) hf.coarse_inv[(size_t)((c0 + r) * m0 + i)] = y[(size_t)(i * RB + r)];
     });
   }
   hf.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();

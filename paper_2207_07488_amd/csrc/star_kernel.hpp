@@ -338,8 +338,10 @@ __global__ __launch_bounds__(64) void k_star(StarArgs a, const double *__restric
 template <typename T, int KC>
 void launch_star_t(const StarArgs &a, bool wide, const double *r, const CgScalars *sc, int sel, hipStream_t s) {
   if (a.nstars <= 0) return;
-  if (wide) hipLaunchKernelGGL((k_star<T, true, KC>), dim3(a.nstars), dim3(64), 0, s, a, r, sc, sel);
-  else hipLaunchKernelGGL((k_star<T, false, KC>), dim3(a.nstars), dim3(64), 0, s, a, r, sc, sel);
+  // the kernel uses no LDS; a reservation only limits how many stars share a CU
+  const size_t lds = (size_t)a.lds_reserve;
+  if (wide) hipLaunchKernelGGL((k_star<T, true, KC>), dim3(a.nstars), dim3(64), lds, s, a, r, sc, sel);
+  else hipLaunchKernelGGL((k_star<T, false, KC>), dim3(a.nstars), dim3(64), lds, s, a, r, sc, sel);
 }
 
 }  // namespace spnet

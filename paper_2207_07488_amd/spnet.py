@@ -91,6 +91,7 @@ SIGNATURES = {
     "sn_solve": (C.c_int, [_P, C.c_int, _P, _P, C.POINTER(SolveOpts), C.POINTER(SolveInfo)]),
     "sn_precond_profile": (C.c_int, [_P, C.c_int]),
     "sn_precond_kernel_stats": (C.c_int, [_P, C.POINTER(KernelStats)]),
+    "sn_precond_engine_info": (C.c_int, [_P, C.c_int, C.POINTER(_i32), C.POINTER(_dbl)]),
     "sn_apply_K": (C.c_int, [_P, C.c_int, _P, _P, C.c_int, _P]),
     "sn_apply_B": (C.c_int, [_P, C.c_int, _P, _P, C.c_int, _P]),
     "sn_server_opts_default": (None, [C.POINTER(ServerOpts)]),
@@ -244,6 +245,12 @@ class Precond:
         fi = FactorInfo()
         _check(lib().sn_precond_factor_info(self.h, C.byref(fi)))
         return fi.asdict()
+
+    def engine_info(self, k=1):
+        """(star wavefronts per SIMD chosen for batches of k columns (0 = no limit), sweep us)."""
+        w, us = _i32(), _dbl()
+        _check(lib().sn_precond_engine_info(self.h, k, C.byref(w), C.byref(us)))
+        return w.value, us.value
 
     # ---------------------------------------------------------------- solves
     def _block(self, a):
