@@ -139,6 +139,42 @@ __device__ __forceinline__ void block_partials(const Vec<KC> &v, double *partial
   }
 }
 
+// the per-column totals of partials, as k_scalar forms them (same order), in
+// every thread of the block: lets a consumer kernel reduce redundantly in each
+// block instead of a one-block kernel in between
+template <int KC>
+__device__ __forceinline__ void block_totals(const double *__restrict__ partials, int nparts, const bool (&on)[KC],
+                                             double (&tot)[KC]) {
+  __shared__ double sh[kBlock / 64][KC];
+  __shared__ double res[KC];
+  Vec<KC> sum;
+  sum.zero();
+  for (int i = threadIdx.x; i < nparts; i += kBlock)
+#pragma unroll
+    for (int c = 0; c < KC; ++c)
+      if (on[c]) sum.v[c] += partials[c * kMaxGrid + i];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int c = 0; c < KC; ++c) {
+    const double v = wave_sum(sum.v[c]);
+    if (lane == 0) sh[w][c] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int c = 0; c < KC; ++c) {
+      double t = 0.0;
+      for (int i = 0; i < kBlock / 64; ++i) t += sh[i][c];
+      res[c] = t;
+    }
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < KC; ++c) tot[c] = res[c];
+}
+
+// few columns: alpha and beta are reduced inside the update kernels
+template <int KC>
+constexpr bool kFuseScalars = KC <= 2;
+
 template <int KC>
 __device__ __forceinline__ bool any_selected(const CgScalars *sc, int sel, uint32_t mask) {
   if (sel == SEL_ALL) return true;
@@ -186,7 +222,7 @@ __global__ __launch_bounds__(kBlock) void k_scalar(const double *__restrict__ pa
     switch (op) {
       case OP_ALPHA:
         x.pq = tot;
-        x.alpha = x.rho / tot;
+        x.alpha = cg_alpha(x, tot);
         break;
       case OP_CONV: {
         x.rr = tot;
@@ -201,9 +237,8 @@ __global__ __launch_bounds__(kBlock) void k_scalar(const double *__restrict__ pa
       }
       case OP_BETA:
         x.rz = tot;
-        x.beta = x.first ? 0.0 : tot / x.rho;
-        x.rho = tot;
-        x.first = 0;
+        x.beta = cg_beta(x, tot);
+        x.rho[x.iters & 1] = tot;
         x.fresh = 0;
         x.restart = 0;
         break;
@@ -232,7 +267,7 @@ __global__ __launch_bounds__(kBlock) void k_scalar(const double *__restrict__ pa
           x.replacements += 1;
           x.rr = tot;
           x.done = 0;
-          x.first = 1;
+          x.first_it = x.iters;
           x.fresh = 1;
           x.restart = 1;
         }
@@ -284,17 +319,35 @@ __global__ __launch_bounds__(kBlock) void k_spmv(Sell A, const double *__restric
   if (partials) block_partials<KC>(dot, partials);
 }
 
-// first-half columns: u += alpha p, r -= alpha q, r.r partials
+// first-half columns: u += alpha p, r -= alpha q, r.r partials (rr_parts);
+// with few columns alpha = rho / p.q is reduced here from the SpMV's partials
 template <int KC>
 __global__ __launch_bounds__(kBlock) void k_cg_update(double *u, double *r, const double *p, const double *q, int n,
-                                                      const CgScalars *sc, double *partials) {
-  if (!any_selected<KC>(sc, SEL_FIRST, 0u)) return;
+                                                      CgScalars *sc, const double *__restrict__ pq_parts, int nparts,
+                                                      double *rr_parts) {
   bool on[KC];
-  double a[KC];
+  bool any = false;
 #pragma unroll
   for (int c = 0; c < KC; ++c) {
     on[c] = column_selected(sc[c], SEL_FIRST, 0u, c);
-    a[c] = sc[c].alpha;
+    any |= on[c];
+  }
+  if (!any) return;
+  double a[KC];
+  if constexpr (kFuseScalars<KC>) {
+    double tot[KC];
+    block_totals<KC>(pq_parts, nparts, on, tot);
+#pragma unroll
+    for (int c = 0; c < KC; ++c) a[c] = on[c] ? cg_alpha(sc[c], tot[c]) : 0.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+      for (int c = 0; c < KC; ++c)
+        if (on[c]) {
+          sc[c].pq = tot[c];
+          sc[c].alpha = a[c];
+        }
+  } else {
+#pragma unroll
+    for (int c = 0; c < KC; ++c) a[c] = sc[c].alpha;
   }
   Vec<KC> rr;
   rr.zero();
@@ -314,7 +367,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(double *u, double *r, cons
     uv.store(u + (size_t)i * KC);
     rv.store(r + (size_t)i * KC);
   }
-  block_partials<KC>(rr, partials);
+  block_partials<KC>(rr, rr_parts);
 }
 
 // z = P c + sum of the star slots of every dof (ascending star order), r.z partials
@@ -360,16 +413,39 @@ __global__ __launch_bounds__(kBlock) void k_reduce(double *z, const double *r, c
   if (partials) block_partials<KC>(rz, partials);
 }
 
-// second-half columns: p = z + beta p
+// second-half columns: p = z + beta p; with few columns beta = r.z / rho is
+// reduced here from the accumulation's partials, and block 0 records the new
+// rho (in the other parity slot than the one the blocks read)
 template <int KC>
-__global__ __launch_bounds__(kBlock) void k_p_update(double *p, const double *z, int n, const CgScalars *sc) {
-  if (!any_selected<KC>(sc, SEL_SECOND, 0u)) return;
+__global__ __launch_bounds__(kBlock) void k_p_update(double *p, const double *z, int n, CgScalars *sc,
+                                                     const double *__restrict__ rz_parts, int nparts) {
   bool on[KC];
-  double b[KC];
+  bool any = false;
 #pragma unroll
   for (int c = 0; c < KC; ++c) {
     on[c] = column_selected(sc[c], SEL_SECOND, 0u, c);
-    b[c] = sc[c].beta;
+    any |= on[c];
+  }
+  if (!any) return;
+  double b[KC];
+  if constexpr (kFuseScalars<KC>) {
+    double tot[KC];
+    block_totals<KC>(rz_parts, nparts, on, tot);
+#pragma unroll
+    for (int c = 0; c < KC; ++c) b[c] = on[c] ? cg_beta(sc[c], tot[c]) : 0.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+      for (int c = 0; c < KC; ++c)
+        if (on[c]) {
+          CgScalars &x = sc[c];
+          x.rz = tot[c];
+          x.beta = b[c];
+          x.rho[x.iters & 1] = tot[c];
+          x.fresh = 0;
+          x.restart = 0;
+        }
+  } else {
+#pragma unroll
+    for (int c = 0; c < KC; ++c) b[c] = sc[c].beta;
   }
   for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
     Vec<KC> pv, zv;
@@ -644,7 +720,7 @@ struct Engine {
   Precond *pre = nullptr;
   DeviceState *d = nullptr;
   int kc = 1;
-  DBuf<double> u, r, p, q, z, f, rH, c, partials;
+  DBuf<double> u, r, p, q, z, f, rH, c, partials, partials2;
   DBuf<CgScalars> sc;
   DBuf<float> slots32;
   DBuf<double> slots64;
@@ -1127,7 +1203,7 @@ void launch_B(Engine &e, const double *r, double *z, int sel, bool dot, hipStrea
     else
       hipLaunchKernelGGL((k_reduce<double, KC>), dim3(G), dim3(kBlock), 0, s, z, r, e.slots64.p, d.slot_of.p, d.Pc.p,
                          d.Pw.p, e.c.p, (int)d.npad, d.nv, e.sc.p, sel, parts);
-    if (dot)
+    if (dot && !kFuseScalars<KC>)
       hipLaunchKernelGGL(k_scalar<KC>, dim3(1), dim3(kBlock), 0, s, e.partials.p, (int)G, e.sc.p, (int)OP_BETA, sel,
                          0u);
   });
@@ -1142,7 +1218,7 @@ void launch_spmv(Engine &e, const double *x, double *y, int sel, bool dot, hipSt
     constexpr int KC = decltype(K)::value;
     hipLaunchKernelGGL(k_spmv<KC>, dim3(G), dim3(kBlock), 0, s, A, x, y, (int)d.npad, e.sc.p, sel,
                        dot ? e.partials.p : nullptr);
-    if (dot)
+    if (dot && !kFuseScalars<KC>)
       hipLaunchKernelGGL(k_scalar<KC>, dim3(1), dim3(kBlock), 0, s, e.partials.p, (int)G, e.sc.p, (int)OP_ALPHA, sel,
                          0u);
   });
@@ -1156,14 +1232,15 @@ void launch_iteration(Engine &e, hipStream_t s) {
   with_kc(e.kc, [&](auto K) {
     constexpr int KC = decltype(K)::value;
     hipLaunchKernelGGL(k_cg_update<KC>, dim3(G), dim3(kBlock), 0, s, e.u.p, e.r.p, e.p.p, e.q.p, (int)d.npad, e.sc.p,
-                       e.partials.p);
-    hipLaunchKernelGGL(k_scalar<KC>, dim3(1), dim3(kBlock), 0, s, e.partials.p, (int)G, e.sc.p, (int)OP_CONV,
+                       e.partials.p, (int)G, e.partials2.p);
+    hipLaunchKernelGGL(k_scalar<KC>, dim3(1), dim3(kBlock), 0, s, e.partials2.p, (int)G, e.sc.p, (int)OP_CONV,
                        (int)SEL_FIRST, 0u);
   });
   launch_B(e, e.r.p, e.z.p, SEL_SECOND, true, s);
   with_kc(e.kc, [&](auto K) {
     constexpr int KC = decltype(K)::value;
-    hipLaunchKernelGGL(k_p_update<KC>, dim3(G), dim3(kBlock), 0, s, e.p.p, e.z.p, (int)d.npad, e.sc.p);
+    hipLaunchKernelGGL(k_p_update<KC>, dim3(G), dim3(kBlock), 0, s, e.p.p, e.z.p, (int)d.npad, e.sc.p, e.partials.p,
+                       (int)G);
   });
 }
 
@@ -1255,7 +1332,7 @@ CgScalars column_init(double rtol, int64_t max_iter, int64_t fixed) {
   x.max_iter = (int32_t)std::min<int64_t>(max_iter > 0 ? max_iter : 1000, 1 << 30);
   x.fixed = (int32_t)std::max<int64_t>(std::min<int64_t>(fixed, 1 << 30), 0);
   x.active = 1;
-  x.first = 1;
+  x.first_it = 0;
   x.fresh = 1;
   return x;
 }
@@ -1378,7 +1455,7 @@ int64_t engine_footprint(const Precond &pre, int kc) {
   const int64_t m0 = std::max<int64_t>(pre.m0, 1);
   const int prec = pre.dev ? pre.finfo.star_precision : pre.precision;
   const int64_t ts = prec == SN_PREC_FP32_STARS ? 4 : 8;
-  return (6 * npad * kc + 2 * m0 * kc + (int64_t)kc * kMaxGrid) * 8 + kc * (int64_t)sizeof(CgScalars) +
+  return (6 * npad * kc + 2 * m0 * kc + (int64_t)2 * kc * kMaxGrid) * 8 + kc * (int64_t)sizeof(CgScalars) +
          (int64_t)pre.star_dofs.size() * kc * ts;
 }
 
@@ -1403,6 +1480,8 @@ Engine *engine_create(Precond &pre, int kc) {
   e->c.zero();
   e->partials.alloc((size_t)kc * kMaxGrid);
   e->partials.zero();
+  e->partials2.alloc((size_t)kc * kMaxGrid);
+  e->partials2.zero();
   e->sc.alloc((size_t)kc);
   e->sc.zero();
   if (d.precision == SN_PREC_FP32_STARS) {
@@ -1423,7 +1502,7 @@ Engine *engine_create(Precond &pre, int kc) {
   HIPCHK(hipEventCreateWithFlags(&e->join2, hipEventDisableTiming));
   HIPCHK(hipEventCreateWithFlags(&e->tick_done, hipEventDisableTiming));
   HIPCHK(hipDeviceSynchronize());
-  e->bytes = (int64_t)(6 * np * 8 + 2 * nm * 8 + e->partials.bytes() + e->sc.bytes() + e->slots32.bytes() +
+  e->bytes = (int64_t)(6 * np * 8 + 2 * nm * 8 + 2 * e->partials.bytes() + e->sc.bytes() + e->slots32.bytes() +
                        e->slots64.bytes());
   tune_stars(*e);
   return e.release();

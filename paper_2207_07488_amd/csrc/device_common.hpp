@@ -29,11 +29,21 @@ namespace spnet {
 //   verify  stopped, its true residual f - K u is still to be checked
 //   restart the check asked for a restart from the true residual
 // ---------------------------------------------------------------------------
+// rho = r.z is kept twice, by the parity of the iteration count: the kernel
+// that computes a new rho (every block redundantly) stores it in
+// rho[iters & 1] while its blocks still read the previous one from the other
+// slot. first_it: the iteration count at which the recurrence (re)starts
+// (beta = 0 there).
 struct CgScalars {
-  double rho, alpha, beta, rr, f2, tol2, t2, rtol;
-  double tmp, pq, rz, pad0;
-  int32_t iters, done, max_iter, fixed, first, fresh, verify, restart, replacements, active, pad1, pad2;
+  double rho[2], alpha, beta, rr, f2, tol2, t2, rtol;
+  double tmp, pq, rz;
+  int32_t iters, done, max_iter, fixed, first_it, fresh, verify, restart, replacements, active, pad1, pad2;
 };
+
+__device__ __forceinline__ double cg_alpha(const CgScalars &x, double pq) { return x.rho[x.iters & 1] / pq; }
+__device__ __forceinline__ double cg_beta(const CgScalars &x, double rz) {
+  return x.first_it == x.iters ? 0.0 : rz / x.rho[(x.iters & 1) ^ 1];
+}
 
 // which columns a kernel works on
 enum ColumnSel : int32_t {
