@@ -240,9 +240,7 @@ def main():
 
     roof_m, roof_p = roof(fim, rm_prof["stats"]), roof(fip, rp_prof["stats"])
     for rf, pre in ((roof_m, mixed), (roof_p, plain)):
-        cap, us = pre.engine_info(1)
-        rf["star_waves_per_simd_limit"] = cap
-        rf["tuned_sweep_us"] = round(us, 2)
+        rf["tuning"] = pre.engine_info(1)
     traffic = None
     if os.path.exists(args.traffic):
         try:

@@ -230,13 +230,19 @@ sn_status sn_precond_profile(sn_precond pre, int enable);
 sn_status sn_precond_kernel_stats(sn_precond pre, sn_kernel_stats *stats);
 
 /*
- * Occupancy of the star sweeps chosen for batches of k columns: when the
- * preconditioner first solves with a batch width, every candidate limit of
- * resident star wavefronts per SIMD (none, 4, 3, 2, 1) is timed on the device
- * and the fastest kept. Returns that limit (0 = none) and its sweep time
- * (microseconds per application of B, all stars).
+ * Launch shape chosen for batches of k columns (measured on the device when
+ * the preconditioner first solves with that batch width):
+ *   star_waves_per_simd  limit of resident star wavefronts per SIMD: every
+ *                        candidate (none, 4, 3, 2, 1) is timed and the
+ *                        fastest kept (0 = no limit);
+ *   star_sweep_us        its sweep time, microseconds per application of B;
+ *   coarse_first         1: the coarse solve runs before the sweeps, 0: beside
+ *                        them on a second stream (whichever applies B faster);
+ *   b_apply_us           the time of one application of B in that order.
+ * Any output pointer may be NULL.
  */
-sn_status sn_precond_engine_info(sn_precond pre, int k, int32_t *star_waves_per_simd, double *star_sweep_us);
+sn_status sn_precond_engine_info(sn_precond pre, int k, int32_t *star_waves_per_simd, double *star_sweep_us,
+                                 int32_t *coarse_first, double *b_apply_us);
 
 /* y = K x for k columns (n x k row-major). */
 sn_status sn_apply_K(sn_precond pre, int k, const double *x, double *y, int device_ptrs, void *stream);

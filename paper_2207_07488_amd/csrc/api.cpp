@@ -230,11 +230,12 @@ sn_status sn_precond_kernel_stats(sn_precond pre, sn_kernel_stats *stats) {
   });
 }
 
-sn_status sn_precond_engine_info(sn_precond pre, int k, int32_t *star_waves_per_simd, double *star_sweep_us) {
+sn_status sn_precond_engine_info(sn_precond pre, int k, int32_t *star_waves_per_simd, double *star_sweep_us,
+                                 int32_t *coarse_first, double *b_apply_us) {
   return guarded([&] {
     REQUIRE(pre && pre->p->dev, "null argument or not factored");
     REQUIRE(k >= 1 && k <= 16, "k must be in 1..16");
-    spnet::device_engine_info(*pre->p, k, star_waves_per_simd, star_sweep_us);
+    spnet::device_engine_info(*pre->p, k, star_waves_per_simd, star_sweep_us, coarse_first, b_apply_us);
   });
 }
 

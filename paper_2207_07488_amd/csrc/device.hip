@@ -149,10 +149,14 @@ __device__ __forceinline__ void block_totals(const double *__restrict__ partials
   __shared__ double res[KC];
   Vec<KC> sum;
   sum.zero();
-  for (int i = threadIdx.x; i < nparts; i += kBlock)
+  for (int i = threadIdx.x; i < nparts; i += kBlock) {
+    double v[KC];
 #pragma unroll
-    for (int c = 0; c < KC; ++c)
-      if (on[c]) sum.v[c] += partials[c * kMaxGrid + i];
+    for (int c = 0; c < KC; ++c) v[c] = partials[c * kMaxGrid + i];
+#pragma unroll
+    for (int c = 0; c < KC; ++c) sum.v[c] += v[c];
+  }
+  (void)on;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
   for (int c = 0; c < KC; ++c) {
@@ -200,12 +204,17 @@ __global__ __launch_bounds__(kBlock) void k_scalar(const double *__restrict__ pa
     any |= on[c];
   }
   if (!any) return;
+  // every column is loaded (the sums of unselected ones are not used), so that
+  // all loads of a thread are in flight together
   Vec<KC> sum;
   sum.zero();
-  for (int i = threadIdx.x; i < nparts; i += kBlock)
+  for (int i = threadIdx.x; i < nparts; i += kBlock) {
+    double v[KC];
 #pragma unroll
-    for (int c = 0; c < KC; ++c)
-      if (on[c]) sum.v[c] += partials[c * kMaxGrid + i];
+    for (int c = 0; c < KC; ++c) v[c] = partials[c * kMaxGrid + i];
+#pragma unroll
+    for (int c = 0; c < KC; ++c) sum.v[c] += v[c];
+  }
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
   for (int c = 0; c < KC; ++c) {
@@ -459,23 +468,38 @@ __global__ __launch_bounds__(kBlock) void k_p_update(double *p, const double *z,
 }
 
 // r_H = P^T r: one wavefront per coarse dof (four per block); lane l sums the
-// entries l, l+64, ... of the dof's list, then a fixed wavefront tree
+// entries l, l+64, ... of the dof's list, then a fixed wavefront tree. The
+// entries of a lane are fetched U at a time (indices, then the gathers), so
+// that the dependent loads overlap.
 template <int KC>
 __global__ __launch_bounds__(kBlock) void k_restrict(const int32_t *__restrict__ ptr, const int32_t *__restrict__ dof,
                                                      const double *__restrict__ w, const double *__restrict__ r,
                                                      double *rH, int m0, const CgScalars *sc, int sel) {
+  constexpr int U = KC <= 2 ? 8 : 4;
   if (!any_selected<KC>(sc, sel, 0u)) return;
   const int g = (blockIdx.x * kBlock + threadIdx.x) >> 6, lane = threadIdx.x & 63;
   if (g >= m0) return;
   Vec<KC> acc;
   acc.zero();
-  const int q1 = ptr[g + 1];
-  for (int q = ptr[g] + lane; q < q1; q += 64) {
-    const double wq = w[q];
-    Vec<KC> rv;
-    rv.load(r + (size_t)dof[q] * KC);
+  const int q0 = ptr[g], q1 = ptr[g + 1];
+  for (int qb = q0 + lane; qb < q1; qb += 64 * U) {
+    int idx[U];
+    double wq[U];
 #pragma unroll
-    for (int k = 0; k < KC; ++k) acc.v[k] = __builtin_fma(wq, rv.v[k], acc.v[k]);
+    for (int u = 0; u < U; ++u) {
+      const int q = qb + 64 * u;
+      idx[u] = q < q1 ? dof[q] : 0;
+      wq[u] = q < q1 ? w[q] : 0.0;
+    }
+    Vec<KC> rv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) rv[u].load(r + (size_t)idx[u] * KC);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (qb + 64 * u >= q1) break;
+#pragma unroll
+      for (int k = 0; k < KC; ++k) acc.v[k] = __builtin_fma(wq[u], rv[u].v[k], acc.v[k]);
+    }
   }
   Vec<KC> out;
 #pragma unroll
@@ -486,13 +510,14 @@ __global__ __launch_bounds__(kBlock) void k_restrict(const int32_t *__restrict__
 // c = K_0^{-1} r_H. A wavefront computes RW rows; lane l takes the columns
 // 2l, 2l+1 of every 128-column chunk (16-byte loads of the row), in chunk
 // order, then a fixed wavefront tree: the same order for every column count.
-// With several columns the chunk of r_H is staged in LDS once per block and
-// shared by its 4 RW rows.
+// With one column, UC chunks are loaded before they are used; with several,
+// each chunk of r_H is staged in LDS once per block and shared by its 4 RW rows.
 template <int KC>
 __global__ __launch_bounds__(kBlock) void k_coarse_gemv(const double *__restrict__ Kinv, const double *__restrict__ rH,
                                                         double *cvec, int m0, const CgScalars *sc, int sel) {
   constexpr int RW = KC >= 4 ? 4 : 1;  // rows per wavefront
   constexpr int CH = 128;              // columns per chunk
+  constexpr int UC = KC == 1 ? 8 : 1;  // chunks in flight
   __shared__ double xs[KC > 1 ? CH * KC : 1];
   if (!any_selected<KC>(sc, sel, 0u)) return;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -500,50 +525,69 @@ __global__ __launch_bounds__(kBlock) void k_coarse_gemv(const double *__restrict
   Vec<KC> acc[RW];
 #pragma unroll
   for (int i = 0; i < RW; ++i) acc[i].zero();
-  for (int j0 = 0; j0 < m0; j0 += CH) {
-    if constexpr (KC > 1) {
+  auto load_a = [&](const double *a, int ja, double &a0, double &a1) {
+    a0 = 0.0;
+    a1 = 0.0;
+    if (ja + 1 < m0) {
+      if ((m0 & 1) == 0) {
+        const double2 t = *reinterpret_cast<const double2 *>(a + ja);
+        a0 = t.x;
+        a1 = t.y;
+      } else {
+        a0 = a[ja];
+        a1 = a[ja + 1];
+      }
+    } else if (ja < m0) {
+      a0 = a[ja];
+    }
+  };
+  if constexpr (KC == 1) {
+    const int row = row0;
+    if (row < m0) {
+      const double *a = Kinv + (size_t)row * m0;
+      for (int j0 = 0; j0 < m0; j0 += CH * UC) {
+        double a0[UC], a1[UC], x0[UC], x1[UC];
+#pragma unroll
+        for (int u = 0; u < UC; ++u) {
+          const int ja = j0 + CH * u + 2 * lane;
+          load_a(a, ja, a0[u], a1[u]);
+          x0[u] = ja < m0 ? rH[ja] : 0.0;
+          x1[u] = ja + 1 < m0 ? rH[ja + 1] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < UC; ++u) {
+          acc[0].v[0] = __builtin_fma(a0[u], x0[u], acc[0].v[0]);
+          acc[0].v[0] = __builtin_fma(a1[u], x1[u], acc[0].v[0]);
+        }
+      }
+    }
+  } else {
+    // xs[k][j]: lane l reads the pair (2l, 2l+1) of every column k, so that
+    // consecutive lanes read consecutive LDS words
+    for (int j0 = 0; j0 < m0; j0 += CH) {
       __syncthreads();
       for (int t = threadIdx.x; t < CH * KC; t += kBlock) {
-        const int j = j0 + t / KC;
-        xs[t] = j < m0 ? rH[(size_t)j0 * KC + t] : 0.0;
+        const int j = t / KC, k = t % KC;
+        xs[k * CH + j] = j0 + j < m0 ? rH[(size_t)j0 * KC + t] : 0.0;
       }
       __syncthreads();
-    }
-    const int ja = j0 + 2 * lane;
+      const int ja = j0 + 2 * lane;
+      double2 xp[KC];
 #pragma unroll
-    for (int i = 0; i < RW; ++i) {
-      const int row = row0 + i;
-      if (row >= m0) break;
-      const double *a = Kinv + (size_t)row * m0;
-      double a0 = 0.0, a1 = 0.0;
-      if (ja + 1 < m0) {
-        if ((m0 & 1) == 0) {
-          const double2 t = *reinterpret_cast<const double2 *>(a + ja);
-          a0 = t.x;
-          a1 = t.y;
-        } else {
-          a0 = a[ja];
-          a1 = a[ja + 1];
-        }
-      } else if (ja < m0) {
-        a0 = a[ja];
+      for (int k = 0; k < KC; ++k) xp[k] = *reinterpret_cast<const double2 *>(&xs[k * CH + 2 * lane]);
+      double a0[RW], a1[RW];
+#pragma unroll
+      for (int i = 0; i < RW; ++i) {
+        const int row = row0 + i < m0 ? row0 + i : m0 - 1;
+        load_a(Kinv + (size_t)row * m0, ja, a0[i], a1[i]);
       }
-      Vec<KC> x0, x1;
-      if constexpr (KC > 1) {
+#pragma unroll
+      for (int i = 0; i < RW; ++i)
 #pragma unroll
         for (int k = 0; k < KC; ++k) {
-          x0.v[k] = xs[(2 * lane) * KC + k];
-          x1.v[k] = xs[(2 * lane + 1) * KC + k];
+          acc[i].v[k] = __builtin_fma(a0[i], xp[k].x, acc[i].v[k]);
+          acc[i].v[k] = __builtin_fma(a1[i], xp[k].y, acc[i].v[k]);
         }
-      } else {
-        x0.v[0] = ja < m0 ? rH[ja] : 0.0;
-        x1.v[0] = ja + 1 < m0 ? rH[ja + 1] : 0.0;
-      }
-#pragma unroll
-      for (int k = 0; k < KC; ++k) {
-        acc[i].v[k] = __builtin_fma(a0, x0.v[k], acc[i].v[k]);
-        acc[i].v[k] = __builtin_fma(a1, x1.v[k], acc[i].v[k]);
-      }
     }
   }
 #pragma unroll
@@ -729,6 +773,8 @@ struct Engine {
   // and the LDS reservation that enforces it
   int32_t star_cap = 0, star_lds = 0;
   double star_us = 0.0;
+  bool coarse_first = false;  // coarse solve before the sweeps rather than beside them
+  double b_us = 0.0;
   bool sc_dirty = false;         // host_sc changed since the last upload
   hipStream_t own = nullptr;     // the engine's stream (and graph capture)
   hipStream_t aux = nullptr;     // wide stars run beside the narrow ones
@@ -1175,24 +1221,33 @@ void launch_stars(Engine &e, const double *r, int sel, hipStream_t s) {
 // z = B r on the selected columns; with dot, r.z -> rho, beta (second half)
 void launch_B(Engine &e, const double *r, double *z, int sel, bool dot, hipStream_t s) {
   DeviceState &d = *e.d;
-  if (d.m0 > 0) {
+  auto coarse = [&](hipStream_t cs) {
+    with_kc(e.kc, [&](auto K) {
+      constexpr int KC = decltype(K)::value;
+      hipLaunchKernelGGL(k_restrict<KC>, dim3(nblk(d.m0 * 64)), dim3(kBlock), 0, cs, d.PTptr.p, d.PTdof.p, d.PTw.p,
+                         r, e.rH.p, (int)d.m0, e.sc.p, sel);
+      constexpr int RW = KC >= 4 ? 4 : 1;
+      const unsigned gb = (unsigned)((d.m0 + 4 * RW - 1) / (4 * RW));
+      hipLaunchKernelGGL(k_coarse_gemv<KC>, dim3(gb), dim3(kBlock), 0, cs, d.Kinv.p, e.rH.p, e.c.p, (int)d.m0,
+                         e.sc.p, sel);
+    });
+  };
+  if (d.m0 > 0 && e.coarse_first) {
+    // the coarse solve first, on the whole device, then the star sweeps
+    coarse(s);
+    launch_stars(e, r, sel, s);
+  } else if (d.m0 > 0) {
     // the coarse solve is independent of the local solves (the preconditioner
     // is additive): it runs on its own stream beside the star sweeps
     HIPCHK(hipEventRecord(e.fork2, s));
     HIPCHK(hipStreamWaitEvent(e.aux2, e.fork2, 0));
-    with_kc(e.kc, [&](auto K) {
-      constexpr int KC = decltype(K)::value;
-      hipLaunchKernelGGL(k_restrict<KC>, dim3(nblk(d.m0 * 64)), dim3(kBlock), 0, e.aux2, d.PTptr.p, d.PTdof.p,
-                         d.PTw.p, r, e.rH.p, (int)d.m0, e.sc.p, sel);
-      constexpr int RW = KC >= 4 ? 4 : 1;
-      const unsigned gb = (unsigned)((d.m0 + 4 * RW - 1) / (4 * RW));
-      hipLaunchKernelGGL(k_coarse_gemv<KC>, dim3(gb), dim3(kBlock), 0, e.aux2, d.Kinv.p, e.rH.p, e.c.p, (int)d.m0,
-                         e.sc.p, sel);
-    });
+    coarse(e.aux2);
     HIPCHK(hipEventRecord(e.join2, e.aux2));
+    launch_stars(e, r, sel, s);
+    HIPCHK(hipStreamWaitEvent(s, e.join2, 0));
+  } else {
+    launch_stars(e, r, sel, s);
   }
-  launch_stars(e, r, sel, s);
-  if (d.m0 > 0) HIPCHK(hipStreamWaitEvent(s, e.join2, 0));
   with_kc(e.kc, [&](auto K) {
     constexpr int KC = decltype(K)::value;
     const unsigned G = grid_for(d.npad);
@@ -1430,11 +1485,28 @@ void tune_stars(Engine &e) {
       best_cap = cap;
     }
   }
-  (void)hipEventDestroy(t0);
-  (void)hipEventDestroy(t1);
   e.star_cap = best_cap;
   e.star_lds = best_cap == 0 ? 0 : (160 * 1024 / (4 * best_cap)) & ~511;
   e.star_us = best;
+  // the coarse solve beside the sweeps (sharing the device) or before them
+  if (d.m0 > 0) {
+    double tb[2] = {0.0, 0.0};
+    for (int order = 0; order < 2; ++order) {
+      e.coarse_first = order == 1;
+      for (int w = 0; w < 2; ++w) launch_B(e, e.r.p, e.z.p, SEL_ALL, false, e.own);
+      HIPCHK(hipEventRecord(t0, e.own));
+      for (int it = 0; it < 3; ++it) launch_B(e, e.r.p, e.z.p, SEL_ALL, false, e.own);
+      HIPCHK(hipEventRecord(t1, e.own));
+      HIPCHK(hipEventSynchronize(t1));
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, t0, t1));
+      tb[order] = 1e3 * ms / 3.0;
+    }
+    e.coarse_first = tb[1] < 0.98 * tb[0];
+    e.b_us = std::min(tb[0], tb[1]);
+  }
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
   d.profiling = prof;
 }
 
@@ -1610,10 +1682,13 @@ void device_stats(Precond &pre, sn_kernel_stats *st) {
 
 int64_t device_bytes(const Precond &pre) { return pre.dev ? pre.dev->bytes : 0; }
 
-void device_engine_info(Precond &pre, int k, int32_t *waves_per_simd, double *sweep_us) {
+void device_engine_info(Precond &pre, int k, int32_t *waves_per_simd, double *sweep_us, int32_t *coarse_first,
+                        double *b_us) {
   Engine &e = solve_engine(pre, k);
   if (waves_per_simd) *waves_per_simd = e.star_cap;
   if (sweep_us) *sweep_us = e.star_us;
+  if (coarse_first) *coarse_first = e.coarse_first ? 1 : 0;
+  if (b_us) *b_us = e.b_us;
 }
 
 void device_apply_K(Precond &pre, int k, const double *x, double *y, int device_ptrs, void *stream) {

@@ -108,7 +108,8 @@ void device_release(DeviceState *d);
 void device_profile(Precond &pre, int enable);
 void device_stats(Precond &pre, sn_kernel_stats *st);
 int64_t device_bytes(const Precond &pre);
-void device_engine_info(Precond &pre, int k, int32_t *waves_per_simd, double *sweep_us);
+void device_engine_info(Precond &pre, int k, int32_t *waves_per_simd, double *sweep_us, int32_t *coarse_first,
+                        double *b_us);
 
 // ---------------------------------------------------------------------------
 // Engine: the device workspace of kc PCG columns (independent recurrences, one

@@ -91,7 +91,8 @@ SIGNATURES = {
     "sn_solve": (C.c_int, [_P, C.c_int, _P, _P, C.POINTER(SolveOpts), C.POINTER(SolveInfo)]),
     "sn_precond_profile": (C.c_int, [_P, C.c_int]),
     "sn_precond_kernel_stats": (C.c_int, [_P, C.POINTER(KernelStats)]),
-    "sn_precond_engine_info": (C.c_int, [_P, C.c_int, C.POINTER(_i32), C.POINTER(_dbl)]),
+    "sn_precond_engine_info": (C.c_int, [_P, C.c_int, C.POINTER(_i32), C.POINTER(_dbl), C.POINTER(_i32),
+                                         C.POINTER(_dbl)]),
     "sn_apply_K": (C.c_int, [_P, C.c_int, _P, _P, C.c_int, _P]),
     "sn_apply_B": (C.c_int, [_P, C.c_int, _P, _P, C.c_int, _P]),
     "sn_server_opts_default": (None, [C.POINTER(ServerOpts)]),
@@ -247,10 +248,13 @@ class Precond:
         return fi.asdict()
 
     def engine_info(self, k=1):
-        """(star wavefronts per SIMD chosen for batches of k columns (0 = no limit), sweep us)."""
-        w, us = _i32(), _dbl()
-        _check(lib().sn_precond_engine_info(self.h, k, C.byref(w), C.byref(us)))
-        return w.value, us.value
+        """Launch shape measured for batches of k columns: dict with the star
+        wavefronts per SIMD limit (0 = none), the sweep time, whether the coarse
+        solve runs before the sweeps, and the time of one application of B."""
+        w, us, cf, bus = _i32(), _dbl(), _i32(), _dbl()
+        _check(lib().sn_precond_engine_info(self.h, k, C.byref(w), C.byref(us), C.byref(cf), C.byref(bus)))
+        return {"star_waves_per_simd_limit": w.value, "sweep_us": round(us.value, 2),
+                "coarse_first": bool(cf.value), "b_apply_us": round(bus.value, 2)}
 
     # ---------------------------------------------------------------- solves
     def _block(self, a):
