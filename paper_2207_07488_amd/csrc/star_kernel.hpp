@@ -46,6 +46,23 @@ struct Pack<float> {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), L));
   }
   static __device__ __forceinline__ float fnma(float m, float g, float x) { return __builtin_fmaf(-m, g, x); }
+  // per-lane selects at a step: lanes whose bit is set in `up` (an SGPR pair)
+  // take `hi`, the others `lo`
+  static __device__ __forceinline__ float pick(float hi, float lo, uint64_t up) {
+    float r;
+    asm("v_cndmask_b32_e64 %0, %1, %2, %3" : "=v"(r) : "v"(lo), "v"(hi), "s"(up));
+    return r;
+  }
+  static __device__ __forceinline__ float pick_or_zero(float hi, uint64_t up) {
+    float r;
+    asm("v_cndmask_b32_e64 %0, 0, %1, %2" : "=v"(r) : "v"(hi), "s"(up));
+    return r;
+  }
+  static __device__ __forceinline__ float zero_or_pick(float lo, uint64_t up) {
+    float r;
+    asm("v_cndmask_b32_e64 %0, %1, 0, %2" : "=v"(r) : "v"(lo), "s"(up));
+    return r;
+  }
 };
 template <>
 struct Pack<double> {
@@ -62,6 +79,32 @@ struct Pack<double> {
     return mk(__builtin_amdgcn_readlane(lo(v), L), __builtin_amdgcn_readlane(hi(v), L));
   }
   static __device__ __forceinline__ double fnma(double m, double g, double x) { return __builtin_fma(-m, g, x); }
+  // per-lane selects at a step: lanes whose bit is set in `up` take `hi`
+  // (both 32-bit halves selected with the same SGPR-pair mask)
+  static __device__ __forceinline__ int sel32(int hi, int lo, uint64_t up) {
+    int r;
+    asm("v_cndmask_b32_e64 %0, %1, %2, %3" : "=v"(r) : "v"(lo), "v"(hi), "s"(up));
+    return r;
+  }
+  static __device__ __forceinline__ int sel32_or_zero(int hi, uint64_t up) {
+    int r;
+    asm("v_cndmask_b32_e64 %0, 0, %1, %2" : "=v"(r) : "v"(hi), "s"(up));
+    return r;
+  }
+  static __device__ __forceinline__ int zero_or_sel32(int lo, uint64_t up) {
+    int r;
+    asm("v_cndmask_b32_e64 %0, %1, 0, %2" : "=v"(r) : "v"(lo), "s"(up));
+    return r;
+  }
+  static __device__ __forceinline__ double pick(double hi, double lo, uint64_t up) {
+    return mk(sel32(Pack::lo(hi), Pack::lo(lo), up), sel32(Pack::hi(hi), Pack::hi(lo), up));
+  }
+  static __device__ __forceinline__ double pick_or_zero(double hi, uint64_t up) {
+    return mk(sel32_or_zero(lo(hi), up), sel32_or_zero(Pack::hi(hi), up));
+  }
+  static __device__ __forceinline__ double zero_or_pick(double lo_v, uint64_t up) {
+    return mk(zero_or_sel32(lo(lo_v), up), zero_or_sel32(hi(lo_v), up));
+  }
 };
 
 template <int S, int E>
@@ -198,24 +241,25 @@ __device__ __forceinline__ void sweep(T *sl, int c0, int n, const uint16_t *__re
       const T hinvN = jb + 64 + lane < n ? inv[jb + 64 + lane] : T(0);
       T incN[CW];
       load_row(jb + 64 * (Q + 2) + lane, incN);
-      // an opaque copy of the lane id per block keeps the per-step lane
-      // comparisons inside the loop
-      int lid = lane;
-      asm volatile("; lane id %0" : "+v"(lid));
+      // lanes whose R[0] row is still open: bits s+1..63 at step s. The mask
+      // is shifted once per step from an opaque start, so that the compiler
+      // neither compares lane ids per step nor keeps 64 constant masks
+      uint64_t up = ~1ull;
+      asm volatile("; lane mask %0" : "+s"(up));
       StaticFor<0, 64>::run([&](auto sc) {
         constexpr int s = decltype(sc)::value;
         constexpr int gi = s / SG, k = s % SG;
         constexpr int slot = (H * GPB + gi) % RG;
         const V(&cur)[Q] = ring[slot];
-        const bool up = lid > s;  // lanes whose R[0] row is still open
         T g[CW];
 #pragma unroll
         for (int c = 0; c < CW; ++c) g[c] = P::template lane<s>(R[0][c]);
         T M[Q + 1];
-        M[0] = up ? P::get(cur[0], k) : T(0);
+        M[0] = P::pick_or_zero(P::get(cur[0], k), up);
 #pragma unroll
-        for (int q = 1; q < Q; ++q) M[q] = up ? P::get(cur[q], k) : P::get(cur[q - 1], k);
-        M[Q] = up ? T(0) : P::get(cur[Q - 1], k);
+        for (int q = 1; q < Q; ++q) M[q] = P::pick(P::get(cur[q], k), P::get(cur[q - 1], k), up);
+        M[Q] = P::zero_or_pick(P::get(cur[Q - 1], k), up);
+        up <<= 1;
 #pragma unroll
         for (int q = 0; q <= Q; ++q)
 #pragma unroll
