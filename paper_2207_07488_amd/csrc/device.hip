@@ -662,13 +662,15 @@ __global__ __launch_bounds__(kBlock) void k_copy_sel(double *dst, const double *
   }
 }
 
-// Start column `col` from column j of the n x k block `src`: f = r = src,
-// u = p = 0 (rows n..npad-1 zero).
+// Start column `col` from column j of the n x k block `src` (canonical dof
+// order; perm maps internal to canonical): f = r = src, u = p = 0 (rows
+// n..npad-1 zero).
 template <int KC>
 __global__ __launch_bounds__(kBlock) void k_admit(double *f, double *r, double *u, double *p, const double *src,
-                                                  int n, int npad, int k, int j, int col) {
+                                                  const int32_t *__restrict__ perm, int n, int npad, int k, int j,
+                                                  int col) {
   for (int i = blockIdx.x * kBlock + threadIdx.x; i < npad; i += gridDim.x * kBlock) {
-    const double v = i < n ? src[(size_t)i * k + j] : 0.0;
+    const double v = i < n ? src[(size_t)perm[i] * k + j] : 0.0;
     const size_t o = (size_t)i * KC + col;
     f[o] = v;
     r[o] = v;
@@ -677,17 +679,19 @@ __global__ __launch_bounds__(kBlock) void k_admit(double *f, double *r, double *
   }
 }
 
-// column col of a batch vector <-> column j of an n x k block
+// column col of a batch vector (internal order) <-> column j of an n x k
+// block (canonical order)
 template <int KC>
-__global__ __launch_bounds__(kBlock) void k_col_in(double *dst, const double *src, int n, int npad, int k, int j,
-                                                   int col) {
+__global__ __launch_bounds__(kBlock) void k_col_in(double *dst, const double *src, const int32_t *__restrict__ perm,
+                                                   int n, int npad, int k, int j, int col) {
   for (int i = blockIdx.x * kBlock + threadIdx.x; i < npad; i += gridDim.x * kBlock)
-    dst[(size_t)i * KC + col] = i < n ? src[(size_t)i * k + j] : 0.0;
+    dst[(size_t)i * KC + col] = i < n ? src[(size_t)perm[i] * k + j] : 0.0;
 }
 template <int KC>
-__global__ __launch_bounds__(kBlock) void k_col_out(double *dst, const double *src, int n, int k, int j, int col) {
+__global__ __launch_bounds__(kBlock) void k_col_out(double *dst, const double *src, const int32_t *__restrict__ perm,
+                                                    int n, int k, int j, int col) {
   for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock)
-    dst[(size_t)i * k + j] = src[(size_t)i * KC + col];
+    dst[(size_t)perm[i] * k + j] = src[(size_t)i * KC + col];
 }
 
 // ---------------------------------------------------------------------------
@@ -747,6 +751,10 @@ struct DeviceState {
   // coarse
   DBuf<double> Kinv, PTw, Pw;
   DBuf<int32_t> PTptr, PTdof, Pc;
+  // internal dof order: free nodes grouped by coarse element (gather
+  // locality); perm[internal] = canonical dof, iperm the inverse
+  DBuf<int32_t> perm;
+  std::vector<int32_t> perm_h, iperm_h;
   int64_t bytes = 0;
   // engines of sn_solve / sn_apply_*, one per width
   std::unique_ptr<Engine> solve_engine[5];
@@ -899,7 +907,7 @@ void upload_stars(DeviceState &d, const Precond &pre, const HostFactors &hf, sn_
     if (f_hdr.size() != b_hdr.size()) fail(SN_EINVAL, "internal: header arrays out of step");
     const int32_t *dofs = &pre.star_dofs[pre.star_ptr[s]];
     for (int p = 0; p < F.n; ++p) {
-      pos_dof.push_back(dofs[F.perm[p]]);
+      pos_dof.push_back(d.iperm_h[dofs[F.perm[p]]]);
       f_inv.push_back((T)finv[p]);
       b_inv.push_back((T)binv[p]);
     }
@@ -995,6 +1003,39 @@ void device_setup(Precond &pre, const HostFactors &hf, int precision) {
   if (n >= (int64_t)1 << 30) fail(SN_EINVAL, "system too large for 32-bit indices");
   sn_factor_info fi{};
 
+  // internal order: free nodes sorted by the mesh element that holds them
+  // (lexicographic), then by index; the components of a node stay together.
+  // Rows, star gathers and the slot accumulation then touch nearby memory.
+  {
+    const Network &net = *sys.net;
+    const int dim = net.dim, nc = sys.ncomp;
+    const int64_t nf = (int64_t)sys.free_node.size();
+    std::vector<int64_t> cell((size_t)nf);
+    for (int64_t f = 0; f < nf; ++f) {
+      const double *x = &net.x[(size_t)sys.free_node[f] * dim];
+      int64_t c = 0;
+      for (int k = dim - 1; k >= 0; --k) {
+        int64_t e = (int64_t)std::floor(x[k] * pre.nH);
+        e = std::min<int64_t>(std::max<int64_t>(e, 0), pre.nH - 1);
+        c = c * pre.nH + e;
+      }
+      cell[f] = c;
+    }
+    std::vector<int32_t> order((size_t)nf);
+    for (int64_t f = 0; f < nf; ++f) order[f] = (int32_t)f;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return cell[a] < cell[b]; });
+    d->perm_h.assign((size_t)n, 0);
+    d->iperm_h.assign((size_t)n, 0);
+    for (int64_t i = 0; i < nf; ++i)
+      for (int c = 0; c < nc; ++c) {
+        const int32_t can = (int32_t)(order[i] * nc + c), in = (int32_t)(i * nc + c);
+        d->perm_h[in] = can;
+        d->iperm_h[can] = in;
+      }
+    d->perm.upload(d->perm_h);
+  }
+  const std::vector<int32_t> &iperm = d->iperm_h, &perm = d->perm_h;
+
   // sliced ELL
   {
     const int ns = (int)(npad / kSlice);
@@ -1004,8 +1045,11 @@ void device_setup(Precond &pre, const HostFactors &hf, int precision) {
     for (int s = 0; s < ns; ++s) {
       int w = 0;
       for (int l = 0; l < kSlice; ++l) {
-        const int64_t r = (int64_t)s * kSlice + l;
-        if (r < n) w = std::max<int>(w, (int)(sys.rowptr[r + 1] - sys.rowptr[r]));
+        const int64_t ri = (int64_t)s * kSlice + l;
+        if (ri < n) {
+          const int64_t r = perm[ri];
+          w = std::max<int>(w, (int)(sys.rowptr[r + 1] - sys.rowptr[r]));
+        }
       }
       sptr[s] = (int32_t)tot;
       slen[s] = w;
@@ -1016,15 +1060,16 @@ void device_setup(Precond &pre, const HostFactors &hf, int precision) {
     std::vector<double> val((size_t)tot, 0.0);
     for (int s = 0; s < ns; ++s)
       for (int l = 0; l < kSlice; ++l) {
-        const int64_t r = (int64_t)s * kSlice + l;
-        const int64_t len = r < n ? sys.rowptr[r + 1] - sys.rowptr[r] : 0;
+        const int64_t ri = (int64_t)s * kSlice + l;
+        const int64_t r = ri < n ? perm[ri] : 0;
+        const int64_t len = ri < n ? sys.rowptr[r + 1] - sys.rowptr[r] : 0;
         for (int c = 0; c < slen[s]; ++c) {
           const size_t e = (size_t)sptr[s] + (size_t)c * kSlice + l;
           if (c < len) {
-            col[e] = sys.col[sys.rowptr[r] + c];
+            col[e] = iperm[sys.col[sys.rowptr[r] + c]];
             val[e] = sys.val[sys.rowptr[r] + c];
           } else {
-            col[e] = (int32_t)std::min<int64_t>(r, n - 1);
+            col[e] = (int32_t)std::min<int64_t>(ri, n - 1);
             val[e] = 0.0;
           }
         }
@@ -1055,7 +1100,7 @@ void device_setup(Precond &pre, const HostFactors &hf, int precision) {
         const int32_t g = pre.vert_coarse[pre.Pvert[(size_t)f * nv + b]];
         if (g < 0) continue;
         for (int c = 0; c < nc; ++c) {
-          const int64_t dof = f * nc + c;
+          const int64_t dof = iperm[f * nc + c];
           Pc[(size_t)dof * nv + b] = g * nc + c;
           Pw[(size_t)dof * nv + b] = pre.Pphi[(size_t)f * nv + b];
           ++cnt[(size_t)g * nc + c + 1];
@@ -1082,7 +1127,7 @@ void device_setup(Precond &pre, const HostFactors &hf, int precision) {
     d->Pw.upload(std::vector<double>((size_t)npad * nv, 0.0));
   }
   HIPCHK(hipDeviceSynchronize());
-  d->bytes = (int64_t)(d->sptr.bytes() + d->slen.bytes() + d->col.bytes() + d->val.bytes() + d->order_narrow.bytes() +
+  d->bytes = (int64_t)(d->sptr.bytes() + d->slen.bytes() + d->col.bytes() + d->val.bytes() + d->order_narrow.bytes() + d->perm.bytes() +
                        d->order_wide.bytes() +
                        d->st_n.bytes() + d->st_vb.bytes() + d->st_q.bytes() + d->st_gb.bytes() + d->st_fb.bytes() +
                        d->st_bb.bytes() + d->pos_dof.bytes() + d->f_hdr.bytes() + d->b_hdr.bytes() +
@@ -1424,7 +1469,8 @@ void store_block(Engine &e, double *dst, const double *src, int k, bool dev_ptrs
     with_kc(e.kc, [&](auto K) {
       constexpr int KC = decltype(K)::value;
       for (int j = 0; j < k; ++j)
-        hipLaunchKernelGGL(k_col_out<KC>, dim3(grid_for(d.n)), dim3(kBlock), 0, s, dst, src, (int)d.n, k, j, j);
+        hipLaunchKernelGGL(k_col_out<KC>, dim3(grid_for(d.n)), dim3(kBlock), 0, s, dst, src, d.perm.p, (int)d.n, k, j,
+                           j);
     });
     HIPCHK(hipStreamSynchronize(s));
     return;
@@ -1433,7 +1479,7 @@ void store_block(Engine &e, double *dst, const double *src, int k, bool dev_ptrs
   HIPCHK(hipMemcpyAsync(tmp.data(), src, tmp.size() * sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   for (int64_t i = 0; i < d.n; ++i)
-    for (int j = 0; j < k; ++j) dst[(size_t)i * k + j] = tmp[(size_t)i * e.kc + j];
+    for (int j = 0; j < k; ++j) dst[(size_t)d.perm_h[i] * k + j] = tmp[(size_t)i * e.kc + j];
 }
 
 // n x k block (device) -> batch vector columns 0..k-1 (the rest zero)
@@ -1443,11 +1489,11 @@ void load_block(Engine &e, double *dst, const double *src_dev, int k, hipStream_
     constexpr int KC = decltype(K)::value;
     for (int j = 0; j < e.kc; ++j) {
       if (j < k)
-        hipLaunchKernelGGL(k_col_in<KC>, dim3(grid_for(d.npad)), dim3(kBlock), 0, s, dst, src_dev, (int)d.n,
-                           (int)d.npad, k, j, j);
+        hipLaunchKernelGGL(k_col_in<KC>, dim3(grid_for(d.npad)), dim3(kBlock), 0, s, dst, src_dev, d.perm.p,
+                           (int)d.n, (int)d.npad, k, j, j);
       else
-        hipLaunchKernelGGL(k_col_in<KC>, dim3(grid_for(d.npad)), dim3(kBlock), 0, s, dst, src_dev, 0, (int)d.npad,
-                           k, 0, j);
+        hipLaunchKernelGGL(k_col_in<KC>, dim3(grid_for(d.npad)), dim3(kBlock), 0, s, dst, src_dev, d.perm.p, 0,
+                           (int)d.npad, k, 0, j);
     }
   });
 }
@@ -1597,7 +1643,7 @@ void engine_admit(Engine *e, int k, const int32_t *cols, const double *f, const 
       const int c = cols[j];
       if (c < 0 || c >= e->kc || e->host_sc[c].active) fail(SN_EINVAL, "internal: column not free");
       hipLaunchKernelGGL(k_admit<KC>, dim3(grid_for(d.npad)), dim3(kBlock), 0, s, e->f.p, e->r.p, e->u.p, e->p.p,
-                         src, (int)d.n, (int)d.npad, k, j, c);
+                         src, d.perm.p, (int)d.n, (int)d.npad, k, j, c);
       e->host_sc[c] = column_init(rtol[j], max_iter[j], 0);
       mask |= 1u << c;
     }
@@ -1644,7 +1690,8 @@ void engine_retire(Engine *e, int c, double *u, int64_t ld) {
   const hipStream_t s = e->own;
   with_kc(e->kc, [&](auto K) {
     constexpr int KC = decltype(K)::value;
-    hipLaunchKernelGGL(k_col_out<KC>, dim3(grid_for(d.n)), dim3(kBlock), 0, s, e->q.p, e->u.p, (int)d.n, 1, 0, c);
+    hipLaunchKernelGGL(k_col_out<KC>, dim3(grid_for(d.n)), dim3(kBlock), 0, s, e->q.p, e->u.p, d.perm.p, (int)d.n, 1,
+                       0, c);
   });
   std::vector<double> tmp((size_t)d.n);
   HIPCHK(hipMemcpyAsync(tmp.data(), e->q.p, tmp.size() * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -1726,7 +1773,7 @@ void device_solve(Precond &pre, int k, const double *f, double *u, const sn_solv
     constexpr int KC = decltype(K)::value;
     for (int j = 0; j < e.kc; ++j)
       hipLaunchKernelGGL(k_admit<KC>, dim3(grid_for(d.npad)), dim3(kBlock), 0, s, e.f.p, e.r.p, e.u.p, e.p.p, src,
-                         j < k ? (int)d.n : 0, (int)d.npad, k, j < k ? j : 0, j);
+                         d.perm.p, j < k ? (int)d.n : 0, (int)d.npad, k, j < k ? j : 0, j);
   });
   for (int j = 0; j < e.kc; ++j) {
     if (j < k) {
