@@ -85,12 +85,14 @@ def copy_probe(mib):
     print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8, "launches": 5}), flush=True)
 
 
-def serving_leg(n_requests, rate, pool_size=8, seed=5):
+def serving_leg(n_requests, rate, pool_size=8, seed=5, load=0.7):
     """Poisson arrivals of solve requests (1-8 right-hand sides, uniform[0,1]
     loads) on a pool of 2D and 3D fiber networks of 2k-500k nodes, served by
     one continuous-batching server (FP32 stars). The pool's factors are made
-    resident by one untimed request per network first. Latency runs from the
-    scheduled arrival to the poll that returns the result."""
+    resident by one untimed request per network first. First the saturation
+    throughput: every request submitted at once. Then arrivals at `load` times
+    that request rate (or at `rate` if given); latency runs from the scheduled
+    arrival to the poll that returns the result."""
     import numpy as np
     from paper_2207_07488_amd import spnet as S
     from paper_2207_07488_amd import workloads as W
@@ -108,40 +110,51 @@ def serving_leg(n_requests, rate, pool_size=8, seed=5):
     while warm:
         srv.step()
         warm = [t for t in warm if srv.poll(t) is None]
-    arrivals = W.poisson_arrivals(n_requests, rate, seed + 1)
     pick = W.uniform01(seed + 2, 0, 2 * n_requests)
     reqs = []
     for i in range(n_requests):
         j = min(int(pick[2 * i] * len(pres)), len(pres) - 1)
         k = 1 + min(int(pick[2 * i + 1] * 8), 7)
         reqs.append((j, k, W.rhs(pres[j].sys.n, k, seed=100 + i)))
-    pending, lat, iters, worst = {}, [], [], 0.0
-    nxt, solved = 0, 0
-    t0 = time.perf_counter()
-    while nxt < n_requests or pending:
-        now = time.perf_counter() - t0
-        while nxt < n_requests and arrivals[nxt] <= now:
-            j, k, F = reqs[nxt]
-            pending[srv.submit(pres[j], F)] = (nxt, k)
-            nxt += 1
-        srv.step()
-        for t in list(pending):
-            r = srv.poll(t)
-            if r is None:
-                continue
-            i, k = pending.pop(t)
-            lat.append((time.perf_counter() - t0 - arrivals[i]) * 1e3)
-            iters.extend(x["iters"] for x in r[1])
-            worst = max(worst, max(x["res_true"] for x in r[1]))
-            solved += k
-        if nxt < n_requests and not pending:
-            time.sleep(max(0.0, arrivals[nxt] - (time.perf_counter() - t0)))
-    makespan = time.perf_counter() - t0
+
+    def run(arrivals):
+        pending, lat, iters, worst = {}, [], [], 0.0
+        nxt, solved = 0, 0
+        t0 = time.perf_counter()
+        while nxt < n_requests or pending:
+            now = time.perf_counter() - t0
+            while nxt < n_requests and arrivals[nxt] <= now:
+                j, k, F = reqs[nxt]
+                pending[srv.submit(pres[j], F)] = (nxt, k)
+                nxt += 1
+            srv.step()
+            for t in list(pending):
+                r = srv.poll(t)
+                if r is None:
+                    continue
+                i, k = pending.pop(t)
+                lat.append((time.perf_counter() - t0 - arrivals[i]) * 1e3)
+                iters.extend(x["iters"] for x in r[1])
+                worst = max(worst, max(x["res_true"] for x in r[1]))
+                solved += k
+            if nxt < n_requests and not pending:
+                time.sleep(max(0.0, arrivals[nxt] - (time.perf_counter() - t0)))
+        return time.perf_counter() - t0, lat, iters, worst, solved
+
+    sat_s, sat_lat, _, _, solved = run(np.zeros(n_requests))
+    sat_req_rate = n_requests / sat_s
+    arr_rate = rate if rate and rate > 0 else load * sat_req_rate
+    arrivals = W.poisson_arrivals(n_requests, arr_rate, seed + 1)
+    makespan, lat, iters, worst, solved = run(arrivals)
     used, neng = srv.usage()
     srv.close()
-    return {"requests": n_requests, "arrival_rate_per_s": rate, "rhs_solved": solved,
-            "solves_per_s": round(solved / makespan, 2), "makespan_s": round(makespan, 3),
-            "latency_ms": {"p50": round(percentile(lat, 0.5), 3), "p99": round(percentile(lat, 0.99), 3)},
+    return {"requests": n_requests, "rhs_solved": solved,
+            "saturation": {"solves_per_s": round(solved / sat_s, 2), "requests_per_s": round(sat_req_rate, 2),
+                           "latency_ms": {"p50": round(percentile(sat_lat, 0.5), 3),
+                                          "p99": round(percentile(sat_lat, 0.99), 3)}},
+            "poisson": {"arrival_rate_per_s": round(arr_rate, 2), "load": None if rate else load,
+                        "solves_per_s": round(solved / makespan, 2), "makespan_s": round(makespan, 3),
+                        "latency_ms": {"p50": round(percentile(lat, 0.5), 3), "p99": round(percentile(lat, 0.99), 3)}},
             "median_iterations": int(np.median(iters)), "max_res_true": worst,
             "networks": [{"dim": p["dim"], "dofs": pre.sys.n, "nH": p["nH"], "stars": pre.nstars} for p, pre in
                          zip(pool, pres)],
@@ -159,7 +172,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-h-sweep", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=64)
-    ap.add_argument("--serving-rate", type=float, default=100.0, help="Poisson arrival rate (requests/s)")
+    ap.add_argument("--serving-rate", type=float, default=0.0,
+                    help="Poisson arrival rate (requests/s); 0: 70%% of the measured saturation rate")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic_star_sweep_fiber2d_20k.json"),
                     help="HBM traffic per sweep launch from rocprofv3 counters (JSON), if present")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",

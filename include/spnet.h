@@ -292,14 +292,18 @@ sn_status sn_server_create(const sn_server_opts *opts, sn_server *out);
 sn_status sn_server_submit(sn_server srv, sn_precond pre, int k, const double *f, double rtol,
                            int64_t max_iter, uint64_t *ticket);
 /*
- * One scheduling tick: wait for the previous tick of every engine, retire the
- * converged columns, admit queued requests that fit, and queue the next
- * iterations of every engine (asynchronously). n_active: requests iterating,
- * n_queued: requests waiting.
+ * One scheduling step: retire the converged columns of every engine whose
+ * last tick has completed (waiting for the first one if none has), admit
+ * queued requests into idle engines that have room, and queue the next
+ * iterations of every idle engine with running columns (asynchronously).
+ * Engines advance independently. n_active: requests iterating, n_queued:
+ * requests waiting.
  */
 sn_status sn_server_step(sn_server srv, int32_t *n_active, int32_t *n_queued);
 /* SN_EBUSY while pending; when done copies u (n x k) and k info entries and
- * forgets the ticket. A request that failed returns its error once. */
+ * forgets the ticket. With u and info both NULL it only reports the status
+ * (SN_OK when done) and keeps the result. A request that failed returns its
+ * error once. */
 sn_status sn_server_poll(sn_server srv, uint64_t ticket, double *u, sn_solve_info *info);
 /* Device bytes the server holds (engines and the factors it uploaded). */
 sn_status sn_server_usage(sn_server srv, int64_t *device_bytes, int32_t *n_engines);

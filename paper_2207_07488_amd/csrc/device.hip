@@ -1648,7 +1648,16 @@ void engine_admit(Engine *e, int k, const int32_t *cols, const double *f, const 
       mask |= 1u << c;
     }
   });
-  upload_scalars(*e, s);
+  // Upload the new columns' states only: an earlier admission in the same
+  // idle period has queued its own start-up kernels, which must not see their
+  // columns reset by this upload. Retired columns (sc_dirty) go up with the
+  // whole array before any start-up work of this period.
+  if (e->sc_dirty) {
+    upload_scalars(*e, s);
+  } else {
+    for (int j = 0; j < k; ++j)
+      HIPCHK(hipMemcpyAsync(e->sc.p + cols[j], &e->host_sc[cols[j]], sizeof(CgScalars), hipMemcpyHostToDevice, s));
+  }
   launch_start_dots(*e, mask, s);
 }
 

@@ -8,6 +8,7 @@
 #include <deque>
 #include <future>
 #include <map>
+#include <thread>
 #include <unordered_map>
 #include <vector>
 
@@ -272,13 +273,20 @@ sn_status sn_server_step(sn_server srv, int32_t *n_active, int32_t *n_queued) {
     if (!srv) spnet::fail(SN_EINVAL, "null server");
     sn_server_s &S = *srv;
     ++S.tick_no;
-    // 1. the previous tick of every engine, then retire converged columns
-    for (auto &e : S.engines)
-      if (e->ticking) {
-        spnet::engine_wait(e->eng);
-        e->ticking = false;
-        retire_finished(S, *e);
-      }
+    // 1. engines whose tick has completed: retire their converged columns.
+    //    Engines advance independently: a small network does not wait for the
+    //    ticks of a large one. When none has completed yet, wait for the first.
+    bool any_ticking = false, progressed = false;
+    for (auto &e : S.engines) any_ticking |= e->ticking;
+    while (any_ticking && !progressed) {
+      for (auto &e : S.engines)
+        if (e->ticking && spnet::engine_query(e->eng)) {
+          e->ticking = false;
+          retire_finished(S, *e);
+          progressed = true;
+        }
+      if (!progressed) std::this_thread::yield();
+    }
     // 2. admit queued requests that fit (in arrival order; a request that
     //    cannot start yet does not hold back later ones)
     for (auto it = S.queue.begin(); it != S.queue.end();) {
@@ -288,7 +296,7 @@ sn_status sn_server_step(sn_server srv, int32_t *n_active, int32_t *n_queued) {
         it = S.queue.erase(it);
         continue;
       }
-      if (!e) {
+      if (!e || e->ticking) {
         ++it;
         continue;
       }
@@ -313,9 +321,9 @@ sn_status sn_server_step(sn_server srv, int32_t *n_active, int32_t *n_queued) {
       r->f.shrink_to_fit();
       it = S.queue.erase(it);
     }
-    // 3. queue the next iterations of every engine with running columns
+    // 3. queue the next iterations of every idle engine with running columns
     for (auto &e : S.engines)
-      if (e->active_columns() > 0) {
+      if (!e->ticking && e->active_columns() > 0) {
         spnet::engine_tick(e->eng, S.o.iters_per_tick, S.o.use_graph != 0);
         e->ticking = true;
         e->last_tick = S.tick_no;
@@ -344,6 +352,7 @@ sn_status sn_server_poll(sn_server srv, uint64_t ticket, double *u, sn_solve_inf
       rc = SN_EBUSY;
       return;
     }
+    if (!u && !info) return;  // status query: the result stays
     if (u) std::memcpy(u, r.u.data(), r.u.size() * sizeof(double));
     if (info) std::memcpy(info, r.info.data(), r.info.size() * sizeof(sn_solve_info));
     srv->reqs.erase(it);

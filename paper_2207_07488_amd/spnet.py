@@ -354,11 +354,12 @@ class Server:
     def poll(self, ticket):
         """(u, [info]) when the request is done, None while it is pending."""
         pre, k, shape = self._keep[ticket]
-        u = np.zeros(shape)
-        infos = (SolveInfo * k)()
-        rc = lib().sn_server_poll(self.h, ticket, _ptr(u), infos)
+        rc = lib().sn_server_poll(self.h, ticket, None, None)  # status only
         if rc == SN_EBUSY:
             return None
+        u = np.empty(shape)
+        infos = (SolveInfo * k)()
+        rc = lib().sn_server_poll(self.h, ticket, _ptr(u), infos)
         del self._keep[ticket]
         _check(rc)
         return u, [i.asdict() for i in infos]

@@ -95,6 +95,23 @@ def test_same_alone_and_in_the_mix(S, pres):
         assert all(x["converged"] for x in info_mix)
 
 
+def test_requests_admitted_together_into_one_engine(S, pres):
+    """Several requests on one network submitted before a step start in the same
+    engine at once; each converges as it does alone (regression: a later
+    admission must not reset the start-up state of an earlier one)."""
+    srv = S.Server(max_columns=8, iters_per_tick=4)
+    pre = pres["p2d_2k"]
+    F = [_rhs(pre, k, 60 + k) for k in (3, 2, 1, 2)]
+    tickets = [srv.submit(pre, f) for f in F]
+    got = _drain(srv, list(tickets))
+    for f, t in zip(F, tickets):
+        u, infos = got[t]
+        u1, i1 = pre.solve(f, rtol=1e-8)
+        assert all(x["converged"] and x["iters"] < 200 for x in infos)
+        assert [x["iters"] for x in infos] == [x["iters"] for x in i1]
+        assert np.array_equal(u.reshape(u1.shape), u1)
+
+
 def test_server_matches_sn_solve_and_oracle(S, pres, orc):
     srv = S.Server(max_columns=8, iters_per_tick=4)
     name, k, seed = "p2d_2k", 3, 31
