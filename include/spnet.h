@@ -150,7 +150,8 @@ sn_status sn_precond_export_coarse(sn_precond pre, int32_t *coarse_vertex);
 /* ------------------------------------------------------------------ */
 #define SN_PREC_FP64 0       /* star factors and sweeps in FP64 */
 #define SN_PREC_FP32_STARS 1 /* star factors stored and swept in FP32 with FP32 accumulation;
-                                CG recurrences, dots and the coarse solve stay FP64 */
+                                the coarse inverse stored in FP32 (products accumulate in
+                                FP64); CG recurrences and dots stay FP64 */
 
 typedef struct {
   int64_t star_factor_nnz;   /* entries of all local factors (incl. diagonal) */
@@ -170,7 +171,9 @@ typedef struct {
   int32_t star_precision;    /* precision the sweeps run in: SN_PREC_FP32_STARS falls back to
                                 SN_PREC_FP64 when max_pivot_ratio * 2^-24 > 0.05, i.e. when FP32
                                 factors could not resolve the local solves */
-  int32_t pad0;
+  int32_t coarse_precision;  /* precision K_0^{-1} is stored in: SN_PREC_FP32_STARS only when the
+                                sweeps run in FP32 and coarse_pivot_ratio * 2^-24 <= 0.05 */
+  double coarse_pivot_ratio; /* largest / smallest Cholesky pivot of K_0 */
 } sn_factor_info;
 
 /* Order, factor in FP64 on the host (threads over stars) and upload to the GPU.

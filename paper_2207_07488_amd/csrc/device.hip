@@ -507,96 +507,111 @@ __global__ __launch_bounds__(kBlock) void k_restrict(const int32_t *__restrict__
   if (lane == 0) out.store(rH + (size_t)g * KC);
 }
 
-// c = K_0^{-1} r_H. A wavefront computes RW rows; lane l takes the columns
-// 2l, 2l+1 of every 128-column chunk (16-byte loads of the row), in chunk
-// order, then a fixed wavefront tree: the same order for every column count.
-// With one column, UC chunks are loaded before they are used; with several,
-// each chunk of r_H is staged in LDS once per block and shared by its 4 RW rows.
-template <int KC>
-__global__ __launch_bounds__(kBlock) void k_coarse_gemv(const double *__restrict__ Kinv, const double *__restrict__ rH,
-                                                        double *cvec, int m0, const CgScalars *sc, int sel) {
-  constexpr int RW = KC >= 4 ? 4 : 1;  // rows per wavefront
-  constexpr int CH = 128;              // columns per chunk
-  constexpr int UC = KC == 1 ? 8 : 1;  // chunks in flight
-  __shared__ double xs[KC > 1 ? CH * KC : 1];
+// c = K_0^{-1} r_H on the matrix cores (v_mfma_f64_16x16x4f64: a 16 x 4 by
+// 4 x 16 product per instruction, accumulated in FP64). The inverse is stored
+// symmetric, padded with zeros to ld x ld (ld a multiple of 16), in TA (double,
+// or float in the mixed-precision form, converted exactly to double on load).
+// r_H and c have ld rows (r_H zero past m0).
+// A workgroup of kMmWaves wavefronts owns a 16-row tile; wavefront w takes a
+// contiguous range of 16-column groups and accumulates its 16 x 16 tile of
+// products (rows x columns of r_H; columns past KC are discarded); the
+// wavefront tiles are summed in LDS in wavefront order. Every column of the
+// product is computed by the same instructions whatever KC is, so a batched
+// column equals the single-column result bit for bit.
+typedef double mm_d4 __attribute__((ext_vector_type(4)));
+constexpr int kMmWaves = 16;
+
+template <typename TA>
+struct MmLoad;
+// FP64: a lane loads two 16-byte pieces of its row (columns 2q, 2q+1 and
+// 8+2q, 8+2q+1 of the group, q = lane / 16): both loads of a wavefront are
+// 64 contiguous bytes per row
+template <>
+struct MmLoad<double> {
+  static __device__ __forceinline__ int col(int q, int s) { return (s >> 1) * 8 + 2 * q + (s & 1); }
+  static __device__ __forceinline__ void load(const double *p, int q, double (&a)[4]) {
+    const double2 u = *reinterpret_cast<const double2 *>(p + 2 * q);
+    const double2 v = *reinterpret_cast<const double2 *>(p + 8 + 2 * q);
+    a[0] = u.x;
+    a[1] = u.y;
+    a[2] = v.x;
+    a[3] = v.y;
+  }
+};
+// FP32: one 16-byte load of columns 4q..4q+3 of the group
+template <>
+struct MmLoad<float> {
+  static __device__ __forceinline__ int col(int q, int s) { return 4 * q + s; }
+  static __device__ __forceinline__ void load(const float *p, int q, double (&a)[4]) {
+    const float4 u = *reinterpret_cast<const float4 *>(p + 4 * q);
+    a[0] = (double)u.x;
+    a[1] = (double)u.y;
+    a[2] = (double)u.z;
+    a[3] = (double)u.w;
+  }
+};
+
+template <typename TA, int KC>
+__global__ __launch_bounds__(64 * kMmWaves) void k_coarse_mm(const TA *__restrict__ Kinv, int ld,
+                                                             const double *__restrict__ rH, double *cvec, int m0,
+                                                             const CgScalars *sc, int sel) {
+  static_assert(KC >= 1 && KC <= 16, "the product tile holds 16 columns");
+  __shared__ double part[kMmWaves][256];
   if (!any_selected<KC>(sc, sel, 0u)) return;
+  constexpr int UG = 4;  // groups loaded before their products
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int row0 = (blockIdx.x * (kBlock / 64) + wv) * RW;
-  Vec<KC> acc[RW];
+  const int i = lane & 15, q = lane >> 4;  // A operand: row i; B operand: column i; k quad q
+  const int row0 = blockIdx.x * 16;
+  const int groups = ld / 16;
+  const int gpw = (groups + kMmWaves - 1) / kMmWaves;
+  const int g0 = min(groups, wv * gpw), g1 = min(groups, g0 + gpw);
+  const TA *arow = Kinv + (size_t)(row0 + i) * ld;
+  auto load_group = [&](int g, double (&a)[4], double (&b)[4]) {
+    MmLoad<TA>::load(arow + 16 * g, q, a);
+    // r_H has ld rows (zero past m0), so no masks: product columns past KC
+    // repeat column KC - 1 and are never stored
+    if constexpr (KC == 1) {
+      // the column pairs (0, 1) and (2, 3) of a lane are adjacent
+      const double2 u = *reinterpret_cast<const double2 *>(rH + 16 * g + MmLoad<TA>::col(q, 0));
+      const double2 v = *reinterpret_cast<const double2 *>(rH + 16 * g + MmLoad<TA>::col(q, 2));
+      b[0] = u.x;
+      b[1] = u.y;
+      b[2] = v.x;
+      b[3] = v.y;
+    } else {
 #pragma unroll
-  for (int i = 0; i < RW; ++i) acc[i].zero();
-  auto load_a = [&](const double *a, int ja, double &a0, double &a1) {
-    a0 = 0.0;
-    a1 = 0.0;
-    if (ja + 1 < m0) {
-      if ((m0 & 1) == 0) {
-        const double2 t = *reinterpret_cast<const double2 *>(a + ja);
-        a0 = t.x;
-        a1 = t.y;
-      } else {
-        a0 = a[ja];
-        a1 = a[ja + 1];
-      }
-    } else if (ja < m0) {
-      a0 = a[ja];
+      for (int s = 0; s < 4; ++s) b[s] = rH[(size_t)(16 * g + MmLoad<TA>::col(q, s)) * KC + min(i, KC - 1)];
     }
   };
-  if constexpr (KC == 1) {
-    const int row = row0;
-    if (row < m0) {
-      const double *a = Kinv + (size_t)row * m0;
-      for (int j0 = 0; j0 < m0; j0 += CH * UC) {
-        double a0[UC], a1[UC], x0[UC], x1[UC];
+  mm_d4 acc = {0.0, 0.0, 0.0, 0.0};
+  int g = g0;
+  for (; g + UG <= g1; g += UG) {
+    double a[UG][4], b[UG][4];
 #pragma unroll
-        for (int u = 0; u < UC; ++u) {
-          const int ja = j0 + CH * u + 2 * lane;
-          load_a(a, ja, a0[u], a1[u]);
-          x0[u] = ja < m0 ? rH[ja] : 0.0;
-          x1[u] = ja + 1 < m0 ? rH[ja + 1] : 0.0;
-        }
+    for (int u = 0; u < UG; ++u) load_group(g + u, a[u], b[u]);
+    // every load of the UG groups is issued before the first product waits
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int u = 0; u < UC; ++u) {
-          acc[0].v[0] = __builtin_fma(a0[u], x0[u], acc[0].v[0]);
-          acc[0].v[0] = __builtin_fma(a1[u], x1[u], acc[0].v[0]);
-        }
-      }
-    }
-  } else {
-    // xs[k][j]: lane l reads the pair (2l, 2l+1) of every column k, so that
-    // consecutive lanes read consecutive LDS words
-    for (int j0 = 0; j0 < m0; j0 += CH) {
-      __syncthreads();
-      for (int t = threadIdx.x; t < CH * KC; t += kBlock) {
-        const int j = t / KC, k = t % KC;
-        xs[k * CH + j] = j0 + j < m0 ? rH[(size_t)j0 * KC + t] : 0.0;
-      }
-      __syncthreads();
-      const int ja = j0 + 2 * lane;
-      double2 xp[KC];
+    for (int u = 0; u < UG; ++u)
 #pragma unroll
-      for (int k = 0; k < KC; ++k) xp[k] = *reinterpret_cast<const double2 *>(&xs[k * CH + 2 * lane]);
-      double a0[RW], a1[RW];
-#pragma unroll
-      for (int i = 0; i < RW; ++i) {
-        const int row = row0 + i < m0 ? row0 + i : m0 - 1;
-        load_a(Kinv + (size_t)row * m0, ja, a0[i], a1[i]);
-      }
-#pragma unroll
-      for (int i = 0; i < RW; ++i)
-#pragma unroll
-        for (int k = 0; k < KC; ++k) {
-          acc[i].v[k] = __builtin_fma(a0[i], xp[k].x, acc[i].v[k]);
-          acc[i].v[k] = __builtin_fma(a1[i], xp[k].y, acc[i].v[k]);
-        }
-    }
+      for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][s], b[u][s], acc, 0, 0, 0);
   }
+  for (; g < g1; ++g) {
+    double a[4], b[4];
+    load_group(g, a, b);
 #pragma unroll
-  for (int i = 0; i < RW; ++i) {
-    const int row = row0 + i;
-    Vec<KC> out;
+    for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], b[s], acc, 0, 0, 0);
+  }
+  // result layout: lane l, element v holds row l / 16 + 4 v, column l % 16
 #pragma unroll
-    for (int k = 0; k < KC; ++k) out.v[k] = wave_sum(acc[i].v[k]);
-    if (lane == 0 && row < m0) out.store(cvec + (size_t)row * KC);
+  for (int v = 0; v < 4; ++v) part[wv][(q + 4 * v) * 16 + i] = acc[v];
+  __syncthreads();
+  if (threadIdx.x < 256) {
+    const int t = threadIdx.x, row = t >> 4, col = t & 15;
+    double sum = part[0][t];
+#pragma unroll
+    for (int w = 1; w < kMmWaves; ++w) sum += part[w][t];
+    if (col < KC && row0 + row < m0) cvec[(size_t)(row0 + row) * KC + col] = sum;
   }
 }
 
@@ -749,7 +764,12 @@ struct DeviceState {
   DBuf<float> f_inv32, b_inv32, f_val32, b_val32;
   DBuf<double> f_inv64, b_inv64, f_val64, b_val64;
   // coarse
-  DBuf<double> Kinv, PTw, Pw;
+  // K_0^{-1}, symmetric, zero-padded to ld0 x ld0: FP32 in the mixed form
+  // unless the coarse factor's pivot ratio rules it out, else FP64
+  DBuf<double> Kinv64, PTw, Pw;
+  DBuf<float> Kinv32;
+  int64_t ld0 = 0;
+  bool coarse32 = false;
   DBuf<int32_t> PTptr, PTdof, Pc;
   // internal dof order: free nodes grouped by coarse element (gather
   // locality); perm[internal] = canonical dof, iperm the inverse
@@ -1089,7 +1109,24 @@ void device_setup(Precond &pre, const HostFactors &hf, int precision) {
   // coarse operator
   const int nc = sys.ncomp, nv = d->nv;
   if (d->m0 > 0) {
-    d->Kinv.upload(hf.coarse_inv);
+    // symmetric (the mean of the two computed triangles) and padded
+    const int64_t m0 = d->m0, ld = (m0 + 15) / 16 * 16;
+    d->ld0 = ld;
+    d->coarse32 = precision == SN_PREC_FP32_STARS && hf.coarse_pivot_ratio * std::ldexp(1.0, -24) <= 0.05;
+    auto sym = [&](int64_t i, int64_t j) {
+      return 0.5 * (hf.coarse_inv[(size_t)(i * m0 + j)] + hf.coarse_inv[(size_t)(j * m0 + i)]);
+    };
+    if (d->coarse32) {
+      std::vector<float> A((size_t)(ld * ld), 0.0f);
+      for (int64_t i = 0; i < m0; ++i)
+        for (int64_t j = 0; j < m0; ++j) A[(size_t)(i * ld + j)] = (float)sym(i, j);
+      d->Kinv32.upload(A);
+    } else {
+      std::vector<double> A((size_t)(ld * ld), 0.0);
+      for (int64_t i = 0; i < m0; ++i)
+        for (int64_t j = 0; j < m0; ++j) A[(size_t)(i * ld + j)] = sym(i, j);
+      d->Kinv64.upload(A);
+    }
     // P per dof (npad x nv) and P^T as CSR over coarse dofs
     std::vector<int32_t> Pc((size_t)npad * nv, -1);
     std::vector<double> Pw((size_t)npad * nv, 0.0);
@@ -1131,7 +1168,7 @@ void device_setup(Precond &pre, const HostFactors &hf, int precision) {
                        d->order_wide.bytes() +
                        d->st_n.bytes() + d->st_vb.bytes() + d->st_q.bytes() + d->st_gb.bytes() + d->st_fb.bytes() +
                        d->st_bb.bytes() + d->pos_dof.bytes() + d->f_hdr.bytes() + d->b_hdr.bytes() +
-                       d->slot_of.bytes() + d->Kinv.bytes() + d->Pc.bytes() + d->Pw.bytes() +
+                       d->slot_of.bytes() + d->Kinv64.bytes() + d->Kinv32.bytes() + d->Pc.bytes() + d->Pw.bytes() +
                        d->PTptr.bytes() + d->PTdof.bytes() + d->PTw.bytes() + d->f_inv32.bytes() +
                        d->b_inv32.bytes() + d->f_inv64.bytes() + d->b_inv64.bytes()) +
              fi.star_stream_bytes;
@@ -1140,7 +1177,9 @@ void device_setup(Precond &pre, const HostFactors &hf, int precision) {
   fi.max_pivot_ratio = max_ratio;
   fi.star_precision = precision;
   fi.star_factor_nnz = star_nnz;
-  fi.coarse_bytes = (int64_t)d->Kinv.bytes();
+  fi.coarse_bytes = (int64_t)(d->Kinv64.bytes() + d->Kinv32.bytes());
+  fi.coarse_precision = d->coarse32 ? SN_PREC_FP32_STARS : SN_PREC_FP64;
+  fi.coarse_pivot_ratio = hf.coarse_pivot_ratio;
   fi.device_bytes = d->bytes;
   fi.factor_seconds = hf.seconds;
   pre.finfo = fi;
@@ -1271,10 +1310,13 @@ void launch_B(Engine &e, const double *r, double *z, int sel, bool dot, hipStrea
       constexpr int KC = decltype(K)::value;
       hipLaunchKernelGGL(k_restrict<KC>, dim3(nblk(d.m0 * 64)), dim3(kBlock), 0, cs, d.PTptr.p, d.PTdof.p, d.PTw.p,
                          r, e.rH.p, (int)d.m0, e.sc.p, sel);
-      constexpr int RW = KC >= 4 ? 4 : 1;
-      const unsigned gb = (unsigned)((d.m0 + 4 * RW - 1) / (4 * RW));
-      hipLaunchKernelGGL(k_coarse_gemv<KC>, dim3(gb), dim3(kBlock), 0, cs, d.Kinv.p, e.rH.p, e.c.p, (int)d.m0,
-                         e.sc.p, sel);
+      const unsigned gb = (unsigned)(d.ld0 / 16);
+      if (d.coarse32)
+        hipLaunchKernelGGL((k_coarse_mm<float, KC>), dim3(gb), dim3(64 * kMmWaves), 0, cs, d.Kinv32.p, (int)d.ld0,
+                           e.rH.p, e.c.p, (int)d.m0, e.sc.p, sel);
+      else
+        hipLaunchKernelGGL((k_coarse_mm<double, KC>), dim3(gb), dim3(64 * kMmWaves), 0, cs, d.Kinv64.p, (int)d.ld0,
+                           e.rH.p, e.c.p, (int)d.m0, e.sc.p, sel);
     });
   };
   if (d.m0 > 0 && e.coarse_first) {
@@ -1570,7 +1612,7 @@ int engine_width_for(int k) {
 
 int64_t engine_footprint(const Precond &pre, int kc) {
   const int64_t n = pre.sys->n, npad = (n + kBlock - 1) / kBlock * kBlock;
-  const int64_t m0 = std::max<int64_t>(pre.m0, 1);
+  const int64_t m0 = (std::max<int64_t>(pre.m0, 1) + 15) / 16 * 16;
   const int prec = pre.dev ? pre.finfo.star_precision : pre.precision;
   const int64_t ts = prec == SN_PREC_FP32_STARS ? 4 : 8;
   return (6 * npad * kc + 2 * m0 * kc + (int64_t)2 * kc * kMaxGrid) * 8 + kc * (int64_t)sizeof(CgScalars) +
@@ -1591,7 +1633,9 @@ Engine *engine_create(Precond &pre, int kc) {
     b->alloc(np);
     b->zero();
   }
-  const size_t nm = (size_t)std::max<int64_t>(d.m0, 1) * kc;
+  // r_H and c padded to the coarse operator's 16-row tiles; the padding of r_H
+  // stays zero (the restriction writes rows below m0 only)
+  const size_t nm = (size_t)std::max<int64_t>(d.ld0, 16) * kc;
   e->rH.alloc(nm);
   e->c.alloc(nm);
   e->rH.zero();

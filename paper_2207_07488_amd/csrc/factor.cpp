@@ -294,10 +294,13 @@ HostFactors factor_host(const Precond &pre) {
       if (A_ >= B_) Lb[(size_t)(B_ * W + (A_ - B_))] += v;
     });
     // right-looking band Cholesky
+    double dmin = HUGE_VAL, dmax = 0.0;
     for (int64_t j = 0; j < m0; ++j) {
       double *cj = &Lb[(size_t)(j * W)];
       const double d = cj[0];
       if (!(d > 0.0)) fail(SN_ENOTSPD, "coarse matrix P^T K P is not positive definite");
+      dmin = std::min(dmin, d);
+      dmax = std::max(dmax, d);
       const double sd = std::sqrt(d);
       cj[0] = sd;
       const int64_t len = std::min(W, m0 - j);
@@ -309,6 +312,7 @@ HostFactors factor_host(const Precond &pre) {
         for (int64_t k = t; k < len; ++k) cc[k - t] -= cj[k] * l;
       }
     }
+    hf.coarse_pivot_ratio = dmax / dmin;
     // K_0^{-1}: columns solved with the band factor, eight at a time so that
     // one pass over the factor serves eight right-hand sides
     constexpr int RB = 8;

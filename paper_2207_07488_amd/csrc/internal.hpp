@@ -94,6 +94,7 @@ struct StarFactor {
 struct HostFactors {
   std::vector<StarFactor> stars;
   std::vector<double> coarse_inv;   // m0 x m0 dense inverse of K_0 (symmetric)
+  double coarse_pivot_ratio = 1.0;  // largest / smallest pivot of the band Cholesky of K_0
   double seconds = 0;
 };
 

@@ -40,7 +40,7 @@ class FactorInfo(C.Structure):
                 ("device_bytes", C.c_int64), ("max_star_dofs", C.c_int32), ("max_band", C.c_int32),
                 ("factor_seconds", C.c_double), ("sweep_bytes", C.c_int64), ("spmv_bytes", C.c_int64),
                 ("sweep_flops", C.c_int64), ("max_pivot_ratio", C.c_double), ("star_precision", C.c_int32),
-                ("pad0", C.c_int32)]
+                ("coarse_precision", C.c_int32), ("coarse_pivot_ratio", C.c_double)]
 
     def asdict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -67,6 +67,7 @@ def test_fiber2d_20k_plain_and_mixed(S, orc):
     assert info_t[0]["iters"] == it_o and info_t[0]["res_true"] <= 1.0001e-8
     gmixed = S.Precond(gplain.sys, 32, S.STARS_ALL, 1, 1, precision=S.FP32_STARS)
     assert gmixed.factor_info()["star_precision"] == S.FP32_STARS
+    assert gmixed.factor_info()["coarse_precision"] == S.FP32_STARS
     u_m, info_m = gmixed.solve(fd, rtol=1e-8, use_graph=True)
     assert info_m[0]["res_true"] <= 1.0001e-8 and info_m[0]["iters"] <= it_o + 3
     assert _rel(u_m.cpu().numpy(), u_o) <= 1e-6

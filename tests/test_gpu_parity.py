@@ -105,6 +105,10 @@ def test_preconditioner_fp32_stars(S, orc, name):
     else:
         # FP32 factors and sweeps: ~ cond(K_j) * 6e-8
         assert _rel(z, ref) <= 5e-3
+    # the coarse inverse is stored in FP32 only beside FP32 sweeps and when its
+    # factor's pivot ratio leaves FP32 room to resolve it
+    coarse32 = fi["star_precision"] == S.FP32_STARS and fi["coarse_pivot_ratio"] * 2.0 ** -24 <= 0.05
+    assert fi["coarse_precision"] == (S.FP32_STARS if coarse32 else S.FP64)
 
 
 @pytest.mark.parametrize("name", list(CASES))
