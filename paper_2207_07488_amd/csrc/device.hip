@@ -32,7 +32,7 @@ namespace spnet {
 
 constexpr int kBlock = 256;     // threads of the vector kernels
 constexpr int kSlice = 64;      // rows per ELL slice (one wavefront)
-constexpr int kMaxGrid = 1024;  // blocks of the grid-stride vector kernels (= partial sums per column)
+constexpr int kMaxGrid = 2048;  // blocks of the grid-stride vector kernels (= partial sums per column)
 constexpr int kMaxCols = 16;
 
 enum ScalarOp { OP_ALPHA = 0, OP_CONV = 1, OP_BETA = 2, OP_F2 = 3, OP_R2 = 4, OP_TRUE = 5, OP_DOT = 6 };
@@ -298,29 +298,44 @@ struct Sell {
   const double *val;
 };
 
+// A slice is one wavefront, so its width is uniform across the wavefront; the
+// entries of a row are fetched U at a time (column indices, then the gathers of
+// x) with clamped unconditional loads, so that the loads of a chunk overlap.
+// Entries past the width are masked by a zero factor (padding entries already
+// hold zeros), which leaves the sum unchanged.
 template <int KC>
 __global__ __launch_bounds__(kBlock) void k_spmv(Sell A, const double *__restrict__ x, double *__restrict__ y,
                                                  int nrows, const CgScalars *sc, int sel, double *partials) {
   if (!any_selected<KC>(sc, sel, 0u)) return;
+  constexpr int U = KC <= 2 ? 8 : 4;
   Vec<KC> dot;
   dot.zero();
   for (int row = blockIdx.x * kBlock + threadIdx.x; row < nrows; row += gridDim.x * kBlock) {
     const int s = row >> 6, lane = row & 63;
     const int base = A.sptr[s], len = A.slen[s];
+    Vec<KC> xr;
+    if (partials) xr.load(x + (size_t)row * KC);
     Vec<KC> acc;
     acc.zero();
-    for (int c = 0; c < len; ++c) {
-      const int e = base + c * kSlice + lane;
-      const double a = A.val[e];
-      Vec<KC> xv;
-      xv.load(x + (size_t)A.col[e] * KC);
+    for (int c0 = 0; c0 < len; c0 += U) {
+      int cl[U];
+      double a[U];
 #pragma unroll
-      for (int k = 0; k < KC; ++k) acc.v[k] = __builtin_fma(a, xv.v[k], acc.v[k]);
+      for (int u = 0; u < U; ++u) {
+        const int e = base + min(c0 + u, len - 1) * kSlice + lane;
+        cl[u] = A.col[e];
+        a[u] = A.val[e] * (c0 + u < len ? 1.0 : 0.0);
+      }
+      Vec<KC> xv[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) xv[u].load(x + (size_t)cl[u] * KC);
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int k = 0; k < KC; ++k) acc.v[k] = __builtin_fma(a[u], xv[u].v[k], acc.v[k]);
     }
     acc.store(y + (size_t)row * KC);
     if (partials) {
-      Vec<KC> xr;
-      xr.load(x + (size_t)row * KC);
 #pragma unroll
       for (int k = 0; k < KC; ++k) dot.v[k] = __builtin_fma(xr.v[k], acc.v[k], dot.v[k]);
     }
@@ -379,42 +394,64 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(double *u, double *r, cons
   block_partials<KC>(rr, rr_parts);
 }
 
-// z = P c + sum of the star slots of every dof (ascending star order), r.z partials
-template <typename TS, int KC>
+// z = P c + sum of the star slots of every dof (ascending star order), r.z partials.
+// The NV prolongation entries and slot indices of a dof are adjacent (vector
+// loads); absent ones (index -1, weight 0) are read at index 0 and masked by a
+// zero factor, so every gather is issued before the first one is used.
+template <typename TS, int KC, int NV>
 __global__ __launch_bounds__(kBlock) void k_reduce(double *z, const double *r, const TS *__restrict__ slots,
                                                    const int32_t *__restrict__ slot_of,
                                                    const int32_t *__restrict__ Pc, const double *__restrict__ Pw,
-                                                   const double *__restrict__ cvec, int n, int nv,
+                                                   const double *__restrict__ cvec, int n,
                                                    const CgScalars *sc, int sel, double *partials) {
   if (!any_selected<KC>(sc, sel, 0u)) return;
   Vec<KC> rz;
   rz.zero();
   for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+    int pc[NV], so[NV];
+    double pw[NV];
+#pragma unroll
+    for (int b = 0; b < NV; b += 4) {
+      const int4 c4 = *reinterpret_cast<const int4 *>(Pc + (size_t)i * NV + b);
+      const int4 s4 = *reinterpret_cast<const int4 *>(slot_of + (size_t)i * NV + b);
+      const double2 w0 = *reinterpret_cast<const double2 *>(Pw + (size_t)i * NV + b);
+      const double2 w1 = *reinterpret_cast<const double2 *>(Pw + (size_t)i * NV + b + 2);
+      pc[b] = c4.x;
+      pc[b + 1] = c4.y;
+      pc[b + 2] = c4.z;
+      pc[b + 3] = c4.w;
+      so[b] = s4.x;
+      so[b + 1] = s4.y;
+      so[b + 2] = s4.z;
+      so[b + 3] = s4.w;
+      pw[b] = w0.x;
+      pw[b + 1] = w0.y;
+      pw[b + 2] = w1.x;
+      pw[b + 3] = w1.y;
+    }
+    Vec<KC> cv[NV];
+    SlotVec<TS, KC> sv[NV];
+#pragma unroll
+    for (int b = 0; b < NV; ++b) {
+      cv[b].load(cvec + (size_t)max(pc[b], 0) * KC);
+      sv[b].load(slots + (size_t)max(so[b], 0) * KC);
+    }
+    Vec<KC> rv;
+    if (partials) rv.load(r + (size_t)i * KC);
     Vec<KC> acc;
     acc.zero();
-    for (int b = 0; b < nv; ++b) {
-      const int c = Pc[(size_t)i * nv + b];
-      if (c >= 0) {
-        const double w = Pw[(size_t)i * nv + b];
-        Vec<KC> cv;
-        cv.load(cvec + (size_t)c * KC);
 #pragma unroll
-        for (int k = 0; k < KC; ++k) acc.v[k] = __builtin_fma(w, cv.v[k], acc.v[k]);
-      }
-    }
-    for (int b = 0; b < nv; ++b) {
-      const int s = slot_of[(size_t)i * nv + b];
-      if (s >= 0) {
-        SlotVec<TS, KC> sv;
-        sv.load(slots + (size_t)s * KC);
+    for (int b = 0; b < NV; ++b)
 #pragma unroll
-        for (int k = 0; k < KC; ++k) acc.v[k] += (double)sv.v[k];
-      }
+      for (int k = 0; k < KC; ++k) acc.v[k] = __builtin_fma(pw[b], cv[b].v[k], acc.v[k]);
+#pragma unroll
+    for (int b = 0; b < NV; ++b) {
+      const double m = so[b] >= 0 ? 1.0 : 0.0;
+#pragma unroll
+      for (int k = 0; k < KC; ++k) acc.v[k] += m * (double)sv[b].v[k];
     }
     acc.store(z + (size_t)i * KC);
     if (partials) {
-      Vec<KC> rv;
-      rv.load(r + (size_t)i * KC);
 #pragma unroll
       for (int k = 0; k < KC; ++k) rz.v[k] = __builtin_fma(rv.v[k], acc.v[k], rz.v[k]);
     }
@@ -485,21 +522,21 @@ __global__ __launch_bounds__(kBlock) void k_restrict(const int32_t *__restrict__
   for (int qb = q0 + lane; qb < q1; qb += 64 * U) {
     int idx[U];
     double wq[U];
+    // clamped unconditional loads; entries past the list are masked by a zero
+    // weight, which leaves the sum unchanged
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int q = qb + 64 * u;
-      idx[u] = q < q1 ? dof[q] : 0;
-      wq[u] = q < q1 ? w[q] : 0.0;
+      const int q = qb + 64 * u, qc = min(q, q1 - 1);
+      idx[u] = dof[qc];
+      wq[u] = w[qc] * (q < q1 ? 1.0 : 0.0);
     }
     Vec<KC> rv[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) rv[u].load(r + (size_t)idx[u] * KC);
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      if (qb + 64 * u >= q1) break;
+    for (int u = 0; u < U; ++u)
 #pragma unroll
       for (int k = 0; k < KC; ++k) acc.v[k] = __builtin_fma(wq[u], rv[u].v[k], acc.v[k]);
-    }
   }
   Vec<KC> out;
 #pragma unroll
@@ -1019,6 +1056,7 @@ void device_setup(Precond &pre, const HostFactors &hf, int precision) {
   d->npad = (sys.n + kBlock - 1) / kBlock * kBlock;
   d->m0 = pre.m0;
   d->nv = pre.nvert_per_elem;
+  if (d->nv != 4 && d->nv != 8) fail(SN_EINVAL, "coarse elements must have 4 (2D) or 8 (3D) vertices");
   const int64_t n = sys.n, npad = d->npad;
   if (n >= (int64_t)1 << 30) fail(SN_EINVAL, "system too large for 32-bit indices");
   sn_factor_info fi{};
@@ -1339,12 +1377,17 @@ void launch_B(Engine &e, const double *r, double *z, int sel, bool dot, hipStrea
     constexpr int KC = decltype(K)::value;
     const unsigned G = grid_for(d.npad);
     double *parts = dot ? e.partials.p : nullptr;
-    if (d.precision == SN_PREC_FP32_STARS)
-      hipLaunchKernelGGL((k_reduce<float, KC>), dim3(G), dim3(kBlock), 0, s, z, r, e.slots32.p, d.slot_of.p, d.Pc.p,
-                         d.Pw.p, e.c.p, (int)d.npad, d.nv, e.sc.p, sel, parts);
-    else
-      hipLaunchKernelGGL((k_reduce<double, KC>), dim3(G), dim3(kBlock), 0, s, z, r, e.slots64.p, d.slot_of.p, d.Pc.p,
-                         d.Pw.p, e.c.p, (int)d.npad, d.nv, e.sc.p, sel, parts);
+    auto red = [&](auto nvc) {
+      constexpr int NV = decltype(nvc)::value;
+      if (d.precision == SN_PREC_FP32_STARS)
+        hipLaunchKernelGGL((k_reduce<float, KC, NV>), dim3(G), dim3(kBlock), 0, s, z, r, e.slots32.p, d.slot_of.p,
+                           d.Pc.p, d.Pw.p, e.c.p, (int)d.npad, e.sc.p, sel, parts);
+      else
+        hipLaunchKernelGGL((k_reduce<double, KC, NV>), dim3(G), dim3(kBlock), 0, s, z, r, e.slots64.p, d.slot_of.p,
+                           d.Pc.p, d.Pw.p, e.c.p, (int)d.npad, e.sc.p, sel, parts);
+    };
+    if (d.nv == 4) red(std::integral_constant<int, 4>{});
+    else red(std::integral_constant<int, 8>{});
     if (dot && !kFuseScalars<KC>)
       hipLaunchKernelGGL(k_scalar<KC>, dim3(1), dim3(kBlock), 0, s, e.partials.p, (int)G, e.sc.p, (int)OP_BETA, sel,
                          0u);
