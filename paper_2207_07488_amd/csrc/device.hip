@@ -139,6 +139,29 @@ __device__ __forceinline__ void block_partials(const Vec<KC> &v, double *partial
   }
 }
 
+// thread t adds partials t, t+256, ... of every column in order; IB of them are
+// loaded before the first is added (entries past nparts are skipped by a zero
+// factor: adding +0 leaves a sum unchanged)
+template <int KC>
+__device__ __forceinline__ void partial_sums(const double *__restrict__ partials, int nparts, int t, Vec<KC> &sum) {
+  constexpr int IB = KC <= 4 ? 8 : (KC <= 8 ? 4 : 2);
+  static_assert(kMaxGrid % (kBlock * IB) == 0, "batches of partials");
+  for (int i0 = 0; i0 < nparts; i0 += kBlock * IB) {
+    double v[IB][KC];
+#pragma unroll
+    for (int u = 0; u < IB; ++u) {
+      const int i = i0 + kBlock * u + t;
+      const double m = i < nparts ? 1.0 : 0.0;
+#pragma unroll
+      for (int c = 0; c < KC; ++c) v[u][c] = partials[c * kMaxGrid + min(i, kMaxGrid - 1)] * m;
+    }
+#pragma unroll
+    for (int u = 0; u < IB; ++u)
+#pragma unroll
+      for (int c = 0; c < KC; ++c) sum.v[c] += v[u][c];
+  }
+}
+
 // the per-column totals of partials, as k_scalar forms them (same order), in
 // every thread of the block: lets a consumer kernel reduce redundantly in each
 // block instead of a one-block kernel in between
@@ -149,13 +172,7 @@ __device__ __forceinline__ void block_totals(const double *__restrict__ partials
   __shared__ double res[KC];
   Vec<KC> sum;
   sum.zero();
-  for (int i = threadIdx.x; i < nparts; i += kBlock) {
-    double v[KC];
-#pragma unroll
-    for (int c = 0; c < KC; ++c) v[c] = partials[c * kMaxGrid + i];
-#pragma unroll
-    for (int c = 0; c < KC; ++c) sum.v[c] += v[c];
-  }
+  partial_sums<KC>(partials, nparts, (int)threadIdx.x, sum);
   (void)on;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
@@ -190,43 +207,41 @@ __device__ __forceinline__ bool any_selected(const CgScalars *sc, int sel, uint3
 
 // one block: combine the partials of the previous kernel per column and update
 // the scalars of the selected columns. Every column is summed like a single
-// one (thread t adds partials t, t+256, ... in order, then a fixed block tree),
-// all columns at once.
+// one (thread t adds partials t, t+256, ... in order, then a fixed block tree).
+// Columns come in groups of at most four, one group per 256 threads.
 template <int KC>
-__global__ __launch_bounds__(kBlock) void k_scalar(const double *__restrict__ partials, int nparts, CgScalars *sc,
-                                                   int op, int sel, uint32_t mask) {
-  __shared__ double sh[kBlock / 64][KC];
-  bool on[KC];
+constexpr int scalar_groups() {
+  return KC > 4 ? KC / 4 : 1;
+}
+
+template <int KC>
+__global__ __launch_bounds__(kBlock * 4) void k_scalar(const double *__restrict__ partials, int nparts, CgScalars *sc,
+                                                       int op, int sel, uint32_t mask) {
+  constexpr int NG = scalar_groups<KC>(), CPG = KC / NG;
+  __shared__ double sh[NG][kBlock / 64][CPG];
   bool any = false;
 #pragma unroll
-  for (int c = 0; c < KC; ++c) {
-    on[c] = column_selected(sc[c], sel, mask, c);
-    any |= on[c];
-  }
+  for (int c = 0; c < KC; ++c) any |= column_selected(sc[c], sel, mask, c);
   if (!any) return;
-  // every column is loaded (the sums of unselected ones are not used), so that
-  // all loads of a thread are in flight together
-  Vec<KC> sum;
+  const int g = threadIdx.x / kBlock, t = threadIdx.x % kBlock;
+  // every column of the group is loaded (the sums of unselected ones are not
+  // used), so that all loads of a thread are in flight together
+  Vec<CPG> sum;
   sum.zero();
-  for (int i = threadIdx.x; i < nparts; i += kBlock) {
-    double v[KC];
+  partial_sums<CPG>(partials + (size_t)g * CPG * kMaxGrid, nparts, t, sum);
+  const int lane = t & 63, w = t >> 6;
 #pragma unroll
-    for (int c = 0; c < KC; ++c) v[c] = partials[c * kMaxGrid + i];
-#pragma unroll
-    for (int c = 0; c < KC; ++c) sum.v[c] += v[c];
-  }
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-#pragma unroll
-  for (int c = 0; c < KC; ++c) {
+  for (int c = 0; c < CPG; ++c) {
     const double v = wave_sum(sum.v[c]);
-    if (lane == 0) sh[w][c] = v;
+    if (lane == 0) sh[g][w][c] = v;
   }
   __syncthreads();
-  if (threadIdx.x != 0) return;
-  for (int c = 0; c < KC; ++c) {
-    if (!on[c]) continue;
+  if (t != 0) return;
+  for (int cc = 0; cc < CPG; ++cc) {
+    const int c = g * CPG + cc;
+    if (!column_selected(sc[c], sel, mask, c)) continue;
     double tot = 0.0;
-    for (int i = 0; i < kBlock / 64; ++i) tot += sh[i][c];
+    for (int i = 0; i < kBlock / 64; ++i) tot += sh[g][i][cc];
     CgScalars &x = sc[c];
     switch (op) {
       case OP_ALPHA:
@@ -1389,8 +1404,8 @@ void launch_B(Engine &e, const double *r, double *z, int sel, bool dot, hipStrea
     if (d.nv == 4) red(std::integral_constant<int, 4>{});
     else red(std::integral_constant<int, 8>{});
     if (dot && !kFuseScalars<KC>)
-      hipLaunchKernelGGL(k_scalar<KC>, dim3(1), dim3(kBlock), 0, s, e.partials.p, (int)G, e.sc.p, (int)OP_BETA, sel,
-                         0u);
+      hipLaunchKernelGGL(k_scalar<KC>, dim3(1), dim3(kBlock * scalar_groups<KC>()), 0, s,
+                       e.partials.p, (int)G, e.sc.p, (int)OP_BETA, sel, 0u);
   });
 }
 
@@ -1404,8 +1419,8 @@ void launch_spmv(Engine &e, const double *x, double *y, int sel, bool dot, hipSt
     hipLaunchKernelGGL(k_spmv<KC>, dim3(G), dim3(kBlock), 0, s, A, x, y, (int)d.npad, e.sc.p, sel,
                        dot ? e.partials.p : nullptr);
     if (dot && !kFuseScalars<KC>)
-      hipLaunchKernelGGL(k_scalar<KC>, dim3(1), dim3(kBlock), 0, s, e.partials.p, (int)G, e.sc.p, (int)OP_ALPHA, sel,
-                         0u);
+      hipLaunchKernelGGL(k_scalar<KC>, dim3(1), dim3(kBlock * scalar_groups<KC>()), 0, s,
+                       e.partials.p, (int)G, e.sc.p, (int)OP_ALPHA, sel, 0u);
   });
 }
 
@@ -1418,7 +1433,8 @@ void launch_iteration(Engine &e, hipStream_t s) {
     constexpr int KC = decltype(K)::value;
     hipLaunchKernelGGL(k_cg_update<KC>, dim3(G), dim3(kBlock), 0, s, e.u.p, e.r.p, e.p.p, e.q.p, (int)d.npad, e.sc.p,
                        e.partials.p, (int)G, e.partials2.p);
-    hipLaunchKernelGGL(k_scalar<KC>, dim3(1), dim3(kBlock), 0, s, e.partials2.p, (int)G, e.sc.p, (int)OP_CONV,
+    hipLaunchKernelGGL(k_scalar<KC>, dim3(1), dim3(kBlock * scalar_groups<KC>()), 0, s,
+                       e.partials2.p, (int)G, e.sc.p, (int)OP_CONV,
                        (int)SEL_FIRST, 0u);
   });
   launch_B(e, e.r.p, e.z.p, SEL_SECOND, true, s);
@@ -1438,7 +1454,8 @@ void launch_verify(Engine &e, hipStream_t s) {
     constexpr int KC = decltype(K)::value;
     hipLaunchKernelGGL(k_sub_dot<KC>, dim3(G), dim3(kBlock), 0, s, e.q.p, e.f.p, e.q.p, (int)d.npad, e.sc.p,
                        (int)SEL_VERIFY, 0u, e.partials.p);
-    hipLaunchKernelGGL(k_scalar<KC>, dim3(1), dim3(kBlock), 0, s, e.partials.p, (int)G, e.sc.p, (int)OP_TRUE,
+    hipLaunchKernelGGL(k_scalar<KC>, dim3(1), dim3(kBlock * scalar_groups<KC>()), 0, s,
+                       e.partials.p, (int)G, e.sc.p, (int)OP_TRUE,
                        (int)SEL_VERIFY, 0u);
     hipLaunchKernelGGL(k_copy_sel<KC>, dim3(G), dim3(kBlock), 0, s, e.r.p, e.q.p, (int)d.npad, e.sc.p,
                        (int)SEL_RESTART, 0u);
@@ -1454,11 +1471,13 @@ void launch_start_dots(Engine &e, uint32_t mask, hipStream_t s) {
     constexpr int KC = decltype(K)::value;
     hipLaunchKernelGGL(k_dot<KC>, dim3(G), dim3(kBlock), 0, s, e.f.p, e.f.p, (int)d.npad, e.partials.p, e.sc.p,
                        (int)SEL_MASK, mask);
-    hipLaunchKernelGGL(k_scalar<KC>, dim3(1), dim3(kBlock), 0, s, e.partials.p, (int)G, e.sc.p, (int)OP_F2,
+    hipLaunchKernelGGL(k_scalar<KC>, dim3(1), dim3(kBlock * scalar_groups<KC>()), 0, s,
+                       e.partials.p, (int)G, e.sc.p, (int)OP_F2,
                        (int)SEL_MASK, mask);
     hipLaunchKernelGGL(k_dot<KC>, dim3(G), dim3(kBlock), 0, s, e.r.p, e.r.p, (int)d.npad, e.partials.p, e.sc.p,
                        (int)SEL_MASK, mask);
-    hipLaunchKernelGGL(k_scalar<KC>, dim3(1), dim3(kBlock), 0, s, e.partials.p, (int)G, e.sc.p, (int)OP_R2,
+    hipLaunchKernelGGL(k_scalar<KC>, dim3(1), dim3(kBlock * scalar_groups<KC>()), 0, s,
+                       e.partials.p, (int)G, e.sc.p, (int)OP_R2,
                        (int)SEL_MASK, mask);
   });
 }
