@@ -45,6 +45,12 @@ struct Pack<float> {
   static __device__ __forceinline__ float lane(float v) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), L));
   }
+  // v with lane L replaced by the wavefront-uniform value u
+  template <int L>
+  static __device__ __forceinline__ float put(float u, float v) {
+    asm("v_writelane_b32 %0, %1, %2" : "+v"(v) : "s"(u), "i"(L));
+    return v;
+  }
   static __device__ __forceinline__ float fnma(float m, float g, float x) { return __builtin_fmaf(-m, g, x); }
   // per-lane selects at a step: lanes whose bit is set in `up` (an SGPR pair)
   // take `hi`, the others `lo`
@@ -77,6 +83,13 @@ struct Pack<double> {
   template <int L>
   static __device__ __forceinline__ double lane(double v) {
     return mk(__builtin_amdgcn_readlane(lo(v), L), __builtin_amdgcn_readlane(hi(v), L));
+  }
+  template <int L>
+  static __device__ __forceinline__ double put(double u, double v) {
+    int vl = lo(v), vh = hi(v);
+    asm("v_writelane_b32 %0, %1, %2" : "+v"(vl) : "s"(lo(u)), "i"(L));
+    asm("v_writelane_b32 %0, %1, %2" : "+v"(vh) : "s"(hi(u)), "i"(L));
+    return mk(vl, vh);
   }
   static __device__ __forceinline__ double fnma(double m, double g, double x) { return __builtin_fma(-m, g, x); }
   // per-lane selects at a step: lanes whose bit is set in `up` take `hi`
@@ -183,7 +196,13 @@ __device__ __forceinline__ void sweep(T *sl, int c0, int n, const uint16_t *__re
 #pragma unroll
     for (int c = 0; c < CW; ++c) dst[c] = p < n ? rw.v[c] : T(0);
   };
+  // One column and a window of one register (rows 64 b + l, and 64 (b + 1) + l
+  // in R[1]): lane l keeps only its open row in R[0] and swaps in its next row
+  // at step l, so that every step applies one multiplier per lane; the same
+  // updates as the general form, without the zero ones.
+  constexpr bool ROT = Q == 1 && CW == 1;
   T R[Q + 1][CW];
+  T done = T(0);  // ROT: the finished rows of the block, lane l at step l
 #pragma unroll
   for (int q = 0; q <= Q; ++q) load_row(lane + 64 * q, R[q]);
   T inc[CW];
@@ -251,24 +270,34 @@ __device__ __forceinline__ void sweep(T *sl, int c0, int n, const uint16_t *__re
         constexpr int gi = s / SG, k = s % SG;
         constexpr int slot = (H * GPB + gi) % RG;
         const V(&cur)[Q] = ring[slot];
-        T g[CW];
+        if constexpr (ROT) {
+          // one open row per lane: lane s hands its finished row to `done`
+          // and takes its next row; then every lane takes its multiplier
+          const T g = P::template lane<s>(R[0][0]);
+          done = P::template put<s>(g, done);
+          R[0][0] = P::pick(R[1][0], R[0][0], 1ull << s);
+          R[0][0] = P::fnma(P::get(cur[0], k), g, R[0][0]);
+          asm volatile("" : "+v"(R[0][0]));
+        } else {
+          T g[CW];
 #pragma unroll
-        for (int c = 0; c < CW; ++c) g[c] = P::template lane<s>(R[0][c]);
-        T M[Q + 1];
-        M[0] = P::pick_or_zero(P::get(cur[0], k), up);
+          for (int c = 0; c < CW; ++c) g[c] = P::template lane<s>(R[0][c]);
+          T M[Q + 1];
+          M[0] = P::pick_or_zero(P::get(cur[0], k), up);
 #pragma unroll
-        for (int q = 1; q < Q; ++q) M[q] = P::pick(P::get(cur[q], k), P::get(cur[q - 1], k), up);
-        M[Q] = P::zero_or_pick(P::get(cur[Q - 1], k), up);
-        up <<= 1;
+          for (int q = 1; q < Q; ++q) M[q] = P::pick(P::get(cur[q], k), P::get(cur[q - 1], k), up);
+          M[Q] = P::zero_or_pick(P::get(cur[Q - 1], k), up);
+          up <<= 1;
 #pragma unroll
-        for (int q = 0; q <= Q; ++q)
+          for (int q = 0; q <= Q; ++q)
 #pragma unroll
-          for (int c = 0; c < CW; ++c) {
-            R[q][c] = P::fnma(M[q], g[c], R[q][c]);
-            // keep every update in its step: otherwise updates of registers
-            // not read during the block sink to its end with their operands live
-            asm volatile("" : "+v"(R[q][c]));
-          }
+            for (int c = 0; c < CW; ++c) {
+              R[q][c] = P::fnma(M[q], g[c], R[q][c]);
+              // keep every update in its step: otherwise updates of registers
+              // not read during the block sink to its end with their operands live
+              asm volatile("" : "+v"(R[q][c]));
+            }
+        }
         if constexpr (k == SG - 1) {
           // the group is consumed: fetch the group RG positions ahead into its slot
           constexpr int li = gi + RG;
@@ -278,13 +307,15 @@ __device__ __forceinline__ void sweep(T *sl, int c0, int n, const uint16_t *__re
       if (jb + lane < n) {
         Row<T, CW> rw;
 #pragma unroll
-        for (int c = 0; c < CW; ++c) rw.v[c] = R[0][c] * hinv;
+        for (int c = 0; c < CW; ++c) rw.v[c] = (ROT ? done : R[0][c]) * hinv;
         rw.store(sl + (size_t)(REV ? n - 1 - (jb + lane) : jb + lane) * KC + c0);
       }
+      if constexpr (!ROT) {
 #pragma unroll
-      for (int q = 0; q < Q; ++q)
+        for (int q = 0; q < Q; ++q)
 #pragma unroll
-        for (int c = 0; c < CW; ++c) R[q][c] = R[q + 1][c];
+          for (int c = 0; c < CW; ++c) R[q][c] = R[q + 1][c];
+      }
 #pragma unroll
       for (int c = 0; c < CW; ++c) {
         R[Q][c] = inc[c];
