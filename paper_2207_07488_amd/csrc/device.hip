@@ -559,47 +559,47 @@ __global__ __launch_bounds__(kBlock) void k_restrict(const int32_t *__restrict__
   if (lane == 0) out.store(rH + (size_t)g * KC);
 }
 
-// c = K_0^{-1} r_H on the matrix cores (v_mfma_f64_16x16x4f64: a 16 x 4 by
-// 4 x 16 product per instruction, accumulated in FP64). The inverse is stored
-// symmetric, padded with zeros to ld x ld (ld a multiple of 16), in TA (double,
-// or float in the mixed-precision form, converted exactly to double on load).
-// r_H and c have ld rows (r_H zero past m0).
-// A workgroup of kMmWaves wavefronts owns a 16-row tile; wavefront w takes a
-// contiguous range of 16-column groups and accumulates its 16 x 16 tile of
-// products (rows x columns of r_H; columns past KC are discarded); the
-// wavefront tiles are summed in LDS in wavefront order. Every column of the
-// product is computed by the same instructions whatever KC is, so a batched
-// column equals the single-column result bit for bit.
-typedef double mm_d4 __attribute__((ext_vector_type(4)));
+// c = K_0^{-1} r_H on the matrix cores: v_mfma_f64_4x4x4_4b_f64 computes four
+// independent 4 x 4 by 4 x 4 products (blocks y = 0..3) per instruction,
+// accumulated in FP64. Lane l = 16 k + 4 y + i supplies A_y[i][k] and
+// B_y[k][j = i]; the result D_y[i][j] sits in lane 16 i + 4 y + j (layout
+// checked on the device). The inverse is stored symmetric, padded with zeros
+// to ld x ld (ld a multiple of 64), in TA (double, or float in the mixed form,
+// converted exactly on load); r_H and c have ld rows (r_H zero past m0).
+// A workgroup of 16 wavefronts owns 16 rows: wavefront w takes rows
+// 4 (w mod 4) .. + 3 and the (w / 4)-th quarter of the 64-column chunks. In a
+// chunk, lane (k, y, i) loads 4 adjacent columns 16 y + 4 k .. + 3 of its row
+// (a load instruction reads 4 rows x 64 contiguous columns) and the four
+// instructions s = 0..3 of the chunk take one of them each; block y thus sums
+// the columns 16 y .. 16 y + 15 of every chunk. Column j NG + g of r_H
+// (j = 0..3) goes to accumulator g, NG = ceil(KC / 4) accumulators; with fewer
+// than four columns, positions past KC repeat column KC - 1 and are discarded. The partial products are added in LDS in a fixed order (column
+// quarter, then block), so every column is computed by the same instructions
+// whatever KC is and a batched column equals the single-column result bit for bit.
 constexpr int kMmWaves = 16;
 
 template <typename TA>
 struct MmLoad;
-// FP64: a lane loads two 16-byte pieces of its row (columns 2q, 2q+1 and
-// 8+2q, 8+2q+1 of the group, q = lane / 16): both loads of a wavefront are
-// 64 contiguous bytes per row
 template <>
 struct MmLoad<double> {
-  static __device__ __forceinline__ int col(int q, int s) { return (s >> 1) * 8 + 2 * q + (s & 1); }
-  static __device__ __forceinline__ void load(const double *p, int q, double (&a)[4]) {
-    const double2 u = *reinterpret_cast<const double2 *>(p + 2 * q);
-    const double2 v = *reinterpret_cast<const double2 *>(p + 8 + 2 * q);
+  static __device__ __forceinline__ void load(const double *p, double (&a)[4]) {
+    const double2 u = *reinterpret_cast<const double2 *>(p);
+    const double2 v = *reinterpret_cast<const double2 *>(p + 2);
     a[0] = u.x;
     a[1] = u.y;
     a[2] = v.x;
     a[3] = v.y;
   }
 };
-// FP32: one 16-byte load of columns 4q..4q+3 of the group
+// FP32 values stay FP32 until the product that uses them converts them
 template <>
 struct MmLoad<float> {
-  static __device__ __forceinline__ int col(int q, int s) { return 4 * q + s; }
-  static __device__ __forceinline__ void load(const float *p, int q, double (&a)[4]) {
-    const float4 u = *reinterpret_cast<const float4 *>(p + 4 * q);
-    a[0] = (double)u.x;
-    a[1] = (double)u.y;
-    a[2] = (double)u.z;
-    a[3] = (double)u.w;
+  static __device__ __forceinline__ void load(const float *p, float (&a)[4]) {
+    const float4 u = *reinterpret_cast<const float4 *>(p);
+    a[0] = u.x;
+    a[1] = u.y;
+    a[2] = u.z;
+    a[3] = u.w;
   }
 };
 
@@ -607,63 +607,83 @@ template <typename TA, int KC>
 __global__ __launch_bounds__(64 * kMmWaves) void k_coarse_mm(const TA *__restrict__ Kinv, int ld,
                                                              const double *__restrict__ rH, double *cvec, int m0,
                                                              const CgScalars *sc, int sel) {
-  static_assert(KC >= 1 && KC <= 16, "the product tile holds 16 columns");
-  __shared__ double part[kMmWaves][256];
+  static_assert(KC >= 1 && KC <= 16, "up to four groups of four columns");
+  constexpr int NG = (KC + 3) / 4;  // column groups
+  constexpr int UC = (NG >= 3 || sizeof(TA) == 8) ? 2 : 4;  // chunks loaded before their products
+  __shared__ double part[kMmWaves][4][4 * NG * 4];  // [wave][block][row * 4 NG + column]
   if (!any_selected<KC>(sc, sel, 0u)) return;
-  constexpr int UG = 4;  // groups loaded before their products
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int i = lane & 15, q = lane >> 4;  // A operand: row i; B operand: column i; k quad q
-  const int row0 = blockIdx.x * 16;
-  const int groups = ld / 16;
-  const int gpw = (groups + kMmWaves - 1) / kMmWaves;
-  const int g0 = min(groups, wv * gpw), g1 = min(groups, g0 + gpw);
-  const TA *arow = Kinv + (size_t)(row0 + i) * ld;
-  auto load_group = [&](int g, double (&a)[4], double (&b)[4]) {
-    MmLoad<TA>::load(arow + 16 * g, q, a);
-    // r_H has ld rows (zero past m0), so no masks: product columns past KC
-    // repeat column KC - 1 and are never stored
-    if constexpr (KC == 1) {
-      // the column pairs (0, 1) and (2, 3) of a lane are adjacent
-      const double2 u = *reinterpret_cast<const double2 *>(rH + 16 * g + MmLoad<TA>::col(q, 0));
-      const double2 v = *reinterpret_cast<const double2 *>(rH + 16 * g + MmLoad<TA>::col(q, 2));
-      b[0] = u.x;
-      b[1] = u.y;
-      b[2] = v.x;
-      b[3] = v.y;
-    } else {
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int i = lane & 3, y = (lane >> 2) & 3, k = lane >> 4;
+  const int rt = wv & 3, qt = wv >> 2;  // row tile, column quarter
+  const int row0 = blockIdx.x * 16 + 4 * rt;
+  const int chunks = ld / 64, cpw = (chunks + 3) / 4;
+  const int c0 = min(chunks, qt * cpw), c1 = min(chunks, c0 + cpw);
+  const int col_l = 16 * y + 4 * k;  // the lane's first column in a chunk
+  const TA *arow = Kinv + (size_t)(row0 + i) * ld + col_l;
+  double acc[NG];
 #pragma unroll
-      for (int s = 0; s < 4; ++s) b[s] = rH[(size_t)(16 * g + MmLoad<TA>::col(q, s)) * KC + min(i, KC - 1)];
+  for (int g = 0; g < NG; ++g) acc[g] = 0.0;
+  for (int c = c0; c < c1; c += UC) {
+    TA a[UC][4];
+    double b[UC][NG][4];
+#pragma unroll
+    for (int u = 0; u < UC; ++u) {
+      // a short last batch repeats the wavefront's last chunk with a zero factor
+      const int cc = min(c + u, c1 - 1);
+      MmLoad<TA>::load(arow + (size_t)cc * 64, a[u]);
+      const int kb = cc * 64 + col_l;
+      if constexpr (KC == 1) {
+        const double2 p = *reinterpret_cast<const double2 *>(rH + kb);
+        const double2 q = *reinterpret_cast<const double2 *>(rH + kb + 2);
+        b[u][0][0] = p.x;
+        b[u][0][1] = p.y;
+        b[u][0][2] = q.x;
+        b[u][0][3] = q.y;
+      } else if constexpr (NG == 1) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) b[u][0][s] = rH[(size_t)(kb + s) * KC + min(i, KC - 1)];
+      } else {
+        // column j NG + g of r_H goes to accumulator g: a lane's NG columns are adjacent
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+          for (int g = 0; g < NG; g += 2) {
+            const double2 v = *reinterpret_cast<const double2 *>(rH + (size_t)(kb + s) * KC + NG * i + g);
+            b[u][g][s] = v.x;
+            b[u][g + 1][s] = v.y;
+          }
+      }
     }
-  };
-  mm_d4 acc = {0.0, 0.0, 0.0, 0.0};
-  int g = g0;
-  for (; g + UG <= g1; g += UG) {
-    double a[UG][4], b[UG][4];
-#pragma unroll
-    for (int u = 0; u < UG; ++u) load_group(g + u, a[u], b[u]);
-    // every load of the UG groups is issued before the first product waits
+    // every load of the batch is issued before the first product waits
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int u = 0; u < UG; ++u)
+    for (int u = 0; u < UC; ++u) {
+      const double m = c + u < c1 ? 1.0 : 0.0;
 #pragma unroll
-      for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][s], b[u][s], acc, 0, 0, 0);
+      for (int s = 0; s < 4; ++s) {
+        const double av = (double)a[u][s] * m;
+#pragma unroll
+        for (int g = 0; g < NG; ++g) acc[g] = __builtin_amdgcn_mfma_f64_4x4x4f64(av, b[u][g][s], acc[g], 0, 0, 0);
+      }
+    }
   }
-  for (; g < g1; ++g) {
-    double a[4], b[4];
-    load_group(g, a, b);
+  // lane l = 16 i' + 4 y' + j' holds block y', row i', column j' of each group
+  {
+    const int ir = lane >> 4, yb = (lane >> 2) & 3, jc = lane & 3;
 #pragma unroll
-    for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], b[s], acc, 0, 0, 0);
+    for (int g = 0; g < NG; ++g) part[wv][yb][ir * 4 * NG + NG * jc + g] = acc[g];
   }
-  // result layout: lane l, element v holds row l / 16 + 4 v, column l % 16
-#pragma unroll
-  for (int v = 0; v < 4; ++v) part[wv][(q + 4 * v) * 16 + i] = acc[v];
   __syncthreads();
-  if (threadIdx.x < 256) {
-    const int t = threadIdx.x, row = t >> 4, col = t & 15;
-    double sum = part[0][t];
+  // rows 4 rt + i'' of the workgroup, columns: quarters in order, blocks in order
+  for (int t = threadIdx.x; t < 16 * 4 * NG; t += 64 * kMmWaves) {
+    const int row = t / (4 * NG), col = t % (4 * NG), rtt = row >> 2, ir = row & 3;
+    double sum = 0.0;
 #pragma unroll
-    for (int w = 1; w < kMmWaves; ++w) sum += part[w][t];
-    if (col < KC && row0 + row < m0) cvec[(size_t)(row0 + row) * KC + col] = sum;
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int yb = 0; yb < 4; ++yb) sum += part[4 * q + rtt][yb][ir * 4 * NG + col];
+    const int grow = blockIdx.x * 16 + row;
+    if (col < KC && grow < m0) cvec[(size_t)grow * KC + col] = sum;
   }
 }
 
@@ -816,7 +836,7 @@ struct DeviceState {
   DBuf<float> f_inv32, b_inv32, f_val32, b_val32;
   DBuf<double> f_inv64, b_inv64, f_val64, b_val64;
   // coarse
-  // K_0^{-1}, symmetric, zero-padded to ld0 x ld0: FP32 in the mixed form
+  // K_0^{-1}, symmetric, zero-padded to ld0 x ld0 (ld0 a multiple of 64): FP32 in the mixed form
   // unless the coarse factor's pivot ratio rules it out, else FP64
   DBuf<double> Kinv64, PTw, Pw;
   DBuf<float> Kinv32;
@@ -1163,7 +1183,7 @@ void device_setup(Precond &pre, const HostFactors &hf, int precision) {
   const int nc = sys.ncomp, nv = d->nv;
   if (d->m0 > 0) {
     // symmetric (the mean of the two computed triangles) and padded
-    const int64_t m0 = d->m0, ld = (m0 + 15) / 16 * 16;
+    const int64_t m0 = d->m0, ld = (m0 + 63) / 64 * 64;
     d->ld0 = ld;
     d->coarse32 = precision == SN_PREC_FP32_STARS && hf.coarse_pivot_ratio * std::ldexp(1.0, -24) <= 0.05;
     auto sym = [&](int64_t i, int64_t j) {
@@ -1674,7 +1694,7 @@ int engine_width_for(int k) {
 
 int64_t engine_footprint(const Precond &pre, int kc) {
   const int64_t n = pre.sys->n, npad = (n + kBlock - 1) / kBlock * kBlock;
-  const int64_t m0 = (std::max<int64_t>(pre.m0, 1) + 15) / 16 * 16;
+  const int64_t m0 = (std::max<int64_t>(pre.m0, 1) + 63) / 64 * 64;
   const int prec = pre.dev ? pre.finfo.star_precision : pre.precision;
   const int64_t ts = prec == SN_PREC_FP32_STARS ? 4 : 8;
   return (6 * npad * kc + 2 * m0 * kc + (int64_t)2 * kc * kMaxGrid) * 8 + kc * (int64_t)sizeof(CgScalars) +
@@ -1695,9 +1715,9 @@ Engine *engine_create(Precond &pre, int kc) {
     b->alloc(np);
     b->zero();
   }
-  // r_H and c padded to the coarse operator's 16-row tiles; the padding of r_H
+  // r_H and c padded to the coarse operator's 64-row chunks; the padding of r_H
   // stays zero (the restriction writes rows below m0 only)
-  const size_t nm = (size_t)std::max<int64_t>(d.ld0, 16) * kc;
+  const size_t nm = (size_t)std::max<int64_t>(d.ld0, 64) * kc;
   e->rH.alloc(nm);
   e->c.alloc(nm);
   e->rH.zero();
