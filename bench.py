@@ -164,7 +164,7 @@ def serving_leg(n_requests, rate, pool_size=8, seed=5, load=0.7):
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--nH", type=int, default=64)
     ap.add_argument("--rtol", type=float, default=1e-8)
