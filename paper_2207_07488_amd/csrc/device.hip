@@ -1314,6 +1314,7 @@ StarArgs star_args(DeviceState &d, Engine &e) {
   a.f_zero = d.f_zero;
   a.b_zero = d.b_zero;
   a.lds_reserve = e.star_lds;
+  a.maxn = d.maxn;
   if (d.precision == SN_PREC_FP32_STARS) {
     a.f_inv = d.f_inv32.p;
     a.b_inv = d.b_inv32.p;

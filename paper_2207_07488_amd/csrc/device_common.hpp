@@ -81,7 +81,8 @@ struct StarArgs {
   const void *f_inv, *b_inv;                 // 1/pivot per step (T)
   const void *f_val, *b_val;                 // packed stream values (T)
   int64_t f_zero, b_zero;                    // element offset of a zero region (16 KB) in f_val / b_val
-  int32_t lds_reserve;                       // dynamic LDS per workgroup (unused; caps waves per CU)
+  int32_t lds_reserve;                       // dynamic LDS per workgroup: caps waves per CU
+  int32_t maxn;                              // largest star (positions)
   void *slots;                               // T, per position and column (position-major)
 };
 

@@ -11,8 +11,10 @@ namespace spnet {
 // once. One wavefront per star; the factor streams are read once for all
 // columns.
 //
-// The star's vector lives in its slot segment (global memory, position-major:
-// the KC values of a position are adjacent) in factor order. The forward sweep
+// The star's working vector (position-major: the KC values of a position are
+// adjacent) is in factor order; it lives in LDS during the sweeps when the
+// largest star's fits in 32 KB, else in the star's slot segment in global
+// memory; z_j ends in the slot segment either way. The forward sweep
 // walks the columns of L (step j: entries L_{j+1..j+w, j}); the backward sweep
 // walks the rows of L from the last one (step s = row n-1-s: entries
 // L_{i, i-1..i-w}) on the vector read in reverse, which makes it the same
@@ -362,9 +364,13 @@ __device__ __forceinline__ void star_solve(const StarArgs &a, int st, int n, T *
 }
 
 // WIDE = false: stars with windows of 1-2 registers, true: 4-16 registers (kept
-// in separate kernels so that each gets the registers its variants need)
-template <typename T, bool WIDE, int KC>
+// in separate kernels so that each gets the registers its variants need).
+// LV: the star's working vector lives in LDS during the sweeps (gathered into
+// it, swept in place, copied to the slots at the end) instead of in its slot
+// segment.
+template <typename T, bool WIDE, int KC, bool LV>
 __global__ __launch_bounds__(64) void k_star(StarArgs a, const double *__restrict__ r, const CgScalars *sc, int sel) {
+  extern __shared__ __align__(16) unsigned char star_lds[];
   if (sel != SEL_ALL) {
     bool any = false;
 #pragma unroll
@@ -377,6 +383,7 @@ __global__ __launch_bounds__(64) void k_star(StarArgs a, const double *__restric
   const int n = a.st_n[st], vb = a.st_vb[st], Q = a.st_q[st];
   const int lane = threadIdx.x;
   T *sl = static_cast<T *>(a.slots) + (size_t)vb * KC;
+  T *vec = LV ? reinterpret_cast<T *>(star_lds) : sl;
   // gather r (KC adjacent values per dof) in factor order, U rows per lane in
   // flight; clamped unconditional loads keep them all in flight
   constexpr int U = KC <= 2 ? 16 : 32 / KC;
@@ -395,28 +402,46 @@ __global__ __launch_bounds__(64) void k_star(StarArgs a, const double *__restric
         Row<T, KC> o;
 #pragma unroll
         for (int c = 0; c < KC; ++c) o.v[c] = (T)val[u].v[c];
-        o.store(sl + (size_t)p * KC);
+        o.store(vec + (size_t)p * KC);
       }
     }
   }
   __syncthreads();
   if constexpr (!WIDE) {
-    if (Q == 1) star_solve<T, KC, 1>(a, st, n, sl);
-    else star_solve<T, KC, 2>(a, st, n, sl);
+    if (Q == 1) star_solve<T, KC, 1>(a, st, n, vec);
+    else star_solve<T, KC, 2>(a, st, n, vec);
   } else {
-    if (Q == 4) star_solve<T, KC, 4>(a, st, n, sl);
-    else if (Q == 8) star_solve<T, KC, 8>(a, st, n, sl);
-    else star_solve<T, KC, 16>(a, st, n, sl);
+    if (Q == 4) star_solve<T, KC, 4>(a, st, n, vec);
+    else if (Q == 8) star_solve<T, KC, 8>(a, st, n, vec);
+    else star_solve<T, KC, 16>(a, st, n, vec);
+  }
+  if constexpr (LV) {
+    // z_j to the star's slots
+    for (int p = lane; p < n; p += 64) {
+      Row<T, KC> o;
+      o.load(vec + (size_t)p * KC);
+      o.store(sl + (size_t)p * KC);
+    }
   }
 }
 
 template <typename T, int KC>
 void launch_star_t(const StarArgs &a, bool wide, const double *r, const CgScalars *sc, int sel, hipStream_t s) {
   if (a.nstars <= 0) return;
-  // the kernel uses no LDS; a reservation only limits how many stars share a CU
+  // the working vector goes to LDS when the largest star's fits in 32 KB (few
+  // columns); the LDS reservation, if larger, limits how many stars share a CU
+  const size_t need = ((size_t)a.maxn * KC * sizeof(T) + 15) / 16 * 16;
+  if constexpr (KC <= 2) {
+    if (need <= 32768) {
+      const size_t lds = std::max<size_t>((size_t)a.lds_reserve, need);
+      if (wide) hipLaunchKernelGGL((k_star<T, true, KC, true>), dim3(a.nstars), dim3(64), lds, s, a, r, sc, sel);
+      else hipLaunchKernelGGL((k_star<T, false, KC, true>), dim3(a.nstars), dim3(64), lds, s, a, r, sc, sel);
+      return;
+    }
+  }
   const size_t lds = (size_t)a.lds_reserve;
-  if (wide) hipLaunchKernelGGL((k_star<T, true, KC>), dim3(a.nstars), dim3(64), lds, s, a, r, sc, sel);
-  else hipLaunchKernelGGL((k_star<T, false, KC>), dim3(a.nstars), dim3(64), lds, s, a, r, sc, sel);
+  if (wide) hipLaunchKernelGGL((k_star<T, true, KC, false>), dim3(a.nstars), dim3(64), lds, s, a, r, sc, sel);
+  else hipLaunchKernelGGL((k_star<T, false, KC, false>), dim3(a.nstars), dim3(64), lds, s, a, r, sc, sel);
 }
 
 }  // namespace spnet
