@@ -872,6 +872,7 @@ struct Engine {
   // star sweep occupancy chosen by measurement: waves per SIMD (0: no limit)
   // and the LDS reservation that enforces it
   int32_t star_cap = 0, star_lds = 0;
+  bool star_lv = true;  // star working vectors in LDS (where they fit), chosen by measurement
   double star_us = 0.0;
   bool coarse_first = false;  // coarse solve before the sweeps rather than beside them
   double b_us = 0.0;
@@ -1315,6 +1316,7 @@ StarArgs star_args(DeviceState &d, Engine &e) {
   a.b_zero = d.b_zero;
   a.lds_reserve = e.star_lds;
   a.maxn = d.maxn;
+  a.use_lds = e.star_lv ? 1 : 0;
   if (d.precision == SN_PREC_FP32_STARS) {
     a.f_inv = d.f_inv32.p;
     a.b_inv = d.b_inv32.p;
@@ -1659,6 +1661,20 @@ void tune_stars(Engine &e) {
   e.star_cap = best_cap;
   e.star_lds = best_cap == 0 ? 0 : (160 * 1024 / (4 * best_cap)) & ~511;
   e.star_us = best;
+  // working vectors in LDS or in the slots, at that occupancy
+  {
+    e.star_lv = false;
+    for (int w = 0; w < 2; ++w) launch_stars(e, e.r.p, SEL_ALL, e.own);
+    HIPCHK(hipEventRecord(t0, e.own));
+    for (int it = 0; it < 3; ++it) launch_stars(e, e.r.p, SEL_ALL, e.own);
+    HIPCHK(hipEventRecord(t1, e.own));
+    HIPCHK(hipEventSynchronize(t1));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, t0, t1));
+    const double us = 1e3 * ms / 3.0;
+    e.star_lv = !(us < 0.98 * best);
+    if (!e.star_lv) e.star_us = us;
+  }
   // the coarse solve beside the sweeps (sharing the device) or before them
   if (d.m0 > 0) {
     double tb[2] = {0.0, 0.0};

@@ -83,6 +83,7 @@ struct StarArgs {
   int64_t f_zero, b_zero;                    // element offset of a zero region (16 KB) in f_val / b_val
   int32_t lds_reserve;                       // dynamic LDS per workgroup: caps waves per CU
   int32_t maxn;                              // largest star (positions)
+  int32_t use_lds;                           // working vectors in LDS where they fit
   void *slots;                               // T, per position and column (position-major)
 };
 

@@ -13,8 +13,8 @@ namespace spnet {
 //
 // The star's working vector (position-major: the KC values of a position are
 // adjacent) is in factor order; it lives in LDS during the sweeps when the
-// largest star's fits in 32 KB, else in the star's slot segment in global
-// memory; z_j ends in the slot segment either way. The forward sweep
+// launch asks for it and the largest star's fits in 32 KB, else in the star's
+// slot segment in global memory; z_j ends in the slot segment either way. The forward sweep
 // walks the columns of L (step j: entries L_{j+1..j+w, j}); the backward sweep
 // walks the rows of L from the last one (step s = row n-1-s: entries
 // L_{i, i-1..i-w}) on the vector read in reverse, which makes it the same
@@ -428,11 +428,12 @@ __global__ __launch_bounds__(64) void k_star(StarArgs a, const double *__restric
 template <typename T, int KC>
 void launch_star_t(const StarArgs &a, bool wide, const double *r, const CgScalars *sc, int sel, hipStream_t s) {
   if (a.nstars <= 0) return;
-  // the working vector goes to LDS when the largest star's fits in 32 KB (few
-  // columns); the LDS reservation, if larger, limits how many stars share a CU
+  // the working vector goes to LDS when asked for and the largest star's fits in
+  // 32 KB (up to eight columns); the LDS reservation, if larger, limits how many
+  // stars share a CU
   const size_t need = ((size_t)a.maxn * KC * sizeof(T) + 15) / 16 * 16;
-  if constexpr (KC <= 2) {
-    if (need <= 32768) {
+  if constexpr (KC <= 8) {
+    if (a.use_lds && need <= 32768) {
       const size_t lds = std::max<size_t>((size_t)a.lds_reserve, need);
       if (wide) hipLaunchKernelGGL((k_star<T, true, KC, true>), dim3(a.nstars), dim3(64), lds, s, a, r, sc, sel);
       else hipLaunchKernelGGL((k_star<T, false, KC, true>), dim3(a.nstars), dim3(64), lds, s, a, r, sc, sel);
