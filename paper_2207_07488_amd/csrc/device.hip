@@ -566,16 +566,18 @@ __global__ __launch_bounds__(kBlock) void k_restrict(const int32_t *__restrict__
 // checked on the device). The inverse is stored symmetric, padded with zeros
 // to ld x ld (ld a multiple of 64), in TA (double, or float in the mixed form,
 // converted exactly on load); r_H and c have ld rows (r_H zero past m0).
-// A workgroup of 16 wavefronts owns 16 rows: wavefront w takes rows
-// 4 (w mod 4) .. + 3 and the (w / 4)-th quarter of the 64-column chunks. In a
-// chunk, lane (k, y, i) loads 4 adjacent columns 16 y + 4 k .. + 3 of its row
-// (a load instruction reads 4 rows x 64 contiguous columns) and the four
-// instructions s = 0..3 of the chunk take one of them each; block y thus sums
-// the columns 16 y .. 16 y + 15 of every chunk. Column j NG + g of r_H
-// (j = 0..3) goes to accumulator g, NG = ceil(KC / 4) accumulators; with fewer
-// than four columns, positions past KC repeat column KC - 1 and are discarded. The partial products are added in LDS in a fixed order (column
-// quarter, then block), so every column is computed by the same instructions
-// whatever KC is and a batched column equals the single-column result bit for bit.
+// A workgroup of 16 wavefronts owns 8 rows: wavefront w takes rows
+// 4 (w mod 2) .. + 3 and the (w / 2)-th eighth of the 64-column chunks (two
+// workgroups per compute unit, for more loads in flight). In a chunk, lane
+// (k, y, i) loads 4 adjacent columns 16 y + 4 k .. + 3 of its row (a load
+// instruction reads 4 rows x 64 contiguous columns) and the four instructions
+// s = 0..3 of the chunk take one of them each; block y thus sums the columns
+// 16 y .. 16 y + 15 of every chunk. Column j NG + g of r_H (j = 0..3) goes to
+// accumulator g, NG = ceil(KC / 4) accumulators; with fewer than four columns,
+// positions past KC repeat column KC - 1 and are discarded. The partial
+// products are added in LDS in a fixed order (column part, then block), so
+// every column is computed by the same instructions whatever KC is and a
+// batched column equals the single-column result bit for bit.
 constexpr int kMmWaves = 16;
 
 template <typename TA>
@@ -614,9 +616,9 @@ __global__ __launch_bounds__(64 * kMmWaves) void k_coarse_mm(const TA *__restric
   if (!any_selected<KC>(sc, sel, 0u)) return;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int i = lane & 3, y = (lane >> 2) & 3, k = lane >> 4;
-  const int rt = wv & 3, qt = wv >> 2;  // row tile, column quarter
-  const int row0 = blockIdx.x * 16 + 4 * rt;
-  const int chunks = ld / 64, cpw = (chunks + 3) / 4;
+  const int rt = wv & 1, qt = wv >> 1;  // row tile, column part
+  const int row0 = blockIdx.x * 8 + 4 * rt;
+  const int chunks = ld / 64, cpw = (chunks + 7) / 8;
   const int c0 = min(chunks, qt * cpw), c1 = min(chunks, c0 + cpw);
   const int col_l = 16 * y + 4 * k;  // the lane's first column in a chunk
   const TA *arow = Kinv + (size_t)(row0 + i) * ld + col_l;
@@ -675,14 +677,14 @@ __global__ __launch_bounds__(64 * kMmWaves) void k_coarse_mm(const TA *__restric
   }
   __syncthreads();
   // rows 4 rt + i'' of the workgroup, columns: quarters in order, blocks in order
-  for (int t = threadIdx.x; t < 16 * 4 * NG; t += 64 * kMmWaves) {
+  for (int t = threadIdx.x; t < 8 * 4 * NG; t += 64 * kMmWaves) {
     const int row = t / (4 * NG), col = t % (4 * NG), rtt = row >> 2, ir = row & 3;
     double sum = 0.0;
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+    for (int q = 0; q < 8; ++q)
 #pragma unroll
-      for (int yb = 0; yb < 4; ++yb) sum += part[4 * q + rtt][yb][ir * 4 * NG + col];
-    const int grow = blockIdx.x * 16 + row;
+      for (int yb = 0; yb < 4; ++yb) sum += part[2 * q + rtt][yb][ir * 4 * NG + col];
+    const int grow = blockIdx.x * 8 + row;
     if (col < KC && grow < m0) cvec[(size_t)grow * KC + col] = sum;
   }
 }
@@ -1386,7 +1388,7 @@ void launch_B(Engine &e, const double *r, double *z, int sel, bool dot, hipStrea
       constexpr int KC = decltype(K)::value;
       hipLaunchKernelGGL(k_restrict<KC>, dim3(nblk(d.m0 * 64)), dim3(kBlock), 0, cs, d.PTptr.p, d.PTdof.p, d.PTw.p,
                          r, e.rH.p, (int)d.m0, e.sc.p, sel);
-      const unsigned gb = (unsigned)(d.ld0 / 16);
+      const unsigned gb = (unsigned)(d.ld0 / 8);
       if (d.coarse32)
         hipLaunchKernelGGL((k_coarse_mm<float, KC>), dim3(gb), dim3(64 * kMmWaves), 0, cs, d.Kinv32.p, (int)d.ld0,
                            e.rH.p, e.c.p, (int)d.m0, e.sc.p, sel);
