@@ -345,10 +345,12 @@ template <typename T, int KC, int Q>
 __device__ __forceinline__ void star_solve(const StarArgs &a, int st, int n, T *sl) {
   constexpr int GPB = 64 / Pack<T>::SG;
   constexpr int CW = pass_columns<T, Q, KC>();
-  // ring of 16-byte group loads: 32 slots (128 registers) for windows of 1-2
-  // registers, 16 for wider ones, fewer when many columns share a step (a step
-  // then takes longer, so fewer steps of lookahead hide the same latency)
-  constexpr int SLOTS = (Q <= 2 ? 32 : 16) / (CW >= 8 ? CW / 4 : 1);
+  // ring of 16-byte group loads: 16 slots (64 registers; 32 at eight columns
+  // in narrow windows), fewer when many columns share a step (a step then takes
+  // longer, so fewer steps of lookahead hide the same latency). Measured: a
+  // 32-slot ring at one column held the narrow kernel to three wavefronts per
+  // SIMD and was slower; at eight columns the deeper ring wins.
+  constexpr int SLOTS = (Q <= 2 && CW == 8 ? 32 : 16) / (CW >= 8 ? CW / 4 : 1);
   constexpr int RG0 = SLOTS / Q > 2 * GPB ? 2 * GPB : SLOTS / Q;
   constexpr int RG = RG0 >= 32 ? 32 : RG0 >= 16 ? 16 : RG0 >= 8 ? 8 : RG0 >= 4 ? 4 : RG0 >= 2 ? 2 : 1;
   const int vb = a.st_vb[st], gbase = a.st_gb[st];
