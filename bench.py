@@ -141,6 +141,7 @@ def serving_leg(n_requests, rate, pool_size=8, seed=5, load=0.7):
                 time.sleep(max(0.0, arrivals[nxt] - (time.perf_counter() - t0)))
         return time.perf_counter() - t0, lat, iters, worst, solved
 
+    run(np.zeros(n_requests))  # untimed pass: every engine's graphs and tick shapes exist afterwards
     sat_s, sat_lat, _, _, solved = run(np.zeros(n_requests))
     sat_req_rate = n_requests / sat_s
     arr_rate = rate if rate and rate > 0 else load * sat_req_rate
