@@ -220,7 +220,8 @@ sn_status sn_solve(sn_precond pre, int k, const double *f, double *u, const sn_s
                    sn_solve_info *info);
 
 /* Kernel timing: while enabled, the star-sweep launches of every B application
- * are bracketed by HIP events on the solve stream. */
+ * are bracketed by HIP events on the solve stream, and the coarse solve runs
+ * before the sweeps (not beside them) so that the sweeps are timed alone. */
 typedef struct {
   int64_t sweep_launches;  /* B applications timed */
   double sweep_ms;         /* summed device time of the star sweeps of those applications */

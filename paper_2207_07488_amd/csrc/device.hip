@@ -1397,7 +1397,9 @@ void launch_B(Engine &e, const double *r, double *z, int sel, bool dot, hipStrea
                            e.rH.p, e.c.p, (int)d.m0, e.sc.p, sel);
     });
   };
-  if (d.m0 > 0 && e.coarse_first) {
+  // while profiling, the coarse solve always runs first, so that the timed
+  // sweeps have the device to themselves
+  if (d.m0 > 0 && (e.coarse_first || d.profiling)) {
     // the coarse solve first, on the whole device, then the star sweeps
     coarse(s);
     launch_stars(e, r, sel, s);
