@@ -370,8 +370,18 @@ __device__ __forceinline__ void star_solve(const StarArgs &a, int st, int n, T *
 // LV: the star's working vector lives in LDS during the sweeps (gathered into
 // it, swept in place, copied to the slots at the end) instead of in its slot
 // segment.
+// resident wavefronts per SIMD the register allocation must allow: four (at
+// most 128 registers) for the narrow kernels that fit without spilling; the
+// one-column FP64 kernel with the vector in LDS would otherwise take 129 and
+// run three wavefronts per SIMD
 template <typename T, bool WIDE, int KC, bool LV>
-__global__ __launch_bounds__(64) void k_star(StarArgs a, const double *__restrict__ r, const CgScalars *sc, int sel) {
+constexpr int star_min_waves() {
+  return !WIDE && (sizeof(T) == 4 ? KC <= 2 : (KC == 1 && LV)) ? 4 : 1;
+}
+
+template <typename T, bool WIDE, int KC, bool LV>
+__global__ __launch_bounds__(64, (star_min_waves<T, WIDE, KC, LV>())) void k_star(StarArgs a, const double *__restrict__ r,
+                                                                              const CgScalars *sc, int sel) {
   extern __shared__ __align__(16) unsigned char star_lds[];
   if (sel != SEL_ALL) {
     bool any = false;
