@@ -1676,7 +1676,7 @@ void tune_stars(Engine &e) {
     float ms = 0.f;
     HIPCHK(hipEventElapsedTime(&ms, t0, t1));
     const double us = 1e3 * ms / 3.0;
-    e.star_lv = !(us < 0.98 * best);
+    e.star_lv = !(us < 0.95 * best);  // slots only when clearly faster (a 3-launch timing moves by a few %)
     if (!e.star_lv) e.star_us = us;
   }
   // the coarse solve beside the sweeps (sharing the device) or before them
