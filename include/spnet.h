@@ -240,9 +240,12 @@ sn_status sn_precond_kernel_stats(sn_precond pre, sn_kernel_stats *stats);
  *                        candidate (none, 4, 3, 2, 1) is timed and the
  *                        fastest kept (0 = no limit);
  *   star_sweep_us        its sweep time, microseconds per application of B;
- *   coarse_first         1: the coarse solve runs before the sweeps, 0: beside
- *                        them on a second stream (whichever applies B faster);
- *   b_apply_us           the time of one application of B in that order.
+ *   coarse_first         1: the coarse solve runs before the sweeps (and its
+ *                        restriction also runs the convergence test), 0: beside
+ *                        them on a second stream (whichever makes the second
+ *                        half of an iteration faster);
+ *   b_apply_us           the time of that second half (convergence test and one
+ *                        application of B) in that order.
  * Any output pointer may be NULL.
  */
 sn_status sn_precond_engine_info(sn_precond pre, int k, int32_t *star_waves_per_simd, double *star_sweep_us,

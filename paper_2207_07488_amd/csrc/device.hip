@@ -205,6 +205,67 @@ __device__ __forceinline__ bool any_selected(const CgScalars *sc, int sel, uint3
   return any;
 }
 
+// the scalar update of one column from the total of its partials
+__device__ __forceinline__ void apply_scalar(CgScalars &x, int op, double tot) {
+  switch (op) {
+    case OP_ALPHA:
+      x.pq = tot;
+      x.alpha = cg_alpha(x, tot);
+      break;
+    case OP_CONV: {
+      x.rr = tot;
+      const int it = x.iters + 1;
+      x.iters = it;
+      const bool stop = x.fixed > 0 ? it >= x.fixed : (tot <= x.tol2 || it >= x.max_iter);
+      if (stop) {
+        x.done = 1;
+        x.verify = 1;
+      }
+      break;
+    }
+    case OP_BETA:
+      x.rz = tot;
+      x.beta = cg_beta(x, tot);
+      x.rho[x.iters & 1] = tot;
+      x.fresh = 0;
+      x.restart = 0;
+      break;
+    case OP_F2:
+      x.f2 = tot;
+      x.tol2 = x.rtol * x.rtol * tot;
+      break;
+    case OP_R2:
+      x.rr = tot;
+      if (x.fixed == 0 && (tot <= x.tol2 || x.f2 == 0.0)) {
+        // nothing to iterate: r^(0) is the true residual
+        x.done = 1;
+        x.t2 = tot;
+      }
+      break;
+    case OP_TRUE: {
+      // The recurrence stopped; t2 = ||f - K u||^2. When it exceeds the
+      // tolerance by a small factor the recurrence has drifted: restart from
+      // the true residual. A true residual far above the tolerance is the
+      // attainable accuracy of the system in FP64, which a restart cannot
+      // improve.
+      x.t2 = tot;
+      x.verify = 0;
+      if (x.fixed == 0 && x.rr <= x.tol2 && x.iters < x.max_iter && tot > x.tol2 * 1.0000001 &&
+          tot < 100.0 * x.tol2 && x.replacements < 3) {
+        x.replacements += 1;
+        x.rr = tot;
+        x.done = 0;
+        x.first_it = x.iters;
+        x.fresh = 1;
+        x.restart = 1;
+      }
+      break;
+    }
+    default:
+      x.tmp = tot;
+  }
+}
+
 // one block: combine the partials of the previous kernel per column and update
 // the scalars of the selected columns. Every column is summed like a single
 // one (thread t adds partials t, t+256, ... in order, then a fixed block tree).
@@ -242,64 +303,7 @@ __global__ __launch_bounds__(kBlock * 4) void k_scalar(const double *__restrict_
     if (!column_selected(sc[c], sel, mask, c)) continue;
     double tot = 0.0;
     for (int i = 0; i < kBlock / 64; ++i) tot += sh[g][i][cc];
-    CgScalars &x = sc[c];
-    switch (op) {
-      case OP_ALPHA:
-        x.pq = tot;
-        x.alpha = cg_alpha(x, tot);
-        break;
-      case OP_CONV: {
-        x.rr = tot;
-        const int it = x.iters + 1;
-        x.iters = it;
-        const bool stop = x.fixed > 0 ? it >= x.fixed : (tot <= x.tol2 || it >= x.max_iter);
-        if (stop) {
-          x.done = 1;
-          x.verify = 1;
-        }
-        break;
-      }
-      case OP_BETA:
-        x.rz = tot;
-        x.beta = cg_beta(x, tot);
-        x.rho[x.iters & 1] = tot;
-        x.fresh = 0;
-        x.restart = 0;
-        break;
-      case OP_F2:
-        x.f2 = tot;
-        x.tol2 = x.rtol * x.rtol * tot;
-        break;
-      case OP_R2:
-        x.rr = tot;
-        if (x.fixed == 0 && (tot <= x.tol2 || x.f2 == 0.0)) {
-          // nothing to iterate: r^(0) is the true residual
-          x.done = 1;
-          x.t2 = tot;
-        }
-        break;
-      case OP_TRUE: {
-        // The recurrence stopped; t2 = ||f - K u||^2. When it exceeds the
-        // tolerance by a small factor the recurrence has drifted: restart from
-        // the true residual. A true residual far above the tolerance is the
-        // attainable accuracy of the system in FP64, which a restart cannot
-        // improve.
-        x.t2 = tot;
-        x.verify = 0;
-        if (x.fixed == 0 && x.rr <= x.tol2 && x.iters < x.max_iter && tot > x.tol2 * 1.0000001 &&
-            tot < 100.0 * x.tol2 && x.replacements < 3) {
-          x.replacements += 1;
-          x.rr = tot;
-          x.done = 0;
-          x.first_it = x.iters;
-          x.fresh = 1;
-          x.restart = 1;
-        }
-        break;
-      }
-      default:
-        x.tmp = tot;
-    }
+    apply_scalar(sc[c], op, tot);
   }
 }
 
@@ -526,8 +530,23 @@ __global__ __launch_bounds__(kBlock) void k_p_update(double *p, const double *z,
 template <int KC>
 __global__ __launch_bounds__(kBlock) void k_restrict(const int32_t *__restrict__ ptr, const int32_t *__restrict__ dof,
                                                      const double *__restrict__ w, const double *__restrict__ r,
-                                                     double *rH, int m0, const CgScalars *sc, int sel) {
+                                                     double *rH, int m0, CgScalars *sc, int sel,
+                                                     const double *__restrict__ rr_parts, int nparts) {
   constexpr int U = KC <= 2 ? 8 : 4;
+  if (rr_parts && blockIdx.x == 0) {
+    // the first half's convergence test (what k_scalar does with OP_CONV), by
+    // block 0 only. The other blocks may read a column's flags before or after
+    // this update: the update only ever stops a column, and a stopped column's
+    // r_H is not used, so skipping or computing it is correct either way.
+    bool on[KC];
+#pragma unroll
+    for (int c = 0; c < KC; ++c) on[c] = column_selected(sc[c], SEL_FIRST, 0u, c);
+    double tot[KC];
+    block_totals<KC>(rr_parts, nparts, on, tot);
+    if (threadIdx.x == 0)
+      for (int c = 0; c < KC; ++c)
+        if (on[c]) apply_scalar(sc[c], OP_CONV, tot[c]);
+  }
   if (!any_selected<KC>(sc, sel, 0u)) return;
   const int g = (blockIdx.x * kBlock + threadIdx.x) >> 6, lane = threadIdx.x & 63;
   if (g >= m0) return;
@@ -1381,13 +1400,19 @@ void launch_stars(Engine &e, const double *r, int sel, hipStream_t s) {
 }
 
 // z = B r on the selected columns; with dot, r.z -> rho, beta (second half)
-void launch_B(Engine &e, const double *r, double *z, int sel, bool dot, hipStream_t s) {
+// conv: the convergence test of the first half (r.r partials in partials2) is
+// left to the restriction, which then runs before everything else of B
+bool coarse_runs_first(const Engine &e) { return e.d->m0 > 0 && (e.coarse_first || e.d->profiling); }
+
+void launch_B(Engine &e, const double *r, double *z, int sel, bool dot, hipStream_t s, bool conv) {
   DeviceState &d = *e.d;
+  if (conv && !coarse_runs_first(e))
+    fail(SN_EINVAL, "internal: convergence test in a restriction that does not run first");
   auto coarse = [&](hipStream_t cs) {
     with_kc(e.kc, [&](auto K) {
       constexpr int KC = decltype(K)::value;
       hipLaunchKernelGGL(k_restrict<KC>, dim3(nblk(d.m0 * 64)), dim3(kBlock), 0, cs, d.PTptr.p, d.PTdof.p, d.PTw.p,
-                         r, e.rH.p, (int)d.m0, e.sc.p, sel);
+                         r, e.rH.p, (int)d.m0, e.sc.p, sel, conv ? e.partials2.p : nullptr, (int)grid_for(d.npad));
       const unsigned gb = (unsigned)(d.ld0 / 8);
       if (d.coarse32)
         hipLaunchKernelGGL((k_coarse_mm<float, KC>), dim3(gb), dim3(64 * kMmWaves), 0, cs, d.Kinv32.p, (int)d.ld0,
@@ -1399,7 +1424,7 @@ void launch_B(Engine &e, const double *r, double *z, int sel, bool dot, hipStrea
   };
   // while profiling, the coarse solve always runs first, so that the timed
   // sweeps have the device to themselves
-  if (d.m0 > 0 && (e.coarse_first || d.profiling)) {
+  if (coarse_runs_first(e)) {
     // the coarse solve first, on the whole device, then the star sweeps
     coarse(s);
     launch_stars(e, r, sel, s);
@@ -1460,11 +1485,14 @@ void launch_iteration(Engine &e, hipStream_t s) {
     constexpr int KC = decltype(K)::value;
     hipLaunchKernelGGL(k_cg_update<KC>, dim3(G), dim3(kBlock), 0, s, e.u.p, e.r.p, e.p.p, e.q.p, (int)d.npad, e.sc.p,
                        e.partials.p, (int)G, e.partials2.p);
-    hipLaunchKernelGGL(k_scalar<KC>, dim3(1), dim3(kBlock * scalar_groups<KC>()), 0, s,
-                       e.partials2.p, (int)G, e.sc.p, (int)OP_CONV,
-                       (int)SEL_FIRST, 0u);
+    // the convergence test: by the restriction when the coarse solve runs first
+    // (one launch fewer), else by a one-block kernel before the fork
+    if (!coarse_runs_first(e))
+      hipLaunchKernelGGL(k_scalar<KC>, dim3(1), dim3(kBlock * scalar_groups<KC>()), 0, s,
+                         e.partials2.p, (int)G, e.sc.p, (int)OP_CONV,
+                         (int)SEL_FIRST, 0u);
   });
-  launch_B(e, e.r.p, e.z.p, SEL_SECOND, true, s);
+  launch_B(e, e.r.p, e.z.p, SEL_SECOND, true, s, coarse_runs_first(e));
   with_kc(e.kc, [&](auto K) {
     constexpr int KC = decltype(K)::value;
     hipLaunchKernelGGL(k_p_update<KC>, dim3(G), dim3(kBlock), 0, s, e.p.p, e.z.p, (int)d.npad, e.sc.p, e.partials.p,
@@ -1679,14 +1707,26 @@ void tune_stars(Engine &e) {
     e.star_lv = !(us < 0.95 * best);  // slots only when clearly faster (a 3-launch timing moves by a few %)
     if (!e.star_lv) e.star_us = us;
   }
-  // the coarse solve beside the sweeps (sharing the device) or before them
+  // the coarse solve beside the sweeps (sharing the device) or before them; the
+  // second half of an iteration is timed: with the coarse solve first the
+  // restriction also runs the convergence test, beside it a one-block kernel
+  // does (no column is active here, so neither changes a column's state)
   if (d.m0 > 0) {
     double tb[2] = {0.0, 0.0};
     for (int order = 0; order < 2; ++order) {
       e.coarse_first = order == 1;
-      for (int w = 0; w < 2; ++w) launch_B(e, e.r.p, e.z.p, SEL_ALL, false, e.own);
+      auto half = [&]() {
+        if (!e.coarse_first)
+          with_kc(e.kc, [&](auto K) {
+            constexpr int KC = decltype(K)::value;
+            hipLaunchKernelGGL(k_scalar<KC>, dim3(1), dim3(kBlock * scalar_groups<KC>()), 0, e.own,
+                               e.partials2.p, (int)grid_for(d.npad), e.sc.p, (int)OP_CONV, (int)SEL_FIRST, 0u);
+          });
+        launch_B(e, e.r.p, e.z.p, SEL_ALL, false, e.own, e.coarse_first);
+      };
+      for (int w = 0; w < 2; ++w) half();
       HIPCHK(hipEventRecord(t0, e.own));
-      for (int it = 0; it < 3; ++it) launch_B(e, e.r.p, e.z.p, SEL_ALL, false, e.own);
+      for (int it = 0; it < 3; ++it) half();
       HIPCHK(hipEventRecord(t1, e.own));
       HIPCHK(hipEventSynchronize(t1));
       float ms = 0.f;
@@ -1910,7 +1950,7 @@ void device_apply_B(Precond &pre, int k, const double *r, double *z, int device_
   const hipStream_t s = stream ? (hipStream_t)stream : e.own;
   const double *src = stage_block(e, r, k, device_ptrs != 0, s);
   load_block(e, e.r.p, src, k, s);
-  launch_B(e, e.r.p, e.z.p, SEL_ALL, false, s);
+  launch_B(e, e.r.p, e.z.p, SEL_ALL, false, s, false);
   store_block(e, z, e.z.p, k, device_ptrs != 0, s);
 }
 

@@ -250,7 +250,8 @@ class Precond:
     def engine_info(self, k=1):
         """Launch shape measured for batches of k columns: dict with the star
         wavefronts per SIMD limit (0 = none), the sweep time, whether the coarse
-        solve runs before the sweeps, and the time of one application of B."""
+        solve runs before the sweeps, and the time of the second half of an
+        iteration (convergence test and one application of B)."""
         w, us, cf, bus = _i32(), _dbl(), _i32(), _dbl()
         _check(lib().sn_precond_engine_info(self.h, k, C.byref(w), C.byref(us), C.byref(cf), C.byref(bus)))
         return {"star_waves_per_simd_limit": w.value, "sweep_us": round(us.value, 2),
