@@ -9,13 +9,16 @@
 //   first half   q = K p (sliced ELL, 64-row slices) and p.q   -> alpha
 //                u += alpha p, r -= alpha q, r.r, convergence
 //   second half  star sweeps z_j = K_j^{-1} r[S_j] (one wavefront per star)
-//                r_H = P^T r, c = K_0^{-1} r_H (dense inverse)
+//                r_H = P^T r, c = K_0^{-1} r_H (dense inverse, matrix cores)
 //                z = P c + sum of the star slots of every dof, r.z -> beta
 //                p = z + beta p
 // Dot products are reduced per block in a fixed order and the partials are
-// combined in a fixed order by a one-block kernel, per column, with the same
-// arithmetic for every column and every KC: a column's iterates do not depend
-// on the other columns of its batch. The star sweeps live in star_kernel.hpp.
+// combined in a fixed order, per column: by a one-block kernel, by every block
+// of the consuming kernel redundantly (alpha, beta for few columns), or by
+// block 0 of the restriction (the convergence test, when the coarse solve runs
+// first); always with the same arithmetic for every column and every KC, so a
+// column's iterates do not depend on the other columns of its batch. The star
+// sweeps live in star_kernel.hpp.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
