@@ -103,9 +103,31 @@ struct SlotVec<float, KC> {
 // reductions: per-block partials in a fixed order, then one block combines
 // them in a fixed order, so every result is independent of scheduling
 // ---------------------------------------------------------------------------
+// one DPP step on both halves of a double: the value of the lane `ctrl` names
+// (0 where that lane is outside the row or masked)
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, ROW_MASK, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, ROW_MASK, 0xf, true);
+  return __longlong_as_double(((long long)(uint32_t)hi << 32) | (long long)(uint32_t)lo);
+}
+
+// sum over the wavefront in a fixed tree, in every lane: shifts by 1, 2, 4, 8
+// inside each 16-lane row (lane 15 of a row then holds the row), then row 1
+// takes row 0's and row 3 row 2's total (row_bcast:15), then rows 2-3 take
+// lane 31's (row_bcast:31); lane 63 holds the total, which is broadcast
 __device__ __forceinline__ double wave_sum(double v) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-  return v;  // lane 0
+  v += dpp_f64<0x111, 0xf>(v);  // row_shr:1
+  v += dpp_f64<0x112, 0xf>(v);  // row_shr:2
+  v += dpp_f64<0x114, 0xf>(v);  // row_shr:4
+  v += dpp_f64<0x118, 0xf>(v);  // row_shr:8
+  v += dpp_f64<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+  v += dpp_f64<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(uint32_t)b, 63);
+  const int hi = __builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), 63);
+  return __longlong_as_double(((long long)(uint32_t)hi << 32) | (long long)(uint32_t)lo);
 }
 
 __device__ __forceinline__ double block_sum(double v, double *sh) {
