@@ -266,8 +266,8 @@ def main():
         except Exception:
             traffic = None
     roof_m["traffic"] = traffic
-    roof_m["kernel"] = ("star sweeps, FP32 factors: k_star narrow (1-2 window registers) and wide (4-16) kernels, "
-                        "timed together per application of B")
+    roof_m["kernel"] = ("local solves, FP32 factors: k_star (level-scheduled supernodal solve, one star per "
+                        "workgroup), all launches of one application of B timed together")
 
     u_m = rm["u"].cpu().numpy()
     u_p = rp["u"].cpu().numpy()
@@ -288,7 +288,7 @@ def main():
             "workload": f"fiber2d_20k_H{args.nH}", "launch": "captured HIP graphs of 2^i iterations",
             "dim": 2, "n_segments": preset["n_segments"], "length": preset["length"], "nH": args.nH,
             "nodes": net.n_nodes, "dofs": sysm.n, "nnz": sysm.nnz, "stars": mixed.nstars, "m0": mixed.m0,
-            "rtol": args.rtol, "rhs_per_solve": 1, "precision": "FP32 star factors and sweeps, FP32-stored coarse inverse with FP64 accumulation, FP64 CG",
+            "rtol": args.rtol, "rhs_per_solve": 1, "precision": "FP32 star factors and local solves, FP64 coarse operator, FP64 CG recurrences and dots",
         },
         "latency_ms": {"p50": round(percentile(rm["lat_ms"], 0.5), 3),
                        "p99": round(percentile(rm["lat_ms"], 0.99), 3)},
@@ -306,7 +306,7 @@ def main():
         "h_sweep": h_sweep,
         "roofline": roof_m,
         "setup_s": round(t_setup, 2),
-        "factor_info": {"mixed": {k: fim[k] for k in ("star_factor_nnz", "sweep_bytes", "max_band", "max_star_dofs",
+        "factor_info": {"mixed": {k: fim[k] for k in ("star_factor_nnz", "star_stored", "star_blob_bytes", "star_index_bytes", "sweep_bytes", "max_levels", "max_star_dofs",
                                                      "factor_seconds")}},
     }
 

@@ -148,36 +148,44 @@ sn_status sn_precond_export_coarse(sn_precond pre, int32_t *coarse_vertex);
 /* ------------------------------------------------------------------ */
 /* 4. Factorisation (direct local and coarse solves, Sec. 4.1)          */
 /* ------------------------------------------------------------------ */
-#define SN_PREC_FP64 0       /* star factors and sweeps in FP64 */
-#define SN_PREC_FP32_STARS 1 /* star factors stored and swept in FP32 with FP32 accumulation;
-                                the coarse inverse stored in FP32 (products accumulate in
-                                FP64); CG recurrences and dots stay FP64 */
+#define SN_PREC_FP64 0              /* star factors, star solves and the coarse operator in FP64 */
+#define SN_PREC_FP32_STARS 1        /* star factors stored and solved in FP32 with FP32 accumulation;
+                                       the coarse operator, CG recurrences, residual replacement and
+                                       dots stay FP64 (the mixed form) */
+#define SN_PREC_FP32_STARS_COARSE 2 /* as SN_PREC_FP32_STARS, and the coarse inverse stored in FP32
+                                       (its products accumulate in FP64) */
 
 typedef struct {
-  int64_t star_factor_nnz;   /* entries of all local factors (incl. diagonal) */
-  int64_t star_stream_bytes; /* device bytes of the two sweep streams */
+  int64_t star_factor_nnz;   /* structural non-zeros of all local Cholesky factors (incl. the
+                                diagonal) in the minimum degree order the library uses */
+  int64_t star_stored;       /* entries the supernodal blocks store: the non-zeros plus the explicit
+                                zeros of relaxed supernodes (L_CC^{-1} has the pattern of L_CC) */
+  int64_t star_blob_bytes;   /* device bytes of the local factors: index part and values */
+  int64_t star_index_bytes;  /* of which the index part (headers, level tables, 16-bit lists) */
   int64_t coarse_bytes;      /* device bytes of the coarse operator */
   int64_t device_bytes;      /* all device memory held by the preconditioner */
   int32_t max_star_dofs;
-  int32_t max_band;          /* widest factor row/column */
+  int32_t max_levels;        /* most supernode levels of a star: a local solve runs 3 x levels - 1
+                                dependent phases */
   double factor_seconds;     /* host time of ordering + numeric factorisation */
-  int64_t sweep_bytes;       /* algorithmic bytes of one application of all star sweeps:
-                                factor values of both sweeps, step headers, gathers of r,
-                                slot writes */
+  int64_t sweep_bytes;       /* algorithmic bytes of one application of all local solves to one
+                                column: the values of the structural non-zeros once, and per
+                                position its dof index, the FP64 gather of r and the slot write */
   int64_t spmv_bytes;        /* algorithmic bytes of one y = K x (values, columns, x, y) */
-  int64_t sweep_flops;       /* 2 flops per factor entry and sweep */
+  int64_t sweep_flops;       /* 4 flops per structural non-zero (forward and backward solve) */
   double max_pivot_ratio;    /* max over stars of (largest / smallest Cholesky pivot), a lower
                                 bound of cond(K_j) */
-  int32_t star_precision;    /* precision the sweeps run in: SN_PREC_FP32_STARS falls back to
+  int32_t star_precision;    /* precision the local solves run in: FP32 falls back to
                                 SN_PREC_FP64 when max_pivot_ratio * 2^-24 > 0.05, i.e. when FP32
                                 factors could not resolve the local solves */
-  int32_t coarse_precision;  /* precision K_0^{-1} is stored in: SN_PREC_FP32_STARS only when the
-                                sweeps run in FP32 and coarse_pivot_ratio * 2^-24 <= 0.05 */
+  int32_t coarse_precision;  /* SN_PREC_FP64, or SN_PREC_FP32_STARS_COARSE when that was asked for,
+                                the stars run in FP32 and coarse_pivot_ratio * 2^-24 <= 0.05 */
   double coarse_pivot_ratio; /* largest / smallest Cholesky pivot of K_0 */
 } sn_factor_info;
 
 /* Order, factor in FP64 on the host (threads over stars) and upload to the GPU.
- * precision is SN_PREC_FP64 or SN_PREC_FP32_STARS (the FP64 factor cast once).
+ * precision is one of SN_PREC_* (the FP64 factor cast once). The local matrices are
+ * ordered by minimum degree and factored in supernodes; see sn_factor_info.
  * Errors: SN_ENOTSPD naming the star, SN_EDEVICE, SN_ENOMEM. */
 sn_status sn_precond_factor(sn_precond pre, int precision);
 sn_status sn_precond_factor_info(sn_precond pre, sn_factor_info *info);
@@ -235,21 +243,29 @@ sn_status sn_precond_kernel_stats(sn_precond pre, sn_kernel_stats *stats);
 
 /*
  * Launch shape chosen for batches of k columns (measured on the device when
- * the preconditioner first solves with that batch width):
- *   star_waves_per_simd  limit of resident star wavefronts per SIMD: every
- *                        candidate (none, 4, 3, 2, 1) is timed and the
- *                        fastest kept (0 = no limit);
- *   star_sweep_us        its sweep time, microseconds per application of B;
- *   coarse_first         1: the coarse solve runs before the sweeps (and its
- *                        restriction also runs the convergence test), 0: beside
- *                        them on a second stream (whichever makes the second
- *                        half of an iteration faster);
- *   b_apply_us           the time of that second half (convergence test and one
- *                        application of B) in that order.
- * Any output pointer may be NULL.
+ * the preconditioner first solves with that batch width): the local solves
+ * run one star per workgroup of star_waves wavefronts, each carrying
+ * star_cols_per_wave of the k columns in turn; the workgroups of the main
+ * launch get star_lds_bytes of LDS (every candidate cap is timed), the
+ * star_big stars whose index part and vectors need more run in a second
+ * launch beside it with star_big_lds_bytes each, and the star_global stars
+ * that exceed the LDS of a compute unit are solved by 256-thread workgroups
+ * from global memory.
  */
-sn_status sn_precond_engine_info(sn_precond pre, int k, int32_t *star_waves_per_simd, double *star_sweep_us,
-                                 int32_t *coarse_first, double *b_apply_us);
+typedef struct {
+  int32_t star_lds_bytes;
+  int32_t star_cols_per_wave;
+  int32_t star_waves;
+  int32_t star_big;
+  int32_t star_big_lds_bytes;
+  int32_t star_global;
+  int32_t coarse_first;  /* 1: the coarse solve runs before the local solves (and its restriction
+                            also runs the convergence test), 0: beside them on a second stream */
+  double star_sweep_us;  /* time of all local solves, microseconds per application of B */
+  double b_apply_us;     /* time of the second half of an iteration (convergence test and B) */
+} sn_engine_info;
+
+sn_status sn_precond_engine_info(sn_precond pre, int k, sn_engine_info *info);
 
 /* y = K x for k columns (n x k row-major). */
 sn_status sn_apply_K(sn_precond pre, int k, const double *x, double *y, int device_ptrs, void *stream);

@@ -17,7 +17,7 @@ HIPCC = os.path.join(ROCM, "bin", "hipcc")
 
 HOST_SOURCES = ["network.cpp", "assemble.cpp", "spaces.cpp", "factor.cpp", "api.cpp", "serve.cpp"]
 DEVICE_SOURCES = ["device.hip"]
-# the star sweep launcher, once per factor precision and column count
+# the star kernel launcher, once per factor precision and column count
 STAR_VARIANTS = [(t, kc) for t in ("float", "double") for kc in (1, 2, 4, 8, 16)]
 
 HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-ffp-contract=off", "-Wall", "-Wno-unused-function", "-pthread"]

@@ -169,7 +169,9 @@ sn_status sn_precond_export_coarse(sn_precond pre, int32_t *coarse_vertex) {
 sn_status sn_precond_factor(sn_precond pre, int precision) {
   return guarded([&] {
     REQUIRE(pre, "null preconditioner");
-    REQUIRE(precision == SN_PREC_FP64 || precision == SN_PREC_FP32_STARS, "unknown precision");
+    REQUIRE(precision == SN_PREC_FP64 || precision == SN_PREC_FP32_STARS ||
+                precision == SN_PREC_FP32_STARS_COARSE,
+            "unknown precision");
     spnet::Precond &p = *pre->p;
     if (p.dev) {
       spnet::device_release(p.dev.release());
@@ -230,12 +232,11 @@ sn_status sn_precond_kernel_stats(sn_precond pre, sn_kernel_stats *stats) {
   });
 }
 
-sn_status sn_precond_engine_info(sn_precond pre, int k, int32_t *star_waves_per_simd, double *star_sweep_us,
-                                 int32_t *coarse_first, double *b_apply_us) {
+sn_status sn_precond_engine_info(sn_precond pre, int k, sn_engine_info *info) {
   return guarded([&] {
-    REQUIRE(pre && pre->p->dev, "null argument or not factored");
+    REQUIRE(pre && info && pre->p->dev, "null argument or not factored");
     REQUIRE(k >= 1 && k <= 16, "k must be in 1..16");
-    spnet::device_engine_info(*pre->p, k, star_waves_per_simd, star_sweep_us, coarse_first, b_apply_us);
+    spnet::device_engine_info(*pre->p, k, info);
   });
 }
 

@@ -871,16 +871,14 @@ struct DeviceState {
   int nslices = 0;
   DBuf<int32_t> sptr, slen, col;
   DBuf<double> val;
-  // stars
-  int32_t nstars = 0, maxn = 0;
-  int32_t n_narrow = 0, n_wide = 0;
+  // stars: one blob per star (index part, then values), slots = positions of
+  // all stars back to back
+  int32_t nstars = 0, maxn = 0, maxlev = 0;
   int64_t slot_count = 0;
-  int64_t f_zero = 0, b_zero = 0;
-  DBuf<int32_t> order_narrow, order_wide, st_n, st_vb, st_q, st_gb, pos_dof, slot_of;
-  DBuf<uint16_t> f_hdr, b_hdr;
-  DBuf<int64_t> st_fb, st_bb;
-  DBuf<float> f_inv32, b_inv32, f_val32, b_val32;
-  DBuf<double> f_inv64, b_inv64, f_val64, b_val64;
+  DBuf<unsigned char> blob;
+  DBuf<int64_t> st_blob;
+  DBuf<int32_t> st_pos, pos_dof, slot_of;
+  std::vector<uint32_t> h_idx, h_val, h_n, h_nu;  // per star: blob part bytes, positions, u-slots
   // coarse
   // K_0^{-1}, symmetric, zero-padded to ld0 x ld0 (ld0 a multiple of 64): FP32 in the mixed form
   // unless the coarse factor's pivot ratio rules it out, else FP64
@@ -915,10 +913,18 @@ struct Engine {
   DBuf<float> slots32;
   DBuf<double> slots64;
   CgScalars *host_sc = nullptr;  // pinned: last read-back, and the source of uploads
-  // star sweep occupancy chosen by measurement: waves per SIMD (0: no limit)
-  // and the LDS reservation that enforces it
-  int32_t star_cap = 0, star_lds = 0;
-  bool star_lv = true;  // star working vectors in LDS (where they fit), chosen by measurement
+  // star launches (chosen by measurement, see tune_stars): launch 0 on the
+  // solve stream with lds_cap bytes of LDS per workgroup, launches 1 (stars
+  // whose index part and vectors need more) and 2 (stars beyond the LDS of a
+  // compute unit) beside it on aux
+  struct StarLaunch {
+    DBuf<int32_t> order;
+    int32_t count = 0, lds = 0;
+  } sl[3];
+  // launch 2: stars too large for LDS, solved from global memory (vectors in vscratch)
+  DBuf<unsigned char> vscratch;
+  DBuf<int64_t> st_vs;
+  int32_t star_cw = 1, star_nteam = 1, star_lcap = 0;
   double star_us = 0.0;
   bool coarse_first = false;  // coarse solve before the sweeps rather than beside them
   double b_us = 0.0;
@@ -966,160 +972,125 @@ void DeviceDeleter::operator()(DeviceState *d) const { delete d; }
 
 namespace {
 
-int window_regs(int band) {
-  const int q = (band + 63) / 64;
-  for (int w = 1; w <= 16; w *= 2)
-    if (q <= w) return w;
-  return -1;
-}
-
 inline unsigned nblk(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 inline unsigned grid_for(int64_t n) { return std::max(1u, std::min<unsigned>(kMaxGrid, nblk(n))); }
 
-// Pack one sweep stream of a star: steps in groups of SG (the first step of
-// every group a multiple of SG), values divided by the step's pivot. Lane l
-// and window register q read slot u = ((l - j0 - 1) mod 64) + 64 q of the group
-// with first step j0 (mod 64); slot u holds, for k = 0..SG-1, entry
-// t = 64 q + ((u mod 64 - k) mod 64) of step j0 + k (zero past the step's width).
-// The group stores slots 0..W-1, W one past the last non-zero slot, right after
-// the previous group; `widths` gets W (16-bit) per group, so a group's offset is
-// the sum of the widths before it.
+// One star's blob: header, level table, position records, 16-bit index lists
+// (padded to 16 bytes: the index part), then the values of the S_k in T
+// (padded to 16 bytes).
 template <typename T>
-void pack_stream(const std::vector<int32_t> &width, const std::vector<double> &vals, const std::vector<double> &inv,
-                 int SG, int Q, std::vector<T> &out, std::vector<uint16_t> &widths) {
-  const int n = (int)width.size();
-  std::vector<int64_t> start((size_t)n + 1, 0);
-  for (int j = 0; j < n; ++j) start[j + 1] = start[j] + width[j];
-  auto entry = [&](int j, int slot, int k) -> double {
-    const int jj = j + k;
-    if (jj >= n) return 0.0;
-    const int q = slot / 64, u = slot % 64;
-    const int t = 64 * q + ((u - k) & 63);
-    if (t >= width[jj]) return 0.0;
-    return vals[(size_t)(start[jj] + t)] * inv[jj];
-  };
-  for (int j0 = 0; j0 < n; j0 += SG) {
-    int W = 0;
-    for (int slot = 0; slot < 64 * Q; ++slot)
-      for (int k = 0; k < SG; ++k)
-        if (entry(j0, slot, k) != 0.0) W = slot + 1;
-    widths.push_back((uint16_t)W);
-    for (int slot = 0; slot < W; ++slot)
-      for (int k = 0; k < SG; ++k) out.push_back((T)entry(j0, slot, k));
+void pack_blob(const StarFactor &F, std::vector<unsigned char> &out, uint32_t &idx_bytes, uint32_t &val_bytes) {
+  if (F.n >= 65536 || F.nu >= 65536)
+    fail(SN_EINVAL, "star too large for 16-bit local indices (" + std::to_string(F.n) + " positions, " +
+                        std::to_string(F.nu) + " updates)");
+  if ((int64_t)F.S.size() >= (int64_t)1 << 31) fail(SN_EINVAL, "star factor too large");
+  auto a16 = [](size_t b) { return (b + 15) & ~(size_t)15; };
+  SnHeader h{};
+  h.n = (uint32_t)F.n;
+  h.nsn = (uint32_t)F.nsn;
+  h.nu = (uint32_t)F.nu;
+  h.nlev = (uint32_t)F.nlev;
+  size_t off = sizeof(SnHeader);
+  h.off_lev = (uint32_t)off;
+  off = a16(off + 4 * ((size_t)F.nlev + 1));
+  h.off_pos = (uint32_t)off;
+  off += sizeof(SnPos) * (size_t)F.n;
+  h.off_R = (uint32_t)off;
+  off += 2 * (size_t)F.nu;
+  h.off_alist = (uint32_t)off;
+  off += 2 * (size_t)F.nu;
+  h.idx_bytes = (uint32_t)a16(off);
+  h.val_bytes = (uint32_t)a16(F.S.size() * sizeof(T));
+  const size_t base = out.size();
+  out.resize(base + h.idx_bytes + h.val_bytes, 0);
+  unsigned char *b = out.data() + base;
+  std::memcpy(b, &h, sizeof(h));
+  uint32_t *lev = reinterpret_cast<uint32_t *>(b + h.off_lev);
+  for (int32_t l = 0; l <= F.nlev; ++l) lev[l] = (uint32_t)F.lev_pos[l];
+  for (int32_t p = 0; p < F.n; ++p) {
+    const int32_t k = F.snpos[p];
+    SnPos r{};
+    r.sbase = (uint32_t)F.sbase[k];
+    r.c0 = (uint16_t)F.c0[k];
+    r.w = (uint16_t)F.w[k];
+    r.h = (uint16_t)F.h[k];
+    r.ubase = (uint16_t)F.ubase[k];
+    r.a0 = (uint16_t)F.aptr[p];
+    r.a1 = (uint16_t)F.aptr[p + 1];
+    std::memcpy(b + h.off_pos + sizeof(SnPos) * (size_t)p, &r, sizeof(r));
   }
-  // zero widths past the end: the sweep reads whole blocks of widths up to
-  // four blocks ahead
-  const int GPB = 64 / SG;
-  const size_t ng = (size_t)(n + SG - 1) / SG;
-  const size_t padded = (ng + GPB - 1) / GPB * GPB + 4 * GPB;
-  widths.resize(widths.size() + (padded - ng), 0);
+  auto put16 = [&](uint32_t o, const std::vector<int32_t> &v) {
+    uint16_t *d16 = reinterpret_cast<uint16_t *>(b + o);
+    for (size_t i = 0; i < v.size(); ++i) d16[i] = (uint16_t)v[i];
+  };
+  put16(h.off_R, F.R);
+  put16(h.off_alist, F.alist);
+  T *val = reinterpret_cast<T *>(b + h.idx_bytes);
+  for (size_t i = 0; i < F.S.size(); ++i) val[i] = (T)F.S[i];
+  idx_bytes = h.idx_bytes;
+  val_bytes = h.val_bytes;
 }
 
 template <typename T>
 void upload_stars(DeviceState &d, const Precond &pre, const HostFactors &hf, sn_factor_info &fi) {
-  constexpr int SG = 16 / (int)sizeof(T);
   const int64_t ns = (int64_t)hf.stars.size();
-  std::vector<int32_t> st_n(ns), st_vb(ns), st_q(ns), st_gb(ns), pos_dof;
-  std::vector<uint16_t> f_hdr, b_hdr;
-  std::vector<int64_t> st_fb(ns), st_bb(ns);
-  std::vector<T> f_val, b_val, f_inv, b_inv;
-  int64_t tot = 0, real_vals = 0;
-  int maxband = 0, maxq = 1;
+  std::vector<unsigned char> blob;
+  std::vector<int64_t> st_blob((size_t)ns);
+  std::vector<int32_t> st_pos((size_t)ns), pos_dof;
+  d.h_idx.assign((size_t)ns, 0);
+  d.h_val.assign((size_t)ns, 0);
+  d.h_n.assign((size_t)ns, 0);
+  d.h_nu.assign((size_t)ns, 0);
+  int64_t tot = 0, nnz = 0, stored = 0, idx_tot = 0;
   for (int64_t s = 0; s < ns; ++s) {
     const StarFactor &F = hf.stars[s];
-    const int q = window_regs(std::max(F.band, 1));
-    if (q < 0) fail(SN_EINVAL, "star band " + std::to_string(F.band) + " exceeds the widest sweep window (1024)");
-    st_n[s] = F.n;
-    st_vb[s] = (int32_t)tot;
-    st_q[s] = q;
-    st_gb[s] = (int32_t)f_hdr.size();
-    maxq = std::max(maxq, q);
-    maxband = std::max(maxband, F.band);
+    st_blob[s] = (int64_t)blob.size();
+    st_pos[s] = (int32_t)tot;
+    pack_blob<T>(F, blob, d.h_idx[s], d.h_val[s]);
+    d.h_n[s] = (uint32_t)F.n;
+    d.h_nu[s] = (uint32_t)F.nu;
     d.maxn = std::max(d.maxn, F.n);
-    // forward: columns j; backward: rows n-1-s
-    std::vector<double> finv(F.invdiag), binv((size_t)F.n);
-    for (int p = 0; p < F.n; ++p) binv[p] = F.invdiag[F.n - 1 - p];
-    st_fb[s] = (int64_t)f_val.size();
-    pack_stream<T>(F.width_fwd, F.colvals, finv, SG, q, f_val, f_hdr);
-    st_bb[s] = (int64_t)b_val.size();
-    pack_stream<T>(F.width_bwd, F.rowvals, binv, SG, q, b_val, b_hdr);
-    if (f_hdr.size() != b_hdr.size()) fail(SN_EINVAL, "internal: header arrays out of step");
+    d.maxlev = std::max(d.maxlev, F.nlev);
     const int32_t *dofs = &pre.star_dofs[pre.star_ptr[s]];
-    for (int p = 0; p < F.n; ++p) {
-      pos_dof.push_back(d.iperm_h[dofs[F.perm[p]]]);
-      f_inv.push_back((T)finv[p]);
-      b_inv.push_back((T)binv[p]);
-    }
+    for (int p = 0; p < F.n; ++p) pos_dof.push_back(d.iperm_h[dofs[F.perm[p]]]);
     tot += F.n;
-    real_vals += (int64_t)(F.colvals.size() + F.rowvals.size());
+    nnz += F.nnz;
+    stored += (int64_t)F.S.size();
+    idx_tot += d.h_idx[s];
   }
-  if (tot >= (int64_t)1 << 31 || (int64_t)std::max(f_val.size(), b_val.size()) >= (int64_t)1 << 31)
-    fail(SN_EINVAL, "star streams too large for 32-bit offsets");
-  // zero region: lanes past a group's width load from here (64*Q lanes of SG
-  // values, Q <= 16)
-  const size_t slack = (size_t)64 * 16 * SG + 64;
-  d.f_zero = (int64_t)f_val.size();
-  d.b_zero = (int64_t)b_val.size();
-  f_val.resize(f_val.size() + slack, T(0));
-  b_val.resize(b_val.size() + slack, T(0));
-  // schedule: longest chain first, narrow and wide windows in separate kernels
-  std::vector<int32_t> narrow, wide;
-  for (int64_t s = 0; s < ns; ++s) (st_q[s] <= 2 ? narrow : wide).push_back((int32_t)s);
-  auto by_len = [&](int32_t a, int32_t b) { return st_n[a] > st_n[b]; };
-  std::stable_sort(narrow.begin(), narrow.end(), by_len);
-  std::stable_sort(wide.begin(), wide.end(), by_len);
-  d.n_narrow = (int32_t)narrow.size();
-  d.n_wide = (int32_t)wide.size();
+  if (tot >= (int64_t)1 << 31) fail(SN_EINVAL, "stars too large for 32-bit slot indices");
   // dof -> slots in ascending star order
   std::vector<int32_t> slot_of((size_t)d.npad * d.nv, -1);
   {
     std::vector<int32_t> cnt((size_t)d.n, 0);
     for (int64_t s = 0; s < ns; ++s)
-      for (int p = 0; p < st_n[s]; ++p) {
-        const int32_t dof = pos_dof[st_vb[s] + p];
+      for (uint32_t p = 0; p < d.h_n[s]; ++p) {
+        const int32_t dof = pos_dof[st_pos[s] + p];
         if (cnt[dof] >= d.nv) fail(SN_EINVAL, "a dof lies in more stars than its element has mesh nodes");
-        slot_of[(size_t)dof * d.nv + cnt[dof]++] = st_vb[s] + p;
+        slot_of[(size_t)dof * d.nv + cnt[dof]++] = st_pos[s] + (int32_t)p;
       }
   }
   d.nstars = (int32_t)ns;
   d.slot_count = tot;
-  d.order_narrow.upload(narrow);
-  d.order_wide.upload(wide);
-  d.st_n.upload(st_n);
-  d.st_vb.upload(st_vb);
-  d.st_q.upload(st_q);
-  d.st_gb.upload(st_gb);
-  d.st_fb.upload(st_fb);
-  d.st_bb.upload(st_bb);
+  d.blob.upload(blob);
+  d.st_blob.upload(st_blob);
+  d.st_pos.upload(st_pos);
   d.pos_dof.upload(pos_dof);
-  d.f_hdr.upload(f_hdr);
-  d.b_hdr.upload(b_hdr);
   d.slot_of.upload(slot_of);
-  int64_t stream_bytes;
-  if constexpr (sizeof(T) == 4) {
-    d.f_inv32.upload(f_inv);
-    d.b_inv32.upload(b_inv);
-    d.f_val32.upload(f_val);
-    d.b_val32.upload(b_val);
-    stream_bytes = (int64_t)(d.f_val32.bytes() + d.b_val32.bytes());
-  } else {
-    d.f_inv64.upload(f_inv);
-    d.b_inv64.upload(b_inv);
-    d.f_val64.upload(f_val);
-    d.b_val64.upload(b_val);
-    stream_bytes = (int64_t)(d.f_val64.bytes() + d.b_val64.bytes());
-  }
   const int64_t sT = sizeof(T);
-  // algorithmic bytes of one application: every off-diagonal factor entry once
-  // per sweep, the pivot of every step, the gather (dof id and r) and the slot
-  // write of every position; the zero padding of the packed groups is not counted
-  fi.sweep_bytes = real_vals * sT + tot * (2 * sT + 4 + 8 + sT);
-  fi.sweep_flops = 2 * real_vals + 2 * tot;
-  fi.star_stream_bytes = stream_bytes;
-  fi.max_band = maxband;
+  // algorithmic bytes of one application (one column): the values of the
+  // structural non-zeros of every local factor once (each is read by one of
+  // the two solves from HBM; the other reads it from LDS or cache), and per
+  // position its dof index, the FP64 gather of r and the slot write
+  fi.sweep_bytes = nnz * sT + tot * (4 + 8 + sT);
+  fi.sweep_flops = 4 * nnz;
+  fi.star_factor_nnz = nnz;
+  fi.star_stored = stored;
+  fi.star_blob_bytes = (int64_t)blob.size();
+  fi.star_index_bytes = idx_tot;
+  fi.max_levels = d.maxlev;
   fi.max_star_dofs = d.maxn;
 }
-
 
 }  // namespace
 
@@ -1127,6 +1098,10 @@ void device_setup(Precond &pre, const HostFactors &hf, int precision) {
   double max_ratio = 1.0;
   for (const StarFactor &F : hf.stars) max_ratio = std::max(max_ratio, F.pivot_ratio);
   const int requested = precision;
+  if (precision != SN_PREC_FP64 && precision != SN_PREC_FP32_STARS && precision != SN_PREC_FP32_STARS_COARSE)
+    fail(SN_EINVAL, "unknown precision " + std::to_string(precision));
+  const bool want_coarse32 = precision == SN_PREC_FP32_STARS_COARSE;
+  if (precision == SN_PREC_FP32_STARS_COARSE) precision = SN_PREC_FP32_STARS;
   if (precision == SN_PREC_FP32_STARS && max_ratio * std::ldexp(1.0, -24) > 0.05) precision = SN_PREC_FP64;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) fail(SN_EDEVICE, "no HIP device available");
@@ -1223,8 +1198,6 @@ void device_setup(Precond &pre, const HostFactors &hf, int precision) {
   // stars
   if (precision == SN_PREC_FP32_STARS) upload_stars<float>(*d, pre, hf, fi);
   else upload_stars<double>(*d, pre, hf, fi);
-  int64_t star_nnz = 0;
-  for (const StarFactor &F : hf.stars) star_nnz += F.nnz;
 
   // coarse operator
   const int nc = sys.ncomp, nv = d->nv;
@@ -1232,7 +1205,8 @@ void device_setup(Precond &pre, const HostFactors &hf, int precision) {
     // symmetric (the mean of the two computed triangles) and padded
     const int64_t m0 = d->m0, ld = (m0 + 63) / 64 * 64;
     d->ld0 = ld;
-    d->coarse32 = precision == SN_PREC_FP32_STARS && hf.coarse_pivot_ratio * std::ldexp(1.0, -24) <= 0.05;
+    d->coarse32 = want_coarse32 && precision == SN_PREC_FP32_STARS &&
+                  hf.coarse_pivot_ratio * std::ldexp(1.0, -24) <= 0.05;
     auto sym = [&](int64_t i, int64_t j) {
       return 0.5 * (hf.coarse_inv[(size_t)(i * m0 + j)] + hf.coarse_inv[(size_t)(j * m0 + i)]);
     };
@@ -1284,21 +1258,16 @@ void device_setup(Precond &pre, const HostFactors &hf, int precision) {
     d->Pw.upload(std::vector<double>((size_t)npad * nv, 0.0));
   }
   HIPCHK(hipDeviceSynchronize());
-  d->bytes = (int64_t)(d->sptr.bytes() + d->slen.bytes() + d->col.bytes() + d->val.bytes() + d->order_narrow.bytes() + d->perm.bytes() +
-                       d->order_wide.bytes() +
-                       d->st_n.bytes() + d->st_vb.bytes() + d->st_q.bytes() + d->st_gb.bytes() + d->st_fb.bytes() +
-                       d->st_bb.bytes() + d->pos_dof.bytes() + d->f_hdr.bytes() + d->b_hdr.bytes() +
+  d->bytes = (int64_t)(d->sptr.bytes() + d->slen.bytes() + d->col.bytes() + d->val.bytes() + d->perm.bytes() +
+                       d->blob.bytes() + d->st_blob.bytes() + d->st_pos.bytes() + d->pos_dof.bytes() +
                        d->slot_of.bytes() + d->Kinv64.bytes() + d->Kinv32.bytes() + d->Pc.bytes() + d->Pw.bytes() +
-                       d->PTptr.bytes() + d->PTdof.bytes() + d->PTw.bytes() + d->f_inv32.bytes() +
-                       d->b_inv32.bytes() + d->f_inv64.bytes() + d->b_inv64.bytes()) +
-             fi.star_stream_bytes;
+                       d->PTptr.bytes() + d->PTdof.bytes() + d->PTw.bytes());
   const int64_t nnz = (int64_t)sys.col.size();
   fi.spmv_bytes = nnz * (8 + 4 + 8) + n * 8;
   fi.max_pivot_ratio = max_ratio;
   fi.star_precision = precision;
-  fi.star_factor_nnz = star_nnz;
   fi.coarse_bytes = (int64_t)(d->Kinv64.bytes() + d->Kinv32.bytes());
-  fi.coarse_precision = d->coarse32 ? SN_PREC_FP32_STARS : SN_PREC_FP64;
+  fi.coarse_precision = d->coarse32 ? SN_PREC_FP32_STARS_COARSE : SN_PREC_FP64;
   fi.coarse_pivot_ratio = hf.coarse_pivot_ratio;
   fi.device_bytes = d->bytes;
   fi.factor_seconds = hf.seconds;
@@ -1308,27 +1277,31 @@ void device_setup(Precond &pre, const HostFactors &hf, int precision) {
 }
 
 // ---------------------------------------------------------------------------
-// star sweep dispatch over the column counts (instantiated in star_inst.hip)
+// star kernel dispatch over the column counts (instantiated in star_inst.hip)
 // ---------------------------------------------------------------------------
+template <typename T, int KC>
+static void launch_star_cw(int cw, const SnArgs &a, int nteam, bool global, const double *r, const CgScalars *sc,
+                           int sel, hipStream_t s) {
+  if (cw == 1) launch_star_t<T, KC, 1>(a, nteam, global, r, sc, sel, s);
+  else if constexpr (KC >= 2) {
+    if (cw == 2) launch_star_t<T, KC, 2>(a, nteam, global, r, sc, sel, s);
+    else if constexpr (KC >= 4) {
+      if (cw == 4) launch_star_t<T, KC, 4>(a, nteam, global, r, sc, sel, s);
+      else fail(SN_EINVAL, "unsupported columns per wavefront");
+    } else fail(SN_EINVAL, "unsupported columns per wavefront");
+  } else fail(SN_EINVAL, "unsupported columns per wavefront");
+}
 template <typename T>
-static void launch_star_kc(int kc, const StarArgs &a, bool wide, const double *r, const CgScalars *sc, int sel,
-                           hipStream_t s) {
+static void launch_star_kc(int kc, int cw, const SnArgs &a, int nteam, bool global, const double *r,
+                           const CgScalars *sc, int sel, hipStream_t s) {
   switch (kc) {
-    case 1: launch_star_t<T, 1>(a, wide, r, sc, sel, s); break;
-    case 2: launch_star_t<T, 2>(a, wide, r, sc, sel, s); break;
-    case 4: launch_star_t<T, 4>(a, wide, r, sc, sel, s); break;
-    case 8: launch_star_t<T, 8>(a, wide, r, sc, sel, s); break;
-    case 16: launch_star_t<T, 16>(a, wide, r, sc, sel, s); break;
+    case 1: launch_star_cw<T, 1>(cw, a, nteam, global, r, sc, sel, s); break;
+    case 2: launch_star_cw<T, 2>(cw, a, nteam, global, r, sc, sel, s); break;
+    case 4: launch_star_cw<T, 4>(cw, a, nteam, global, r, sc, sel, s); break;
+    case 8: launch_star_cw<T, 8>(cw, a, nteam, global, r, sc, sel, s); break;
+    case 16: launch_star_cw<T, 16>(cw, a, nteam, global, r, sc, sel, s); break;
     default: fail(SN_EINVAL, "unsupported column count");
   }
-}
-void launch_star_fp32(int kc, const StarArgs &a, bool wide, const double *r, const CgScalars *sc, int sel,
-                      hipStream_t s) {
-  launch_star_kc<float>(kc, a, wide, r, sc, sel, s);
-}
-void launch_star_fp64(int kc, const StarArgs &a, bool wide, const double *r, const CgScalars *sc, int sel,
-                      hipStream_t s) {
-  launch_star_kc<double>(kc, a, wide, r, sc, sel, s);
 }
 
 namespace {
@@ -1345,42 +1318,23 @@ void with_kc(int kc, F &&f) {
   }
 }
 
-StarArgs star_args(DeviceState &d, Engine &e) {
-  StarArgs a{};
-  a.nstars = d.n_narrow;
-  a.order = d.order_narrow.p;
-  a.st_n = d.st_n.p;
-  a.st_vb = d.st_vb.p;
-  a.st_q = d.st_q.p;
-  a.st_gb = d.st_gb.p;
-  a.st_fb = d.st_fb.p;
-  a.st_bb = d.st_bb.p;
+SnArgs star_args(DeviceState &d, Engine &e, int which) {
+  SnArgs a{};
+  a.nstars = e.sl[which].count;
+  a.lds_bytes = e.sl[which].lds;
+  a.order = e.sl[which].order.p;
+  a.blob = d.blob.p;
+  a.st_blob = d.st_blob.p;
+  a.st_pos = d.st_pos.p;
   a.pos_dof = d.pos_dof.p;
-  a.f_hdr = d.f_hdr.p;
-  a.b_hdr = d.b_hdr.p;
-  a.f_zero = d.f_zero;
-  a.b_zero = d.b_zero;
-  a.lds_reserve = e.star_lds;
-  a.maxn = d.maxn;
-  a.use_lds = e.star_lv ? 1 : 0;
-  if (d.precision == SN_PREC_FP32_STARS) {
-    a.f_inv = d.f_inv32.p;
-    a.b_inv = d.b_inv32.p;
-    a.f_val = d.f_val32.p;
-    a.b_val = d.b_val32.p;
-    a.slots = e.slots32.p;
-  } else {
-    a.f_inv = d.f_inv64.p;
-    a.b_inv = d.b_inv64.p;
-    a.f_val = d.f_val64.p;
-    a.b_val = d.b_val64.p;
-    a.slots = e.slots64.p;
-  }
+  a.slots = d.precision == SN_PREC_FP32_STARS ? (void *)e.slots32.p : (void *)e.slots64.p;
+  a.vscratch = e.vscratch.p;
+  a.st_vs = e.st_vs.p;
   return a;
 }
 
-// star sweeps of the selected columns (all columns are swept; the kernels
-// return at once when no column is selected)
+// local solves of the selected columns (a workgroup returns at once when none
+// of its columns is selected)
 void launch_stars(Engine &e, const double *r, int sel, hipStream_t s) {
   DeviceState &d = *e.d;
   std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
@@ -1395,27 +1349,26 @@ void launch_stars(Engine &e, const double *r, int sel, hipStream_t s) {
     HIPCHK(hipEventRecord(ev.first, s));
   }
   if (d.nstars > 0) {
-    StarArgs a = star_args(d, e);
-    StarArgs aw = a;
-    aw.nstars = d.n_wide;
-    aw.order = d.order_wide.p;
     const bool f32 = d.precision == SN_PREC_FP32_STARS;
-    auto L = [&](const StarArgs &x, bool wide, hipStream_t st) {
-      if (f32) launch_star_fp32(e.kc, x, wide, r, e.sc.p, sel, st);
-      else launch_star_fp64(e.kc, x, wide, r, e.sc.p, sel, st);
+    auto L = [&](int which, hipStream_t st) {
+      const SnArgs a = star_args(d, e, which);
+      if (f32) launch_star_kc<float>(e.kc, e.star_cw, a, e.star_nteam, which == 2, r, e.sc.p, sel, st);
+      else launch_star_kc<double>(e.kc, e.star_cw, a, e.star_nteam, which == 2, r, e.sc.p, sel, st);
     };
-    if (d.n_wide > 0 && d.n_narrow > 0) {
-      // fork: the wide stars run on the auxiliary stream beside the narrow ones
+    const bool side = e.sl[1].count > 0 || e.sl[2].count > 0;
+    if (side && e.sl[0].count > 0) {
+      // fork: the large stars run on the auxiliary stream beside the others
       HIPCHK(hipEventRecord(e.fork, s));
       HIPCHK(hipStreamWaitEvent(e.aux, e.fork, 0));
-      L(aw, true, e.aux);
+      L(2, e.aux);
+      L(1, e.aux);
       HIPCHK(hipEventRecord(e.join, e.aux));
-      L(a, false, s);
+      L(0, s);
       HIPCHK(hipStreamWaitEvent(s, e.join, 0));
-    } else if (d.n_wide > 0) {
-      L(aw, true, s);
     } else {
-      L(a, false, s);
+      L(2, s);
+      L(1, s);
+      L(0, s);
     }
   }
   if (d.profiling) {
@@ -1682,12 +1635,60 @@ void load_block(Engine &e, double *dst, const double *src_dev, int k, hipStream_
   });
 }
 
-// Star sweep occupancy: all stars are resident at once unless registers or an
-// LDS reservation limit them. Few resident waves per SIMD leave the hardware
-// to hand out the remaining (shorter, longest-first ordered) stars as waves
-// finish, which balances uneven stars; many hide more latency. The best limit
-// depends on the star sizes and the column count, so it is measured: every
-// candidate sweeps all stars (zero input) a few times and the fastest wins.
+// Star launch plan for an LDS cap (bytes per workgroup), CW columns per
+// wavefront and nteam wavefronts per workgroup. A star needs its index part
+// plus nteam sets of vectors (x and y: n x CW, u: nu x CW) in LDS, and its
+// values too if they are to be staged; the kernel stages them when they fit
+// the launch's LDS. Stars whose index part and vectors fit the cap go to
+// launch 0, the others to launch 1 with as much LDS as its largest star wants
+// (at most 160 KB). Each launch takes its stars longest first. Returns false
+// when some star does not fit in 160 KB.
+bool plan_stars(Engine &e, int lcap, int cw, int nteam) {
+  DeviceState &d = *e.d;
+  const int64_t ts = d.precision == SN_PREC_FP32_STARS ? 4 : 8;
+  const int64_t kMaxLds = kStarMaxLds;
+  std::vector<int32_t> o[3];
+  std::vector<int64_t> vs((size_t)d.nstars, -1);
+  int64_t l1 = 0, vbytes = 0;
+  for (int32_t s = 0; s < d.nstars; ++s) {
+    const int64_t xb = (d.h_n[s] * cw * ts + 15) & ~15, ub = (d.h_nu[s] * cw * ts + 15) & ~15;
+    const int64_t need = d.h_idx[s] + nteam * (2 * xb + ub);
+    if (need <= lcap) {
+      o[0].push_back(s);
+    } else if (need <= kMaxLds) {
+      o[1].push_back(s);
+      l1 = std::max(l1, std::min(kMaxLds, need + d.h_val[s]));
+    } else {
+      o[2].push_back(s);
+      vs[s] = vbytes;
+      vbytes += 2 * xb + ub;
+    }
+  }
+  auto by_len = [&](int32_t a, int32_t b) { return d.h_n[a] > d.h_n[b]; };
+  for (int w = 0; w < 3; ++w) {
+    std::stable_sort(o[w].begin(), o[w].end(), by_len);
+    e.sl[w].order.upload(o[w]);
+    e.sl[w].count = (int32_t)o[w].size();
+  }
+  e.sl[0].lds = lcap;
+  e.sl[1].lds = (int32_t)l1;
+  e.sl[2].lds = 0;
+  if ((int64_t)e.vscratch.n < vbytes) {
+    e.vscratch.alloc((size_t)vbytes);
+    e.bytes += vbytes;
+  }
+  e.st_vs.upload(vs);
+  e.star_cw = cw;
+  e.star_nteam = nteam;
+  e.star_lcap = lcap;
+  return true;
+}
+
+// The star launch shape is measured: candidate LDS caps, then columns per
+// wavefront and wavefronts per workgroup at the best cap, then the caps again;
+// each candidate solves all stars (zero input) a few times and the fastest
+// wins. A large cap stages more factors in LDS but fits fewer workgroups per
+// compute unit.
 void tune_stars(Engine &e) {
   DeviceState &d = *e.d;
   if (d.nstars == 0) return;
@@ -1696,12 +1697,8 @@ void tune_stars(Engine &e) {
   hipEvent_t t0, t1;
   HIPCHK(hipEventCreate(&t0));
   HIPCHK(hipEventCreate(&t1));
-  const int caps[] = {0, 4, 3, 2, 1};
-  double best = 1e30;
-  int best_cap = 0;
-  for (int cap : caps) {
-    e.star_cap = cap;
-    e.star_lds = cap == 0 ? 0 : (160 * 1024 / (4 * cap)) & ~511;
+  auto time_plan = [&](int lcap, int cw, int nteam) -> double {
+    if (!plan_stars(e, lcap, cw, nteam)) return 1e30;
     for (int w = 0; w < 2; ++w) launch_stars(e, e.r.p, SEL_ALL, e.own);
     HIPCHK(hipEventRecord(t0, e.own));
     for (int it = 0; it < 3; ++it) launch_stars(e, e.r.p, SEL_ALL, e.own);
@@ -1709,29 +1706,28 @@ void tune_stars(Engine &e) {
     HIPCHK(hipEventSynchronize(t1));
     float ms = 0.f;
     HIPCHK(hipEventElapsedTime(&ms, t0, t1));
-    const double us = 1e3 * ms / 3.0;
+    return 1e3 * ms / 3.0;
+  };
+  const int caps[] = {12 << 10, 16 << 10, 20 << 10, 24 << 10, 32 << 10, 40 << 10, 48 << 10, 64 << 10, 80 << 10};
+  std::vector<std::pair<int, int>> shapes;  // (cw, nteam)
+  for (int cw = 1; cw <= std::min(e.kc, 4); cw *= 2)
+    for (int nt = 1; nt <= std::min(e.kc / cw, 4); nt *= 2) shapes.push_back({cw, nt});
+  double best = 1e30;
+  int bcap = caps[0], bcw = std::min(e.kc, 4), bnt = 1;
+  auto try_one = [&](int cap, int cw, int nt) {
+    const double us = time_plan(cap, cw, nt);
     if (us < 0.98 * best) {
       best = us;
-      best_cap = cap;
+      bcap = cap;
+      bcw = cw;
+      bnt = nt;
     }
-  }
-  e.star_cap = best_cap;
-  e.star_lds = best_cap == 0 ? 0 : (160 * 1024 / (4 * best_cap)) & ~511;
+  };
+  for (int cap : caps) try_one(cap, bcw, bnt);
+  for (auto &sh : shapes) try_one(bcap, sh.first, sh.second);
+  for (int cap : caps) try_one(cap, bcw, bnt);
+  if (best >= 1e30 || !plan_stars(e, bcap, bcw, bnt)) fail(SN_EINVAL, "internal: no star launch plan");
   e.star_us = best;
-  // working vectors in LDS or in the slots, at that occupancy
-  {
-    e.star_lv = false;
-    for (int w = 0; w < 2; ++w) launch_stars(e, e.r.p, SEL_ALL, e.own);
-    HIPCHK(hipEventRecord(t0, e.own));
-    for (int it = 0; it < 3; ++it) launch_stars(e, e.r.p, SEL_ALL, e.own);
-    HIPCHK(hipEventRecord(t1, e.own));
-    HIPCHK(hipEventSynchronize(t1));
-    float ms = 0.f;
-    HIPCHK(hipEventElapsedTime(&ms, t0, t1));
-    const double us = 1e3 * ms / 3.0;
-    e.star_lv = !(us < 0.95 * best);  // slots only when clearly faster (a 3-launch timing moves by a few %)
-    if (!e.star_lv) e.star_us = us;
-  }
   // the coarse solve beside the sweeps (sharing the device) or before them; the
   // second half of an iteration is timed: with the coarse solve first the
   // restriction also runs the convergence test, beside it a one-block kernel
@@ -1782,7 +1778,7 @@ int64_t engine_footprint(const Precond &pre, int kc) {
   const int64_t n = pre.sys->n, npad = (n + kBlock - 1) / kBlock * kBlock;
   const int64_t m0 = (std::max<int64_t>(pre.m0, 1) + 63) / 64 * 64;
   const int prec = pre.dev ? pre.finfo.star_precision : pre.precision;
-  const int64_t ts = prec == SN_PREC_FP32_STARS ? 4 : 8;
+  const int64_t ts = prec == SN_PREC_FP64 ? 8 : 4;
   return (6 * npad * kc + 2 * m0 * kc + (int64_t)2 * kc * kMaxGrid) * 8 + kc * (int64_t)sizeof(CgScalars) +
          (int64_t)pre.star_dofs.size() * kc * ts;
 }
@@ -1950,13 +1946,17 @@ void device_stats(Precond &pre, sn_kernel_stats *st) {
 
 int64_t device_bytes(const Precond &pre) { return pre.dev ? pre.dev->bytes : 0; }
 
-void device_engine_info(Precond &pre, int k, int32_t *waves_per_simd, double *sweep_us, int32_t *coarse_first,
-                        double *b_us) {
+void device_engine_info(Precond &pre, int k, sn_engine_info *info) {
   Engine &e = solve_engine(pre, k);
-  if (waves_per_simd) *waves_per_simd = e.star_cap;
-  if (sweep_us) *sweep_us = e.star_us;
-  if (coarse_first) *coarse_first = e.coarse_first ? 1 : 0;
-  if (b_us) *b_us = e.b_us;
+  info->star_lds_bytes = e.star_lcap;
+  info->star_cols_per_wave = e.star_cw;
+  info->star_waves = e.star_nteam;
+  info->star_big = e.sl[1].count;
+  info->star_global = e.sl[2].count;
+  info->star_big_lds_bytes = e.sl[1].lds;
+  info->star_sweep_us = e.star_us;
+  info->coarse_first = e.coarse_first ? 1 : 0;
+  info->b_apply_us = e.b_us;
 }
 
 void device_apply_K(Precond &pre, int k, const double *x, double *y, int device_ptrs, void *stream) {

@@ -66,37 +66,56 @@ __device__ __forceinline__ bool column_selected(const CgScalars &s, int sel, uin
   }
 }
 
-// Arguments of the star sweep kernel (see star_kernel.hpp).
-struct StarArgs {
-  int32_t nstars;
-  const int32_t *order;    // stars, longest first
-  const int32_t *st_n;     // positions of the star
-  const int32_t *st_vb;    // base in the per-position arrays
-  const int32_t *st_q;     // window registers
-  const int32_t *st_gb;    // base in the per-group header arrays
-  const int64_t *st_fb;    // forward stream value base
-  const int64_t *st_bb;    // backward stream value base
-  const int32_t *pos_dof;  // global dof of each position (factor order)
-  const uint16_t *f_hdr, *b_hdr;             // per group: width in 16-byte slots (groups are contiguous)
-  const void *f_inv, *b_inv;                 // 1/pivot per step (T)
-  const void *f_val, *b_val;                 // packed stream values (T)
-  int64_t f_zero, b_zero;                    // element offset of a zero region (16 KB) in f_val / b_val
-  int32_t lds_reserve;                       // dynamic LDS per workgroup: caps waves per CU
-  int32_t maxn;                              // largest star (positions)
-  int32_t use_lds;                           // working vectors in LDS where they fit
-  void *slots;                               // T, per position and column (position-major)
+// Device layout of one star's factor (a "blob", 16-byte aligned; see
+// factor.cpp and star_kernel.hpp). The index part (header, level table,
+// position records, 16-bit index lists) comes first, padded to 16 bytes,
+// then the values of the matrices S_k.
+struct SnHeader {
+  uint32_t n, nsn, nu, nlev;   // positions, supernodes, u-slots, levels
+  uint32_t idx_bytes;          // bytes of the index part (multiple of 16)
+  uint32_t val_bytes;          // bytes of the values (multiple of 16)
+  uint32_t off_lev;            // uint32 [nlev + 1]: first position of each level
+  uint32_t off_pos;            // SnPos [n]
+  uint32_t off_R;              // uint16 [nu]: the position each u-slot updates
+  uint32_t off_alist;          // uint16 [nu]: per position (ranges in SnPos), the u-slots aimed at it
+  uint32_t pad[6];
+};
+static_assert(sizeof(SnHeader) == 64, "blob header");
+
+// the supernode of a position and the u-slots aimed at it
+struct SnPos {
+  uint32_t sbase;  // first value of its supernode's S_k (elements of T from the start of the values)
+  uint16_t c0;     // first position of the supernode
+  uint16_t w;      // positions of the supernode (columns of its diagonal block)
+  uint16_t h;      // rows below the diagonal block
+  uint16_t ubase;  // first u-slot of the supernode
+  uint16_t a0, a1; // alist[a0 .. a1-1]: the u-slots aimed at this position, ascending
+};
+static_assert(sizeof(SnPos) == 16, "position record");
+
+// LDS a star workgroup may use: the 160 KB of a gfx950 compute unit
+constexpr int kStarMaxLds = 160 * 1024;
+
+// Arguments of the star kernel (see star_kernel.hpp).
+struct SnArgs {
+  int32_t nstars;                 // workgroups of the launch
+  int32_t lds_bytes;              // dynamic LDS per workgroup
+  const int32_t *order;           // star of each workgroup
+  const unsigned char *blob;      // all blobs
+  const int64_t *st_blob;         // byte offset of each star's blob
+  const int32_t *st_pos;          // first slot of each star (its positions are consecutive slots)
+  const int32_t *pos_dof;         // dof of every slot
+  void *slots;                    // T, KC values per slot
+  unsigned char *vscratch;        // vectors of the stars solved from global memory
+  const int64_t *st_vs;           // byte offset of each such star's vectors in vscratch
 };
 
-// one launch over the stars of a.order, narrow (windows of 1-2 registers) or
-// wide (4-16), for kc columns; defined in star_inst.hip (one object per
-// precision and column count)
-void launch_star_fp32(int kc, const StarArgs &a, bool wide, const double *r, const CgScalars *sc, int sel,
-                      hipStream_t s);
-void launch_star_fp64(int kc, const StarArgs &a, bool wide, const double *r, const CgScalars *sc, int sel,
-                      hipStream_t s);
-
-// per precision and column count
-template <typename T, int KC>
-void launch_star_t(const StarArgs &a, bool wide, const double *r, const CgScalars *sc, int sel, hipStream_t s);
+// one launch over the stars of a.order: k_star with nteam wavefronts per
+// workgroup, or (global) k_star_global with 256 threads per star; defined in
+// star_inst.hip (one object per precision, column count and columns per
+// wavefront)
+template <typename T, int KC, int CW>
+void launch_star_t(const SnArgs &a, int nteam, bool global, const double *r, const CgScalars *sc, int sel,
+                   hipStream_t s);
 
 }  // namespace spnet

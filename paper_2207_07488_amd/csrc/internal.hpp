@@ -73,21 +73,25 @@ std::shared_ptr<System> assemble(std::shared_ptr<const Network> net, int model, 
 std::unique_ptr<Precond> build_spaces(std::shared_ptr<const System> sys, int nH, int policy, int dir_lo,
                                       int dir_hi);
 
-// factor.cpp: one local factor in the two sweep-stream layouts used on the GPU.
-//   Both streams hold, per step, a header (width w, 1/diag) and w off-diagonal
-//   values; the forward stream walks the columns of L from the first, the
-//   backward stream walks the rows of L from the last, each listing the
-//   entries nearest the diagonal first.
+// factor.cpp: the factor of one local matrix in the layout of the GPU solve.
+// Positions are the local dofs in factor order, numbered level by level; a
+// supernode s owns positions c0[s] .. c0[s]+w[s]-1 and sends updates to the
+// h[s] positions R[ubase[s] ..] below its diagonal block (its u-slots).
 struct StarFactor {
-  int32_t n = 0;
-  int32_t band = 0;                 // max width
-  std::vector<int32_t> perm;        // factor position -> canonical local index
-  std::vector<int32_t> width_fwd;   // per step
-  std::vector<int32_t> width_bwd;
-  std::vector<double> invdiag;      // per position
-  std::vector<double> colvals;      // forward stream values (no headers), column j entries j+1..j+w
-  std::vector<double> rowvals;      // backward stream values, row i (from n-1 down) entries i-1..i-w
-  int64_t nnz = 0;                  // stored factor entries incl. diagonal
+  int32_t n = 0;                    // positions
+  int32_t nsn = 0, nu = 0, nlev = 0;  // supernodes, u-slots, levels
+  std::vector<int32_t> perm;        // position -> canonical local index
+  std::vector<int32_t> lev_pos;     // nlev + 1: first position of each level
+  std::vector<int32_t> lev_u;       // nlev + 1: first u-slot of each level
+  std::vector<int32_t> c0, w, h;    // per supernode
+  std::vector<int64_t> sbase;       // per supernode: offset of S_s in S
+  std::vector<int64_t> ubase;       // per supernode: its first u-slot
+  std::vector<int32_t> snpos;       // per position: its supernode
+  std::vector<int32_t> snu;         // per u-slot: its supernode
+  std::vector<int32_t> R;           // per u-slot: the position it updates
+  std::vector<int32_t> aptr, alist; // per position: the u-slots updating it, ascending (CSR)
+  std::vector<double> S;            // per supernode [L_CC^{-1}; L_RC L_CC^{-1}], column c: rows c..w+h-1
+  int64_t nnz = 0;                  // structural non-zeros of L (incl. diagonal)
   double pivot_ratio = 1.0;         // largest / smallest pivot L_jj^2
 };
 
@@ -99,6 +103,9 @@ struct HostFactors {
 };
 
 HostFactors factor_host(const Precond &pre);
+// the same factorisation of a symmetric positive definite matrix given in CSR
+// (both triangles and the diagonal)
+StarFactor factor_csr_local(int32_t n, const int32_t *ptr, const int32_t *col, const double *val);
 
 // device.hip
 void device_setup(Precond &pre, const HostFactors &hf, int precision);
@@ -109,8 +116,7 @@ void device_release(DeviceState *d);
 void device_profile(Precond &pre, int enable);
 void device_stats(Precond &pre, sn_kernel_stats *st);
 int64_t device_bytes(const Precond &pre);
-void device_engine_info(Precond &pre, int k, int32_t *waves_per_simd, double *sweep_us, int32_t *coarse_first,
-                        double *b_us);
+void device_engine_info(Precond &pre, int k, sn_engine_info *info);
 
 // ---------------------------------------------------------------------------
 // Engine: the device workspace of kc PCG columns (independent recurrences, one

@@ -91,15 +91,17 @@ struct sn_server_s {
 namespace {
 
 int64_t factor_estimate(const Precond &pre, const HostFactors &hf, int precision) {
-  // stream values with packing overhead, per-position arrays, matrix, coarse
-  const int64_t ts = precision == SN_PREC_FP32_STARS ? 4 : 8;
-  int64_t vals = 0, pos = 0;
+  // star blobs (values, about 20 bytes of index per position and update),
+  // per-position arrays, matrix, coarse operator
+  const int64_t ts = precision == SN_PREC_FP64 ? 8 : 4;
+  int64_t vals = 0, pos = 0, upd = 0;
   for (const auto &F : hf.stars) {
-    vals += (int64_t)(F.colvals.size() + F.rowvals.size());
+    vals += (int64_t)F.S.size();
     pos += F.n;
+    upd += F.nu;
   }
   const int64_t n = pre.sys->n, nnz = (int64_t)pre.sys->col.size();
-  return (vals * ts + pos * (4 + 2 * ts) + n * pre.nvert_per_elem * 16 + nnz * 12 + pre.m0 * pre.m0 * 8) * 13 / 10;
+  return (vals * ts + pos * 32 + upd * 8 + n * pre.nvert_per_elem * 16 + nnz * 12 + pre.m0 * pre.m0 * 8) * 13 / 10;
 }
 
 // start the host factorisation of pre on a worker thread (once)
@@ -170,12 +172,23 @@ EngineSlot *engine_for(sn_server_s &S, Request *r) {
   if (!make_room(S, need)) return nullptr;
   auto slot = std::make_unique<EngineSlot>();
   slot->pre = r->pre;
-  if (!pre.dev) {
-    spnet::device_setup(pre, *hf, S.o.precision);
-    slot->uploaded_here = true;
-    S.factoring.erase(&pre);
+  // a failure to upload the factors or to create the engine fails this
+  // request only; the others keep running
+  try {
+    if (!pre.dev) {
+      S.factoring.erase(&pre);
+      spnet::device_setup(pre, *hf, S.o.precision);
+      slot->uploaded_here = true;
+    }
+    slot->eng = spnet::engine_create(pre, S.o.max_columns);
+  } catch (const spnet::Error &e) {
+    if (slot->uploaded_here && pre.dev) {
+      spnet::device_release(pre.dev.release());
+      pre.precision = -1;
+    }
+    fail_request(r, e.code, e.what());
+    return nullptr;
   }
-  slot->eng = spnet::engine_create(pre, S.o.max_columns);
   slot->bytes = spnet::engine_footprint(pre, S.o.max_columns) + (slot->uploaded_here ? spnet::device_bytes(pre) : 0);
   slot->col_req.assign((size_t)S.o.max_columns, nullptr);
   slot->col_j.assign((size_t)S.o.max_columns, -1);
@@ -232,7 +245,9 @@ sn_status sn_server_create(const sn_server_opts *opts, sn_server *out) {
       spnet::fail(SN_EINVAL, "max_columns must be 1, 2, 4, 8 or 16");
     if (o.iters_per_tick < 1) spnet::fail(SN_EINVAL, "iters_per_tick must be positive");
     if (o.hbm_budget <= 0) spnet::fail(SN_EINVAL, "hbm_budget must be positive");
-    if (o.precision != SN_PREC_FP64 && o.precision != SN_PREC_FP32_STARS) spnet::fail(SN_EINVAL, "unknown precision");
+    if (o.precision != SN_PREC_FP64 && o.precision != SN_PREC_FP32_STARS &&
+        o.precision != SN_PREC_FP32_STARS_COARSE)
+      spnet::fail(SN_EINVAL, "unknown precision");
     auto *s = new sn_server_s;
     s->o = o;
     *out = s;
@@ -286,6 +301,20 @@ sn_status sn_server_step(sn_server srv, int32_t *n_active, int32_t *n_queued) {
           progressed = true;
         }
       if (!progressed) std::this_thread::yield();
+    }
+    // nothing iterates but requests wait for their host factorisation: wait
+    // for the first of those to finish, so that a step always makes progress
+    if (!any_ticking) {
+      bool running = false;
+      for (auto &e : S.engines) running |= e->active_columns() > 0;
+      if (!running)
+        for (Request *r : S.queue) {
+          auto it = S.factoring.find(r->pre.get());
+          if (it != S.factoring.end()) {
+            it->second.wait();
+            break;
+          }
+        }
     }
     // 2. admit queued requests that fit (in arrival order; a request that
     //    cannot start yet does not hold back later ones)

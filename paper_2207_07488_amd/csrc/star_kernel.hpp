@@ -1,140 +1,32 @@
-// Star sweep kernel, templated on the factor precision T and the number of
-// right-hand-side columns KC. Included by star_inst.hip only.
+// Local solves z_j = K_j^{-1} r[S_j] for every star j (the direct solves
+// behind the projections P_j, Sec. 4.1), templated on the factor precision T,
+// the column count KC and the columns CW a wavefront carries. Included by
+// star_inst.hip only.
+//
+// One workgroup per star; its wavefronts ("teams") take the star's column
+// chunks of CW columns in turn and share the star's factor, which is staged in
+// LDS once (index part always, values when they fit the launch's LDS size)
+// and read from there by both solves.
+//
+// The factor of a star (see factor.cpp) is level-scheduled: its supernodes are
+// grouped by height in the supernodal tree and positions are numbered level by
+// level. Supernode k owns positions c0 .. c0+w-1 and has h rows below its
+// diagonal block; S_k = [L_CC^{-1}; L_RC L_CC^{-1}] is stored lower
+// trapezoidal, column c holding rows c .. w+h-1. With x the gathered r, per
+// level l = 0, 1, ... (forward, L y = x):
+//   A(l)  x_p -= sum of the u-slots aimed at p          (p in level l, l > 0)
+//   B(l)  y_p  = sum_{c <= p-c0} S_k[p-c0][c] x_{c0+c}  (p in level l)
+//         u_e  = sum_{c < w}     S_k[w+e-ub][c] x_{c0+c} (u-slots e of level l)
+// and per level l = top .. 0 (backward, L^T z = y), z kept in x:
+//   C(l)  z_p  = sum_{r >= j} S_k[r][j] y_{c0+r} - sum_i S_k[w+i][j] z_{R_i}  (j = p-c0)
+// Every phase is a set of independent dot products between wavefront-ordered
+// LDS accesses; each dot product adds its terms in a fixed order, so the
+// result does not depend on scheduling. All arithmetic is in T (FP32 with FP32
+// accumulation in the mixed form).
 #pragma once
 #include "device_common.hpp"
 
 namespace spnet {
-
-// ---------------------------------------------------------------------------
-// Star sweeps: z_j = K_j^{-1} r[S_j] = L_j^{-T} L_j^{-1} r[S_j] for every star j
-// (the local solves behind the projections P_j, Sec. 4.1), for KC columns at
-// once. One wavefront per star; the factor streams are read once for all
-// columns.
-//
-// The star's working vector (position-major: the KC values of a position are
-// adjacent) is in factor order; it lives in LDS during the sweeps when the
-// launch asks for it and the largest star's fits in 32 KB, else in the star's
-// slot segment in global memory; z_j ends in the slot segment either way. The forward sweep
-// walks the columns of L (step j: entries L_{j+1..j+w, j}); the backward sweep
-// walks the rows of L from the last one (step s = row n-1-s: entries
-// L_{i, i-1..i-w}) on the vector read in reverse, which makes it the same
-// recurrence. Stream values are divided by the pivot of their step, so step j
-// subtracts m_t g_j from row j+1+t with the raw running value g_j; the pivot
-// division is applied when a row is written back.
-//
-// Window: lane l holds the rows r = l (mod 64) in registers R[0..Q]: R[q] is
-// the row 64(b+q) + l during block b. At step j = 64b + s the finished row j
-// sits in lane s of R[0]; the rows still to be updated are, for lanes l > s,
-// R[0..Q-1], for lanes l <= s, R[1..Q]. The q-th of them needs stream entry
-// t = ((l - j - 1) mod 64) + 64 q, which the host stores so that lane l loads
-// it for SG consecutive steps with one 16-byte load (lanes past the group's
-// width load zeros from a zero region). A per-lane select routes
-// the loaded multiplier q to R[q] or R[q+1]; no row moves between lanes. At
-// the end of a block R[0] holds 64 finished rows, the registers shift by one
-// and the next rows enter from memory (loaded one block ahead).
-// ---------------------------------------------------------------------------
-
-template <typename T>
-struct Pack;
-template <>
-struct Pack<float> {
-  using V = float4;
-  static constexpr int SG = 4;
-  static __device__ __forceinline__ float get(const V &v, int k) {
-    return k == 0 ? v.x : (k == 1 ? v.y : (k == 2 ? v.z : v.w));
-  }
-  template <int L>
-  static __device__ __forceinline__ float lane(float v) {
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), L));
-  }
-  // v with lane L replaced by the wavefront-uniform value u
-  template <int L>
-  static __device__ __forceinline__ float put(float u, float v) {
-    asm("v_writelane_b32 %0, %1, %2" : "+v"(v) : "s"(u), "i"(L));
-    return v;
-  }
-  static __device__ __forceinline__ float fnma(float m, float g, float x) { return __builtin_fmaf(-m, g, x); }
-  // per-lane selects at a step: lanes whose bit is set in `up` (an SGPR pair)
-  // take `hi`, the others `lo`
-  static __device__ __forceinline__ float pick(float hi, float lo, uint64_t up) {
-    float r;
-    asm("v_cndmask_b32_e64 %0, %1, %2, %3" : "=v"(r) : "v"(lo), "v"(hi), "s"(up));
-    return r;
-  }
-  static __device__ __forceinline__ float pick_or_zero(float hi, uint64_t up) {
-    float r;
-    asm("v_cndmask_b32_e64 %0, 0, %1, %2" : "=v"(r) : "v"(hi), "s"(up));
-    return r;
-  }
-  static __device__ __forceinline__ float zero_or_pick(float lo, uint64_t up) {
-    float r;
-    asm("v_cndmask_b32_e64 %0, %1, 0, %2" : "=v"(r) : "v"(lo), "s"(up));
-    return r;
-  }
-};
-template <>
-struct Pack<double> {
-  using V = double2;
-  static constexpr int SG = 2;
-  static __device__ __forceinline__ double get(const V &v, int k) { return k == 0 ? v.x : v.y; }
-  static __device__ __forceinline__ int lo(double v) { return (int)(uint32_t)(__double_as_longlong(v)); }
-  static __device__ __forceinline__ int hi(double v) { return (int)(uint32_t)(__double_as_longlong(v) >> 32); }
-  static __device__ __forceinline__ double mk(int l, int h) {
-    return __longlong_as_double(((long long)(uint32_t)h << 32) | (long long)(uint32_t)l);
-  }
-  template <int L>
-  static __device__ __forceinline__ double lane(double v) {
-    return mk(__builtin_amdgcn_readlane(lo(v), L), __builtin_amdgcn_readlane(hi(v), L));
-  }
-  template <int L>
-  static __device__ __forceinline__ double put(double u, double v) {
-    int vl = lo(v), vh = hi(v);
-    asm("v_writelane_b32 %0, %1, %2" : "+v"(vl) : "s"(lo(u)), "i"(L));
-    asm("v_writelane_b32 %0, %1, %2" : "+v"(vh) : "s"(hi(u)), "i"(L));
-    return mk(vl, vh);
-  }
-  static __device__ __forceinline__ double fnma(double m, double g, double x) { return __builtin_fma(-m, g, x); }
-  // per-lane selects at a step: lanes whose bit is set in `up` take `hi`
-  // (both 32-bit halves selected with the same SGPR-pair mask)
-  static __device__ __forceinline__ int sel32(int hi, int lo, uint64_t up) {
-    int r;
-    asm("v_cndmask_b32_e64 %0, %1, %2, %3" : "=v"(r) : "v"(lo), "v"(hi), "s"(up));
-    return r;
-  }
-  static __device__ __forceinline__ int sel32_or_zero(int hi, uint64_t up) {
-    int r;
-    asm("v_cndmask_b32_e64 %0, 0, %1, %2" : "=v"(r) : "v"(hi), "s"(up));
-    return r;
-  }
-  static __device__ __forceinline__ int zero_or_sel32(int lo, uint64_t up) {
-    int r;
-    asm("v_cndmask_b32_e64 %0, %1, 0, %2" : "=v"(r) : "v"(lo), "s"(up));
-    return r;
-  }
-  static __device__ __forceinline__ double pick(double hi, double lo, uint64_t up) {
-    return mk(sel32(Pack::lo(hi), Pack::lo(lo), up), sel32(Pack::hi(hi), Pack::hi(lo), up));
-  }
-  static __device__ __forceinline__ double pick_or_zero(double hi, uint64_t up) {
-    return mk(sel32_or_zero(lo(hi), up), sel32_or_zero(Pack::hi(hi), up));
-  }
-  static __device__ __forceinline__ double zero_or_pick(double lo_v, uint64_t up) {
-    return mk(zero_or_sel32(lo(lo_v), up), zero_or_sel32(hi(lo_v), up));
-  }
-};
-
-template <int S, int E>
-struct StaticFor {
-  template <typename F>
-  static __device__ __forceinline__ void run(F &&f) {
-    f(std::integral_constant<int, S>{});
-    StaticFor<S + 1, E>::run(f);
-  }
-};
-template <int E>
-struct StaticFor<E, E> {
-  template <typename F>
-  static __device__ __forceinline__ void run(F &&) {}
-};
 
 // N consecutive values of type T, moved with the widest aligned accesses
 template <typename T, int N>
@@ -144,10 +36,9 @@ struct Row {
   static constexpr int CH = BYTES >= 16 ? 16 : BYTES;  // chunk bytes
   __device__ __forceinline__ void load(const T *p) {
     if constexpr (CH == 16) {
-      using C = float4;
 #pragma unroll
       for (int i = 0; i < BYTES / 16; ++i) {
-        const C c = reinterpret_cast<const C *>(p)[i];
+        const float4 c = reinterpret_cast<const float4 *>(p)[i];
         __builtin_memcpy(reinterpret_cast<char *>(v) + 16 * i, &c, 16);
       }
     } else if constexpr (CH == 8) {
@@ -159,12 +50,11 @@ struct Row {
   }
   __device__ __forceinline__ void store(T *p) const {
     if constexpr (CH == 16) {
-      using C = float4;
 #pragma unroll
       for (int i = 0; i < BYTES / 16; ++i) {
-        C c;
+        float4 c;
         __builtin_memcpy(&c, reinterpret_cast<const char *>(v) + 16 * i, 16);
-        reinterpret_cast<C *>(p)[i] = c;
+        reinterpret_cast<float4 *>(p)[i] = c;
       }
     } else if constexpr (CH == 8) {
       float2 c;
@@ -176,285 +66,363 @@ struct Row {
   }
 };
 
-// read-only data read through the constant address space (scalar loads)
-typedef const __attribute__((address_space(4))) uint32_t *const_u32_ptr;
+// LDS accesses of one wavefront complete in order; the fences keep the
+// compiler from moving them across a phase boundary
+__device__ __forceinline__ void team_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
-// One sweep over the n steps of a stream for CW columns c0..c0+CW-1 of the
-// star's slot segment `sl` (KC values per position). REV reads and writes the
-// vector in reverse position order.
-template <typename T, int KC, int CW, int Q, int RG, bool REV>
-__device__ __forceinline__ void sweep(T *sl, int c0, int n, const uint16_t *__restrict__ hdr_g,
-                                      const T *__restrict__ inv, const T *__restrict__ vals, uint32_t sbase,
-                                      uint32_t zbase) {
-  using P = Pack<T>;
-  using V = typename P::V;
-  constexpr int SG = P::SG, GPB = 64 / SG;
-  const int lane = threadIdx.x & 63;
-  // row p of the sweep (clamped into the star; rows past the end read as 0)
-  auto load_row = [&](int p, T (&dst)[CW]) {
-    const int pc = p < n ? p : n - 1;
-    Row<T, CW> rw;
-    rw.load(sl + (size_t)(REV ? n - 1 - pc : pc) * KC + c0);
+struct SnView {
+  const uint32_t *lev;  // lev[l]: first position of level l (nlev + 1 entries)
+  const SnPos *pos;     // per position: its supernode and the u-slots aimed at it
+  const uint16_t *R, *alist;
+  // the level table held in registers (nlev < 64 and a wavefront team): lane
+  // l has the first position of level l, read with readlane
+  int lv_pos;
+  bool lv_reg;
+  __device__ __forceinline__ int level(int l) const {
+    return lv_reg ? __builtin_amdgcn_readlane(lv_pos, l) : (int)lev[l];
+  }
+};
+
+// offset of column c in a lower-trapezoidal block of leading dimension ld
+// (column c holds rows c .. ld-1)
+__device__ __forceinline__ uint32_t col_off(uint32_t c, uint32_t ld) { return c * ld - (c * (c - 1u)) / 2u; }
+
+// a * b + c with one rounding, in the precision of T
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// acc += s * v (CW columns), s taken as 0 when !on
+template <typename T, int CW>
+__device__ __forceinline__ void fma_row(T (&acc)[CW], bool on, T s, const Row<T, CW> &v) {
+  const T f = on ? s : T(0);
 #pragma unroll
-    for (int c = 0; c < CW; ++c) dst[c] = p < n ? rw.v[c] : T(0);
-  };
-  // One column and a window of one register (rows 64 b + l, and 64 (b + 1) + l
-  // in R[1]): lane l keeps only its open row in R[0] and swaps in its next row
-  // at step l, so that every step applies one multiplier per lane; the same
-  // updates as the general form, without the zero ones.
-  constexpr bool ROT = Q == 1 && CW == 1;
-  T R[Q + 1][CW];
-  T done = T(0);  // ROT: the finished rows of the block, lane l at step l
+  for (int c = 0; c < CW; ++c) acc[c] = fma_t(f, v.v[c], acc[c]);
+}
+
+// One team: CW columns of one star. G = false: the team is one wavefront and
+// the vectors x, y (n x CW), u (nu x CW) and the index part are in LDS, S (the
+// star's values) in LDS or global memory. G = true: the team is the whole
+// workgroup and everything is in global memory (stars too large for LDS).
+//
+// Work per level: every position p of the level is one task (one lane).
+//   forward A  x_p -= u-slots aimed at p (its u-slot list, ascending)
+//   forward B  y_p = row r = p - c0 of L_CC^{-1} times x_C, and the update rows
+//              i = r, r + w, r + 2w, ... < h of its supernode:
+//              u_{ubase+i} = row i of L_RC L_CC^{-1} times x_C
+//   backward   z_p = column j = p - c0 of S_k against (y_C, -z_R)
+// Terms are added in ascending order (columns, rows, list entries); loads go
+// in batches of eight with clamped indices (masked terms contribute zero), so
+// that a task waits for few dependent memory round trips.
+template <bool G>
+__device__ __forceinline__ void phase_sync() {
+  if constexpr (G) __syncthreads();
+  else team_sync();
+}
+
+template <typename T, int CW, bool G>
+__device__ __forceinline__ void team_solve(const SnView &B, const T *__restrict__ S, int nlev, T *x, T *y, T *u) {
+  const int lane = G ? (int)threadIdx.x : (int)(threadIdx.x & 63);
+  const int NT = G ? (int)blockDim.x : 64;
+  using RowT = Row<T, CW>;
+  // forward
+  for (int l = 0; l < nlev; ++l) {
+    const int p0 = B.level(l), p1 = B.level(l + 1);
+    if (l > 0) {
+      for (int p = p0 + lane; p < p1; p += NT) {
+        const SnPos P = B.pos[p];
+        const int a0 = P.a0, a1 = P.a1;
+        if (a0 == a1) continue;
+        RowT a;
+        a.load(x + (size_t)p * CW);
+        for (int q0 = a0; q0 < a1; q0 += 8) {
+          int idx[8];
 #pragma unroll
-  for (int q = 0; q <= Q; ++q) load_row(lane + 64 * q, R[q]);
-  T inc[CW];
-  load_row(64 * (Q + 1) + lane, inc);
-  T hinv = lane < n ? inv[lane] : T(0);
-  // Group widths (16-bit, two per word; zero past the end of the stream). A
-  // group starts where the previous one ends, so the fetches, which come in
-  // group order, keep a running offset. The ring reaches RG groups ahead, i.e.
-  // into block b + HB - 1. Lane i of `wcur` holds width word i counted from the
-  // current block's first group; `wnext` (the same from the next block on) is
-  // loaded at the start of a block, a block before it is used. Vector loads
-  // complete in order, so waiting for it does not wait for later loads. A ring
-  // longer than a block repeats its slots every UB blocks, so the loop body
-  // covers UB blocks.
-  constexpr int HB = RG > GPB ? 3 : 2;
-  constexpr int UB = RG > GPB ? RG / GPB : 1;
-  constexpr int WPB = GPB / 2;  // width words per block
-  static_assert(RG <= GPB ? GPB % RG == 0 : (RG % GPB == 0 && UB <= 2), "ring and block sizes do not fit");
-  const uint32_t *hw = reinterpret_cast<const uint32_t *>(hdr_g);
-  const int wl = lane < HB * WPB ? lane : HB * WPB - 1;
-  uint32_t wcur = hw[wl];
-  auto width_of = [&](auto gc) -> uint32_t {  // group index from the current block's first
-    constexpr int g = decltype(gc)::value;
-    const uint32_t w = (uint32_t)__builtin_amdgcn_readlane((int)wcur, g / 2);
-    return (w >> (16 * (g % 2))) & 0xFFFFu;
-  };
-  uint32_t foff = 0;  // 16-byte offset of the next group to fetch
-  // ring of group loads RG groups ahead; lanes past a group's width read the
-  // zero region instead, so a loaded group is used as it is
-  V ring[RG][Q];
-  auto fetch = [&](uint32_t w, int s0, int rg) {
-    const uint32_t gbase = sbase + foff * SG;
-    foff += w;
-    // lane offsets computed at each fetch rather than kept for every group
-    int l = lane;
-    asm volatile("; fetch lane %0" : "+v"(l));
-    const uint32_t ub = (uint32_t)((l - s0 - 1) & 63);
+          for (int i = 0; i < 8; ++i) idx[i] = B.alist[min(q0 + i, a1 - 1)];
+          RowT t[8];
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      const uint32_t u = ub + 64u * q;
-      const uint32_t off = (u < w ? gbase : zbase) + u * SG;
-      ring[rg][q] = *reinterpret_cast<const V *>(vals + off);
-    }
-  };
-  StaticFor<0, RG>::run([&](auto rc) {
-    constexpr int rg = decltype(rc)::value;
-    fetch(width_of(rc), (rg * SG) & 63, rg);
-  });
-  for (int jb0 = 0; jb0 < n; jb0 += 64 * UB) {
-    StaticFor<0, UB>::run([&](auto hc_) {
-      constexpr int H = decltype(hc_)::value;
-      const int jb = jb0 + 64 * H;
-      if (jb >= n) return;
-      const uint32_t wnext = hw[(jb / 64 + 1) * WPB + wl];
-      const T hinvN = jb + 64 + lane < n ? inv[jb + 64 + lane] : T(0);
-      T incN[CW];
-      load_row(jb + 64 * (Q + 2) + lane, incN);
-      // lanes whose R[0] row is still open: bits s+1..63 at step s. The mask
-      // is shifted once per step from an opaque start, so that the compiler
-      // neither compares lane ids per step nor keeps 64 constant masks
-      uint64_t up = ~1ull;
-      asm volatile("; lane mask %0" : "+s"(up));
-      StaticFor<0, 64>::run([&](auto sc) {
-        constexpr int s = decltype(sc)::value;
-        constexpr int gi = s / SG, k = s % SG;
-        constexpr int slot = (H * GPB + gi) % RG;
-        const V(&cur)[Q] = ring[slot];
-        if constexpr (ROT) {
-          // one open row per lane: lane s hands its finished row to `done`
-          // and takes its next row; then every lane takes its multiplier
-          const T g = P::template lane<s>(R[0][0]);
-          done = P::template put<s>(g, done);
-          R[0][0] = P::pick(R[1][0], R[0][0], 1ull << s);
-          R[0][0] = P::fnma(P::get(cur[0], k), g, R[0][0]);
-          asm volatile("" : "+v"(R[0][0]));
-        } else {
-          T g[CW];
+          for (int i = 0; i < 8; ++i) t[i].load(u + (size_t)idx[i] * CW);
 #pragma unroll
-          for (int c = 0; c < CW; ++c) g[c] = P::template lane<s>(R[0][c]);
-          T M[Q + 1];
-          M[0] = P::pick_or_zero(P::get(cur[0], k), up);
+          for (int i = 0; i < 8; ++i)
+            if (q0 + i < a1) {
 #pragma unroll
-          for (int q = 1; q < Q; ++q) M[q] = P::pick(P::get(cur[q], k), P::get(cur[q - 1], k), up);
-          M[Q] = P::zero_or_pick(P::get(cur[Q - 1], k), up);
-          up <<= 1;
-#pragma unroll
-          for (int q = 0; q <= Q; ++q)
-#pragma unroll
-            for (int c = 0; c < CW; ++c) {
-              R[q][c] = P::fnma(M[q], g[c], R[q][c]);
-              // keep every update in its step: otherwise updates of registers
-              // not read during the block sink to its end with their operands live
-              asm volatile("" : "+v"(R[q][c]));
+              for (int c = 0; c < CW; ++c) a.v[c] -= t[i].v[c];
             }
         }
-        if constexpr (k == SG - 1) {
-          // the group is consumed: fetch the group RG positions ahead into its slot
-          constexpr int li = gi + RG;
-          fetch(width_of(std::integral_constant<int, li>{}), (li * SG) & 63, slot);
+        a.store(x + (size_t)p * CW);
+      }
+      phase_sync<G>();
+    }
+    for (int p = p0 + lane; p < p1; p += NT) {
+      const SnPos P = B.pos[p];
+      const int c0 = P.c0, w = P.w, h = P.h, r = p - c0;
+      const uint32_t ld = (uint32_t)(w + h);
+      const T *sk = S + P.sbase;
+      T *ub = u + (size_t)P.ubase * CW;
+      if (w <= 8) {
+        // x_C in registers; row r of L_CC^{-1}, then the update rows
+        RowT xc[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) xc[c].load(x + (size_t)(c0 + min(c, w - 1)) * CW);
+        T acc[CW];
+#pragma unroll
+        for (int c = 0; c < CW; ++c) acc[c] = T(0);
+        T sv[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) sv[c] = sk[c <= r ? col_off((uint32_t)c, ld) + (uint32_t)(r - c) : 0u];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) fma_row<T, CW>(acc, c <= r, sv[c], xc[c]);
+        RowT o;
+#pragma unroll
+        for (int c = 0; c < CW; ++c) o.v[c] = acc[c];
+        o.store(y + (size_t)p * CW);
+        for (int i = r; i < h; i += w) {
+          const uint32_t row = (uint32_t)(w + i);
+#pragma unroll
+          for (int c = 0; c < 8; ++c) sv[c] = sk[c < w ? col_off((uint32_t)c, ld) + row - (uint32_t)c : 0u];
+#pragma unroll
+          for (int c = 0; c < CW; ++c) acc[c] = T(0);
+#pragma unroll
+          for (int c = 0; c < 8; ++c) fma_row<T, CW>(acc, c < w, sv[c], xc[c]);
+#pragma unroll
+          for (int c = 0; c < CW; ++c) o.v[c] = acc[c];
+          o.store(ub + (size_t)i * CW);
         }
-      });
-      if (jb + lane < n) {
-        Row<T, CW> rw;
+      } else {
+        // wide supernode: every row in chunks of eight columns
+        for (int i = r - w; i < h; i = (i < 0 ? r : i + w)) {
+          const bool tri = i < 0;
+          const uint32_t row = tri ? (uint32_t)r : (uint32_t)(w + i);
+          const int len = tri ? r + 1 : w;
+          T acc[CW];
 #pragma unroll
-        for (int c = 0; c < CW; ++c) rw.v[c] = (ROT ? done : R[0][c]) * hinv;
-        rw.store(sl + (size_t)(REV ? n - 1 - (jb + lane) : jb + lane) * KC + c0);
+          for (int c = 0; c < CW; ++c) acc[c] = T(0);
+          for (int q0 = 0; q0 < len; q0 += 8) {
+            T sv[8];
+            RowT xv[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+              const int c = min(q0 + q, len - 1);
+              sv[q] = sk[col_off((uint32_t)c, ld) + row - (uint32_t)c];
+              xv[q].load(x + (size_t)(c0 + c) * CW);
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) fma_row<T, CW>(acc, q0 + q < len, sv[q], xv[q]);
+          }
+          RowT o;
+#pragma unroll
+          for (int c = 0; c < CW; ++c) o.v[c] = acc[c];
+          o.store(tri ? y + (size_t)p * CW : ub + (size_t)i * CW);
+        }
       }
-      if constexpr (!ROT) {
+    }
+    phase_sync<G>();
+  }
+  // backward, z in x
+  for (int l = nlev - 1; l >= 0; --l) {
+    const int p0 = B.level(l), p1 = B.level(l + 1);
+    for (int p = p0 + lane; p < p1; p += NT) {
+      const SnPos P = B.pos[p];
+      const int c0 = P.c0, w = P.w, h = P.h, j = p - c0;
+      const T *col = S + P.sbase + col_off((uint32_t)j, (uint32_t)(w + h));
+      T acc[CW];
 #pragma unroll
-        for (int q = 0; q < Q; ++q)
+      for (int c = 0; c < CW; ++c) acc[c] = T(0);
+      // rows j .. w-1 of the column against y
+      const int m1 = w - j;
+      for (int q0 = 0; q0 < m1; q0 += 8) {
+        T sv[8];
+        RowT yv[8];
 #pragma unroll
-          for (int c = 0; c < CW; ++c) R[q][c] = R[q + 1][c];
+        for (int q = 0; q < 8; ++q) {
+          const int t = min(q0 + q, m1 - 1);
+          sv[q] = col[t];
+          yv[q].load(y + (size_t)(p + t) * CW);
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) fma_row<T, CW>(acc, q0 + q < m1, sv[q], yv[q]);
       }
+      // rows below the block against -z_R
+      const T *mc = col + m1;
+      const uint16_t *Rk = B.R + P.ubase;
+      for (int q0 = 0; q0 < h; q0 += 8) {
+        int ri[8];
+        T sv[8];
 #pragma unroll
-      for (int c = 0; c < CW; ++c) {
-        R[Q][c] = inc[c];
-        inc[c] = incN[c];
+        for (int q = 0; q < 8; ++q) {
+          const int t = min(q0 + q, h - 1);
+          ri[q] = Rk[t];
+          sv[q] = -mc[t];
+        }
+        RowT zv[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) zv[q].load(x + (size_t)ri[q] * CW);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) fma_row<T, CW>(acc, q0 + q < h, sv[q], zv[q]);
       }
-      hinv = hinvN;
-      wcur = wnext;
-    });
+      RowT o;
+#pragma unroll
+      for (int c = 0; c < CW; ++c) o.v[c] = acc[c];
+      o.store(x + (size_t)p * CW);
+    }
+    phase_sync<G>();
   }
 }
 
-// columns per pass: keeps the window (Q+1 registers per column) within the
-// register file next to the stream ring
-template <typename T, int Q, int KC>
-constexpr int pass_columns() {
-  constexpr int words = (int)sizeof(T) / 4;
-  constexpr int cap = (Q + 1) * words * 16 <= 96 ? 16
-                      : (Q + 1) * words * 8 <= 96 ? 8
-                      : (Q + 1) * words * 4 <= 96 ? 4
-                      : (Q + 1) * words * 2 <= 96 ? 2 : 1;
-  return KC < cap ? KC : cap;
-}
-
-template <typename T, int KC, int Q>
-__device__ __forceinline__ void star_solve(const StarArgs &a, int st, int n, T *sl) {
-  constexpr int GPB = 64 / Pack<T>::SG;
-  constexpr int CW = pass_columns<T, Q, KC>();
-  // ring of 16-byte group loads: 16 slots (64 registers; 32 at eight columns
-  // in narrow windows), fewer when many columns share a step (a step then takes
-  // longer, so fewer steps of lookahead hide the same latency). Measured: a
-  // 32-slot ring at one column held the narrow kernel to three wavefronts per
-  // SIMD and was slower; at eight columns the deeper ring wins.
-  constexpr int SLOTS = (Q <= 2 && CW == 8 ? 32 : 16) / (CW >= 8 ? CW / 4 : 1);
-  constexpr int RG0 = SLOTS / Q > 2 * GPB ? 2 * GPB : SLOTS / Q;
-  constexpr int RG = RG0 >= 32 ? 32 : RG0 >= 16 ? 16 : RG0 >= 8 ? 8 : RG0 >= 4 ? 4 : RG0 >= 2 ? 2 : 1;
-  const int vb = a.st_vb[st], gbase = a.st_gb[st];
-  const T *finv = static_cast<const T *>(a.f_inv) + vb, *binv = static_cast<const T *>(a.b_inv) + vb;
-  const T *fval = static_cast<const T *>(a.f_val), *bval = static_cast<const T *>(a.b_val);
-  const uint32_t fb = (uint32_t)a.st_fb[st], bb = (uint32_t)a.st_bb[st];
-  for (int c0 = 0; c0 < KC; c0 += CW) {
-    sweep<T, KC, CW, Q, RG, false>(sl, c0, n, a.f_hdr + gbase, finv, fval, fb, (uint32_t)a.f_zero);
-    __syncthreads();
-    sweep<T, KC, CW, Q, RG, true>(sl, c0, n, a.b_hdr + gbase, binv, bval, bb, (uint32_t)a.b_zero);
-    __syncthreads();
-  }
-}
-
-// WIDE = false: stars with windows of 1-2 registers, true: 4-16 registers (kept
-// in separate kernels so that each gets the registers its variants need).
-// LV: the star's working vector lives in LDS during the sweeps (gathered into
-// it, swept in place, copied to the slots at the end) instead of in its slot
-// segment.
-// resident wavefronts per SIMD the register allocation must allow: four (at
-// most 128 registers) for the narrow kernels that fit without spilling; the
-// one-column FP64 kernel with the vector in LDS would otherwise take 129 and
-// run three wavefronts per SIMD
-template <typename T, bool WIDE, int KC, bool LV>
-constexpr int star_min_waves() {
-  return !WIDE && (sizeof(T) == 4 ? KC <= 2 : (KC == 1 && LV)) ? 4 : 1;
-}
-
-template <typename T, bool WIDE, int KC, bool LV>
-__global__ __launch_bounds__(64, (star_min_waves<T, WIDE, KC, LV>())) void k_star(StarArgs a, const double *__restrict__ r,
-                                                                              const CgScalars *sc, int sel) {
-  extern __shared__ __align__(16) unsigned char star_lds[];
-  if (sel != SEL_ALL) {
-    bool any = false;
+// gather r (CW of the KC adjacent columns, from col0) in factor order, eight
+// positions per thread in flight; NT threads from `lane`
+template <typename T, int KC, int CW>
+__device__ __forceinline__ void gather(T *x, const double *__restrict__ r, const int32_t *__restrict__ dofs, int n,
+                                       int col0, int lane, int NT) {
+  for (int p0 = 0; p0 < n; p0 += NT * 8) {
+    int idx[8];
 #pragma unroll
-    for (int c = 0; c < KC; ++c) any |= column_selected(sc[c], sel, 0u, c);
-    if (!any) return;
-  }
-  const int wv = blockIdx.x;
-  if (wv >= a.nstars) return;
-  const int st = a.order[wv];
-  const int n = a.st_n[st], vb = a.st_vb[st], Q = a.st_q[st];
-  const int lane = threadIdx.x;
-  T *sl = static_cast<T *>(a.slots) + (size_t)vb * KC;
-  T *vec = LV ? reinterpret_cast<T *>(star_lds) : sl;
-  // gather r (KC adjacent values per dof) in factor order, U rows per lane in
-  // flight; clamped unconditional loads keep them all in flight
-  constexpr int U = KC <= 2 ? 16 : 32 / KC;
-  const int32_t *dofs = a.pos_dof + vb;
-  for (int p0 = 0; p0 < n; p0 += 64 * U) {
-    int idx[U];
+    for (int q = 0; q < 8; ++q) idx[q] = dofs[min(p0 + NT * q + lane, n - 1)];
+    Row<double, CW> v[8];
 #pragma unroll
-    for (int u = 0; u < U; ++u) idx[u] = dofs[min(p0 + 64 * u + lane, n - 1)];
-    Row<double, KC> val[U];
+    for (int q = 0; q < 8; ++q) v[q].load(r + (size_t)idx[q] * KC + col0);
 #pragma unroll
-    for (int u = 0; u < U; ++u) val[u].load(r + (size_t)idx[u] * KC);
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int p = p0 + 64 * u + lane;
+    for (int q = 0; q < 8; ++q) {
+      const int p = p0 + NT * q + lane;
       if (p < n) {
-        Row<T, KC> o;
+        Row<T, CW> o;
 #pragma unroll
-        for (int c = 0; c < KC; ++c) o.v[c] = (T)val[u].v[c];
-        o.store(vec + (size_t)p * KC);
+        for (int c = 0; c < CW; ++c) o.v[c] = (T)v[q].v[c];
+        o.store(x + (size_t)p * CW);
       }
     }
   }
-  __syncthreads();
-  if constexpr (!WIDE) {
-    if (Q == 1) star_solve<T, KC, 1>(a, st, n, vec);
-    else star_solve<T, KC, 2>(a, st, n, vec);
-  } else {
-    if (Q == 4) star_solve<T, KC, 4>(a, st, n, vec);
-    else if (Q == 8) star_solve<T, KC, 8>(a, st, n, vec);
-    else star_solve<T, KC, 16>(a, st, n, vec);
+}
+
+template <typename T, int KC, int CW>
+__global__ __launch_bounds__(256) void k_star(SnArgs a, const double *__restrict__ r, const CgScalars *sc, int sel) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  const int st = a.order[blockIdx.x];
+  const unsigned char *gb = a.blob + a.st_blob[st];
+  const SnHeader hd = *reinterpret_cast<const SnHeader *>(gb);
+  const int n = (int)hd.n, nu = (int)hd.nu, nlev = (int)hd.nlev;
+  const int nteam = (int)(blockDim.x >> 6), team = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
+  constexpr int NCH = KC / CW;
+  // the column chunks this workgroup has to solve
+  uint32_t chunks = 0;
+#pragma unroll
+  for (int ch = 0; ch < NCH; ++ch) {
+    bool on = false;
+#pragma unroll
+    for (int c = 0; c < CW; ++c) on |= sel == SEL_ALL || column_selected(sc[ch * CW + c], sel, 0u, ch * CW + c);
+    if (on) chunks |= 1u << ch;
   }
-  if constexpr (LV) {
+  if (!chunks) return;
+  const uint32_t xb = (uint32_t)((n * CW * (int)sizeof(T) + 15) & ~15);
+  const uint32_t ub = (uint32_t)((nu * CW * (int)sizeof(T) + 15) & ~15);
+  const uint32_t vec = 2 * xb + ub;
+  const bool vl = hd.idx_bytes + hd.val_bytes + (uint32_t)nteam * vec <= (uint32_t)a.lds_bytes;
+  const uint32_t staged = hd.idx_bytes + (vl ? hd.val_bytes : 0u);
+  {
+    // index part (and values) to LDS, 16 bytes per thread and load, sixteen
+    // loads per thread in flight
+    const float4 *src = reinterpret_cast<const float4 *>(gb);
+    float4 *dst = reinterpret_cast<float4 *>(lds);
+    const int n16 = (int)(staged >> 4);
+    const int bs = (int)blockDim.x;
+    // indices past the end are clamped for the loads and the stores alike (a
+    // lane then rewrites the last chunk with its own value), so that no load
+    // sits behind a branch and all of them are in flight together
+    for (int i0 = (int)threadIdx.x; i0 < n16; i0 += 16 * bs) {
+      float4 v[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) v[q] = src[min(i0 + q * bs, n16 - 1)];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) dst[min(i0 + q * bs, n16 - 1)] = v[q];
+    }
+  }
+  SnView B;
+  B.lev = reinterpret_cast<const uint32_t *>(lds + hd.off_lev);
+  B.lv_reg = nlev < 64;
+  B.pos = reinterpret_cast<const SnPos *>(lds + hd.off_pos);
+  B.R = reinterpret_cast<const uint16_t *>(lds + hd.off_R);
+  B.alist = reinterpret_cast<const uint16_t *>(lds + hd.off_alist);
+  unsigned char *tv = lds + staged + (uint32_t)team * vec;
+  T *x = reinterpret_cast<T *>(tv), *y = reinterpret_cast<T *>(tv + xb), *u = reinterpret_cast<T *>(tv + 2 * xb);
+  const int32_t *dofs = a.pos_dof + a.st_pos[st];
+  T *out = static_cast<T *>(a.slots) + (size_t)a.st_pos[st] * KC;
+  __syncthreads();
+  B.lv_pos = (int)B.lev[min(lane, nlev)];
+  for (int ch = team; ch < NCH; ch += nteam) {
+    if (!((chunks >> ch) & 1u)) continue;
+    const int col0 = ch * CW;
+    gather<T, KC, CW>(x, r, dofs, n, col0, lane, 64);
+    team_sync();
+    if (vl) team_solve<T, CW, false>(B, reinterpret_cast<const T *>(lds + hd.idx_bytes), nlev, x, y, u);
+    else team_solve<T, CW, false>(B, reinterpret_cast<const T *>(gb + hd.idx_bytes), nlev, x, y, u);
     // z_j to the star's slots
     for (int p = lane; p < n; p += 64) {
-      Row<T, KC> o;
-      o.load(vec + (size_t)p * KC);
-      o.store(sl + (size_t)p * KC);
+      Row<T, CW> o;
+      o.load(x + (size_t)p * CW);
+      o.store(out + (size_t)p * KC + col0);
     }
+    team_sync();
   }
 }
 
-template <typename T, int KC>
-void launch_star_t(const StarArgs &a, bool wide, const double *r, const CgScalars *sc, int sel, hipStream_t s) {
-  if (a.nstars <= 0) return;
-  // the working vector goes to LDS when asked for and the largest star's fits in
-  // 32 KB (up to eight columns); the LDS reservation, if larger, limits how many
-  // stars share a CU
-  const size_t need = ((size_t)a.maxn * KC * sizeof(T) + 15) / 16 * 16;
-  if constexpr (KC <= 8) {
-    if (a.use_lds && need <= 32768) {
-      const size_t lds = std::max<size_t>((size_t)a.lds_reserve, need);
-      if (wide) hipLaunchKernelGGL((k_star<T, true, KC, true>), dim3(a.nstars), dim3(64), lds, s, a, r, sc, sel);
-      else hipLaunchKernelGGL((k_star<T, false, KC, true>), dim3(a.nstars), dim3(64), lds, s, a, r, sc, sel);
-      return;
+// Stars too large for LDS: the whole workgroup solves one column chunk after
+// the other with the factor read from the blob and the vectors in the global
+// scratch at a.vscratch + a.st_vs[star].
+template <typename T, int KC, int CW>
+__global__ __launch_bounds__(256) void k_star_global(SnArgs a, const double *__restrict__ r, const CgScalars *sc,
+                                                     int sel) {
+  const int st = a.order[blockIdx.x];
+  const unsigned char *gb = a.blob + a.st_blob[st];
+  const SnHeader hd = *reinterpret_cast<const SnHeader *>(gb);
+  const int n = (int)hd.n, nlev = (int)hd.nlev;
+  constexpr int NCH = KC / CW;
+  SnView B;
+  B.lev = reinterpret_cast<const uint32_t *>(gb + hd.off_lev);
+  B.lv_reg = false;
+  B.lv_pos = 0;
+  B.pos = reinterpret_cast<const SnPos *>(gb + hd.off_pos);
+  B.R = reinterpret_cast<const uint16_t *>(gb + hd.off_R);
+  B.alist = reinterpret_cast<const uint16_t *>(gb + hd.off_alist);
+  const uint32_t xb = (uint32_t)((n * CW * (int)sizeof(T) + 15) & ~15);
+  unsigned char *tv = a.vscratch + a.st_vs[st];
+  T *x = reinterpret_cast<T *>(tv), *y = reinterpret_cast<T *>(tv + xb), *u = reinterpret_cast<T *>(tv + 2 * xb);
+  const int32_t *dofs = a.pos_dof + a.st_pos[st];
+  T *out = static_cast<T *>(a.slots) + (size_t)a.st_pos[st] * KC;
+  const int tid = (int)threadIdx.x, NT = (int)blockDim.x;
+  for (int ch = 0; ch < NCH; ++ch) {
+    bool on = false;
+#pragma unroll
+    for (int c = 0; c < CW; ++c) on |= sel == SEL_ALL || column_selected(sc[ch * CW + c], sel, 0u, ch * CW + c);
+    if (!on) continue;
+    const int col0 = ch * CW;
+    gather<T, KC, CW>(x, r, dofs, n, col0, tid, NT);
+    __syncthreads();
+    team_solve<T, CW, true>(B, reinterpret_cast<const T *>(gb + hd.idx_bytes), nlev, x, y, u);
+    for (int p = tid; p < n; p += NT) {
+      Row<T, CW> o;
+      o.load(x + (size_t)p * CW);
+      o.store(out + (size_t)p * KC + col0);
     }
+    __syncthreads();
   }
-  const size_t lds = (size_t)a.lds_reserve;
-  if (wide) hipLaunchKernelGGL((k_star<T, true, KC, false>), dim3(a.nstars), dim3(64), lds, s, a, r, sc, sel);
-  else hipLaunchKernelGGL((k_star<T, false, KC, false>), dim3(a.nstars), dim3(64), lds, s, a, r, sc, sel);
+}
+
+template <typename T, int KC, int CW>
+void launch_star_t(const SnArgs &a, int nteam, bool global, const double *r, const CgScalars *sc, int sel,
+                   hipStream_t s) {
+  if (a.nstars <= 0) return;
+  if (global) {
+    hipLaunchKernelGGL((k_star_global<T, KC, CW>), dim3(a.nstars), dim3(256), 0, s, a, r, sc, sel);
+    return;
+  }
+  // allow the kernel the whole LDS of a compute unit (once per instantiation)
+  static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_star<T, KC, CW>),
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize, kStarMaxLds);
+  if (attr != hipSuccess) fail(SN_EDEVICE, std::string("star kernel LDS limit: ") + hipGetErrorString(attr));
+  hipLaunchKernelGGL((k_star<T, KC, CW>), dim3(a.nstars), dim3(64 * nteam), (size_t)a.lds_bytes, s, a, r, sc, sel);
 }
 
 }  // namespace spnet

@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(_HERE, "libspnet.so")
 SN_OK, SN_EINVAL, SN_ENOMEM, SN_EDEVICE, SN_ESINGULAR, SN_ENOTSPD, SN_ENOCONV, SN_EBUSY = 0, -1, -2, -3, -4, -5, -6, -7
 MODEL_HEAT, MODEL_TRUSS = 0, 1
 STARS_ALL, STARS_FREE = 0, 1
-FP64, FP32_STARS = 0, 1
+FP64, FP32_STARS, FP32_STARS_COARSE = 0, 1, 2
 
 _P = C.c_void_p
 _i64, _i32, _dbl = C.c_int64, C.c_int32, C.c_double
@@ -36,11 +36,22 @@ class SolveInfo(C.Structure):
 
 
 class FactorInfo(C.Structure):
-    _fields_ = [("star_factor_nnz", C.c_int64), ("star_stream_bytes", C.c_int64), ("coarse_bytes", C.c_int64),
-                ("device_bytes", C.c_int64), ("max_star_dofs", C.c_int32), ("max_band", C.c_int32),
-                ("factor_seconds", C.c_double), ("sweep_bytes", C.c_int64), ("spmv_bytes", C.c_int64),
-                ("sweep_flops", C.c_int64), ("max_pivot_ratio", C.c_double), ("star_precision", C.c_int32),
-                ("coarse_precision", C.c_int32), ("coarse_pivot_ratio", C.c_double)]
+    _fields_ = [("star_factor_nnz", C.c_int64), ("star_stored", C.c_int64), ("star_blob_bytes", C.c_int64),
+                ("star_index_bytes", C.c_int64), ("coarse_bytes", C.c_int64), ("device_bytes", C.c_int64),
+                ("max_star_dofs", C.c_int32), ("max_levels", C.c_int32), ("factor_seconds", C.c_double),
+                ("sweep_bytes", C.c_int64), ("spmv_bytes", C.c_int64), ("sweep_flops", C.c_int64),
+                ("max_pivot_ratio", C.c_double), ("star_precision", C.c_int32), ("coarse_precision", C.c_int32),
+                ("coarse_pivot_ratio", C.c_double)]
+
+    def asdict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class EngineInfo(C.Structure):
+    _fields_ = [("star_lds_bytes", C.c_int32), ("star_cols_per_wave", C.c_int32), ("star_waves", C.c_int32),
+                ("star_big", C.c_int32), ("star_big_lds_bytes", C.c_int32), ("star_global", C.c_int32),
+                ("coarse_first", C.c_int32),
+                ("star_sweep_us", C.c_double), ("b_apply_us", C.c_double)]
 
     def asdict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -91,8 +102,7 @@ SIGNATURES = {
     "sn_solve": (C.c_int, [_P, C.c_int, _P, _P, C.POINTER(SolveOpts), C.POINTER(SolveInfo)]),
     "sn_precond_profile": (C.c_int, [_P, C.c_int]),
     "sn_precond_kernel_stats": (C.c_int, [_P, C.POINTER(KernelStats)]),
-    "sn_precond_engine_info": (C.c_int, [_P, C.c_int, C.POINTER(_i32), C.POINTER(_dbl), C.POINTER(_i32),
-                                         C.POINTER(_dbl)]),
+    "sn_precond_engine_info": (C.c_int, [_P, C.c_int, C.POINTER(EngineInfo)]),
     "sn_apply_K": (C.c_int, [_P, C.c_int, _P, _P, C.c_int, _P]),
     "sn_apply_B": (C.c_int, [_P, C.c_int, _P, _P, C.c_int, _P]),
     "sn_server_opts_default": (None, [C.POINTER(ServerOpts)]),
@@ -248,14 +258,14 @@ class Precond:
         return fi.asdict()
 
     def engine_info(self, k=1):
-        """Launch shape measured for batches of k columns: dict with the star
-        wavefronts per SIMD limit (0 = none), the sweep time, whether the coarse
-        solve runs before the sweeps, and the time of the second half of an
-        iteration (convergence test and one application of B)."""
-        w, us, cf, bus = _i32(), _dbl(), _i32(), _dbl()
-        _check(lib().sn_precond_engine_info(self.h, k, C.byref(w), C.byref(us), C.byref(cf), C.byref(bus)))
-        return {"star_waves_per_simd_limit": w.value, "sweep_us": round(us.value, 2),
-                "coarse_first": bool(cf.value), "b_apply_us": round(bus.value, 2)}
+        """Launch shape measured for batches of k columns (see sn_engine_info)."""
+        ei = EngineInfo()
+        _check(lib().sn_precond_engine_info(self.h, k, C.byref(ei)))
+        d = ei.asdict()
+        d["star_sweep_us"] = round(d["star_sweep_us"], 2)
+        d["b_apply_us"] = round(d["b_apply_us"], 2)
+        d["coarse_first"] = bool(d["coarse_first"])
+        return d
 
     # ---------------------------------------------------------------- solves
     def _block(self, a):
@@ -358,6 +368,9 @@ class Server:
         rc = lib().sn_server_poll(self.h, ticket, None, None)  # status only
         if rc == SN_EBUSY:
             return None
+        if rc != SN_OK:  # a failed request reports its error once
+            del self._keep[ticket]
+            _check(rc)
         u = np.empty(shape)
         infos = (SolveInfo * k)()
         rc = lib().sn_server_poll(self.h, ticket, _ptr(u), infos)

@@ -14,6 +14,8 @@ configuration the benchmark times (captured-graph replay).
 * Serving pool (2k-500k nodes, 2D and 3D): every request reaches the tolerance
   and a sampled request equals sn_solve bit for bit.
 """
+import time
+
 import numpy as np
 import pytest
 
@@ -67,7 +69,7 @@ def test_fiber2d_20k_plain_and_mixed(S, orc):
     assert info_t[0]["iters"] == it_o and info_t[0]["res_true"] <= 1.0001e-8
     gmixed = S.Precond(gplain.sys, 32, S.STARS_ALL, 1, 1, precision=S.FP32_STARS)
     assert gmixed.factor_info()["star_precision"] == S.FP32_STARS
-    assert gmixed.factor_info()["coarse_precision"] == S.FP32_STARS
+    assert gmixed.factor_info()["coarse_precision"] == S.FP64
     u_m, info_m = gmixed.solve(fd, rtol=1e-8, use_graph=True)
     assert info_m[0]["res_true"] <= 1.0001e-8 and info_m[0]["iters"] <= it_o + 3
     assert _rel(u_m.cpu().numpy(), u_o) <= 1e-6
@@ -132,14 +134,13 @@ def test_serving_pool_full_size(S):
         k = 1 + i % 8
         tickets[srv.submit(pre, W.rhs(pre.sys.n, k, seed=200 + i))] = (i, k)
     done = {}
-    for _ in range(100000):
+    t_end = time.time() + 150
+    while tickets and time.time() < t_end:
         srv.step()
         for t in list(tickets):
             r = srv.poll(t)
             if r is not None:
                 done[t] = (tickets.pop(t), r)
-        if not tickets:
-            break
     assert not tickets
     for (i, k), (u, infos) in done.values():
         assert len(infos) == k and all(x["converged"] and x["res_true"] <= 1.0001e-8 for x in infos), i

@@ -105,10 +105,23 @@ def test_preconditioner_fp32_stars(S, orc, name):
     else:
         # FP32 factors and sweeps: ~ cond(K_j) * 6e-8
         assert _rel(z, ref) <= 5e-3
-    # the coarse inverse is stored in FP32 only beside FP32 sweeps and when its
-    # factor's pivot ratio leaves FP32 room to resolve it
+    # the mixed form keeps the coarse operator in FP64
+    assert fi["coarse_precision"] == S.FP64
+
+
+@pytest.mark.parametrize("name", ["fiber2d_2k", "truss3d_1500"])
+def test_preconditioner_fp32_coarse(S, orc, name):
+    """FP32 stars and the FP32-stored coarse inverse (asked for explicitly): the
+    coarse inverse is stored in FP32 only beside FP32 local solves and when the
+    coarse factor's pivot ratio leaves FP32 room to resolve it."""
+    opre, gpre = _pair(S, orc, name, S.FP32_STARS_COARSE)
+    r = W.rhs(opre.sys.n, 1, seed=4)[:, 0]
+    z = gpre.apply_B(r)
+    ref = opre.apply_B(r)
+    fi = gpre.factor_info()
     coarse32 = fi["star_precision"] == S.FP32_STARS and fi["coarse_pivot_ratio"] * 2.0 ** -24 <= 0.05
-    assert fi["coarse_precision"] == (S.FP32_STARS if coarse32 else S.FP64)
+    assert fi["coarse_precision"] == (S.FP32_STARS_COARSE if coarse32 else S.FP64)
+    assert _rel(z, ref) <= (5e-3 if fi["star_precision"] == S.FP32_STARS else _tol(orc, name, opre))
 
 
 @pytest.mark.parametrize("name", list(CASES))
