@@ -157,24 +157,35 @@ sn_status sn_precond_export_coarse(sn_precond pre, int32_t *coarse_vertex);
 
 typedef struct {
   int64_t star_factor_nnz;   /* structural non-zeros of all local Cholesky factors (incl. the
-                                diagonal) in the minimum degree order the library uses */
+                                diagonal) in minimum degree order (the supernodal layout) */
+  int64_t star_rcm_nnz;      /* the same in reverse Cuthill-McKee order (the band layout) */
+  int64_t star_envelope;     /* entries of the band layout's envelopes (incl. the diagonal) */
   int64_t star_stored;       /* entries the supernodal blocks store: the non-zeros plus the explicit
                                 zeros of relaxed supernodes (L_CC^{-1} has the pattern of L_CC) */
-  int64_t star_blob_bytes;   /* device bytes of the local factors: index part and values */
+  int64_t star_blob_bytes;   /* device bytes of the supernodal factors: index part and values */
   int64_t star_index_bytes;  /* of which the index part (headers, level tables, 16-bit lists) */
+  int64_t star_stream_bytes; /* device bytes of the band layout's two sweep streams */
   int64_t coarse_bytes;      /* device bytes of the coarse operator */
   int64_t device_bytes;      /* all device memory held by the preconditioner */
   int32_t max_star_dofs;
-  int32_t max_levels;        /* most supernode levels of a star: a local solve runs 3 x levels - 1
-                                dependent phases */
-  double factor_seconds;     /* host time of ordering + numeric factorisation */
+  int32_t max_band;          /* widest envelope row/column of the band layout */
+  int32_t max_levels;        /* most supernode levels of a star: a supernodal local solve runs
+                                3 x levels - 1 dependent phases */
+  int32_t pad0;
+  double factor_seconds;     /* host time of ordering + numeric factorisation (both layouts) */
   int64_t sweep_bytes;       /* algorithmic bytes of one application of all local solves to one
-                                column: the values of the structural non-zeros once, and per
-                                position its dof index, the FP64 gather of r and the slot write */
+                                column with every star on the band path (the supernodal path where
+                                the band exceeds 1024): per star the structural non-zeros of its
+                                factor in that path's order, twice for the band path (both sweeps
+                                stream the factor) and once for the supernodal path (read once,
+                                kept in LDS or cache), plus per position its dof index, the FP64
+                                gather of r and the slot write; see sn_engine_info for the split
+                                an engine runs */
+  int64_t sweep_bytes_sn;    /* the same with every star on the supernodal path */
   int64_t spmv_bytes;        /* algorithmic bytes of one y = K x (values, columns, x, y) */
-  int64_t sweep_flops;       /* 4 flops per structural non-zero (forward and backward solve) */
-  double max_pivot_ratio;    /* max over stars of (largest / smallest Cholesky pivot), a lower
-                                bound of cond(K_j) */
+  int64_t sweep_flops;       /* 4 flops per structural non-zero of the minimum degree factors */
+  double max_pivot_ratio;    /* max over stars and layouts of (largest / smallest Cholesky pivot),
+                                a lower bound of cond(K_j) */
   int32_t star_precision;    /* precision the local solves run in: FP32 falls back to
                                 SN_PREC_FP64 when max_pivot_ratio * 2^-24 > 0.05, i.e. when FP32
                                 factors could not resolve the local solves */
@@ -243,16 +254,24 @@ sn_status sn_precond_kernel_stats(sn_precond pre, sn_kernel_stats *stats);
 
 /*
  * Launch shape chosen for batches of k columns (measured on the device when
- * the preconditioner first solves with that batch width): the local solves
- * run one star per workgroup of star_waves wavefronts, each carrying
- * star_cols_per_wave of the k columns in turn; the workgroups of the main
- * launch get star_lds_bytes of LDS (every candidate cap is timed), the
- * star_big stars whose index part and vectors need more run in a second
- * launch beside it with star_big_lds_bytes each, and the star_global stars
- * that exceed the LDS of a compute unit are solved by 256-thread workgroups
- * from global memory.
+ * the preconditioner first solves with that batch width). The local solves
+ * are split by size: the star_sn stars with the longest band sweeps (and any
+ * star whose band exceeds 1024) run the supernodal kernel, the others the
+ * band kernel, beside each other; every candidate split is timed.
+ *   band path: at most star_waves_per_simd resident band wavefronts per SIMD
+ *     (0 = no limit), working vectors in LDS (star_band_lds = 1) or in the
+ *     slots;
+ *   supernodal path: one star per workgroup of star_waves wavefronts, each
+ *     carrying star_cols_per_wave of the k columns in turn; the workgroups of
+ *     its main launch get star_lds_bytes of LDS, the star_big stars whose index
+ *     part and vectors need more run with star_big_lds_bytes each, and the
+ *     star_global stars that exceed the LDS of a compute unit are solved by
+ *     256-thread workgroups from global memory.
  */
 typedef struct {
+  int32_t star_sn;
+  int32_t star_waves_per_simd;
+  int32_t star_band_lds;
   int32_t star_lds_bytes;
   int32_t star_cols_per_wave;
   int32_t star_waves;
@@ -261,11 +280,26 @@ typedef struct {
   int32_t star_global;
   int32_t coarse_first;  /* 1: the coarse solve runs before the local solves (and its restriction
                             also runs the convergence test), 0: beside them on a second stream */
+  int64_t sweep_bytes;   /* algorithmic bytes of one application of the local solves to one column
+                            with this split (see sn_factor_info.sweep_bytes) */
   double star_sweep_us;  /* time of all local solves, microseconds per application of B */
   double b_apply_us;     /* time of the second half of an iteration (convergence test and B) */
 } sn_engine_info;
 
 sn_status sn_precond_engine_info(sn_precond pre, int k, sn_engine_info *info);
+
+/*
+ * The split of the local solves between the two kernels. By default it is
+ * measured when the preconditioner first solves (the candidate that solves all
+ * stars fastest) and then kept for every batch width, since the two kernels
+ * round differently and a column's iterates must not depend on its batch.
+ * n_sn >= 0 fixes it instead: the n_sn stars with the most positions (and
+ * every star whose band exceeds 1024) run the supernodal kernel, the others
+ * the band kernel; n_sn < 0 returns to measuring. Drops the preconditioner's
+ * solve engines (the next solve creates them); engines a server already holds
+ * keep their split until they are evicted. Errors: SN_EINVAL if not factored.
+ */
+sn_status sn_precond_set_star_split(sn_precond pre, int64_t n_sn);
 
 /* y = K x for k columns (n x k row-major). */
 sn_status sn_apply_K(sn_precond pre, int k, const double *x, double *y, int device_ptrs, void *stream);

@@ -44,7 +44,7 @@ def _stale(obj, src):
     else:
         hdrs.append("device_common.hpp")
     if src.endswith("star_inst.hip"):
-        hdrs.append("star_kernel.hpp")
+        hdrs += ["star_band.hpp", "star_sn.hpp"]
     deps = [src] + [os.path.join(CSRC, h) for h in hdrs]
     deps.append(os.path.join(os.path.dirname(HERE), "include", "spnet.h"))
     return any(os.path.getmtime(d) > t for d in deps)

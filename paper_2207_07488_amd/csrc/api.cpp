@@ -232,6 +232,13 @@ sn_status sn_precond_kernel_stats(sn_precond pre, sn_kernel_stats *stats) {
   });
 }
 
+sn_status sn_precond_set_star_split(sn_precond pre, int64_t n_sn) {
+  return guarded([&] {
+    REQUIRE(pre && pre->p->dev, "null argument or not factored");
+    spnet::device_set_star_split(*pre->p, n_sn);
+  });
+}
+
 sn_status sn_precond_engine_info(sn_precond pre, int k, sn_engine_info *info) {
   return guarded([&] {
     REQUIRE(pre && info && pre->p->dev, "null argument or not factored");

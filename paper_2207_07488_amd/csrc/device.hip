@@ -871,14 +871,30 @@ struct DeviceState {
   int nslices = 0;
   DBuf<int32_t> sptr, slen, col;
   DBuf<double> val;
-  // stars: one blob per star (index part, then values), slots = positions of
-  // all stars back to back
+  // stars: slots = the positions of all stars back to back, each star's in
+  // its band (RCM) order; st_vb[s] is the first slot of star s
   int32_t nstars = 0, maxn = 0, maxlev = 0;
   int64_t slot_count = 0;
+  DBuf<int32_t> st_vb, pos_dof, slot_of;
+  std::vector<int32_t> h_n;            // per star: positions
+  // band layout (star_band.hpp): windows of Q registers, packed streams
+  std::vector<int32_t> h_q;            // per star: window registers (0: band beyond 1024, supernodal only)
+  DBuf<int32_t> st_n, st_q, st_gb;
+  DBuf<int64_t> st_fb, st_bb;
+  DBuf<uint16_t> f_hdr, b_hdr;
+  DBuf<float> f_inv32, b_inv32, f_val32, b_val32;
+  DBuf<double> f_inv64, b_inv64, f_val64, b_val64;
+  int64_t f_zero = 0, b_zero = 0;
+  // supernodal layout (star_sn.hpp): one blob per star (index part, then values)
   DBuf<unsigned char> blob;
   DBuf<int64_t> st_blob;
-  DBuf<int32_t> st_pos, pos_dof, slot_of;
-  std::vector<uint32_t> h_idx, h_val, h_n, h_nu;  // per star: blob part bytes, positions, u-slots
+  std::vector<uint32_t> h_idx, h_val, h_nu;  // per star: blob part bytes, u-slots
+  std::vector<int64_t> h_bytes_band, h_bytes_sn;  // per star: algorithmic bytes of one solve of one column
+  // stars on the supernodal path besides those the band kernel cannot take:
+  // measured when the first engine is created (or set by the caller) and then
+  // shared by every engine, since the two kernels round differently and a
+  // column's iterates must not depend on its batch; -1: not yet chosen
+  int64_t split = -1;
   // coarse
   // K_0^{-1}, symmetric, zero-padded to ld0 x ld0 (ld0 a multiple of 64): FP32 in the mixed form
   // unless the coarse factor's pivot ratio rules it out, else FP64
@@ -913,16 +929,24 @@ struct Engine {
   DBuf<float> slots32;
   DBuf<double> slots64;
   CgScalars *host_sc = nullptr;  // pinned: last read-back, and the source of uploads
-  // star launches (chosen by measurement, see tune_stars): launch 0 on the
-  // solve stream with lds_cap bytes of LDS per workgroup, launches 1 (stars
-  // whose index part and vectors need more) and 2 (stars beyond the LDS of a
-  // compute unit) beside it on aux
+  // local solves, chosen by measurement (see tune_stars): the stars with the
+  // longest band sweeps (and every star whose band exceeds 1024) run the
+  // supernodal kernel on aux3, the others the band kernel on the solve stream
+  // (narrow windows) and aux (wide windows)
+  int32_t n_sn = 0;                            // stars on the supernodal path
+  std::vector<int32_t> sn_list;                // those stars, longest first
+  int64_t sweep_bytes = 0;                     // algorithmic bytes of one application (one column)
+  // band launches: stars of the band path, narrow and wide windows, longest first
+  DBuf<int32_t> b_narrow, b_wide;
+  int32_t n_narrow = 0, n_wide = 0;
+  int32_t star_cap = 0, star_lds = 0;          // resident band wavefronts per SIMD (0: no limit) and its LDS reservation
+  bool star_lv = true;                         // band working vectors in LDS (where they fit)
+  // supernodal launches: 0 (lds_cap per workgroup), 1 (more LDS), 2 (global memory)
   struct StarLaunch {
     DBuf<int32_t> order;
     int32_t count = 0, lds = 0;
   } sl[3];
-  // launch 2: stars too large for LDS, solved from global memory (vectors in vscratch)
-  DBuf<unsigned char> vscratch;
+  DBuf<unsigned char> vscratch;                // vectors of the launch-2 stars
   DBuf<int64_t> st_vs;
   int32_t star_cw = 1, star_nteam = 1, star_lcap = 0;
   double star_us = 0.0;
@@ -930,9 +954,11 @@ struct Engine {
   double b_us = 0.0;
   bool sc_dirty = false;         // host_sc changed since the last upload
   hipStream_t own = nullptr;     // the engine's stream (and graph capture)
-  hipStream_t aux = nullptr;     // wide stars run beside the narrow ones
+  hipStream_t aux = nullptr;     // wide band stars run beside the narrow ones
   hipStream_t aux2 = nullptr;    // the coarse solve runs beside the star sweeps
-  hipEvent_t fork = nullptr, join = nullptr, fork2 = nullptr, join2 = nullptr, tick_done = nullptr;
+  hipStream_t aux3 = nullptr;    // the supernodal stars run beside the band ones
+  hipEvent_t fork = nullptr, join = nullptr, fork2 = nullptr, join2 = nullptr, fork3 = nullptr, join3 = nullptr;
+  hipEvent_t tick_done = nullptr;
   bool in_flight = false;
   std::vector<hipGraphExec_t> graphs;  // graphs[i] runs 2^i iterations on `own`-captured work
   std::vector<hipGraph_t> graph_defs;
@@ -948,6 +974,9 @@ struct Engine {
     if (join) (void)hipEventDestroy(join);
     if (fork2) (void)hipEventDestroy(fork2);
     if (join2) (void)hipEventDestroy(join2);
+    if (fork3) (void)hipEventDestroy(fork3);
+    if (join3) (void)hipEventDestroy(join3);
+    if (aux3) (void)hipStreamDestroy(aux3);
     if (tick_done) (void)hipEventDestroy(tick_done);
     if (aux2) (void)hipStreamDestroy(aux2);
     if (aux) (void)hipStreamDestroy(aux);
@@ -975,11 +1004,58 @@ namespace {
 inline unsigned nblk(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 inline unsigned grid_for(int64_t n) { return std::max(1u, std::min<unsigned>(kMaxGrid, nblk(n))); }
 
-// One star's blob: header, level table, position records, 16-bit index lists
+int window_regs(int band) {
+  const int q = (band + 63) / 64;
+  for (int w = 1; w <= 16; w *= 2)
+    if (q <= w) return w;
+  return -1;
+}
+
+// Pack one sweep stream of a star: steps in groups of SG (the first step of
+// every group a multiple of SG), values divided by the step's pivot. Lane l
+// and window register q read slot u = ((l - j0 - 1) mod 64) + 64 q of the group
+// with first step j0 (mod 64); slot u holds, for k = 0..SG-1, entry
+// t = 64 q + ((u mod 64 - k) mod 64) of step j0 + k (zero past the step's width).
+// The group stores slots 0..W-1, W one past the last non-zero slot, right after
+// the previous group; `widths` gets W (16-bit) per group, so a group's offset is
+// the sum of the widths before it.
+template <typename T>
+void pack_stream(const std::vector<int32_t> &width, const std::vector<double> &vals, const std::vector<double> &inv,
+                 int SG, int Q, std::vector<T> &out, std::vector<uint16_t> &widths) {
+  const int n = (int)width.size();
+  std::vector<int64_t> start((size_t)n + 1, 0);
+  for (int j = 0; j < n; ++j) start[j + 1] = start[j] + width[j];
+  auto entry = [&](int j, int slot, int k) -> double {
+    const int jj = j + k;
+    if (jj >= n) return 0.0;
+    const int q = slot / 64, u = slot % 64;
+    const int t = 64 * q + ((u - k) & 63);
+    if (t >= width[jj]) return 0.0;
+    return vals[(size_t)(start[jj] + t)] * inv[jj];
+  };
+  for (int j0 = 0; j0 < n; j0 += SG) {
+    int W = 0;
+    for (int slot = 0; slot < 64 * Q; ++slot)
+      for (int k = 0; k < SG; ++k)
+        if (entry(j0, slot, k) != 0.0) W = slot + 1;
+    widths.push_back((uint16_t)W);
+    for (int slot = 0; slot < W; ++slot)
+      for (int k = 0; k < SG; ++k) out.push_back((T)entry(j0, slot, k));
+  }
+  // zero widths past the end: the sweep reads whole blocks of widths up to
+  // four blocks ahead
+  const int GPB = 64 / SG;
+  const size_t ng = (size_t)(n + SG - 1) / SG;
+  const size_t padded = (ng + GPB - 1) / GPB * GPB + 4 * GPB;
+  widths.resize(widths.size() + (padded - ng), 0);
+}
+
+// One star's supernodal blob: header, level table, position records, 16-bit index lists
 // (padded to 16 bytes: the index part), then the values of the S_k in T
 // (padded to 16 bytes).
 template <typename T>
-void pack_blob(const StarFactor &F, std::vector<unsigned char> &out, uint32_t &idx_bytes, uint32_t &val_bytes) {
+void pack_blob(const SnFactor &F, const std::vector<int32_t> &bpos, std::vector<unsigned char> &out,
+               uint32_t &idx_bytes, uint32_t &val_bytes) {
   if (F.n >= 65536 || F.nu >= 65536)
     fail(SN_EINVAL, "star too large for 16-bit local indices (" + std::to_string(F.n) + " positions, " +
                         std::to_string(F.nu) + " updates)");
@@ -999,6 +1075,8 @@ void pack_blob(const StarFactor &F, std::vector<unsigned char> &out, uint32_t &i
   off += 2 * (size_t)F.nu;
   h.off_alist = (uint32_t)off;
   off += 2 * (size_t)F.nu;
+  h.off_bpos = (uint32_t)off;
+  off += 2 * (size_t)F.n;
   h.idx_bytes = (uint32_t)a16(off);
   h.val_bytes = (uint32_t)a16(F.S.size() * sizeof(T));
   const size_t base = out.size();
@@ -1025,78 +1103,154 @@ void pack_blob(const StarFactor &F, std::vector<unsigned char> &out, uint32_t &i
   };
   put16(h.off_R, F.R);
   put16(h.off_alist, F.alist);
+  put16(h.off_bpos, bpos);
   T *val = reinterpret_cast<T *>(b + h.idx_bytes);
   for (size_t i = 0; i < F.S.size(); ++i) val[i] = (T)F.S[i];
   idx_bytes = h.idx_bytes;
   val_bytes = h.val_bytes;
 }
 
+// Both layouts of every star. Slots follow the band order of each star; the
+// supernodal blob maps its positions to them (bpos). Per star the algorithmic
+// bytes of one solve of one column are kept for each path: the structural
+// non-zeros of that path's factor times the factor precision (twice for the
+// band path, whose two sweeps stream their own copies; once for the supernodal
+// path, which reads its factor from HBM once and keeps it in LDS or cache for
+// the second solve), and per position the dof index, the FP64 gather of r and
+// the slot write.
 template <typename T>
 void upload_stars(DeviceState &d, const Precond &pre, const HostFactors &hf, sn_factor_info &fi) {
+  constexpr int SG = 16 / (int)sizeof(T);
   const int64_t ns = (int64_t)hf.stars.size();
+  const int64_t sT = sizeof(T);
+  std::vector<int32_t> st_n(ns), st_vb(ns), st_q(ns), st_gb(ns), pos_dof;
+  std::vector<uint16_t> f_hdr, b_hdr;
+  std::vector<int64_t> st_fb(ns), st_bb(ns), st_blob(ns);
+  std::vector<T> f_val, b_val, f_inv, b_inv;
   std::vector<unsigned char> blob;
-  std::vector<int64_t> st_blob((size_t)ns);
-  std::vector<int32_t> st_pos((size_t)ns), pos_dof;
+  d.h_n.assign((size_t)ns, 0);
+  d.h_q.assign((size_t)ns, 0);
   d.h_idx.assign((size_t)ns, 0);
   d.h_val.assign((size_t)ns, 0);
-  d.h_n.assign((size_t)ns, 0);
   d.h_nu.assign((size_t)ns, 0);
-  int64_t tot = 0, nnz = 0, stored = 0, idx_tot = 0;
+  d.h_bytes_band.assign((size_t)ns, 0);
+  d.h_bytes_sn.assign((size_t)ns, 0);
+  int64_t tot = 0, nnz_md = 0, nnz_rcm = 0, env = 0, stored = 0, idx_tot = 0;
+  int maxband = 0;
   for (int64_t s = 0; s < ns; ++s) {
     const StarFactor &F = hf.stars[s];
-    st_blob[s] = (int64_t)blob.size();
-    st_pos[s] = (int32_t)tot;
-    pack_blob<T>(F, blob, d.h_idx[s], d.h_val[s]);
-    d.h_n[s] = (uint32_t)F.n;
-    d.h_nu[s] = (uint32_t)F.nu;
+    const int q = window_regs(std::max(F.band, 1));
+    st_n[s] = F.n;
+    st_vb[s] = (int32_t)tot;
+    st_q[s] = q < 0 ? 0 : q;
+    d.h_q[s] = st_q[s];
+    d.h_n[s] = F.n;
+    st_gb[s] = (int32_t)f_hdr.size();
+    maxband = std::max(maxband, F.band);
     d.maxn = std::max(d.maxn, F.n);
-    d.maxlev = std::max(d.maxlev, F.nlev);
+    // band streams (empty for a star whose band no window covers)
+    std::vector<double> finv(F.invdiag), binv((size_t)F.n);
+    for (int p = 0; p < F.n; ++p) binv[p] = F.invdiag[F.n - 1 - p];
+    st_fb[s] = (int64_t)f_val.size();
+    st_bb[s] = (int64_t)b_val.size();
+    if (q > 0) {
+      pack_stream<T>(F.width_fwd, F.colvals, finv, SG, q, f_val, f_hdr);
+      pack_stream<T>(F.width_bwd, F.rowvals, binv, SG, q, b_val, b_hdr);
+      if (f_hdr.size() != b_hdr.size()) fail(SN_EINVAL, "internal: header arrays out of step");
+    }
     const int32_t *dofs = &pre.star_dofs[pre.star_ptr[s]];
-    for (int p = 0; p < F.n; ++p) pos_dof.push_back(d.iperm_h[dofs[F.perm[p]]]);
+    for (int p = 0; p < F.n; ++p) {
+      pos_dof.push_back(d.iperm_h[dofs[F.perm[p]]]);
+      f_inv.push_back((T)finv[p]);
+      b_inv.push_back((T)binv[p]);
+    }
+    // supernodal blob; bpos maps its positions to the band positions (slots)
+    std::vector<int32_t> band_of((size_t)F.n), bpos((size_t)F.n);
+    for (int p = 0; p < F.n; ++p) band_of[F.perm[p]] = p;
+    for (int p = 0; p < F.n; ++p) bpos[p] = band_of[F.sn.perm[p]];
+    st_blob[s] = (int64_t)blob.size();
+    pack_blob<T>(F.sn, bpos, blob, d.h_idx[s], d.h_val[s]);
+    d.h_nu[s] = (uint32_t)F.sn.nu;
+    d.maxlev = std::max(d.maxlev, F.sn.nlev);
+    d.h_bytes_band[s] = 2 * F.nnz_rcm * sT + (int64_t)F.n * (4 + 8 + sT);
+    d.h_bytes_sn[s] = F.sn.nnz * sT + (int64_t)F.n * (4 + 8 + sT);
     tot += F.n;
-    nnz += F.nnz;
-    stored += (int64_t)F.S.size();
+    nnz_md += F.sn.nnz;
+    nnz_rcm += F.nnz_rcm;
+    env += F.env;
+    stored += (int64_t)F.sn.S.size();
     idx_tot += d.h_idx[s];
   }
-  if (tot >= (int64_t)1 << 31) fail(SN_EINVAL, "stars too large for 32-bit slot indices");
+  if (tot >= (int64_t)1 << 31 || (int64_t)std::max(f_val.size(), b_val.size()) >= (int64_t)1 << 31)
+    fail(SN_EINVAL, "star streams too large for 32-bit offsets");
+  // zero region: band lanes past a group's width load from here (64*Q lanes of
+  // SG values, Q <= 16)
+  const size_t slack = (size_t)64 * 16 * SG + 64;
+  d.f_zero = (int64_t)f_val.size();
+  d.b_zero = (int64_t)b_val.size();
+  f_val.resize(f_val.size() + slack, T(0));
+  b_val.resize(b_val.size() + slack, T(0));
   // dof -> slots in ascending star order
   std::vector<int32_t> slot_of((size_t)d.npad * d.nv, -1);
   {
     std::vector<int32_t> cnt((size_t)d.n, 0);
     for (int64_t s = 0; s < ns; ++s)
-      for (uint32_t p = 0; p < d.h_n[s]; ++p) {
-        const int32_t dof = pos_dof[st_pos[s] + p];
+      for (int p = 0; p < st_n[s]; ++p) {
+        const int32_t dof = pos_dof[st_vb[s] + p];
         if (cnt[dof] >= d.nv) fail(SN_EINVAL, "a dof lies in more stars than its element has mesh nodes");
-        slot_of[(size_t)dof * d.nv + cnt[dof]++] = st_pos[s] + (int32_t)p;
+        slot_of[(size_t)dof * d.nv + cnt[dof]++] = st_vb[s] + p;
       }
   }
   d.nstars = (int32_t)ns;
   d.slot_count = tot;
+  d.st_n.upload(st_n);
+  d.st_vb.upload(st_vb);
+  d.st_q.upload(st_q);
+  d.st_gb.upload(st_gb);
+  d.st_fb.upload(st_fb);
+  d.st_bb.upload(st_bb);
+  d.pos_dof.upload(pos_dof);
+  d.f_hdr.upload(f_hdr);
+  d.b_hdr.upload(b_hdr);
+  d.slot_of.upload(slot_of);
   d.blob.upload(blob);
   d.st_blob.upload(st_blob);
-  d.st_pos.upload(st_pos);
-  d.pos_dof.upload(pos_dof);
-  d.slot_of.upload(slot_of);
-  const int64_t sT = sizeof(T);
-  // algorithmic bytes of one application (one column): the values of the
-  // structural non-zeros of every local factor once (each is read by one of
-  // the two solves from HBM; the other reads it from LDS or cache), and per
-  // position its dof index, the FP64 gather of r and the slot write
-  fi.sweep_bytes = nnz * sT + tot * (4 + 8 + sT);
-  fi.sweep_flops = 4 * nnz;
-  fi.star_factor_nnz = nnz;
+  int64_t stream_bytes;
+  if constexpr (sizeof(T) == 4) {
+    d.f_inv32.upload(f_inv);
+    d.b_inv32.upload(b_inv);
+    d.f_val32.upload(f_val);
+    d.b_val32.upload(b_val);
+    stream_bytes = (int64_t)(d.f_val32.bytes() + d.b_val32.bytes());
+  } else {
+    d.f_inv64.upload(f_inv);
+    d.b_inv64.upload(b_inv);
+    d.f_val64.upload(f_val);
+    d.b_val64.upload(b_val);
+    stream_bytes = (int64_t)(d.f_val64.bytes() + d.b_val64.bytes());
+  }
+  fi.star_factor_nnz = nnz_md;
+  fi.star_rcm_nnz = nnz_rcm;
+  fi.star_envelope = env;
   fi.star_stored = stored;
   fi.star_blob_bytes = (int64_t)blob.size();
   fi.star_index_bytes = idx_tot;
+  fi.star_stream_bytes = stream_bytes;
   fi.max_levels = d.maxlev;
+  fi.max_band = maxband;
   fi.max_star_dofs = d.maxn;
+  fi.sweep_bytes = 0;
+  for (int64_t s = 0; s < ns; ++s) fi.sweep_bytes += d.h_q[s] > 0 ? d.h_bytes_band[s] : d.h_bytes_sn[s];
+  fi.sweep_bytes_sn = 0;
+  for (int64_t s = 0; s < ns; ++s) fi.sweep_bytes_sn += d.h_bytes_sn[s];
+  fi.sweep_flops = 4 * nnz_md;
 }
 
 }  // namespace
 
 void device_setup(Precond &pre, const HostFactors &hf, int precision) {
   double max_ratio = 1.0;
-  for (const StarFactor &F : hf.stars) max_ratio = std::max(max_ratio, F.pivot_ratio);
+  for (const StarFactor &F : hf.stars) max_ratio = std::max({max_ratio, F.pivot_ratio, F.sn.pivot_ratio});
   const int requested = precision;
   if (precision != SN_PREC_FP64 && precision != SN_PREC_FP32_STARS && precision != SN_PREC_FP32_STARS_COARSE)
     fail(SN_EINVAL, "unknown precision " + std::to_string(precision));
@@ -1259,9 +1413,13 @@ void device_setup(Precond &pre, const HostFactors &hf, int precision) {
   }
   HIPCHK(hipDeviceSynchronize());
   d->bytes = (int64_t)(d->sptr.bytes() + d->slen.bytes() + d->col.bytes() + d->val.bytes() + d->perm.bytes() +
-                       d->blob.bytes() + d->st_blob.bytes() + d->st_pos.bytes() + d->pos_dof.bytes() +
-                       d->slot_of.bytes() + d->Kinv64.bytes() + d->Kinv32.bytes() + d->Pc.bytes() + d->Pw.bytes() +
-                       d->PTptr.bytes() + d->PTdof.bytes() + d->PTw.bytes());
+                       d->st_vb.bytes() + d->pos_dof.bytes() + d->slot_of.bytes() + d->st_n.bytes() +
+                       d->st_q.bytes() + d->st_gb.bytes() + d->st_fb.bytes() + d->st_bb.bytes() + d->f_hdr.bytes() +
+                       d->b_hdr.bytes() + d->f_inv32.bytes() + d->b_inv32.bytes() + d->f_val32.bytes() +
+                       d->b_val32.bytes() + d->f_inv64.bytes() + d->b_inv64.bytes() + d->f_val64.bytes() +
+                       d->b_val64.bytes() + d->blob.bytes() + d->st_blob.bytes() + d->Kinv64.bytes() +
+                       d->Kinv32.bytes() + d->Pc.bytes() + d->Pw.bytes() + d->PTptr.bytes() + d->PTdof.bytes() +
+                       d->PTw.bytes());
   const int64_t nnz = (int64_t)sys.col.size();
   fi.spmv_bytes = nnz * (8 + 4 + 8) + n * 8;
   fi.max_pivot_ratio = max_ratio;
@@ -1279,27 +1437,39 @@ void device_setup(Precond &pre, const HostFactors &hf, int precision) {
 // ---------------------------------------------------------------------------
 // star kernel dispatch over the column counts (instantiated in star_inst.hip)
 // ---------------------------------------------------------------------------
+template <typename T>
+static void launch_band_kc(int kc, const StarArgs &a, bool wide, const double *r, const CgScalars *sc, int sel,
+                           hipStream_t s) {
+  switch (kc) {
+    case 1: launch_star_t<T, 1>(a, wide, r, sc, sel, s); break;
+    case 2: launch_star_t<T, 2>(a, wide, r, sc, sel, s); break;
+    case 4: launch_star_t<T, 4>(a, wide, r, sc, sel, s); break;
+    case 8: launch_star_t<T, 8>(a, wide, r, sc, sel, s); break;
+    case 16: launch_star_t<T, 16>(a, wide, r, sc, sel, s); break;
+    default: fail(SN_EINVAL, "unsupported column count");
+  }
+}
 template <typename T, int KC>
-static void launch_star_cw(int cw, const SnArgs &a, int nteam, bool global, const double *r, const CgScalars *sc,
-                           int sel, hipStream_t s) {
-  if (cw == 1) launch_star_t<T, KC, 1>(a, nteam, global, r, sc, sel, s);
+static void launch_sn_cw(int cw, const SnArgs &a, int nteam, bool global, const double *r, const CgScalars *sc,
+                         int sel, hipStream_t s) {
+  if (cw == 1) launch_sn_t<T, KC, 1>(a, nteam, global, r, sc, sel, s);
   else if constexpr (KC >= 2) {
-    if (cw == 2) launch_star_t<T, KC, 2>(a, nteam, global, r, sc, sel, s);
+    if (cw == 2) launch_sn_t<T, KC, 2>(a, nteam, global, r, sc, sel, s);
     else if constexpr (KC >= 4) {
-      if (cw == 4) launch_star_t<T, KC, 4>(a, nteam, global, r, sc, sel, s);
+      if (cw == 4) launch_sn_t<T, KC, 4>(a, nteam, global, r, sc, sel, s);
       else fail(SN_EINVAL, "unsupported columns per wavefront");
     } else fail(SN_EINVAL, "unsupported columns per wavefront");
   } else fail(SN_EINVAL, "unsupported columns per wavefront");
 }
 template <typename T>
-static void launch_star_kc(int kc, int cw, const SnArgs &a, int nteam, bool global, const double *r,
-                           const CgScalars *sc, int sel, hipStream_t s) {
+static void launch_sn_kc(int kc, int cw, const SnArgs &a, int nteam, bool global, const double *r,
+                         const CgScalars *sc, int sel, hipStream_t s) {
   switch (kc) {
-    case 1: launch_star_cw<T, 1>(cw, a, nteam, global, r, sc, sel, s); break;
-    case 2: launch_star_cw<T, 2>(cw, a, nteam, global, r, sc, sel, s); break;
-    case 4: launch_star_cw<T, 4>(cw, a, nteam, global, r, sc, sel, s); break;
-    case 8: launch_star_cw<T, 8>(cw, a, nteam, global, r, sc, sel, s); break;
-    case 16: launch_star_cw<T, 16>(cw, a, nteam, global, r, sc, sel, s); break;
+    case 1: launch_sn_cw<T, 1>(cw, a, nteam, global, r, sc, sel, s); break;
+    case 2: launch_sn_cw<T, 2>(cw, a, nteam, global, r, sc, sel, s); break;
+    case 4: launch_sn_cw<T, 4>(cw, a, nteam, global, r, sc, sel, s); break;
+    case 8: launch_sn_cw<T, 8>(cw, a, nteam, global, r, sc, sel, s); break;
+    case 16: launch_sn_cw<T, 16>(cw, a, nteam, global, r, sc, sel, s); break;
     default: fail(SN_EINVAL, "unsupported column count");
   }
 }
@@ -1318,14 +1488,48 @@ void with_kc(int kc, F &&f) {
   }
 }
 
-SnArgs star_args(DeviceState &d, Engine &e, int which) {
+StarArgs band_args(DeviceState &d, Engine &e, bool wide) {
+  StarArgs a{};
+  a.nstars = wide ? e.n_wide : e.n_narrow;
+  a.order = wide ? e.b_wide.p : e.b_narrow.p;
+  a.st_n = d.st_n.p;
+  a.st_vb = d.st_vb.p;
+  a.st_q = d.st_q.p;
+  a.st_gb = d.st_gb.p;
+  a.st_fb = d.st_fb.p;
+  a.st_bb = d.st_bb.p;
+  a.pos_dof = d.pos_dof.p;
+  a.f_hdr = d.f_hdr.p;
+  a.b_hdr = d.b_hdr.p;
+  a.f_zero = d.f_zero;
+  a.b_zero = d.b_zero;
+  a.lds_reserve = e.star_lds;
+  a.maxn = d.maxn;
+  a.use_lds = e.star_lv ? 1 : 0;
+  if (d.precision == SN_PREC_FP32_STARS) {
+    a.f_inv = d.f_inv32.p;
+    a.b_inv = d.b_inv32.p;
+    a.f_val = d.f_val32.p;
+    a.b_val = d.b_val32.p;
+    a.slots = e.slots32.p;
+  } else {
+    a.f_inv = d.f_inv64.p;
+    a.b_inv = d.b_inv64.p;
+    a.f_val = d.f_val64.p;
+    a.b_val = d.b_val64.p;
+    a.slots = e.slots64.p;
+  }
+  return a;
+}
+
+SnArgs sn_args(DeviceState &d, Engine &e, int which) {
   SnArgs a{};
   a.nstars = e.sl[which].count;
   a.lds_bytes = e.sl[which].lds;
   a.order = e.sl[which].order.p;
   a.blob = d.blob.p;
   a.st_blob = d.st_blob.p;
-  a.st_pos = d.st_pos.p;
+  a.st_pos = d.st_vb.p;
   a.pos_dof = d.pos_dof.p;
   a.slots = d.precision == SN_PREC_FP32_STARS ? (void *)e.slots32.p : (void *)e.slots64.p;
   a.vscratch = e.vscratch.p;
@@ -1333,8 +1537,44 @@ SnArgs star_args(DeviceState &d, Engine &e, int which) {
   return a;
 }
 
+// band sweeps: narrow windows on s, wide windows beside them on aux
+void launch_band(Engine &e, const double *r, int sel, hipStream_t s) {
+  DeviceState &d = *e.d;
+  const bool f32 = d.precision == SN_PREC_FP32_STARS;
+  auto L = [&](bool wide, hipStream_t st) {
+    const StarArgs a = band_args(d, e, wide);
+    if (f32) launch_band_kc<float>(e.kc, a, wide, r, e.sc.p, sel, st);
+    else launch_band_kc<double>(e.kc, a, wide, r, e.sc.p, sel, st);
+  };
+  if (e.n_wide > 0 && e.n_narrow > 0) {
+    HIPCHK(hipEventRecord(e.fork, s));
+    HIPCHK(hipStreamWaitEvent(e.aux, e.fork, 0));
+    L(true, e.aux);
+    HIPCHK(hipEventRecord(e.join, e.aux));
+    L(false, s);
+    HIPCHK(hipStreamWaitEvent(s, e.join, 0));
+  } else if (e.n_wide > 0) {
+    L(true, s);
+  } else if (e.n_narrow > 0) {
+    L(false, s);
+  }
+}
+
+// supernodal solves: the launches that need the most resources first
+void launch_sn(Engine &e, const double *r, int sel, hipStream_t s) {
+  DeviceState &d = *e.d;
+  const bool f32 = d.precision == SN_PREC_FP32_STARS;
+  for (int which = 2; which >= 0; --which) {
+    if (e.sl[which].count == 0) continue;
+    const SnArgs a = sn_args(d, e, which);
+    if (f32) launch_sn_kc<float>(e.kc, e.star_cw, a, e.star_nteam, which == 2, r, e.sc.p, sel, s);
+    else launch_sn_kc<double>(e.kc, e.star_cw, a, e.star_nteam, which == 2, r, e.sc.p, sel, s);
+  }
+}
+
 // local solves of the selected columns (a workgroup returns at once when none
-// of its columns is selected)
+// of its columns is selected): the supernodal stars on aux3 beside the band
+// stars
 void launch_stars(Engine &e, const double *r, int sel, hipStream_t s) {
   DeviceState &d = *e.d;
   std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
@@ -1348,28 +1588,18 @@ void launch_stars(Engine &e, const double *r, int sel, hipStream_t s) {
     }
     HIPCHK(hipEventRecord(ev.first, s));
   }
-  if (d.nstars > 0) {
-    const bool f32 = d.precision == SN_PREC_FP32_STARS;
-    auto L = [&](int which, hipStream_t st) {
-      const SnArgs a = star_args(d, e, which);
-      if (f32) launch_star_kc<float>(e.kc, e.star_cw, a, e.star_nteam, which == 2, r, e.sc.p, sel, st);
-      else launch_star_kc<double>(e.kc, e.star_cw, a, e.star_nteam, which == 2, r, e.sc.p, sel, st);
-    };
-    const bool side = e.sl[1].count > 0 || e.sl[2].count > 0;
-    if (side && e.sl[0].count > 0) {
-      // fork: the large stars run on the auxiliary stream beside the others
-      HIPCHK(hipEventRecord(e.fork, s));
-      HIPCHK(hipStreamWaitEvent(e.aux, e.fork, 0));
-      L(2, e.aux);
-      L(1, e.aux);
-      HIPCHK(hipEventRecord(e.join, e.aux));
-      L(0, s);
-      HIPCHK(hipStreamWaitEvent(s, e.join, 0));
-    } else {
-      L(2, s);
-      L(1, s);
-      L(0, s);
-    }
+  const bool band = e.n_narrow + e.n_wide > 0, sn = e.n_sn > 0;
+  if (band && sn) {
+    HIPCHK(hipEventRecord(e.fork3, s));
+    HIPCHK(hipStreamWaitEvent(e.aux3, e.fork3, 0));
+    launch_sn(e, r, sel, e.aux3);
+    HIPCHK(hipEventRecord(e.join3, e.aux3));
+    launch_band(e, r, sel, s);
+    HIPCHK(hipStreamWaitEvent(s, e.join3, 0));
+  } else if (sn) {
+    launch_sn(e, r, sel, s);
+  } else {
+    launch_band(e, r, sel, s);
   }
   if (d.profiling) {
     HIPCHK(hipEventRecord(ev.second, s));
@@ -1635,22 +1865,51 @@ void load_block(Engine &e, double *dst, const double *src_dev, int k, hipStream_
   });
 }
 
-// Star launch plan for an LDS cap (bytes per workgroup), CW columns per
-// wavefront and nteam wavefronts per workgroup. A star needs its index part
-// plus nteam sets of vectors (x and y: n x CW, u: nu x CW) in LDS, and its
-// values too if they are to be staged; the kernel stages them when they fit
-// the launch's LDS. Stars whose index part and vectors fit the cap go to
-// launch 0, the others to launch 1 with as much LDS as its largest star wants
-// (at most 160 KB). Each launch takes its stars longest first. Returns false
-// when some star does not fit in 160 KB.
-bool plan_stars(Engine &e, int lcap, int cw, int nteam) {
+// Split of the stars between the two local-solve kernels: the `nsn` stars
+// with the longest band sweeps (2n dependent steps) and every star whose band
+// no window covers go to the supernodal path, the others to the band path
+// (narrow and wide windows in separate launches, longest first).
+void plan_split(Engine &e, int64_t nsn) {
+  DeviceState &d = *e.d;
+  std::vector<int32_t> by_len((size_t)d.nstars);
+  for (int32_t s = 0; s < d.nstars; ++s) by_len[s] = s;
+  std::stable_sort(by_len.begin(), by_len.end(), [&](int32_t a, int32_t b) { return d.h_n[a] > d.h_n[b]; });
+  std::vector<int32_t> narrow, wide;
+  e.sn_list.clear();
+  e.sweep_bytes = 0;
+  for (int64_t i = 0; i < d.nstars; ++i) {
+    const int32_t s = by_len[i];
+    if (d.h_q[s] == 0 || i < nsn) {
+      e.sn_list.push_back(s);
+      e.sweep_bytes += d.h_bytes_sn[s];
+    } else {
+      (d.h_q[s] <= 2 ? narrow : wide).push_back(s);
+      e.sweep_bytes += d.h_bytes_band[s];
+    }
+  }
+  e.b_narrow.upload(narrow);
+  e.b_wide.upload(wide);
+  e.n_narrow = (int32_t)narrow.size();
+  e.n_wide = (int32_t)wide.size();
+  e.n_sn = (int32_t)e.sn_list.size();
+}
+
+// Supernodal launch plan for the stars of sn_list, an LDS cap (bytes per
+// workgroup), CW columns per wavefront and nteam wavefronts per workgroup. A
+// star needs its index part plus nteam sets of vectors (x and y: n x CW, u:
+// nu x CW) in LDS, and its values too if they are to be staged; the kernel
+// stages them when they fit the launch's LDS. Stars whose index part and
+// vectors fit the cap go to launch 0, the others to launch 1 with as much LDS
+// as its largest star wants (at most 160 KB), and stars beyond that to launch
+// 2, solved from global memory. Each launch takes its stars longest first.
+void plan_sn(Engine &e, int lcap, int cw, int nteam) {
   DeviceState &d = *e.d;
   const int64_t ts = d.precision == SN_PREC_FP32_STARS ? 4 : 8;
   const int64_t kMaxLds = kStarMaxLds;
   std::vector<int32_t> o[3];
   std::vector<int64_t> vs((size_t)d.nstars, -1);
   int64_t l1 = 0, vbytes = 0;
-  for (int32_t s = 0; s < d.nstars; ++s) {
+  for (const int32_t s : e.sn_list) {
     const int64_t xb = (d.h_n[s] * cw * ts + 15) & ~15, ub = (d.h_nu[s] * cw * ts + 15) & ~15;
     const int64_t need = d.h_idx[s] + nteam * (2 * xb + ub);
     if (need <= lcap) {
@@ -1664,9 +1923,7 @@ bool plan_stars(Engine &e, int lcap, int cw, int nteam) {
       vbytes += 2 * xb + ub;
     }
   }
-  auto by_len = [&](int32_t a, int32_t b) { return d.h_n[a] > d.h_n[b]; };
   for (int w = 0; w < 3; ++w) {
-    std::stable_sort(o[w].begin(), o[w].end(), by_len);
     e.sl[w].order.upload(o[w]);
     e.sl[w].count = (int32_t)o[w].size();
   }
@@ -1681,14 +1938,16 @@ bool plan_stars(Engine &e, int lcap, int cw, int nteam) {
   e.star_cw = cw;
   e.star_nteam = nteam;
   e.star_lcap = lcap;
-  return true;
 }
 
-// The star launch shape is measured: candidate LDS caps, then columns per
-// wavefront and wavefronts per workgroup at the best cap, then the caps again;
-// each candidate solves all stars (zero input) a few times and the fastest
-// wins. A large cap stages more factors in LDS but fits fewer workgroups per
-// compute unit.
+// The local-solve launch shape is measured: every candidate solves all stars
+// (zero input) a few times and the fastest wins (a candidate must beat the
+// best by 2%, since a three-launch timing moves by a few percent). In turn:
+// the band occupancy limit (few resident band wavefronts per SIMD leave the
+// hardware to hand out the remaining, shorter stars as waves finish; many hide
+// more latency) and where the band working vectors live, with every star on
+// the band path; then the split between the paths; then the supernodal LDS
+// cap and launch shape at that split; then the band occupancy again.
 void tune_stars(Engine &e) {
   DeviceState &d = *e.d;
   if (d.nstars == 0) return;
@@ -1697,8 +1956,7 @@ void tune_stars(Engine &e) {
   hipEvent_t t0, t1;
   HIPCHK(hipEventCreate(&t0));
   HIPCHK(hipEventCreate(&t1));
-  auto time_plan = [&](int lcap, int cw, int nteam) -> double {
-    if (!plan_stars(e, lcap, cw, nteam)) return 1e30;
+  auto time_it = [&]() -> double {
     for (int w = 0; w < 2; ++w) launch_stars(e, e.r.p, SEL_ALL, e.own);
     HIPCHK(hipEventRecord(t0, e.own));
     for (int it = 0; it < 3; ++it) launch_stars(e, e.r.p, SEL_ALL, e.own);
@@ -1708,25 +1966,85 @@ void tune_stars(Engine &e) {
     HIPCHK(hipEventElapsedTime(&ms, t0, t1));
     return 1e3 * ms / 3.0;
   };
-  const int caps[] = {12 << 10, 16 << 10, 20 << 10, 24 << 10, 32 << 10, 40 << 10, 48 << 10, 64 << 10, 80 << 10};
-  std::vector<std::pair<int, int>> shapes;  // (cw, nteam)
-  for (int cw = 1; cw <= std::min(e.kc, 4); cw *= 2)
-    for (int nt = 1; nt <= std::min(e.kc / cw, 4); nt *= 2) shapes.push_back({cw, nt});
-  double best = 1e30;
-  int bcap = caps[0], bcw = std::min(e.kc, 4), bnt = 1;
-  auto try_one = [&](int cap, int cw, int nt) {
-    const double us = time_plan(cap, cw, nt);
-    if (us < 0.98 * best) {
-      best = us;
-      bcap = cap;
-      bcw = cw;
-      bnt = nt;
-    }
+  auto set_cap = [&](int cap) {
+    e.star_cap = cap;
+    e.star_lds = cap == 0 ? 0 : (160 * 1024 / (4 * cap)) & ~511;
   };
-  for (int cap : caps) try_one(cap, bcw, bnt);
-  for (auto &sh : shapes) try_one(bcap, sh.first, sh.second);
-  for (int cap : caps) try_one(cap, bcw, bnt);
-  if (best >= 1e30 || !plan_stars(e, bcap, bcw, bnt)) fail(SN_EINVAL, "internal: no star launch plan");
+  // supernodal defaults
+  int lcap = 24 << 10, cw = std::min(e.kc, 4), nt = 1;
+  // 1. band occupancy and vector placement, all stars on the band path
+  plan_split(e, 0);
+  plan_sn(e, lcap, cw, nt);
+  double best = 1e30;
+  int bcap = 0;
+  if (e.n_narrow + e.n_wide > 0) {
+    for (int cap : {0, 4, 3, 2, 1}) {
+      set_cap(cap);
+      const double us = time_it();
+      if (us < 0.98 * best) {
+        best = us;
+        bcap = cap;
+      }
+    }
+    set_cap(bcap);
+    e.star_lv = false;
+    const double us = time_it();
+    e.star_lv = !(us < 0.95 * best);
+    if (!e.star_lv) best = us;
+  }
+  // 2. the split: the longest stars to the supernodal path (once per
+  //    preconditioner)
+  if (d.split < 0) {
+    int64_t bsplit = 0;
+    for (const double f : {0.01, 0.025, 0.05, 0.1, 0.2, 0.4, 1.0}) {
+      const int64_t k = std::max<int64_t>(1, (int64_t)std::llround(f * d.nstars));
+      plan_split(e, k);
+      plan_sn(e, lcap, cw, nt);
+      const double us = time_it();
+      if (us < 0.98 * best) {
+        best = us;
+        bsplit = k;
+      }
+    }
+    d.split = bsplit;
+  }
+  plan_split(e, d.split);
+  // 3. supernodal LDS cap and launch shape at that split
+  if (e.n_sn > 0) {
+    std::vector<std::pair<int, int>> shapes;  // (cw, nteam)
+    for (int c = 1; c <= std::min(e.kc, 4); c *= 2)
+      for (int w = 1; w <= std::min(e.kc / c, 4); w *= 2) shapes.push_back({c, w});
+    const int caps[] = {12 << 10, 16 << 10, 24 << 10, 32 << 10, 48 << 10, 64 << 10};
+    double sbest = 1e30;
+    auto try_sn = [&](int cap, int c, int w) {
+      plan_sn(e, cap, c, w);
+      const double us = time_it();
+      if (us < 0.98 * sbest) {
+        sbest = us;
+        lcap = cap;
+        cw = c;
+        nt = w;
+      }
+    };
+    for (int cap : caps) try_sn(cap, cw, nt);
+    for (auto &sh : shapes) try_sn(lcap, sh.first, sh.second);
+    best = sbest;
+  }
+  plan_sn(e, lcap, cw, nt);
+  // 4. band occupancy again at that split
+  if (e.n_narrow + e.n_wide > 0) {
+    double bb = 1e30;
+    for (int cap : {0, 4, 3, 2, 1}) {
+      set_cap(cap);
+      const double us = time_it();
+      if (us < 0.98 * bb) {
+        bb = us;
+        bcap = cap;
+      }
+    }
+    set_cap(bcap);
+    best = bb;
+  }
   e.star_us = best;
   // the coarse solve beside the sweeps (sharing the device) or before them; the
   // second half of an iteration is timed: with the coarse solve first the
@@ -1824,6 +2142,9 @@ Engine *engine_create(Precond &pre, int kc) {
   HIPCHK(hipEventCreateWithFlags(&e->fork, hipEventDisableTiming));
   HIPCHK(hipEventCreateWithFlags(&e->join, hipEventDisableTiming));
   HIPCHK(hipStreamCreateWithFlags(&e->aux2, hipStreamNonBlocking));
+  HIPCHK(hipStreamCreateWithFlags(&e->aux3, hipStreamNonBlocking));
+  HIPCHK(hipEventCreateWithFlags(&e->fork3, hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&e->join3, hipEventDisableTiming));
   HIPCHK(hipEventCreateWithFlags(&e->fork2, hipEventDisableTiming));
   HIPCHK(hipEventCreateWithFlags(&e->join2, hipEventDisableTiming));
   HIPCHK(hipEventCreateWithFlags(&e->tick_done, hipEventDisableTiming));
@@ -1946,16 +2267,30 @@ void device_stats(Precond &pre, sn_kernel_stats *st) {
 
 int64_t device_bytes(const Precond &pre) { return pre.dev ? pre.dev->bytes : 0; }
 
+void device_set_star_split(Precond &pre, int64_t n_sn) {
+  DeviceState &d = *pre.dev;
+  for (auto &e : d.solve_engine) {
+    if (e) wait_tick(*e);
+    e.reset();
+  }
+  d.split = n_sn < 0 ? -1 : std::min<int64_t>(n_sn, d.nstars);
+}
+
 void device_engine_info(Precond &pre, int k, sn_engine_info *info) {
   Engine &e = solve_engine(pre, k);
+  std::memset(info, 0, sizeof(*info));
+  info->star_sn = e.n_sn;
+  info->star_waves_per_simd = e.star_cap;
+  info->star_band_lds = e.star_lv ? 1 : 0;
   info->star_lds_bytes = e.star_lcap;
   info->star_cols_per_wave = e.star_cw;
   info->star_waves = e.star_nteam;
   info->star_big = e.sl[1].count;
-  info->star_global = e.sl[2].count;
   info->star_big_lds_bytes = e.sl[1].lds;
-  info->star_sweep_us = e.star_us;
+  info->star_global = e.sl[2].count;
   info->coarse_first = e.coarse_first ? 1 : 0;
+  info->sweep_bytes = e.sweep_bytes;
+  info->star_sweep_us = e.star_us;
   info->b_apply_us = e.b_us;
 }
 

@@ -66,8 +66,74 @@ __device__ __forceinline__ bool column_selected(const CgScalars &s, int sel, uin
   }
 }
 
-// Device layout of one star's factor (a "blob", 16-byte aligned; see
-// factor.cpp and star_kernel.hpp). The index part (header, level table,
+// N consecutive values of type T, moved with the widest aligned accesses
+template <typename T, int N>
+struct Row {
+  T v[N];
+  static constexpr int BYTES = N * (int)sizeof(T);
+  static constexpr int CH = BYTES >= 16 ? 16 : BYTES;  // chunk bytes
+  __device__ __forceinline__ void load(const T *p) {
+    if constexpr (CH == 16) {
+#pragma unroll
+      for (int i = 0; i < BYTES / 16; ++i) {
+        const float4 c = reinterpret_cast<const float4 *>(p)[i];
+        __builtin_memcpy(reinterpret_cast<char *>(v) + 16 * i, &c, 16);
+      }
+    } else if constexpr (CH == 8) {
+      const float2 c = *reinterpret_cast<const float2 *>(p);
+      __builtin_memcpy(v, &c, 8);
+    } else {
+      v[0] = p[0];
+    }
+  }
+  __device__ __forceinline__ void store(T *p) const {
+    if constexpr (CH == 16) {
+#pragma unroll
+      for (int i = 0; i < BYTES / 16; ++i) {
+        float4 c;
+        __builtin_memcpy(&c, reinterpret_cast<const char *>(v) + 16 * i, 16);
+        reinterpret_cast<float4 *>(p)[i] = c;
+      }
+    } else if constexpr (CH == 8) {
+      float2 c;
+      __builtin_memcpy(&c, v, 8);
+      *reinterpret_cast<float2 *>(p) = c;
+    } else {
+      p[0] = v[0];
+    }
+  }
+};
+
+// Arguments of the band sweep kernel (see star_band.hpp).
+struct StarArgs {
+  int32_t nstars;
+  const int32_t *order;    // stars, longest first
+  const int32_t *st_n;     // positions of the star
+  const int32_t *st_vb;    // base in the per-position arrays
+  const int32_t *st_q;     // window registers
+  const int32_t *st_gb;    // base in the per-group header arrays
+  const int64_t *st_fb;    // forward stream value base
+  const int64_t *st_bb;    // backward stream value base
+  const int32_t *pos_dof;  // global dof of each position (factor order)
+  const uint16_t *f_hdr, *b_hdr;             // per group: width in 16-byte slots (groups are contiguous)
+  const void *f_inv, *b_inv;                 // 1/pivot per step (T)
+  const void *f_val, *b_val;                 // packed stream values (T)
+  int64_t f_zero, b_zero;                    // element offset of a zero region (16 KB) in f_val / b_val
+  int32_t lds_reserve;                       // dynamic LDS per workgroup: caps waves per CU
+  int32_t maxn;                              // largest star (positions)
+  int32_t use_lds;                           // working vectors in LDS where they fit
+  void *slots;                               // T, per position and column (position-major)
+};
+
+// one band launch over the stars of a.order, narrow (windows of 1-2
+// registers) or wide (4-16), for kc columns; defined in star_inst.hip (one
+// object per precision and column count)
+// per precision and column count
+template <typename T, int KC>
+void launch_star_t(const StarArgs &a, bool wide, const double *r, const CgScalars *sc, int sel, hipStream_t s);
+
+// Device layout of one star's supernodal factor (a "blob", 16-byte aligned;
+// see factor.cpp and star_sn.hpp). The index part (header, level table,
 // position records, 16-bit index lists) comes first, padded to 16 bytes,
 // then the values of the matrices S_k.
 struct SnHeader {
@@ -78,7 +144,8 @@ struct SnHeader {
   uint32_t off_pos;            // SnPos [n]
   uint32_t off_R;              // uint16 [nu]: the position each u-slot updates
   uint32_t off_alist;          // uint16 [nu]: per position (ranges in SnPos), the u-slots aimed at it
-  uint32_t pad[6];
+  uint32_t off_bpos;           // uint16 [n]: the star's slot (band position) of each position
+  uint32_t pad[5];
 };
 static_assert(sizeof(SnHeader) == 64, "blob header");
 
@@ -96,26 +163,26 @@ static_assert(sizeof(SnPos) == 16, "position record");
 // LDS a star workgroup may use: the 160 KB of a gfx950 compute unit
 constexpr int kStarMaxLds = 160 * 1024;
 
-// Arguments of the star kernel (see star_kernel.hpp).
+// Arguments of the supernodal star kernels (see star_sn.hpp).
 struct SnArgs {
   int32_t nstars;                 // workgroups of the launch
   int32_t lds_bytes;              // dynamic LDS per workgroup
   const int32_t *order;           // star of each workgroup
   const unsigned char *blob;      // all blobs
   const int64_t *st_blob;         // byte offset of each star's blob
-  const int32_t *st_pos;          // first slot of each star (its positions are consecutive slots)
-  const int32_t *pos_dof;         // dof of every slot
+  const int32_t *st_pos;          // first slot of each star (its slots are consecutive)
+  const int32_t *pos_dof;         // dof of every slot (band order)
   void *slots;                    // T, KC values per slot
   unsigned char *vscratch;        // vectors of the stars solved from global memory
   const int64_t *st_vs;           // byte offset of each such star's vectors in vscratch
 };
 
-// one launch over the stars of a.order: k_star with nteam wavefronts per
-// workgroup, or (global) k_star_global with 256 threads per star; defined in
-// star_inst.hip (one object per precision, column count and columns per
-// wavefront)
+// one supernodal launch over the stars of a.order: k_sn with nteam
+// wavefronts per workgroup, or (global) k_sn_global with 256 threads per star;
+// defined in star_inst.hip (one object per precision, column count and
+// columns per wavefront)
 template <typename T, int KC, int CW>
-void launch_star_t(const SnArgs &a, int nteam, bool global, const double *r, const CgScalars *sc, int sel,
-                   hipStream_t s);
+void launch_sn_t(const SnArgs &a, int nteam, bool global, const double *r, const CgScalars *sc, int sel,
+                 hipStream_t s);
 
 }  // namespace spnet

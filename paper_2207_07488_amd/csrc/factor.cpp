@@ -2,7 +2,13 @@
 // K_j = K[S_j, S_j] and of the coarse matrix K_0 = P^T K P: the direct solves
 // behind the projections P_j of eq. 4.1 (Sec. 4.1).
 //
-// Local matrices, in the layout the GPU solve reads:
+// Local matrices, in the two layouts the GPU local solves read.
+// Band layout: reverse Cuthill-McKee from a pseudo-peripheral vertex (George &
+// Liu), a monotone variable-band (envelope) profile, right-looking Cholesky in
+// column storage; the forward stream lists the columns of L, the backward
+// stream the rows of L from the last, each step's entries nearest the
+// diagonal first.
+// Supernodal layout:
 //   1. minimum degree ordering (Tinney-Walker / Rose: repeatedly eliminate a
 //      vertex of least degree in the elimination graph; ties by smallest index);
 //   2. elimination tree (Liu), postorder, column structures of L;
@@ -60,6 +66,239 @@ LocalMatrix extract_local(const System &sys, const int32_t *dofs, int32_t m, std
   }
   for (int32_t a = 0; a < m; ++a) where[dofs[a]] = -1;
   return A;
+}
+
+struct LocalGraph {
+  int32_t n = 0;
+  std::vector<int32_t> ptr, adj;  // off-diagonal adjacency
+  std::vector<int32_t> dptr;      // CSR of the local matrix (incl. diagonal)
+  std::vector<int32_t> dcol;
+  std::vector<double> dval;
+};
+
+LocalGraph extract_local_graph(const System &sys, const int32_t *dofs, int32_t m, std::vector<int32_t> &where) {
+  LocalGraph g;
+  g.n = m;
+  g.ptr.assign((size_t)m + 1, 0);
+  g.dptr.assign((size_t)m + 1, 0);
+  for (int32_t a = 0; a < m; ++a) where[dofs[a]] = a;
+  for (int32_t a = 0; a < m; ++a) {
+    const int32_t d = dofs[a];
+    for (int64_t q = sys.rowptr[d]; q < sys.rowptr[d + 1]; ++q) {
+      const int32_t b = where[sys.col[q]];
+      if (b < 0) continue;
+      g.dcol.push_back(b);
+      g.dval.push_back(sys.val[q]);
+      if (b != a) g.adj.push_back(b);
+    }
+    g.ptr[a + 1] = (int32_t)g.adj.size();
+    g.dptr[a + 1] = (int32_t)g.dcol.size();
+  }
+  for (int32_t a = 0; a < m; ++a) where[dofs[a]] = -1;
+  return g;
+}
+
+// BFS level structure rooted at r restricted to unmarked vertices; returns
+// the levels' vertex list and the start of the last level.
+int32_t level_structure(const LocalGraph &g, int32_t r, const std::vector<uint8_t> &done,
+                        std::vector<int32_t> &order, std::vector<int32_t> &level, int32_t &last_begin) {
+  order.clear();
+  order.push_back(r);
+  level[r] = 0;
+  size_t head = 0;
+  int32_t depth = 0;
+  last_begin = 0;
+  while (head < order.size()) {
+    const int32_t v = order[head++];
+    for (int32_t q = g.ptr[v]; q < g.ptr[v + 1]; ++q) {
+      const int32_t w = g.adj[q];
+      if (done[w] || level[w] >= 0) continue;
+      level[w] = level[v] + 1;
+      if (level[w] > depth) {
+        depth = level[w];
+        last_begin = (int32_t)order.size();
+      }
+      order.push_back(w);
+    }
+  }
+  for (int32_t v : order) level[v] = -1;
+  return depth;
+}
+
+std::vector<int32_t> rcm(const LocalGraph &g) {
+  const int32_t n = g.n;
+  std::vector<int32_t> deg((size_t)n);
+  for (int32_t v = 0; v < n; ++v) deg[v] = g.ptr[v + 1] - g.ptr[v];
+  std::vector<uint8_t> done((size_t)n, 0);
+  std::vector<int32_t> level((size_t)n, -1), order, cm;
+  cm.reserve((size_t)n);
+  std::vector<std::pair<int32_t, int32_t>> nb;
+  for (int32_t seed = 0; seed < n; ++seed) {
+    if (done[seed]) continue;
+    // pseudo-peripheral start: walk to a least-degree vertex of the deepest
+    // level while the eccentricity grows
+    int32_t r = seed, lb = 0;
+    int32_t ecc = level_structure(g, r, done, order, level, lb);
+    for (int guard = 0; guard < 32; ++guard) {
+      int32_t best = -1;
+      for (size_t q = (size_t)lb; q < order.size(); ++q)
+        if (best < 0 || deg[order[q]] < deg[best] || (deg[order[q]] == deg[best] && order[q] < best))
+          best = order[q];
+      int32_t lb2 = 0;
+      const int32_t e2 = level_structure(g, best, done, order, level, lb2);
+      if (e2 <= ecc) break;
+      r = best;
+      ecc = e2;
+      lb = lb2;
+    }
+    // Cuthill-McKee from r
+    const size_t base = cm.size();
+    cm.push_back(r);
+    done[r] = 1;
+    for (size_t head = base; head < cm.size(); ++head) {
+      const int32_t v = cm[head];
+      nb.clear();
+      for (int32_t q = g.ptr[v]; q < g.ptr[v + 1]; ++q) {
+        const int32_t w = g.adj[q];
+        if (!done[w]) {
+          done[w] = 1;
+          nb.push_back({deg[w], w});
+        }
+      }
+      std::sort(nb.begin(), nb.end());
+      for (auto &p : nb) cm.push_back(p.second);
+    }
+  }
+  std::reverse(cm.begin(), cm.end());
+  return cm;  // position -> local index
+}
+
+void factor_star(const System &sys, const int32_t *dofs, int32_t m, std::vector<int32_t> &where, StarFactor &F,
+                 int64_t star_id) {
+  LocalGraph g = extract_local_graph(sys, dofs, m, where);
+  F.n = m;
+  F.perm = rcm(g);
+  std::vector<int32_t> pos((size_t)m);
+  for (int32_t p = 0; p < m; ++p) pos[F.perm[p]] = p;
+  // monotone profile: first[i] = min over i' >= i of the lowest coupled column
+  std::vector<int32_t> first((size_t)m);
+  for (int32_t p = 0; p < m; ++p) first[p] = p;
+  for (int32_t a = 0; a < m; ++a)
+    for (int32_t q = g.ptr[a]; q < g.ptr[a + 1]; ++q) {
+      const int32_t i = pos[a], j = pos[g.adj[q]];
+      if (j < i) first[i] = std::min(first[i], j);
+    }
+  for (int32_t p = m - 2; p >= 0; --p) first[p] = std::min(first[p], first[p + 1]);
+  // column storage: column j holds rows j..last[j]
+  std::vector<int32_t> last((size_t)m);
+  {
+    int32_t i = m - 1;
+    for (int32_t j = m - 1; j >= 0; --j) {
+      while (i > j && first[i] > j) --i;
+      last[j] = std::max(i, j);
+    }
+  }
+  std::vector<int64_t> coff((size_t)m + 1, 0);
+  for (int32_t j = 0; j < m; ++j) coff[j + 1] = coff[j] + (last[j] - j + 1);
+  std::vector<double> A((size_t)coff[m], 0.0);
+  for (int32_t a = 0; a < m; ++a)
+    for (int32_t q = g.dptr[a]; q < g.dptr[a + 1]; ++q) {
+      const int32_t i = pos[a], j = pos[g.dcol[q]];
+      if (i >= j) A[coff[j] + (i - j)] += g.dval[q];
+    }
+  // right-looking Cholesky inside the profile
+  for (int32_t j = 0; j < m; ++j) {
+    double *cj = &A[coff[j]];
+    const int32_t w = last[j] - j;
+    if (!(cj[0] > 0.0))
+      fail(SN_ENOTSPD, "local matrix of star " + std::to_string(star_id) + " is not positive definite");
+    const double d = std::sqrt(cj[0]);
+    cj[0] = d;
+    const double inv = 1.0 / d;
+    for (int32_t t = 1; t <= w; ++t) cj[t] *= inv;
+    for (int32_t c = j + 1; c <= last[j]; ++c) {
+      const double lcj = cj[c - j];
+      if (lcj == 0.0) continue;
+      double *cc = &A[coff[c]];
+      for (int32_t i = c; i <= last[j]; ++i) cc[i - c] -= cj[i - j] * lcj;
+    }
+  }
+  // streams
+  F.width_fwd.resize((size_t)m);
+  F.width_bwd.resize((size_t)m);
+  F.invdiag.resize((size_t)m);
+  F.colvals.clear();
+  F.rowvals.clear();
+  F.colvals.reserve((size_t)(coff[m] - m));
+  F.rowvals.reserve((size_t)(coff[m] - m));
+  int32_t band = 0;
+  for (int32_t j = 0; j < m; ++j) {
+    const int32_t w = last[j] - j;
+    F.width_fwd[j] = w;
+    F.invdiag[j] = 1.0 / A[coff[j]];
+    for (int32_t t = 1; t <= w; ++t) F.colvals.push_back(A[coff[j] + t]);
+    band = std::max(band, w);
+  }
+  for (int32_t s = 0; s < m; ++s) {
+    const int32_t i = m - 1 - s;
+    const int32_t w = i - first[i];
+    F.width_bwd[s] = w;
+    for (int32_t t = 0; t < w; ++t) {
+      const int32_t c = i - 1 - t;
+      F.rowvals.push_back(A[coff[c] + (i - c)]);
+    }
+    band = std::max(band, w);
+  }
+  F.band = band;
+  F.env = coff[m];
+  double dmin = 0.0, dmax = 0.0;
+  for (int32_t j = 0; j < m; ++j) {
+    const double dj = A[coff[j]] * A[coff[j]];
+    if (j == 0 || dj < dmin) dmin = dj;
+    if (j == 0 || dj > dmax) dmax = dj;
+  }
+  F.pivot_ratio = m > 0 ? dmax / dmin : 1.0;
+}
+
+
+// Structural non-zeros of the Cholesky factor of A (incl. the diagonal) in
+// the given order (order[p] = local index at position p): the elimination tree
+// (Liu), then row i of L holds the tree paths from the neighbours j < i up to i.
+int64_t structural_nnz(const LocalMatrix &A, const std::vector<int32_t> &order) {
+  const int32_t n = A.n;
+  std::vector<int32_t> pos((size_t)n), parent((size_t)n, -1), anc((size_t)n, -1), mark((size_t)n, -1);
+  for (int32_t p = 0; p < n; ++p) pos[order[p]] = p;
+  for (int32_t i = 0; i < n; ++i) {
+    const int32_t v = order[i];
+    for (int32_t q = A.ptr[v]; q < A.ptr[v + 1]; ++q) {
+      int32_t r = pos[A.col[q]];
+      if (r >= i) continue;
+      while (anc[r] != -1 && anc[r] != i) {
+        const int32_t nx = anc[r];
+        anc[r] = i;
+        r = nx;
+      }
+      if (anc[r] == -1) {
+        anc[r] = i;
+        parent[r] = i;
+      }
+    }
+  }
+  int64_t nnz = n;
+  for (int32_t i = 0; i < n; ++i) {
+    mark[i] = i;
+    const int32_t v = order[i];
+    for (int32_t q = A.ptr[v]; q < A.ptr[v + 1]; ++q) {
+      int32_t k = pos[A.col[q]];
+      if (k >= i) continue;
+      while (mark[k] != i) {
+        mark[k] = i;
+        ++nnz;
+        k = parent[k];
+      }
+    }
+  }
+  return nnz;
 }
 
 // Minimum degree on the explicit elimination graph: the eliminated vertex's
@@ -135,9 +374,9 @@ struct Super {
 };
 
 // Symbolic analysis and numeric factorisation of one local matrix.
-StarFactor factor_matrix(const LocalMatrix &A, int64_t id, const char *what) {
+SnFactor factor_matrix(const LocalMatrix &A, int64_t id, const char *what) {
   const int32_t n = A.n;
-  StarFactor F;
+  SnFactor F;
   F.n = n;
   if (n == 0) {
     F.lev_pos = {0};
@@ -494,7 +733,7 @@ void parallel_for(int64_t n, Fn fn) {
 
 }  // namespace
 
-StarFactor factor_csr_local(int32_t n, const int32_t *ptr, const int32_t *col, const double *val) {
+SnFactor factor_csr_local(int32_t n, const int32_t *ptr, const int32_t *col, const double *val) {
   LocalMatrix A;
   A.n = n;
   A.ptr.assign(ptr, ptr + n + 1);
@@ -521,8 +760,12 @@ HostFactors factor_host(const Precond &pre) {
     if ((int64_t)where.size() < sys.n) where.assign((size_t)sys.n, -1);
     const int32_t m = (int32_t)(pre.star_ptr[s + 1] - pre.star_ptr[s]);
     if (m >= 65536) fail(SN_EINVAL, "star " + std::to_string(s) + " has 65536 or more dofs");
-    LocalMatrix A = extract_local(sys, &pre.star_dofs[pre.star_ptr[s]], m, where);
-    hf.stars[s] = factor_matrix(A, s, "local matrix of star");
+    const int32_t *dofs = &pre.star_dofs[pre.star_ptr[s]];
+    StarFactor &F = hf.stars[s];
+    factor_star(sys, dofs, m, where, F, s);
+    LocalMatrix A = extract_local(sys, dofs, m, where);
+    F.sn = factor_matrix(A, s, "local matrix of star");
+    F.nnz_rcm = structural_nnz(A, F.perm);
   });
 
   // coarse matrix K_0 = P^T K P in band storage, band Cholesky, explicit inverse

@@ -73,11 +73,14 @@ std::shared_ptr<System> assemble(std::shared_ptr<const Network> net, int model, 
 std::unique_ptr<Precond> build_spaces(std::shared_ptr<const System> sys, int nH, int policy, int dir_lo,
                                       int dir_hi);
 
-// factor.cpp: the factor of one local matrix in the layout of the GPU solve.
-// Positions are the local dofs in factor order, numbered level by level; a
-// supernode s owns positions c0[s] .. c0[s]+w[s]-1 and sends updates to the
-// h[s] positions R[ubase[s] ..] below its diagonal block (its u-slots).
-struct StarFactor {
+// factor.cpp: the factors of one local matrix in the two layouts of the GPU
+// local solves.
+//
+// Supernodal (minimum degree order): positions are the local dofs in factor
+// order, numbered level by level; a supernode s owns positions c0[s] ..
+// c0[s]+w[s]-1 and sends updates to the h[s] positions R[ubase[s] ..] below
+// its diagonal block (its u-slots).
+struct SnFactor {
   int32_t n = 0;                    // positions
   int32_t nsn = 0, nu = 0, nlev = 0;  // supernodes, u-slots, levels
   std::vector<int32_t> perm;        // position -> canonical local index
@@ -95,6 +98,26 @@ struct StarFactor {
   double pivot_ratio = 1.0;         // largest / smallest pivot L_jj^2
 };
 
+// Both layouts of one local matrix. Band (reverse Cuthill-McKee order, the
+// envelope factor): the forward stream walks the columns of L from the first,
+// the backward stream walks the rows of L from the last, each listing the
+// entries nearest the diagonal first. The slots of a star follow the band
+// order whichever kernel solves it.
+struct StarFactor {
+  int32_t n = 0;
+  int32_t band = 0;                 // max width of the envelope
+  std::vector<int32_t> perm;        // band position -> canonical local index
+  std::vector<int32_t> width_fwd;   // per step
+  std::vector<int32_t> width_bwd;
+  std::vector<double> invdiag;      // per position
+  std::vector<double> colvals;      // forward stream values (no headers), column j entries j+1..j+w
+  std::vector<double> rowvals;      // backward stream values, row i (from n-1 down) entries i-1..i-w
+  int64_t env = 0;                  // stored envelope entries incl. diagonal
+  int64_t nnz_rcm = 0;              // structural non-zeros of L in the band order (incl. diagonal)
+  double pivot_ratio = 1.0;         // largest / smallest pivot L_jj^2 (envelope factor)
+  SnFactor sn;                      // the supernodal factor of the same matrix
+};
+
 struct HostFactors {
   std::vector<StarFactor> stars;
   std::vector<double> coarse_inv;   // m0 x m0 dense inverse of K_0 (symmetric)
@@ -103,9 +126,9 @@ struct HostFactors {
 };
 
 HostFactors factor_host(const Precond &pre);
-// the same factorisation of a symmetric positive definite matrix given in CSR
-// (both triangles and the diagonal)
-StarFactor factor_csr_local(int32_t n, const int32_t *ptr, const int32_t *col, const double *val);
+// the supernodal factorisation of a symmetric positive definite matrix given
+// in CSR (both triangles and the diagonal)
+SnFactor factor_csr_local(int32_t n, const int32_t *ptr, const int32_t *col, const double *val);
 
 // device.hip
 void device_setup(Precond &pre, const HostFactors &hf, int precision);
@@ -117,6 +140,7 @@ void device_profile(Precond &pre, int enable);
 void device_stats(Precond &pre, sn_kernel_stats *st);
 int64_t device_bytes(const Precond &pre);
 void device_engine_info(Precond &pre, int k, sn_engine_info *info);
+void device_set_star_split(Precond &pre, int64_t n_sn);
 
 // ---------------------------------------------------------------------------
 // Engine: the device workspace of kc PCG columns (independent recurrences, one

@@ -91,17 +91,18 @@ struct sn_server_s {
 namespace {
 
 int64_t factor_estimate(const Precond &pre, const HostFactors &hf, int precision) {
-  // star blobs (values, about 20 bytes of index per position and update),
-  // per-position arrays, matrix, coarse operator
+  // both star layouts (band streams, supernodal blobs with about 20 bytes of
+  // index per position and update), per-position arrays, matrix, coarse operator
   const int64_t ts = precision == SN_PREC_FP64 ? 8 : 4;
   int64_t vals = 0, pos = 0, upd = 0;
   for (const auto &F : hf.stars) {
-    vals += (int64_t)F.S.size();
+    vals += (int64_t)(F.colvals.size() + F.rowvals.size() + F.sn.S.size());
     pos += F.n;
-    upd += F.nu;
+    upd += F.sn.nu;
   }
   const int64_t n = pre.sys->n, nnz = (int64_t)pre.sys->col.size();
-  return (vals * ts + pos * 32 + upd * 8 + n * pre.nvert_per_elem * 16 + nnz * 12 + pre.m0 * pre.m0 * 8) * 13 / 10;
+  return (vals * ts + pos * (40 + 2 * ts) + upd * 8 + n * pre.nvert_per_elem * 16 + nnz * 12 +
+          pre.m0 * pre.m0 * 8) * 13 / 10;
 }
 
 // start the host factorisation of pre on a worker thread (once)

@@ -1,4 +1,4 @@
-// Local solves z_j = K_j^{-1} r[S_j] for every star j (the direct solves
+// Supernodal local solves z_j = K_j^{-1} r[S_j] (the direct solves
 // behind the projections P_j, Sec. 4.1), templated on the factor precision T,
 // the column count KC and the columns CW a wavefront carries. Included by
 // star_inst.hip only.
@@ -28,44 +28,6 @@
 
 namespace spnet {
 
-// N consecutive values of type T, moved with the widest aligned accesses
-template <typename T, int N>
-struct Row {
-  T v[N];
-  static constexpr int BYTES = N * (int)sizeof(T);
-  static constexpr int CH = BYTES >= 16 ? 16 : BYTES;  // chunk bytes
-  __device__ __forceinline__ void load(const T *p) {
-    if constexpr (CH == 16) {
-#pragma unroll
-      for (int i = 0; i < BYTES / 16; ++i) {
-        const float4 c = reinterpret_cast<const float4 *>(p)[i];
-        __builtin_memcpy(reinterpret_cast<char *>(v) + 16 * i, &c, 16);
-      }
-    } else if constexpr (CH == 8) {
-      const float2 c = *reinterpret_cast<const float2 *>(p);
-      __builtin_memcpy(v, &c, 8);
-    } else {
-      v[0] = p[0];
-    }
-  }
-  __device__ __forceinline__ void store(T *p) const {
-    if constexpr (CH == 16) {
-#pragma unroll
-      for (int i = 0; i < BYTES / 16; ++i) {
-        float4 c;
-        __builtin_memcpy(&c, reinterpret_cast<const char *>(v) + 16 * i, 16);
-        reinterpret_cast<float4 *>(p)[i] = c;
-      }
-    } else if constexpr (CH == 8) {
-      float2 c;
-      __builtin_memcpy(&c, v, 8);
-      *reinterpret_cast<float2 *>(p) = c;
-    } else {
-      p[0] = v[0];
-    }
-  }
-};
-
 // LDS accesses of one wavefront complete in order; the fences keep the
 // compiler from moving them across a phase boundary
 __device__ __forceinline__ void team_sync() {
@@ -77,7 +39,7 @@ __device__ __forceinline__ void team_sync() {
 struct SnView {
   const uint32_t *lev;  // lev[l]: first position of level l (nlev + 1 entries)
   const SnPos *pos;     // per position: its supernode and the u-slots aimed at it
-  const uint16_t *R, *alist;
+  const uint16_t *R, *alist, *bpos;
   // the level table held in registers (nlev < 64 and a wavefront team): lane
   // l has the first position of level l, read with readlane
   int lv_pos;
@@ -272,33 +234,33 @@ __device__ __forceinline__ void team_solve(const SnView &B, const T *__restrict_
   }
 }
 
-// gather r (CW of the KC adjacent columns, from col0) in factor order, eight
-// positions per thread in flight; NT threads from `lane`
+// gather r (CW of the KC adjacent columns, from col0) in factor order: the dof
+// of position p is that of the star's slot bpos[p]; eight positions per
+// thread in flight, NT threads from `lane`
 template <typename T, int KC, int CW>
-__device__ __forceinline__ void gather(T *x, const double *__restrict__ r, const int32_t *__restrict__ dofs, int n,
-                                       int col0, int lane, int NT) {
+__device__ __forceinline__ void gather(T *x, const double *__restrict__ r, const int32_t *__restrict__ dofs,
+                                       const uint16_t *bpos, int n, int col0, int lane, int NT) {
   for (int p0 = 0; p0 < n; p0 += NT * 8) {
     int idx[8];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) idx[q] = dofs[min(p0 + NT * q + lane, n - 1)];
+    for (int q = 0; q < 8; ++q) idx[q] = bpos[min(p0 + NT * q + lane, n - 1)];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) idx[q] = dofs[idx[q]];
     Row<double, CW> v[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) v[q].load(r + (size_t)idx[q] * KC + col0);
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      const int p = p0 + NT * q + lane;
-      if (p < n) {
-        Row<T, CW> o;
+      Row<T, CW> o;
 #pragma unroll
-        for (int c = 0; c < CW; ++c) o.v[c] = (T)v[q].v[c];
-        o.store(x + (size_t)p * CW);
-      }
+      for (int c = 0; c < CW; ++c) o.v[c] = (T)v[q].v[c];
+      o.store(x + (size_t)min(p0 + NT * q + lane, n - 1) * CW);
     }
   }
 }
 
 template <typename T, int KC, int CW>
-__global__ __launch_bounds__(256) void k_star(SnArgs a, const double *__restrict__ r, const CgScalars *sc, int sel) {
+__global__ __launch_bounds__(256) void k_sn(SnArgs a, const double *__restrict__ r, const CgScalars *sc, int sel) {
   extern __shared__ __align__(16) unsigned char lds[];
   const int st = a.order[blockIdx.x];
   const unsigned char *gb = a.blob + a.st_blob[st];
@@ -345,6 +307,7 @@ __global__ __launch_bounds__(256) void k_star(SnArgs a, const double *__restrict
   B.pos = reinterpret_cast<const SnPos *>(lds + hd.off_pos);
   B.R = reinterpret_cast<const uint16_t *>(lds + hd.off_R);
   B.alist = reinterpret_cast<const uint16_t *>(lds + hd.off_alist);
+  B.bpos = reinterpret_cast<const uint16_t *>(lds + hd.off_bpos);
   unsigned char *tv = lds + staged + (uint32_t)team * vec;
   T *x = reinterpret_cast<T *>(tv), *y = reinterpret_cast<T *>(tv + xb), *u = reinterpret_cast<T *>(tv + 2 * xb);
   const int32_t *dofs = a.pos_dof + a.st_pos[st];
@@ -354,7 +317,7 @@ __global__ __launch_bounds__(256) void k_star(SnArgs a, const double *__restrict
   for (int ch = team; ch < NCH; ch += nteam) {
     if (!((chunks >> ch) & 1u)) continue;
     const int col0 = ch * CW;
-    gather<T, KC, CW>(x, r, dofs, n, col0, lane, 64);
+    gather<T, KC, CW>(x, r, dofs, B.bpos, n, col0, lane, 64);
     team_sync();
     if (vl) team_solve<T, CW, false>(B, reinterpret_cast<const T *>(lds + hd.idx_bytes), nlev, x, y, u);
     else team_solve<T, CW, false>(B, reinterpret_cast<const T *>(gb + hd.idx_bytes), nlev, x, y, u);
@@ -362,7 +325,7 @@ __global__ __launch_bounds__(256) void k_star(SnArgs a, const double *__restrict
     for (int p = lane; p < n; p += 64) {
       Row<T, CW> o;
       o.load(x + (size_t)p * CW);
-      o.store(out + (size_t)p * KC + col0);
+      o.store(out + (size_t)B.bpos[p] * KC + col0);
     }
     team_sync();
   }
@@ -372,7 +335,7 @@ __global__ __launch_bounds__(256) void k_star(SnArgs a, const double *__restrict
 // the other with the factor read from the blob and the vectors in the global
 // scratch at a.vscratch + a.st_vs[star].
 template <typename T, int KC, int CW>
-__global__ __launch_bounds__(256) void k_star_global(SnArgs a, const double *__restrict__ r, const CgScalars *sc,
+__global__ __launch_bounds__(256) void k_sn_global(SnArgs a, const double *__restrict__ r, const CgScalars *sc,
                                                      int sel) {
   const int st = a.order[blockIdx.x];
   const unsigned char *gb = a.blob + a.st_blob[st];
@@ -386,6 +349,7 @@ __global__ __launch_bounds__(256) void k_star_global(SnArgs a, const double *__r
   B.pos = reinterpret_cast<const SnPos *>(gb + hd.off_pos);
   B.R = reinterpret_cast<const uint16_t *>(gb + hd.off_R);
   B.alist = reinterpret_cast<const uint16_t *>(gb + hd.off_alist);
+  B.bpos = reinterpret_cast<const uint16_t *>(gb + hd.off_bpos);
   const uint32_t xb = (uint32_t)((n * CW * (int)sizeof(T) + 15) & ~15);
   unsigned char *tv = a.vscratch + a.st_vs[st];
   T *x = reinterpret_cast<T *>(tv), *y = reinterpret_cast<T *>(tv + xb), *u = reinterpret_cast<T *>(tv + 2 * xb);
@@ -398,31 +362,31 @@ __global__ __launch_bounds__(256) void k_star_global(SnArgs a, const double *__r
     for (int c = 0; c < CW; ++c) on |= sel == SEL_ALL || column_selected(sc[ch * CW + c], sel, 0u, ch * CW + c);
     if (!on) continue;
     const int col0 = ch * CW;
-    gather<T, KC, CW>(x, r, dofs, n, col0, tid, NT);
+    gather<T, KC, CW>(x, r, dofs, B.bpos, n, col0, tid, NT);
     __syncthreads();
     team_solve<T, CW, true>(B, reinterpret_cast<const T *>(gb + hd.idx_bytes), nlev, x, y, u);
     for (int p = tid; p < n; p += NT) {
       Row<T, CW> o;
       o.load(x + (size_t)p * CW);
-      o.store(out + (size_t)p * KC + col0);
+      o.store(out + (size_t)B.bpos[p] * KC + col0);
     }
     __syncthreads();
   }
 }
 
 template <typename T, int KC, int CW>
-void launch_star_t(const SnArgs &a, int nteam, bool global, const double *r, const CgScalars *sc, int sel,
-                   hipStream_t s) {
+void launch_sn_t(const SnArgs &a, int nteam, bool global, const double *r, const CgScalars *sc, int sel,
+                 hipStream_t s) {
   if (a.nstars <= 0) return;
   if (global) {
-    hipLaunchKernelGGL((k_star_global<T, KC, CW>), dim3(a.nstars), dim3(256), 0, s, a, r, sc, sel);
+    hipLaunchKernelGGL((k_sn_global<T, KC, CW>), dim3(a.nstars), dim3(256), 0, s, a, r, sc, sel);
     return;
   }
   // allow the kernel the whole LDS of a compute unit (once per instantiation)
-  static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_star<T, KC, CW>),
+  static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_sn<T, KC, CW>),
                                                      hipFuncAttributeMaxDynamicSharedMemorySize, kStarMaxLds);
   if (attr != hipSuccess) fail(SN_EDEVICE, std::string("star kernel LDS limit: ") + hipGetErrorString(attr));
-  hipLaunchKernelGGL((k_star<T, KC, CW>), dim3(a.nstars), dim3(64 * nteam), (size_t)a.lds_bytes, s, a, r, sc, sel);
+  hipLaunchKernelGGL((k_sn<T, KC, CW>), dim3(a.nstars), dim3(64 * nteam), (size_t)a.lds_bytes, s, a, r, sc, sel);
 }
 
 }  // namespace spnet

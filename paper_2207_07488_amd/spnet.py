@@ -36,22 +36,25 @@ class SolveInfo(C.Structure):
 
 
 class FactorInfo(C.Structure):
-    _fields_ = [("star_factor_nnz", C.c_int64), ("star_stored", C.c_int64), ("star_blob_bytes", C.c_int64),
-                ("star_index_bytes", C.c_int64), ("coarse_bytes", C.c_int64), ("device_bytes", C.c_int64),
-                ("max_star_dofs", C.c_int32), ("max_levels", C.c_int32), ("factor_seconds", C.c_double),
-                ("sweep_bytes", C.c_int64), ("spmv_bytes", C.c_int64), ("sweep_flops", C.c_int64),
+    _fields_ = [("star_factor_nnz", C.c_int64), ("star_rcm_nnz", C.c_int64), ("star_envelope", C.c_int64),
+                ("star_stored", C.c_int64), ("star_blob_bytes", C.c_int64), ("star_index_bytes", C.c_int64),
+                ("star_stream_bytes", C.c_int64), ("coarse_bytes", C.c_int64), ("device_bytes", C.c_int64),
+                ("max_star_dofs", C.c_int32), ("max_band", C.c_int32), ("max_levels", C.c_int32),
+                ("pad0", C.c_int32), ("factor_seconds", C.c_double), ("sweep_bytes", C.c_int64),
+                ("sweep_bytes_sn", C.c_int64), ("spmv_bytes", C.c_int64), ("sweep_flops", C.c_int64),
                 ("max_pivot_ratio", C.c_double), ("star_precision", C.c_int32), ("coarse_precision", C.c_int32),
                 ("coarse_pivot_ratio", C.c_double)]
 
     def asdict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad0"}
 
 
 class EngineInfo(C.Structure):
-    _fields_ = [("star_lds_bytes", C.c_int32), ("star_cols_per_wave", C.c_int32), ("star_waves", C.c_int32),
+    _fields_ = [("star_sn", C.c_int32), ("star_waves_per_simd", C.c_int32), ("star_band_lds", C.c_int32),
+                ("star_lds_bytes", C.c_int32), ("star_cols_per_wave", C.c_int32), ("star_waves", C.c_int32),
                 ("star_big", C.c_int32), ("star_big_lds_bytes", C.c_int32), ("star_global", C.c_int32),
-                ("coarse_first", C.c_int32),
-                ("star_sweep_us", C.c_double), ("b_apply_us", C.c_double)]
+                ("coarse_first", C.c_int32), ("sweep_bytes", C.c_int64), ("star_sweep_us", C.c_double),
+                ("b_apply_us", C.c_double)]
 
     def asdict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -103,6 +106,7 @@ SIGNATURES = {
     "sn_precond_profile": (C.c_int, [_P, C.c_int]),
     "sn_precond_kernel_stats": (C.c_int, [_P, C.POINTER(KernelStats)]),
     "sn_precond_engine_info": (C.c_int, [_P, C.c_int, C.POINTER(EngineInfo)]),
+    "sn_precond_set_star_split": (C.c_int, [_P, _i64]),
     "sn_apply_K": (C.c_int, [_P, C.c_int, _P, _P, C.c_int, _P]),
     "sn_apply_B": (C.c_int, [_P, C.c_int, _P, _P, C.c_int, _P]),
     "sn_server_opts_default": (None, [C.POINTER(ServerOpts)]),
@@ -266,6 +270,11 @@ class Precond:
         d["b_apply_us"] = round(d["b_apply_us"], 2)
         d["coarse_first"] = bool(d["coarse_first"])
         return d
+
+    def set_star_split(self, n_sn):
+        """Fix the stars on the supernodal path (the n_sn with most positions);
+        n_sn < 0: measure it at the next solve."""
+        _check(lib().sn_precond_set_star_split(self.h, int(n_sn)))
 
     # ---------------------------------------------------------------- solves
     def _block(self, a):

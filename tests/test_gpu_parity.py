@@ -73,6 +73,11 @@ def _rel(a, b):
     return np.linalg.norm(a - b) / np.linalg.norm(b)
 
 
+def _close(a, b, tol):
+    """Element by element: every |a_i - b_i| <= tol * max_i |b_i|."""
+    return float(np.abs(a - b).max()) <= tol * float(np.abs(b).max())
+
+
 @pytest.mark.parametrize("name", list(CASES))
 def test_spmv_parity(S, orc, name):
     opre, gpre = _pair(S, orc, name, S.FP64)
@@ -227,3 +232,37 @@ def test_batch_apply_B_columns(S, orc):
     Z = gpre.apply_B(R)
     for c in range(3):
         assert _rel(Z[:, c], opre.apply_B(R[:, c])) <= 1e-10
+
+
+@pytest.mark.parametrize("name", ["fiber2d_2k", "fiber3d_6k", "truss3d_1500"])
+@pytest.mark.parametrize("split", ["band", "half", "supernodal"])
+def test_local_solve_paths(S, orc, name, split):
+    """Both local-solve kernels, alone and side by side: B r of three columns
+    against the oracle, element by element, whatever star runs which kernel."""
+    opre, gpre = _pair(S, orc, name, S.FP64)
+    n_sn = {"band": 0, "half": gpre.nstars // 2, "supernodal": gpre.nstars}[split]
+    gpre.set_star_split(n_sn)
+    R = W.rhs(opre.sys.n, 3, seed=4)
+    Z = gpre.apply_B(R)
+    info = gpre.engine_info(3)
+    assert info["star_sn"] >= n_sn
+    tol = _tol(orc, name, opre)
+    for c in range(3):
+        assert _close(Z[:, c], opre.apply_B(R[:, c]), tol), c
+
+
+def test_supernodal_stars_beyond_lds(S, orc):
+    """Stars of thousands of dofs with 16 FP64 columns need more LDS than a
+    compute unit has: they are solved from global memory, to the same bar."""
+    dim, nseg, l, eps, lo, hi, _, model = CASES["fiber2d_2k"]
+    seg = W.fiber_segments(dim, nseg, l, seed=1)
+    on = orc.Network.from_segments(dim, seg, merge_tol=W.merge_tol(l), dir_lo=lo, dir_hi=hi)
+    opre = orc.Precond(orc.System(on, model), 2, 0, lo, hi)
+    gn = S.Network.from_segments(dim, seg, merge_tol=W.merge_tol(l), dir_lo=lo, dir_hi=hi)
+    gpre = S.Precond(S.System(gn, model), 2, S.STARS_ALL, lo, hi, precision=S.FP64)
+    gpre.set_star_split(gpre.nstars)
+    R = W.rhs(opre.sys.n, 16, seed=5)
+    Z = gpre.apply_B(R)
+    assert gpre.engine_info(16)["star_global"] > 0
+    for c in (0, 9, 15):
+        assert _close(Z[:, c], opre.apply_B(R[:, c]), 1e-10), c
