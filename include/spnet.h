@@ -303,6 +303,19 @@ sn_status sn_precond_set_star_split(sn_precond pre, int64_t n_sn);
 
 /* y = K x for k columns (n x k row-major). */
 sn_status sn_apply_K(sn_precond pre, int k, const double *x, double *y, int device_ptrs, void *stream);
+/*
+ * y = K x as sn_apply_K with device pointers, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops): it calls
+ * no allocation routine. Its staging vectors (x and y in the library's
+ * internal dof order, 2 * npad * kc * 8 bytes, npad = n rounded up to 256,
+ * kc = k rounded up to a power of two) live in a workspace of 64 MiB per GPU
+ * that the library holds until the process ends; a larger need returns
+ * SN_EINVAL. Every call on a GPU shares that workspace, so calls that overlap
+ * on one GPU race. x and y are device pointers (n x k row-major) on the
+ * preconditioner's device, which must be current; the work is queued on
+ * `stream` (NULL: the default stream) and the call returns without waiting.
+ */
+sn_status sn_apply_K_noalloc(sn_precond pre, int k, const double *x, double *y, void *stream);
 /* z = B r, B = P K_0^{-1} P^T + sum_j R_j^T K_j^{-1} R_j (so that BK = P_0 + ... + P_m). */
 sn_status sn_apply_B(sn_precond pre, int k, const double *r, double *z, int device_ptrs, void *stream);
 

@@ -256,6 +256,15 @@ sn_status sn_apply_K(sn_precond pre, int k, const double *x, double *y, int devi
   });
 }
 
+sn_status sn_apply_K_noalloc(sn_precond pre, int k, const double *x, double *y, void *stream) {
+  return guarded([&] {
+    REQUIRE(pre && x && y, "null argument");
+    REQUIRE(k >= 1 && k <= 16, "k must be in 1..16");
+    REQUIRE(pre->p->dev, "preconditioner not factored");
+    spnet::device_apply_K_noalloc(*pre->p, k, x, y, stream);
+  });
+}
+
 sn_status sn_apply_B(sn_precond pre, int k, const double *r, double *z, int device_ptrs, void *stream) {
   return guarded([&] {
     REQUIRE(pre && r && z, "null argument");

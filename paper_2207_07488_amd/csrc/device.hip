@@ -25,6 +25,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -37,6 +38,13 @@ constexpr int kBlock = 256;     // threads of the vector kernels
 constexpr int kSlice = 64;      // rows per ELL slice (one wavefront)
 constexpr int kMaxGrid = 2048;  // blocks of the grid-stride vector kernels (= partial sums per column)
 constexpr int kMaxCols = 16;
+
+// Workspace of the entry points that allocate nothing (sn_apply_K_noalloc):
+// one array per GPU, held until the process ends. Host code never uses the
+// array's name as an address: each device's address comes from
+// hipGetSymbolAddress (scratch_ptr) and is passed to the kernels.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 enum ScalarOp { OP_ALPHA = 0, OP_CONV = 1, OP_BETA = 2, OP_F2 = 3, OP_R2 = 4, OP_TRUE = 5, OP_DOT = 6 };
 
@@ -996,6 +1004,29 @@ DeviceState::~DeviceState() {
   }
 }
 
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+// Device address of `scratch` on the current device, looked up once per
+// device (the array's name is a host-side stand-in, not a device address).
+void *scratch_ptr() {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) fail(SN_EDEVICE, "device id out of range for the workspace table");
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      fail(SN_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  return g_scratch_ptr[dev];
+}
+
 void device_release(DeviceState *d) { delete d; }
 void DeviceDeleter::operator()(DeviceState *d) const { delete d; }
 
@@ -1261,6 +1292,7 @@ void device_setup(Precond &pre, const HostFactors &hf, int precision) {
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) fail(SN_EDEVICE, "no HIP device available");
   auto d = std::make_unique<DeviceState>();
   HIPCHK(hipGetDevice(&d->device));
+  (void)scratch_ptr();  // the workspace address of this device, while it is current
   const System &sys = *pre.sys;
   d->precision = precision;
   d->n = sys.n;
@@ -2302,6 +2334,42 @@ void device_apply_K(Precond &pre, int k, const double *x, double *y, int device_
   load_block(e, e.p.p, src, k, s);
   launch_spmv(e, e.p.p, e.z.p, SEL_ALL, false, s);
   store_block(e, y, e.z.p, k, device_ptrs != 0, s);
+}
+
+// y = K x (device pointers, n x k) through the workspace: x in the internal
+// dof order, then the SpMV, then y back in the canonical order, all queued on
+// `stream` without waiting and without allocating. Calls that overlap on one
+// GPU share the workspace and race.
+void device_apply_K_noalloc(Precond &pre, int k, const double *x, double *y, void *stream) {
+  DeviceState &d = *pre.dev;
+  const int kc = engine_width_for(k);
+  const size_t vec = (size_t)d.npad * kc * sizeof(double);
+  const size_t need = 2 * vec + 256 + (size_t)kc * sizeof(CgScalars);
+  if (need > kScratchBytes)
+    fail(SN_EINVAL, "apply_K without allocation needs " + std::to_string(need) + " bytes of workspace, more than its " +
+                        std::to_string(kScratchBytes) + " (fewer columns or sn_apply_K)");
+  int cur = 0;
+  HIPCHK(hipGetDevice(&cur));
+  if (cur != d.device) fail(SN_EINVAL, "the preconditioner lives on another device than the current one");
+  unsigned char *ws = static_cast<unsigned char *>(scratch_ptr());
+  double *xs = reinterpret_cast<double *>(ws);
+  double *ys = reinterpret_cast<double *>(ws + vec);
+  const CgScalars *scs = reinterpret_cast<const CgScalars *>(ws + ((2 * vec + 255) & ~(size_t)255));
+  const hipStream_t s = (hipStream_t)stream;
+  Sell A{d.sptr.p, d.slen.p, d.col.p, d.val.p};
+  with_kc(kc, [&](auto K) {
+    constexpr int KC = decltype(K)::value;
+    // every column of xs is written (past k: zeros), so the workspace needs no clearing
+    for (int j = 0; j < kc; ++j)
+      hipLaunchKernelGGL(k_col_in<KC>, dim3(grid_for(d.npad)), dim3(kBlock), 0, s, xs, x, d.perm.p,
+                         j < k ? (int)d.n : 0, (int)d.npad, k, j < k ? j : 0, j);
+    hipLaunchKernelGGL(k_spmv<KC>, dim3(grid_for(d.npad)), dim3(kBlock), 0, s, A, xs, ys, (int)d.npad, scs,
+                       (int)SEL_ALL, nullptr);
+    for (int j = 0; j < k; ++j)
+      hipLaunchKernelGGL(k_col_out<KC>, dim3(grid_for(d.n)), dim3(kBlock), 0, s, y, ys, d.perm.p, (int)d.n, k, j,
+                         j);
+  });
+  HIPCHK(hipGetLastError());
 }
 
 void device_apply_B(Precond &pre, int k, const double *r, double *z, int device_ptrs, void *stream) {

@@ -135,6 +135,7 @@ void device_setup(Precond &pre, const HostFactors &hf, int precision);
 void device_solve(Precond &pre, int k, const double *f, double *u, const sn_solve_opts &o, sn_solve_info *info);
 void device_apply_K(Precond &pre, int k, const double *x, double *y, int device_ptrs, void *stream);
 void device_apply_B(Precond &pre, int k, const double *r, double *z, int device_ptrs, void *stream);
+void device_apply_K_noalloc(Precond &pre, int k, const double *x, double *y, void *stream);
 void device_release(DeviceState *d);
 void device_profile(Precond &pre, int enable);
 void device_stats(Precond &pre, sn_kernel_stats *st);

@@ -109,6 +109,7 @@ SIGNATURES = {
     "sn_precond_set_star_split": (C.c_int, [_P, _i64]),
     "sn_apply_K": (C.c_int, [_P, C.c_int, _P, _P, C.c_int, _P]),
     "sn_apply_B": (C.c_int, [_P, C.c_int, _P, _P, C.c_int, _P]),
+    "sn_apply_K_noalloc": (C.c_int, [_P, C.c_int, _P, _P, _P]),
     "sn_server_opts_default": (None, [C.POINTER(ServerOpts)]),
     "sn_server_create": (C.c_int, [C.POINTER(ServerOpts), C.POINTER(_P)]),
     "sn_server_submit": (C.c_int, [_P, _P, C.c_int, _P, _dbl, _i64, C.POINTER(C.c_uint64)]),
@@ -329,6 +330,16 @@ class Precond:
         xa, k, dev = self._block(x)
         y = (xa.new_zeros(xa.shape) if dev else np.zeros_like(xa))
         _check(lib().sn_apply_K(self.h, k, self._addr(xa, dev), self._addr(y, dev), int(dev), self._stream(dev)))
+        return y
+
+    def apply_K_noalloc(self, x, y):
+        """y = K x through the library's fixed workspace (no allocation), queued
+        on torch's current stream; x and y are float64 CUDA tensors (n,) or (n, k)."""
+        assert _is_torch(x) and x.is_cuda and _is_torch(y) and y.is_cuda
+        assert x.is_contiguous() and y.is_contiguous() and x.shape == y.shape
+        k = 1 if x.dim() == 1 else x.shape[1]
+        _check(lib().sn_apply_K_noalloc(self.h, k, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()),
+                                        self._stream(True)))
         return y
 
     def apply_B(self, r):
