@@ -2,12 +2,16 @@
 """PCG solves/s at rtol 1e-8 on one MI355X: two-level additive Schwarz PCG on a
 2D fiber network (20,000 segments of length 0.05 in the unit square, Dirichlet
 at x = 0 and x = 1, f uniform[0,1], H = 1/64 by default; H = 1/16 and 1/32 in
-the mesh-size sweep), FP32-star mixed form against the plain FP64 form, with
-p50/p99 latency per solve.
+the mesh-size sweep), mixed form (FP32 local solves, FP64 coarse operator and
+CG) against the plain FP64 form, with p50/p99 latency per solve.
 
 A step is one full PCG solve (u0 = 0 to ||r|| <= 1e-8 ||f||) of one right-hand
 side already resident in HBM, iterations replayed from captured HIP graphs.
-Prints one JSON line.
+Beside the headline: the mesh-size sweep, batched right-hand sides, the small
+2D network with 1,024 right-hand sides, the 3D fiber network (100,000
+segments), the 3D truss network with 16 right-hand sides, the serving mix, and
+the FP64 oracle timed on the host (one core and all cores). Prints one JSON
+line; progress goes to stderr.
 """
 from __future__ import annotations
 
@@ -22,12 +26,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
-KERNEL_SOURCES = ("paper_2207_07488_amd/csrc/star_kernel.hpp", "paper_2207_07488_amd/csrc/star_inst.hip",
-                  "paper_2207_07488_amd/csrc/device_common.hpp")
+PEAK_F64_TFLOPS = 78.6
+KERNEL_SOURCES = ("paper_2207_07488_amd/csrc/star_band.hpp", "paper_2207_07488_amd/csrc/star_sn.hpp",
+                  "paper_2207_07488_amd/csrc/star_inst.hip", "paper_2207_07488_amd/csrc/device_common.hpp")
 
 
 def kernel_source_hash():
-    """Hash of the star sweep sources: counter data taken on other sources is stale."""
+    """Hash of the local-solve kernel sources: counter data taken on other sources is stale."""
     import hashlib
     h = hashlib.sha256()
     for p in KERNEL_SOURCES:
@@ -162,6 +167,136 @@ def serving_leg(n_requests, rate, pool_size=8, seed=5, load=0.7):
             "engines": neng, "device_bytes": used, "engine_width": 8, "iters_per_tick": 4}
 
 
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def build_problem(S, W, preset, nH, precision, model=None):
+    p = dict(preset)
+    seg = W.fiber_segments(p["dim"], p["n_segments"], p["length"], p["seed"])
+    net = S.Network.from_segments(p["dim"], seg, contact_eps=p.get("contact_eps", 0.0),
+                                  merge_tol=W.merge_tol(p["length"]), dir_lo=p["dir_lo"], dir_hi=p["dir_hi"],
+                                  band=W.BAND)
+    sysm = S.System(net, p.get("model", 0) if model is None else model)
+    pre = S.Precond(sysm, nH, S.STARS_ALL, p["dir_lo"], p["dir_hi"], precision=precision)
+    return seg, net, sysm, pre
+
+
+def rate(n, seconds):
+    return round(n / seconds, 3)
+
+
+def c1_leg(S, W, torch, steps):
+    """The small 2D network (300 segments, H = 1/4) with 1,024 right-hand sides:
+    plain FP64 one column at a time, and the mixed form 16 columns per batch."""
+    p = W.PRESETS["fiber2d_300"]
+    _, net, sysm, plain = build_problem(S, W, p, p["nH"], S.FP64)
+    mixed = S.Precond(sysm, p["nH"], S.STARS_ALL, p["dir_lo"], p["dir_hi"], precision=S.FP32_STARS)
+    F = torch.from_numpy(W.rhs(sysm.n, 1024, seed=0)).cuda()
+    cols = [F[:, j].contiguous() for j in range(1024)]
+    batches = [F[:, 16 * b:16 * b + 16].contiguous() for b in range(64)]
+    out = {"workload": "fiber2d_300_H4", "dofs": sysm.n, "rhs": 1024}
+    for name, pre, blocks, k in (("plain_one_at_a_time", plain, cols, 1), ("mixed_16_per_batch", mixed, batches, 16)):
+        pre.solve(blocks[0], rtol=1e-8, use_graph=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        iters = []
+        for b in blocks:
+            _, info = pre.solve(b, rtol=1e-8, use_graph=True)
+            iters.append(max(i["iters"] for i in info))
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[name] = {"solves_per_s": rate(len(blocks) * k, dt), "s": round(dt, 3), "max_iterations": max(iters)}
+    return out
+
+
+def c3_leg(S, W, torch, steps):
+    """3D fiber network: 100,000 segments of length 0.05, contact 0.005,
+    Dirichlet z = 0, 1, H = 1/16; mixed and plain, one right-hand side."""
+    p = W.PRESETS["fiber3d_100k"]
+    t0 = time.perf_counter()
+    _, net, sysm, mixed = build_problem(S, W, p, 16, S.FP32_STARS)
+    setup = time.perf_counter() - t0
+    plain = S.Precond(sysm, 16, S.STARS_ALL, p["dir_lo"], p["dir_hi"], precision=S.FP64)
+    f = torch.from_numpy(W.rhs(sysm.n, 1, seed=7)[:, 0]).cuda()
+    out = {"workload": "fiber3d_100k_H16", "nodes": net.n_nodes, "dofs": sysm.n, "stars": mixed.nstars,
+           "m0": mixed.m0, "setup_s": round(setup, 2)}
+    for name, pre in (("mixed", mixed), ("plain", plain)):
+        r = timed_solves(pre, f, max(3, steps // 5), 1, 1e-8, use_graph=True)
+        out[name] = {"solves_per_s": rate(len(r["iters"]), r["total_s"]), "iterations": int(r["iters"][-1]),
+                     "res_true": r["info"][0]["res_true"], "engine": pre.engine_info(1)}
+    fi = mixed.factor_info()
+    out["factor"] = {k: fi[k] for k in ("star_factor_nnz", "star_rcm_nnz", "max_star_dofs", "max_levels",
+                                        "star_precision", "factor_seconds")}
+    return out
+
+
+def c4_leg(S, W, torch, steps):
+    """3D truss network (3 dofs per node): 30,000 segments of length 0.1 of the
+    3D geometry, clamp z = 0, f uniform[-1, 1], H = 1/16, 16 right-hand sides per
+    solve (FP32 local solves requested; the library keeps FP64 where FP32
+    cannot resolve them). The coarse product is a 16-column GEMM on the FP64
+    matrix cores: its MFMA utilisation is reported."""
+    p = W.PRESETS["truss3d_30k"]
+    t0 = time.perf_counter()
+    _, net, sysm, pre = build_problem(S, W, p, 16, S.FP32_STARS)
+    setup = time.perf_counter() - t0
+    F = torch.from_numpy(W.rhs(sysm.n, 16, seed=9, lo=-1.0, hi=1.0)).cuda()
+    fi = pre.factor_info()
+    out = {"workload": "truss3d_30k_H16_16rhs", "nodes": net.n_nodes, "dofs": sysm.n, "stars": pre.nstars,
+           "m0": pre.m0, "setup_s": round(setup, 2), "star_precision": fi["star_precision"],
+           "max_pivot_ratio": fi["max_pivot_ratio"]}
+    U, info = pre.solve(F, rtol=1e-8, use_graph=True, raise_on_noconv=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    U, info = pre.solve(F, rtol=1e-8, use_graph=True, raise_on_noconv=False)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out["solves_per_s"] = rate(16, dt)
+    out["s_per_batch"] = round(dt, 3)
+    out["iterations"] = [int(i["iters"]) for i in info]
+    out["converged"] = all(i["converged"] for i in info)
+    out["max_res_true"] = max(i["res_true"] for i in info)
+    # the coarse product alone: timed kernel launches over a few iterations
+    S._check(S.lib().sn_precond_profile(pre.h, 1))
+    pre.solve(F, fixed_iters=4, use_graph=False)
+    st = S.KernelStats()
+    S._check(S.lib().sn_precond_kernel_stats(pre.h, S.C.byref(st)))
+    S._check(S.lib().sn_precond_profile(pre.h, 0))
+    st = st.asdict()
+    if st["coarse_launches"]:
+        us = st["coarse_ms"] / st["coarse_launches"] * 1e3
+        tflops = 16 * st["coarse_flops"] / (us * 1e-6) / 1e12
+        out["coarse_product"] = {"us": round(us, 2), "columns": 16, "flops": 16 * st["coarse_flops"],
+                                 "tflops": round(tflops, 2), "peak_tflops": PEAK_F64_TFLOPS,
+                                 "mfma_utilisation": round(tflops / PEAK_F64_TFLOPS, 4),
+                                 "bytes": 8 * pre.m0 * pre.m0, "hbm_frac": round(8 * pre.m0 * pre.m0 / (us * 1e-6) / 1e9 / PEAK_HBM_GBS, 4)}
+    if st["sweep_launches"]:
+        out["local_solves_us"] = round(st["sweep_ms"] / st["sweep_launches"] * 1e3, 2)
+    return out
+
+
+def cpu_oracle_leg(O, W, seg, tol, preset, nH, f_host, rtol, threads):
+    """The FP64 oracle on the host: one solve on one core, and independent
+    solves (other right-hand sides of the same network) on `threads` cores at
+    once (the oracle is single threaded; the C calls release the GIL)."""
+    from concurrent.futures import ThreadPoolExecutor
+    import numpy as np
+    onet = O.Network.from_segments(2, seg, merge_tol=tol, dir_lo=preset["dir_lo"], dir_hi=preset["dir_hi"],
+                                   band=W.BAND)
+    opre = O.Precond(O.System(onet), nH, 0, preset["dir_lo"], preset["dir_hi"])
+    md_nnz = opre.star_md_nnz()
+    t0 = time.perf_counter()
+    u_o, it_o, _ = opre.pcg(f_host, rtol=rtol)
+    t1 = time.perf_counter() - t0
+    F = W.rhs(len(f_host), threads, seed=101)
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(threads) as ex:
+        list(ex.map(lambda j: opre.pcg(np.ascontiguousarray(F[:, j]), rtol=rtol), range(threads)))
+    tn = time.perf_counter() - t0
+    return u_o, it_o, t1, threads / tn, tn, md_nnz
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -172,14 +307,18 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-h-sweep", action="store_true")
+    ap.add_argument("--no-configs", action="store_true", help="skip the other workloads (c1, c3, c4)")
     ap.add_argument("--serving-requests", type=int, default=64)
     ap.add_argument("--serving-rate", type=float, default=0.0,
                     help="Poisson arrival rate (requests/s); 0: 70%% of the measured saturation rate")
-    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic_star_sweep_fiber2d_20k.json"),
-                    help="HBM traffic per sweep launch from rocprofv3 counters (JSON), if present")
+    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic_local_solves_fiber2d_20k_H64.json"),
+                    help="HBM traffic per local-solve launch from rocprofv3 counters (JSON), if present")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (5 times) and exit: the reference "
                          "kernel that scales the FETCH_SIZE / WRITE_SIZE counters to bytes")
+    ap.add_argument("--only-apply-b", type=int, default=0, metavar="N",
+                    help="only set up the headline workload (mixed form) and apply B N times, then exit (the "
+                         "short program the hardware-counter passes profile)")
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe(args.copy_probe)
@@ -195,17 +334,24 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     preset = dict(W.PRESETS["fiber2d_20k"])
-    preset["nH"] = args.nH
-    seg = W.fiber_segments(preset["dim"], preset["n_segments"], preset["length"], preset["seed"])
-    tol = W.merge_tol(preset["length"])
     t_setup = time.perf_counter()
-    net = S.Network.from_segments(2, seg, merge_tol=tol, dir_lo=preset["dir_lo"], dir_hi=preset["dir_hi"], band=W.BAND)
-    sysm = S.System(net)
-    mixed = S.Precond(sysm, args.nH, S.STARS_ALL, preset["dir_lo"], preset["dir_hi"], precision=S.FP32_STARS)
+    seg, net, sysm, mixed = build_problem(S, W, preset, args.nH, S.FP32_STARS)
     t_setup = time.perf_counter() - t_setup
-    plain = S.Precond(sysm, args.nH, S.STARS_ALL, preset["dir_lo"], preset["dir_hi"], precision=S.FP64)
+    tol = W.merge_tol(preset["length"])
     f_host = W.rhs(sysm.n, 1, seed=7)[:, 0]
     f = torch.from_numpy(f_host).cuda()
+    if args.only_apply_b:
+        z = mixed.apply_B(f)
+        torch.cuda.synchronize()
+        for _ in range(args.only_apply_b):
+            z = mixed.apply_B(f)
+        torch.cuda.synchronize()
+        print(json.dumps({"apply_B": args.only_apply_b, "engine": mixed.engine_info(1)}), flush=True)
+        return
+    plain = S.Precond(sysm, args.nH, S.STARS_ALL, preset["dir_lo"], preset["dir_hi"], precision=S.FP64)
+    coarse32 = S.Precond(sysm, args.nH, S.STARS_ALL, preset["dir_lo"], preset["dir_hi"],
+                         precision=S.FP32_STARS_COARSE)
+    log(f"set up fiber2d_20k H=1/{args.nH}: {sysm.n} dofs, {mixed.nstars} stars")
 
     # kernel timing legs (eager launches, one iteration per read-back)
     rp_prof = timed_solves(plain, f, max(3, args.steps // 4), 1, args.rtol, profile=True)
@@ -213,8 +359,10 @@ def main():
     # timed legs: graph replay (the product configuration), and eager launches
     rm = timed_solves(mixed, f, args.steps, args.warmup, args.rtol, use_graph=True)
     rp = timed_solves(plain, f, args.steps, args.warmup, args.rtol, use_graph=True)
+    rc = timed_solves(coarse32, f, args.steps, args.warmup, args.rtol, use_graph=True)
     rme = timed_solves(mixed, f, args.steps, args.warmup, args.rtol)
     rpe = timed_solves(plain, f, args.steps, args.warmup, args.rtol)
+    log("headline legs done")
 
     multi = {}
     for k in (8, 16):
@@ -226,6 +374,7 @@ def main():
                                      "ms_per_batch": round(r["total_s"] / max(2, args.steps // 4) * 1e3, 3),
                                      "max_iterations": int(max(i["iters"] for i in r["info"])),
                                      "max_res_true": max(i["res_true"] for i in r["info"])}
+    log("multi-RHS legs done")
 
     # the mesh-size sweep of the same network (H = 1/16, 1/32, 1/64)
     h_sweep = {}
@@ -236,38 +385,47 @@ def main():
                 pre = S.Precond(sysm, nH, S.STARS_ALL, preset["dir_lo"], preset["dir_hi"], precision=prec)
                 r = timed_solves(pre, f, max(3, args.steps // 4), 1, args.rtol, use_graph=True)
                 row[name] = {"solves_per_s": round(max(3, args.steps // 4) / r["total_s"], 2),
-                             "iterations": int(r["iters"][-1]), "res_true": r["info"][0]["res_true"]}
+                             "iterations": int(r["iters"][-1]), "res_true": r["info"][0]["res_true"],
+                             "local_solves_us": pre.engine_info(1)["star_sweep_us"],
+                             "stars_supernodal": pre.engine_info(1)["star_sn"]}
                 row["stars"], row["m0"] = pre.nstars, pre.m0
                 row["max_star_dofs"] = pre.factor_info()["max_star_dofs"]
                 del pre
             h_sweep[f"H=1/{nH}"] = row
+        log("mesh-size sweep done")
 
     value = args.steps / rm["total_s"]
     plain_value = args.steps / rp["total_s"]
     fim, fip = mixed.factor_info(), plain.factor_info()
 
-    def roof(fi, st):
+    def roof(pre, st):
+        ei = pre.engine_info(1)
         dur_s = st["sweep_ms"] / max(st["sweep_launches"], 1) / 1e3
-        ach = fi["sweep_bytes"] / dur_s / 1e9
+        ach = ei["sweep_bytes"] / dur_s / 1e9
         return dict(bound="hbm", achieved=round(ach, 1), peak=PEAK_HBM_GBS, unit="GB/s",
-                    frac=round(ach / PEAK_HBM_GBS, 4), bytes_per_launch=fi["sweep_bytes"],
-                    avg_launch_us=round(dur_s * 1e6, 2), launches=st["sweep_launches"])
+                    frac=round(ach / PEAK_HBM_GBS, 4), bytes_per_launch=ei["sweep_bytes"],
+                    avg_launch_us=round(dur_s * 1e6, 2), launches=st["sweep_launches"], tuning=ei)
 
-    roof_m, roof_p = roof(fim, rm_prof["stats"]), roof(fip, rp_prof["stats"])
-    for rf, pre in ((roof_m, mixed), (roof_p, plain)):
-        rf["tuning"] = pre.engine_info(1)
+    roof_m, roof_p = roof(mixed, rm_prof["stats"]), roof(plain, rp_prof["stats"])
     traffic = None
     if os.path.exists(args.traffic):
         try:
             with open(args.traffic) as fh:
                 t = json.load(fh)
-            if t.get("sweep_bytes") == fim["sweep_bytes"] and t.get("kernel_src") == kernel_source_hash():
+            if t.get("bytes_per_launch") == roof_m["bytes_per_launch"] and t.get("kernel_src") == kernel_source_hash():
                 traffic = t.get("hbm_bytes_per_launch")
         except Exception:
             traffic = None
     roof_m["traffic"] = traffic
-    roof_m["kernel"] = ("local solves, FP32 factors: k_star (level-scheduled supernodal solve, one star per "
-                        "workgroup), all launches of one application of B timed together")
+    roof_m["kernel"] = ("local solves (all launches of one application of B: k_star band sweeps, FP32 envelope "
+                        "factors, and k_sn supernodal solves for the stars the tuner gives them)")
+    roof_m["bytes_basis"] = ("structural non-zeros of each star's factor in the order its kernel uses (RCM for the "
+                             "band sweeps, read by both sweeps; minimum degree for the supernodal solves, read once), "
+                             "x 4 B, plus 16 B per position (dof index, FP64 gather of r, FP32 slot write)")
+    sc = rm_prof["stats"]
+    if sc and sc.get("coarse_launches"):
+        cus = sc["coarse_ms"] / sc["coarse_launches"] * 1e3
+        roof_m["coarse_product_us"] = round(cus, 2)
 
     u_m = rm["u"].cpu().numpy()
     u_p = rp["u"].cpu().numpy()
@@ -288,7 +446,9 @@ def main():
             "workload": f"fiber2d_20k_H{args.nH}", "launch": "captured HIP graphs of 2^i iterations",
             "dim": 2, "n_segments": preset["n_segments"], "length": preset["length"], "nH": args.nH,
             "nodes": net.n_nodes, "dofs": sysm.n, "nnz": sysm.nnz, "stars": mixed.nstars, "m0": mixed.m0,
-            "rtol": args.rtol, "rhs_per_solve": 1, "precision": "FP32 star factors and local solves, FP64 coarse operator, FP64 CG recurrences and dots",
+            "rtol": args.rtol, "rhs_per_solve": 1,
+            "precision": "FP32 local factors and solves (FP32 accumulation), FP64 coarse operator, FP64 CG "
+                         "recurrences, dots and residual checks",
         },
         "latency_ms": {"p50": round(percentile(rm["lat_ms"], 0.5), 3),
                        "p99": round(percentile(rm["lat_ms"], 0.99), 3)},
@@ -299,36 +459,58 @@ def main():
                        "latency_ms": {"p50": round(percentile(rp["lat_ms"], 0.5), 3),
                                       "p99": round(percentile(rp["lat_ms"], 0.99), 3)},
                        "iterations": int(statistics.median(rp["iters"])), "res_true": rp["info"][0]["res_true"],
-                       "roofline_star_sweeps": roof_p},
+                       "roofline_local_solves": roof_p},
         "mixed_over_plain": round(value / plain_value, 3),
+        "fp32_coarse_variant": {"value": round(args.steps / rc["total_s"], 3), "unit": "solves/s",
+                                "coarse_precision": coarse32.factor_info()["coarse_precision"],
+                                "note": "FP32 local solves and the coarse inverse stored in FP32 (FP64 accumulation)"},
         "eager_launches": {"mixed": round(args.steps / rme["total_s"], 3), "plain": round(args.steps / rpe["total_s"], 3)},
         "multi_rhs": multi,
         "h_sweep": h_sweep,
         "roofline": roof_m,
         "setup_s": round(t_setup, 2),
-        "factor_info": {"mixed": {k: fim[k] for k in ("star_factor_nnz", "star_stored", "star_blob_bytes", "star_index_bytes", "sweep_bytes", "max_levels", "max_star_dofs",
-                                                     "factor_seconds")}},
+        "factor_info": {"mixed": {k: fim[k] for k in ("star_factor_nnz", "star_rcm_nnz", "star_envelope",
+                                                     "star_stored", "star_blob_bytes", "star_index_bytes",
+                                                     "sweep_bytes", "sweep_bytes_sn", "max_levels", "max_band",
+                                                     "max_star_dofs", "factor_seconds", "coarse_bytes")}},
     }
+
+    if not args.no_configs:
+        for name, leg in (("c1", c1_leg), ("c3", c3_leg), ("c4", c4_leg)):
+            try:
+                out[name] = leg(S, W, torch, args.steps)
+            except Exception as ex:  # report, keep the other legs
+                out[name] = {"error": str(ex)}
+            log(f"{name} leg done")
 
     if not args.no_serving:
         out["serving"] = serving_leg(args.serving_requests, args.serving_rate)
+        log("serving leg done")
 
     if not args.no_cpu_baseline:
         sys.path.insert(0, os.path.join(ROOT, "oracle"))
         import oracle as O
         O.build()
-        onet = O.Network.from_segments(2, seg, merge_tol=tol, dir_lo=preset["dir_lo"], dir_hi=preset["dir_hi"],
-                                       band=W.BAND)
-        opre = O.Precond(O.System(onet), args.nH, 0, preset["dir_lo"], preset["dir_hi"])
-        t0 = time.perf_counter()
-        u_o, it_o, _ = opre.pcg(f_host, rtol=args.rtol)
-        t_o = time.perf_counter() - t0
-        out["cpu_baseline"] = {"value": round(1.0 / t_o, 4), "unit": "solves/s", "cores": 1, "kind": "oracle",
-                               "sample": f"one full FP64 oracle PCG solve of the same network and right-hand side "
-                                         f"({it_o} iterations, {t_o:.1f} s; setup untimed)"}
+        threads = max(1, min(16, os.cpu_count() or 1))
+        u_o, it_o, t1, many_rate, tn, md_nnz = cpu_oracle_leg(O, W, seg, tol, preset, args.nH, f_host, args.rtol,
+                                                              threads)
+        out["cpu_baseline"] = {"value": round(many_rate, 4), "unit": "solves/s", "cores": threads, "kind": "oracle",
+                               "sample": f"{threads} full FP64 oracle PCG solves of the same network with other "
+                                         f"right-hand sides, one per core at once ({tn:.1f} s; setup untimed)",
+                               "one_core": {"value": round(1.0 / t1, 4), "cores": 1,
+                                            "sample": f"one oracle solve of the benchmark right-hand side "
+                                                      f"({it_o} iterations, {t1:.1f} s)"}}
         nrm = np.linalg.norm(u_o)
         out["err_vs_oracle"] = {"mixed": float(np.linalg.norm(u_m - u_o) / nrm),
                                 "plain": float(np.linalg.norm(u_p - u_o) / nrm), "oracle_iterations": it_o}
+        npos = mixed.star_total
+        out["roofline"]["md_reference"] = {
+            "oracle_min_degree_nnz": md_nnz,
+            "ratio_credited_to_md": round((roof_m["bytes_per_launch"] - 16 * npos) / (4 * md_nnz), 3),
+            "bytes_if_md_factor_read_once": md_nnz * 4 + 16 * npos,
+            "frac_on_md_bytes": round((md_nnz * 4 + 16 * npos) / (roof_m["avg_launch_us"] * 1e-6) / 1e9 /
+                                      PEAK_HBM_GBS, 4)}
+        log("cpu baseline done")
     print(json.dumps(out), flush=True)
 
 

@@ -238,13 +238,17 @@ void sn_solve_opts_default(sn_solve_opts *opts);
 sn_status sn_solve(sn_precond pre, int k, const double *f, double *u, const sn_solve_opts *opts,
                    sn_solve_info *info);
 
-/* Kernel timing: while enabled, the star-sweep launches of every B application
- * are bracketed by HIP events on the solve stream, and the coarse solve runs
- * before the sweeps (not beside them) so that the sweeps are timed alone. */
+/* Kernel timing: while enabled, the local-solve launches of every B
+ * application and the coarse product are bracketed by HIP events, and the
+ * coarse solve runs before the local solves (not beside them) so that each is
+ * timed alone. */
 typedef struct {
   int64_t sweep_launches;  /* B applications timed */
-  double sweep_ms;         /* summed device time of the star sweeps of those applications */
+  double sweep_ms;         /* summed device time of the local solves of those applications */
   int64_t iterations;      /* PCG iterations run while enabled */
+  int64_t coarse_launches; /* coarse products timed */
+  double coarse_ms;        /* their summed device time */
+  int64_t coarse_flops;    /* flops of one coarse product per column (2 m0^2) */
 } sn_kernel_stats;
 
 /* enable = 1 starts (and resets) the recording, 0 stops it. */

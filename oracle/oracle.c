@@ -1152,6 +1152,72 @@ int64_t orc_pre_factor_nnz(const orc_pre *p, int64_t *coarse_nnz) {
   return t;
 }
 
+/*
+ * Structural non-zeros of the Cholesky factors of all local matrices K_j
+ * (incl. the diagonal) under a minimum degree order (Tinney-Walker / Rose):
+ * repeatedly eliminate a vertex of least degree in the elimination graph,
+ * ties by the smallest local index; eliminating v joins its neighbours
+ * pairwise, and column v of L holds v and those neighbours, so the count is the
+ * sum of 1 + degree at elimination. A measuring stick for the factor sizes the
+ * library stores (it does not enter any solve). Quadratic per star: fine for
+ * stars of a few thousand dofs.
+ */
+int64_t orc_pre_star_md_nnz(const orc_pre *p) {
+  const orc_sys *s = p->sys;
+  int32_t *loc = zalloc((size_t)(s->n ? s->n : 1), sizeof(int32_t));
+  for (int64_t i = 0; i < s->n; i++) loc[i] = -1;
+  int64_t total = 0;
+  for (int64_t st = 0; st < p->nstars; st++) {
+    int64_t b0 = p->star_ptr[st], m = p->star_ptr[st + 1] - b0;
+    const int32_t *dofs = p->star_dofs + b0;
+    for (int64_t a = 0; a < m; a++) loc[dofs[a]] = (int32_t)a;
+    /* neighbour lists of the elimination graph (growable) */
+    const size_t mm = (size_t)(m > 0 ? m : 1);
+    ivec *nb = zalloc(mm, sizeof(ivec));
+    for (int64_t a = 0; a < m; a++)
+      for (int64_t q = s->rowptr[dofs[a]]; q < s->rowptr[dofs[a] + 1]; q++) {
+        int32_t b = loc[s->col[q]];
+        if (b >= 0 && b != a) ivec_push(&nb[a], b);
+      }
+    char *gone = zalloc(mm, 1);
+    int64_t *mark = zalloc(mm, sizeof(int64_t));
+    for (int64_t a = 0; a < m; a++) mark[a] = -1;
+    for (int64_t step = 0; step < m; step++) {
+      int64_t v = -1;
+      for (int64_t a = 0; a < m; a++)
+        if (!gone[a] && (v < 0 || nb[a].n < nb[v].n)) v = a;
+      total += 1 + nb[v].n;
+      gone[v] = 1;
+      /* every neighbour a of v: drop v, add the other neighbours of v */
+      for (int64_t i = 0; i < nb[v].n; i++) {
+        int64_t a = nb[v].a[i];
+        ivec keep = {0, 0, 0};
+        for (int64_t t = 0; t < nb[a].n; t++)
+          if (nb[a].a[t] != v) {
+            ivec_push(&keep, nb[a].a[t]);
+            mark[nb[a].a[t]] = step * m + a;
+          }
+        for (int64_t t = 0; t < nb[v].n; t++) {
+          int64_t b = nb[v].a[t];
+          if (b != a && mark[b] != step * m + a) {
+            ivec_push(&keep, b);
+            mark[b] = step * m + a;
+          }
+        }
+        free(nb[a].a);
+        nb[a] = keep;
+      }
+    }
+    for (int64_t a = 0; a < m; a++) free(nb[a].a);
+    free(nb);
+    free(gone);
+    free(mark);
+    for (int64_t a = 0; a < m; a++) loc[dofs[a]] = -1;
+  }
+  free(loc);
+  return total;
+}
+
 /* z = K_j^{-1} g for one local space (g, z indexed like star_dofs of star st) */
 int orc_star_solve(const orc_pre *p, int64_t st, const double *g, double *z) {
   if (st < 0 || st >= p->nstars || !p->factored) return orc_fail(ORC_EINVAL, "bad star");

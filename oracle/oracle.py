@@ -60,6 +60,8 @@ def lib():
         L.orc_pre_get_K0_dense.argtypes = [P, P]
         L.orc_pre_factor_nnz.argtypes = [P, C.POINTER(i64)]
         L.orc_pre_factor_nnz.restype = i64
+        L.orc_pre_star_md_nnz.argtypes = [P]
+        L.orc_pre_star_md_nnz.restype = i64
         L.orc_star_solve.argtypes = [P, i64, P, P]
         L.orc_apply_B.argtypes = [P, P, P]
         L.orc_pcg.argtypes = [P, P, P, dbl, i64, i64, P, P, P, C.POINTER(dbl)]
@@ -216,6 +218,11 @@ class Precond:
         K0 = np.zeros((self.m0, self.m0))
         _check(lib().orc_pre_get_K0_dense(self.h, _ptr(K0)))
         return K0
+
+    def star_md_nnz(self):
+        """Structural non-zeros of all local Cholesky factors under a minimum
+        degree order (a measuring stick for factor sizes; not used in solves)."""
+        return int(lib().orc_pre_star_md_nnz(self.h))
 
     def factor_nnz(self):
         c = i64()

@@ -920,7 +920,7 @@ struct DeviceState {
   std::unique_ptr<Engine> solve_engine[5];
   // profiling
   bool profiling = false;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_used, ev_free;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_used, ev_free, ev_coarse;
   int64_t prof_iters = 0;
   ~DeviceState();
 };
@@ -995,6 +995,10 @@ struct Engine {
 DeviceState::~DeviceState() {
   for (auto &e : solve_engine) e.reset();
   for (auto &e : ev_used) {
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
+  for (auto &e : ev_coarse) {
     (void)hipEventDestroy(e.first);
     (void)hipEventDestroy(e.second);
   }
@@ -1654,12 +1658,27 @@ void launch_B(Engine &e, const double *r, double *z, int sel, bool dot, hipStrea
       hipLaunchKernelGGL(k_restrict<KC>, dim3(nblk(d.m0 * 64)), dim3(kBlock), 0, cs, d.PTptr.p, d.PTdof.p, d.PTw.p,
                          r, e.rH.p, (int)d.m0, e.sc.p, sel, conv ? e.partials2.p : nullptr, (int)grid_for(d.npad));
       const unsigned gb = (unsigned)(d.ld0 / 8);
+      std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+      if (d.profiling) {
+        if (d.ev_free.empty()) {
+          HIPCHK(hipEventCreate(&ev.first));
+          HIPCHK(hipEventCreate(&ev.second));
+        } else {
+          ev = d.ev_free.back();
+          d.ev_free.pop_back();
+        }
+        HIPCHK(hipEventRecord(ev.first, cs));
+      }
       if (d.coarse32)
         hipLaunchKernelGGL((k_coarse_mm<float, KC>), dim3(gb), dim3(64 * kMmWaves), 0, cs, d.Kinv32.p, (int)d.ld0,
                            e.rH.p, e.c.p, (int)d.m0, e.sc.p, sel);
       else
         hipLaunchKernelGGL((k_coarse_mm<double, KC>), dim3(gb), dim3(64 * kMmWaves), 0, cs, d.Kinv64.p, (int)d.ld0,
                            e.rH.p, e.c.p, (int)d.m0, e.sc.p, sel);
+      if (d.profiling) {
+        HIPCHK(hipEventRecord(ev.second, cs));
+        d.ev_coarse.push_back(ev);
+      }
     });
   };
   // while profiling, the coarse solve always runs first, so that the timed
@@ -2278,7 +2297,9 @@ void device_profile(Precond &pre, int enable) {
   DeviceState &d = *pre.dev;
   HIPCHK(hipDeviceSynchronize());
   for (auto &e : d.ev_used) d.ev_free.push_back(e);
+  for (auto &e : d.ev_coarse) d.ev_free.push_back(e);
   d.ev_used.clear();
+  d.ev_coarse.clear();
   d.prof_iters = 0;
   d.profiling = enable != 0;
 }
@@ -2295,6 +2316,16 @@ void device_stats(Precond &pre, sn_kernel_stats *st) {
   st->sweep_launches = (int64_t)d.ev_used.size();
   st->sweep_ms = ms;
   st->iterations = d.prof_iters;
+  double cms = 0.0;
+  for (auto &e : d.ev_coarse) {
+    HIPCHK(hipEventSynchronize(e.second));
+    float t = 0.f;
+    HIPCHK(hipEventElapsedTime(&t, e.first, e.second));
+    cms += t;
+  }
+  st->coarse_launches = (int64_t)d.ev_coarse.size();
+  st->coarse_ms = cms;
+  st->coarse_flops = 2 * d.m0 * d.m0;
 }
 
 int64_t device_bytes(const Precond &pre) { return pre.dev ? pre.dev->bytes : 0; }

@@ -61,7 +61,8 @@ class EngineInfo(C.Structure):
 
 
 class KernelStats(C.Structure):
-    _fields_ = [("sweep_launches", C.c_int64), ("sweep_ms", C.c_double), ("iterations", C.c_int64)]
+    _fields_ = [("sweep_launches", C.c_int64), ("sweep_ms", C.c_double), ("iterations", C.c_int64),
+                ("coarse_launches", C.c_int64), ("coarse_ms", C.c_double), ("coarse_flops", C.c_int64)]
 
     def asdict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
