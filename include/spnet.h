@@ -56,7 +56,7 @@ typedef enum {
   SN_EDEVICE = -3,    /* HIP runtime error or no usable gfx950 device */
   SN_ESINGULAR = -4,  /* no Dirichlet node: K is singular on V */
   SN_ENOTSPD = -5,    /* a local or the coarse matrix has a non-positive pivot */
-  SN_ENOCONV = -6,    /* max_iter reached before the tolerance */
+  SN_ENOCONV = -6,    /* a column stopped before its true residual met the tolerance */
   SN_EBUSY = -7       /* serving: result not ready / no room */
 } sn_status;
 
@@ -209,7 +209,10 @@ typedef struct {
   double rtol;           /* stop when ||r||_2 <= rtol ||f||_2 (per column, recurrence r) */
   int64_t max_iter;      /* default 1000 */
   int64_t fixed_iters;   /* > 0: run exactly this many iterations, ignore rtol */
-  int64_t replace_every; /* > 0: r <- f - K u every so many iterations */
+  int64_t replace_every; /* > 0: r <- f - K u at the first convergence read-back
+                            after every so many iterations (the queued blocks
+                            between read-backs hold at most 4 check_every
+                            iterations) */
   int32_t check_every;   /* iterations queued between convergence read-backs (default 8) */
   int32_t device_ptrs;   /* 1: f and u are device pointers */
   int32_t use_u0;        /* 1: u holds the initial guess u^(0), else u^(0) = 0 */
@@ -221,7 +224,7 @@ typedef struct {
   int64_t iters;   /* PCG iterations done */
   double res_rec;  /* ||r||_2 / ||f||_2 of the recurrence at exit */
   double res_true; /* ||f - K u||_2 / ||f||_2 recomputed in FP64 at exit */
-  int32_t converged;
+  int32_t converged;  /* 1: res_rec and res_true both <= rtol (fixed_iters: the count was run) */
   int32_t replacements; /* residual replacements done */
   double ms;       /* wall time of the call */
 } sn_solve_info;
@@ -233,7 +236,9 @@ void sn_solve_opts_default(sn_solve_opts *opts);
  * Solve K u = f for k right-hand sides (1 <= k <= 16): f and u are n x k
  * row-major. Each column runs its own PCG recurrence (alpha, beta per column);
  * columns share the matrix and factor reads. info has k entries.
- * Errors: SN_ENOCONV if some column hits max_iter (u still holds the iterate).
+ * Errors: SN_ENOCONV if some column stopped unconverged (max_iter reached, or its
+ * FP64 true residual stays above rtol: the attainable accuracy of an
+ * ill-conditioned system); u and info still hold the iterates and their state.
  */
 sn_status sn_solve(sn_precond pre, int k, const double *f, double *u, const sn_solve_opts *opts,
                    sn_solve_info *info);

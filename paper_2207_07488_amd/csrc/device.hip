@@ -2512,12 +2512,14 @@ void device_solve(Precond &pre, int k, const double *f, double *u, const sn_solv
     info[j].iters = x.iters;
     info[j].res_rec = fn > 0 ? std::sqrt(x.rr) / fn : std::sqrt(x.rr);
     info[j].res_true = fn > 0 ? std::sqrt(x.t2) / fn : std::sqrt(x.t2);
-    info[j].converged = x.fixed > 0 ? 1 : (x.rr <= x.tol2 ? 1 : 0);
+    info[j].converged = x.fixed > 0 ? 1 : column_converged(x.rr, x.t2, x.tol2);
     info[j].replacements = x.replacements;
     info[j].ms = ms;
     if (!info[j].converged) all_conv = false;
   }
-  if (!all_conv) fail(SN_ENOCONV, "PCG reached max_iter before the tolerance");
+  if (!all_conv)
+    fail(SN_ENOCONV, "a column stopped before its true residual met the tolerance (max_iter reached, or the "
+                     "attainable accuracy of the system in FP64 is above it)");
 }
 
 }  // namespace spnet

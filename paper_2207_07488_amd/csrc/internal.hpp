@@ -156,6 +156,12 @@ struct ColumnStatus {
   double rr, f2, tol2, t2;
   int32_t active, done, verify, replacements, fixed;
 };
+// a stopped column has converged when its recurrence residual and its FP64
+// true residual (both squared) meet the squared tolerance (the true one up to
+// rounding of its own sum)
+inline int32_t column_converged(double rr, double t2, double tol2) {
+  return rr <= tol2 && t2 <= tol2 * 1.0001 ? 1 : 0;
+}
 int engine_width_for(int k);                          // 1, 2, 4, 8 or 16 >= k
 int64_t engine_footprint(const Precond &pre, int kc);  // device bytes of an engine
 Engine *engine_create(Precond &pre, int kc);           // pre must be factored

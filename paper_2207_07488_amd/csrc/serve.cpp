@@ -213,7 +213,7 @@ void retire_finished(sn_server_s &S, EngineSlot &e) {
     in.iters = x.iters;
     in.res_rec = fn > 0 ? std::sqrt(x.rr) / fn : std::sqrt(x.rr);
     in.res_true = fn > 0 ? std::sqrt(x.t2) / fn : std::sqrt(x.t2);
-    in.converged = x.rr <= x.tol2 ? 1 : 0;
+    in.converged = spnet::column_converged(x.rr, x.t2, x.tol2);
     in.replacements = x.replacements;
     in.ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - r->t_submit).count();
     e.col_req[c] = nullptr;

@@ -1,10 +1,11 @@
 """GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
 
-Bars: integer structure bit-exact (checked on the CPU in test_lib_structure);
-K x to 1e-14; B r (FP64 stars) and the plain PCG iterate at the oracle's own
-iteration count to tol = max(1e-10, 10 * 2^-52 * kappa), kappa the largest
-condition number of the local and coarse matrices; the mixed path (FP32 stars)
-to the same true residual 1e-8. Derivation: both sides compute the same Krylov
+Bars, element by element (every |a_i - b_i| <= tol * max|b|): integer structure
+bit-exact (checked on the CPU in test_lib_structure); K x to 1e-14; B r (FP64
+stars) and the plain PCG iterate at the oracle's own iteration count to
+tol = max(1e-10, 10 * 2^-52 * kappa), kappa the largest condition number of the
+local and coarse matrices; the mixed path (FP32 stars) to the same true
+residual 1e-8, recomputed here with the oracle's K. Derivation: both sides compute the same Krylov
 iterate; they differ by the rounding of different factor orderings and
 summation orders, which a direct solve amplifies by at most cond(K_j). For the
 heat model kappa ~ 1e4-1e5, so the bar is 1e-10; the truss model's 1e-6
@@ -93,7 +94,7 @@ def test_preconditioner_parity_fp64(S, orc, name):
     r = W.rhs(opre.sys.n, 1, seed=4)[:, 0]
     z = gpre.apply_B(r)
     ref = opre.apply_B(r)
-    assert _rel(z, ref) <= _tol(orc, name, opre)
+    assert _close(z, ref, _tol(orc, name, opre))
 
 
 @pytest.mark.parametrize("name", list(CASES))
@@ -106,10 +107,10 @@ def test_preconditioner_fp32_stars(S, orc, name):
     if fi["star_precision"] == S.FP64:
         # FP32 could not resolve these local solves: the library kept FP64 factors
         assert fi["max_pivot_ratio"] * 2.0 ** -24 > 0.05
-        assert _rel(z, ref) <= _tol(orc, name, opre)
+        assert _close(z, ref, _tol(orc, name, opre))
     else:
-        # FP32 factors and sweeps: ~ cond(K_j) * 6e-8
-        assert _rel(z, ref) <= 5e-3
+        # FP32 factors and solves: every local solve to ~ cond(K_j) * 6e-8 of its size
+        assert _close(z, ref, 5e-3)
     # the mixed form keeps the coarse operator in FP64
     assert fi["coarse_precision"] == S.FP64
 
@@ -129,6 +130,24 @@ def test_preconditioner_fp32_coarse(S, orc, name):
     assert _rel(z, ref) <= (5e-3 if fi["star_precision"] == S.FP32_STARS else _tol(orc, name, opre))
 
 
+def _true_res(opre, u, f):
+    """||f - K u|| / ||f|| with the oracle's K."""
+    return float(np.linalg.norm(f - opre.sys.apply_K(u)) / np.linalg.norm(f))
+
+
+def _res_noise(opre, u, f):
+    """Bound on the rounding error of f - K u computed in FP64 by any summation
+    order (Higham, Accuracy and Stability, 2nd ed., eq. 3.11 applied row by row):
+    |computed - exact| <= gamma_m (|f| + |K| |u|) with m the longest row plus one,
+    returned relative to ||f||."""
+    import scipy.sparse as sp
+    rp, ci, v = opre.sys.csr()
+    A = sp.csr_matrix((np.abs(v), ci, rp), shape=(opre.sys.n, opre.sys.n))
+    m = int(np.diff(rp).max()) + 1
+    gam = m * 2.0 ** -53 / (1 - m * 2.0 ** -53)
+    return float(gam * np.linalg.norm(np.abs(f) + A @ np.abs(u)) / np.linalg.norm(f))
+
+
 @pytest.mark.parametrize("name", list(CASES))
 def test_pcg_plain_parity(S, orc, name):
     opre, gpre = _pair(S, orc, name, S.FP64)
@@ -136,15 +155,21 @@ def test_pcg_plain_parity(S, orc, name):
     u_o, it_o, info_o = opre.pcg(f, rtol=1e-8)
     u_g, info = gpre.solve(f, fixed_iters=it_o)
     assert info[0]["iters"] == it_o
-    assert _rel(u_g, u_o) <= _tol(orc, name, opre)
+    assert _close(u_g, u_o, _tol(orc, name, opre))
     # the tolerance-stopped run takes the same number of iterations
     hist = opre.pcg(f, rtol=1e-8, history=True)[2]["hist_r"]
-    u_t, info_t = gpre.solve(f, rtol=1e-8)
+    u_t, info_t = gpre.solve(f, rtol=1e-8, raise_on_noconv=False)
     near = abs(hist[-1] / np.linalg.norm(f) - 1e-8) < 0.01e-8
     assert info_t[0]["iters"] == it_o or near
     # the true residual reaches the tolerance, or the oracle's own attainable
-    # accuracy where FP64 cannot get there (truss model)
-    assert info_t[0]["res_true"] <= max(1.0001e-8, 2 * info_o["true_res"]) and info_t[0]["converged"]
+    # accuracy where FP64 cannot get there (truss model); the column reports
+    # converged exactly when it reached the tolerance
+    rt = _true_res(opre, u_t, f)
+    assert rt <= max(1.0001e-8, 2 * info_o["true_res"])
+    # the library's own residual agrees with the oracle's to the rounding of the
+    # two computations of f - K u (both are within _res_noise of the exact one)
+    assert abs(info_t[0]["res_true"] - rt) <= 1e-3 * rt + 2 * _res_noise(opre, u_t, f)
+    assert info_t[0]["converged"] == (info_t[0]["res_true"] <= 1.0001e-8)
 
 
 @pytest.mark.parametrize("name", list(CASES))
@@ -152,11 +177,13 @@ def test_pcg_mixed(S, orc, name):
     opre, gpre = _pair(S, orc, name, S.FP32_STARS)
     f = W.rhs(opre.sys.n, 1, seed=7)[:, 0]
     u_o, it_o, info_o = opre.pcg(f, rtol=1e-8)
-    u_g, info = gpre.solve(f, rtol=1e-8)
-    assert info[0]["converged"] and info[0]["res_true"] <= max(1.0001e-8, 2 * info_o["true_res"])
+    u_g, info = gpre.solve(f, rtol=1e-8, raise_on_noconv=False)
+    rt = _true_res(opre, u_g, f)
+    assert rt <= max(1.0001e-8, 2 * info_o["true_res"])
+    assert info[0]["converged"] == (info[0]["res_true"] <= 1.0001e-8)
     assert info[0]["iters"] <= it_o + 3
     # the error against the FP64 oracle solution is of the order of the tolerance times cond
-    assert _rel(u_g, u_o) <= max(1e-5, _tol(orc, name, opre))
+    assert _close(u_g, u_o, max(1e-5, _tol(orc, name, opre)))
 
 
 def test_multi_rhs_columns_independent(S, orc):
@@ -183,7 +210,7 @@ def test_device_pointers(S, orc):
 def test_star_policy_free(S, orc):
     opre, gpre = _pair(S, orc, "fiber2d_300", S.FP64, policy=1)
     r = W.rhs(opre.sys.n, 1, seed=4)[:, 0]
-    assert _rel(gpre.apply_B(r), opre.apply_B(r)) <= 1e-10
+    assert _close(gpre.apply_B(r), opre.apply_B(r), 1e-10)
 
 
 def test_graph_replay_matches_eager(S, orc):
@@ -223,7 +250,7 @@ def test_batch_fixed_iterations_vs_oracle(S, orc):
     for c in range(4):
         u_o, it_o, _ = opre.pcg(F[:, c], fixed_iters=12)
         assert infos[c]["iters"] == 12
-        assert _rel(U[:, c], u_o) <= _tol(orc, "fiber3d_6k", opre)
+        assert _close(U[:, c], u_o, _tol(orc, "fiber3d_6k", opre))
 
 
 def test_batch_apply_B_columns(S, orc):
@@ -231,7 +258,7 @@ def test_batch_apply_B_columns(S, orc):
     R = W.rhs(opre.sys.n, 3, seed=13)
     Z = gpre.apply_B(R)
     for c in range(3):
-        assert _rel(Z[:, c], opre.apply_B(R[:, c])) <= 1e-10
+        assert _close(Z[:, c], opre.apply_B(R[:, c]), 1e-10)
 
 
 @pytest.mark.parametrize("name", ["fiber2d_2k", "fiber3d_6k", "truss3d_1500"])
@@ -266,3 +293,63 @@ def test_supernodal_stars_beyond_lds(S, orc):
     assert gpre.engine_info(16)["star_global"] > 0
     for c in (0, 9, 15):
         assert _close(Z[:, c], opre.apply_B(R[:, c]), 1e-10), c
+
+
+def test_residual_replacement(S, orc):
+    """Periodic residual replacement (r <- f - K u at the first read-back after
+    every 5 iterations; with check_every = 1 a queued block holds at most 4, so
+    two replacements are at most 8 iterations apart) reaches the tolerance within
+    two iterations of the plain count; the iterate matches the oracle's solution
+    to the tolerance."""
+    opre, gpre = _pair(S, orc, "fiber2d_2k", S.FP32_STARS)
+    f = W.rhs(opre.sys.n, 1, seed=7)[:, 0]
+    u_o, it_o, _ = opre.pcg(f, rtol=1e-8)
+    u0, i0 = gpre.solve(f, rtol=1e-8)
+    u_r, i_r = gpre.solve(f, rtol=1e-8, replace_every=5, check_every=1)
+    assert i_r[0]["converged"] and i_r[0]["replacements"] >= (i_r[0]["iters"] - 1) // 8
+    assert abs(i_r[0]["iters"] - i0[0]["iters"]) <= 2
+    assert _true_res(opre, u_r, f) <= 1.0001e-8
+    assert _close(u_r, u_o, 1e-5)
+
+
+def test_warm_start(S, orc):
+    """u0 = the oracle's solution: the initial residual already meets the
+    tolerance, so no (or one) iteration runs; u0 = 0 passed explicitly gives the
+    cold start bit for bit."""
+    opre, gpre = _pair(S, orc, "fiber2d_2k", S.FP64)
+    f = W.rhs(opre.sys.n, 1, seed=7)[:, 0]
+    u_o, it_o, _ = opre.pcg(f, rtol=1e-9)
+    u_w, i_w = gpre.solve(f, u0=u_o, rtol=1e-8)
+    assert i_w[0]["iters"] <= 1 and i_w[0]["converged"]
+    assert _close(u_w, u_o, 1e-8)
+    u_c, i_c = gpre.solve(f, rtol=1e-8)
+    u_z, i_z = gpre.solve(f, u0=np.zeros_like(f), rtol=1e-8)
+    assert i_z[0]["iters"] == i_c[0]["iters"] and np.array_equal(u_z, u_c)
+
+
+def test_max_iter_reports_no_convergence(S, orc):
+    """max_iter = 2: SN_ENOCONV, with the iterate and its state filled in; the
+    iterate equals the oracle's after two iterations."""
+    opre, gpre = _pair(S, orc, "fiber2d_2k", S.FP64)
+    f = W.rhs(opre.sys.n, 1, seed=7)[:, 0]
+    with pytest.raises(S.SpnetError) as ei:
+        gpre.solve(f, rtol=1e-8, max_iter=2)
+    assert ei.value.code == S.SN_ENOCONV
+    u, info = gpre.solve(f, rtol=1e-8, max_iter=2, raise_on_noconv=False)
+    assert info[0]["iters"] == 2 and not info[0]["converged"] and info[0]["res_true"] > 1e-8
+    u_o, _, _ = opre.pcg(f, fixed_iters=2)
+    assert _close(u, u_o, 1e-10)
+
+
+def test_non_finite_right_hand_side_rejected(S, orc):
+    opre, gpre = _pair(S, orc, "fiber2d_300", S.FP64)
+    f = W.rhs(opre.sys.n, 1, seed=7)[:, 0]
+    f[3] = np.nan
+    with pytest.raises(S.SpnetError) as ei:
+        gpre.solve(f, rtol=1e-8)
+    assert ei.value.code == S.SN_EINVAL
+    srv = S.Server(max_columns=2)
+    f[3] = np.inf
+    with pytest.raises(S.SpnetError) as ei:
+        srv.submit(gpre, f)
+    assert ei.value.code == S.SN_EINVAL
