@@ -19,7 +19,10 @@
  *   mesh T_H of half-open boxes, patches U,
  *   Q1 space restricted to the nodes           Sec. 2.3
  *   subspace decomposition V_0 = V_H,
- *   V_j = V(U(y_j)), projections P_j            Sec. 4.1 eq. (4.1)
+ *   V_j = V(U(y_j)), projections P_j            Sec. 4.1 eq. (4.1); the
+ *     nodes of V_j are those at which phi_j is positive (the support of
+ *     phi_j, which Sec. 5 identifies with U(y_j)); the heat experiment of
+ *     Sec. 6.2 (Table 6.2, grid row) is reproduced with this set
  *   PCG on P = BK                              Sec. 4.2
  * The fiber generator is the one of Sec. 6.1 with the workload parameters
  * passed in by the caller (segments are an input; see workloads).
@@ -883,9 +886,12 @@ int orc_pre_build(const orc_sys *s, int nH, int policy, int dir_lo, int dir_hi, 
   for (int k = 0; k < dim; k++) p->nvert *= (nH + 1);
   int64_t nf = s->n_free_nodes;
 
-  /* Q1 basis values at every free node: phi_v(x) = prod_k (b_k ? xi_k : 1 - xi_k) */
+  /* Q1 basis values at every free node: phi_v(x) = prod_k (b_k ? xi_k : 1 - xi_k);
+   * supp[f, b] = 1 when every factor is positive, i.e. x lies in the open
+   * patch |x_k nH - v_k| < 1 of the mesh node v = e + b */
   p->Pvert = zalloc((size_t)(nf ? nf : 1) * nv, sizeof(int32_t));
   p->Pphi = zalloc((size_t)(nf ? nf : 1) * nv, sizeof(double));
+  char *supp = zalloc((size_t)(nf ? nf : 1) * nv, 1);
   int64_t *eidx = zalloc((size_t)(nf ? nf : 1) * dim, sizeof(int64_t));
   for (int64_t f = 0; f < nf; f++) {
     const double *x = s->x + (size_t)s->free_node[f] * dim;
@@ -899,21 +905,24 @@ int orc_pre_build(const orc_sys *s, int nH, int policy, int dir_lo, int dir_hi, 
     for (int b = 0; b < nv; b++) {
       int64_t vid = 0, mul = 1;
       double phi = 1.0;
+      int pos = 1;
       for (int k = 0; k < dim; k++) {
         int bk = (b >> k) & 1;
         vid += (e[k] + bk) * mul;
         mul *= (nH + 1);
         phi = phi * (bk ? xi[k] : 1.0 - xi[k]);
+        if (bk ? !(xi[k] > 0.0) : !(xi[k] < 1.0)) pos = 0;
       }
       p->Pvert[f * nv + b] = (int32_t)vid;
       p->Pphi[f * nv + b] = phi;
+      supp[f * nv + b] = (char)pos;
     }
   }
 
   /* coarse dofs: vertices off Gamma whose restricted basis function is non-zero somewhere */
   char *nonzero = zalloc((size_t)p->nvert, 1);
   for (int64_t q = 0; q < nf * nv; q++)
-    if (p->Pphi[q] != 0.0) nonzero[p->Pvert[q]] = 1;
+    if (supp[q]) nonzero[p->Pvert[q]] = 1;
   p->vert_c = zalloc((size_t)p->nvert, sizeof(int32_t));
   p->cvert = zalloc((size_t)p->nvert, sizeof(int32_t));
   int64_t nk = 0;
@@ -932,17 +941,22 @@ int orc_pre_build(const orc_sys *s, int nH, int policy, int dir_lo, int dir_hi, 
   p->m0 = nk * nc;
   free(nonzero);
 
-  /* local spaces: S_v = free nodes x with v_k - 1 <= e_k(x) <= v_k for all k,
-   * i.e. the nodes of the patch U(y_v) (Sec. 2.3), expanded to their dofs */
+  /* local spaces: S_v = free nodes at which phi_v is positive, i.e. the
+   * network nodes inside the support of the basis function of y_v (the mesh
+   * star; Sec. 4.1 with the support of phi_k taken as U(y_k), as in Sec. 5),
+   * expanded to their dofs. A node strictly inside an element lies in the 2^d
+   * stars of that element's vertices; a node on a face of T_H only in those
+   * of the vertices of that face. */
   int64_t *cnt = zalloc((size_t)p->nvert + 1, sizeof(int64_t));
   for (int64_t f = 0; f < nf; f++)
-    for (int b = 0; b < nv; b++) cnt[p->Pvert[f * nv + b] + 1]++;
-  /* every free node belongs to exactly the 2^d stars of its element's vertices */
+    for (int b = 0; b < nv; b++)
+      if (supp[f * nv + b]) cnt[p->Pvert[f * nv + b] + 1]++;
   for (int64_t vid = 0; vid < p->nvert; vid++) cnt[vid + 1] += cnt[vid];
   int32_t *members = zalloc((size_t)(nf > 0 ? nf * nv : 1), sizeof(int32_t));
   int64_t *fillv = zalloc((size_t)p->nvert, sizeof(int64_t));
   for (int64_t f = 0; f < nf; f++)
     for (int b = 0; b < nv; b++) {
+      if (!supp[f * nv + b]) continue;
       int32_t vid = p->Pvert[f * nv + b];
       members[cnt[vid] + fillv[vid]++] = (int32_t)f;  /* ascending f */
     }
@@ -969,6 +983,7 @@ int orc_pre_build(const orc_sys *s, int nH, int policy, int dir_lo, int dir_hi, 
   free(members);
   free(fillv);
   free(eidx);
+  free(supp);
   *out = p;
   return ORC_OK;
 }

@@ -1,5 +1,6 @@
 // Coarse space V_H (Q1 on T_H restricted to the free nodes, Sec. 2.3) and the
-// local spaces V_j = V(U(y_j)) on mesh stars (Sec. 4.1).
+// local spaces V_j = V(U(y_j)) on mesh stars (Sec. 4.1): the free nodes at which
+// phi_j is positive (its support, which Sec. 5 identifies with U(y_j)).
 #include <algorithm>
 #include <cmath>
 
@@ -27,9 +28,12 @@ std::unique_ptr<Precond> build_spaces(std::shared_ptr<const System> sys, int nH,
 
   // element of each free node and the Q1 basis values at it:
   // e_k = min(floor(x_k nH), nH - 1), xi_k = x_k nH - e_k,
-  // phi_{e+b}(x) = prod_k (b_k ? xi_k : 1 - xi_k)
+  // phi_{e+b}(x) = prod_k (b_k ? xi_k : 1 - xi_k).
+  // in_star[f, b]: every factor is positive, so x lies in the support of the
+  // basis function of mesh node e + b (on a face of T_H some factors vanish)
   pre->Pvert.resize((size_t)nf * nv);
   pre->Pphi.resize((size_t)nf * nv);
+  std::vector<uint8_t> in_star((size_t)nf * nv, 0);
   for (int64_t f = 0; f < nf; ++f) {
     const double *x = &net.x[(size_t)sys->free_node[f] * dim];
     int64_t e[3];
@@ -40,6 +44,12 @@ std::unique_ptr<Precond> build_spaces(std::shared_ptr<const System> sys, int nH,
       e[k] = ek;
       xi[k] = x[k] * (double)nH - (double)ek;
     }
+    // per axis: is the lower (bit 0) / upper (bit 1) vertex's factor positive
+    uint32_t pos_lo = 0, pos_hi = 0;
+    for (int k = 0; k < dim; ++k) {
+      if (xi[k] < 1.0) pos_lo |= 1u << k;
+      if (xi[k] > 0.0) pos_hi |= 1u << k;
+    }
     for (int b = 0; b < nv; ++b) {
       int64_t id = 0, stride = 1;
       double phi = 1.0;
@@ -49,8 +59,11 @@ std::unique_ptr<Precond> build_spaces(std::shared_ptr<const System> sys, int nH,
         stride *= side;
         phi = phi * (bit ? xi[k] : 1.0 - xi[k]);
       }
+      // an upper-vertex axis needs xi > 0, a lower-vertex axis xi < 1
+      const uint32_t ub = (uint32_t)b, lower = ~ub & ((1u << dim) - 1);
       pre->Pvert[(size_t)f * nv + b] = (int32_t)id;
       pre->Pphi[(size_t)f * nv + b] = phi;
+      in_star[(size_t)f * nv + b] = ((ub & ~pos_hi) | (lower & ~pos_lo)) == 0 ? 1 : 0;
     }
   }
   auto on_gamma = [&](int64_t id) {
@@ -65,8 +78,8 @@ std::unique_ptr<Precond> build_spaces(std::shared_ptr<const System> sys, int nH,
   // coarse dofs: mesh nodes off Gamma with a basis function that is non-zero
   // at some free node, lexicographic order
   std::vector<uint8_t> live((size_t)nvert, 0);
-  for (size_t q = 0; q < pre->Pphi.size(); ++q)
-    if (pre->Pphi[q] != 0.0) live[pre->Pvert[q]] = 1;
+  for (size_t q = 0; q < in_star.size(); ++q)
+    if (in_star[q]) live[pre->Pvert[q]] = 1;
   pre->vert_coarse.assign((size_t)nvert, -1);
   for (int64_t id = 0; id < nvert; ++id)
     if (live[id] && !on_gamma(id)) {
@@ -75,15 +88,18 @@ std::unique_ptr<Precond> build_spaces(std::shared_ptr<const System> sys, int nH,
     }
   pre->m0 = (int64_t)pre->coarse_vertex.size() * nc;
 
-  // stars: bucket the free nodes by the 2^d mesh nodes of their element
+  // stars: bucket the free nodes by the mesh nodes whose basis function is
+  // positive at them (at most the 2^d of their element)
   std::vector<int64_t> cnt((size_t)nvert + 1, 0);
-  for (size_t q = 0; q < pre->Pvert.size(); ++q) ++cnt[pre->Pvert[q] + 1];
+  for (size_t q = 0; q < pre->Pvert.size(); ++q)
+    if (in_star[q]) ++cnt[pre->Pvert[q] + 1];
   for (int64_t id = 0; id < nvert; ++id) cnt[id + 1] += cnt[id];
   std::vector<int32_t> members((size_t)cnt[nvert]);
   {
     std::vector<int64_t> pos(cnt.begin(), cnt.end() - 1);
     for (int64_t f = 0; f < nf; ++f)
-      for (int b = 0; b < nv; ++b) members[pos[pre->Pvert[(size_t)f * nv + b]]++] = (int32_t)f;
+      for (int b = 0; b < nv; ++b)
+        if (in_star[(size_t)f * nv + b]) members[pos[pre->Pvert[(size_t)f * nv + b]]++] = (int32_t)f;
   }
   pre->star_ptr.push_back(0);
   for (int64_t id = 0; id < nvert; ++id) {

@@ -87,41 +87,61 @@ def test_truss_operator(orc):
         assert np.abs(r).max() <= 1e-12 * np.abs(np.diag(K)).max()
 
 
-def _elem_exact(xk, nH):
-    """Element index of coordinate xk by exact rational comparison with the
-    half-open boxes [k H, (k+1) H), the last one closed (Sec. 2.3)."""
-    q = Fraction(xk) * nH
-    k = int(q)  # floor for q >= 0
-    return min(k, nH - 1)
+def _in_support(xk, vk, nH):
+    """Exact rational test |x_k nH - v_k| < 1: the hat factor of mesh node v_k
+    is positive at x_k (Sec. 2.3)."""
+    return abs(Fraction(xk) * nH - vk) < 1
 
 
-@pytest.mark.parametrize("dim,nH,policy", [(2, 4, 0), (2, 3, 1), (3, 2, 0)])
-def test_star_membership_literal(orc, dim, nH, policy):
-    if dim == 2:
+def _grid(orc, n, lo, hi):
+    """Example 3.7 grid network with Dirichlet faces lo/hi (bit k: axis k)."""
+    x, e = W.grid_network(n)
+    return orc.Network.from_arrays(x, e, W.boundary_flags(x, lo, hi, 0.25 / n))
+
+
+_MEMBER_CASES = [("fiber", 2, 4, 0), ("fiber", 2, 3, 1), ("fiber", 3, 2, 0), ("grid", 2, 4, 0), ("grid", 2, 4, 1),
+                 ("grid_x", 2, 4, 0), ("grid", 2, 3, 0)]
+
+
+@pytest.mark.parametrize("kind,dim,nH,policy", _MEMBER_CASES)
+def test_star_membership(orc, kind, dim, nH, policy):
+    """Local space of mesh node y_v: the free nodes at which phi_v is positive
+    (the support of phi_v, Sec. 4.1 and Sec. 5), by exact rational arithmetic.
+    The grid networks put nodes on the faces of T_H (n = 8: every second grid
+    line is a mesh line for nH = 4; nH = 3 puts none there), where a node lies
+    only in the stars of the face's mesh nodes."""
+    if kind == "fiber" and dim == 2:
         net, lo, hi = small_net(orc), 1, 1
-    else:
+    elif kind == "fiber":
         net, lo, hi = small_net(orc, n=300, l=0.35, dim=3, lo=4, hi=4, eps=0.03), 4, 4
+    elif kind == "grid":
+        net, lo, hi = _grid(orc, 8, 3, 3), 3, 3
+    else:  # Dirichlet on x0 = 0, 1 only: free nodes on the faces x1 = 0 and x1 = 1
+        net, lo, hi = _grid(orc, 8, 1, 1), 1, 1
     x, _, _ = net.arrays()
     s = orc.System(net, 0)
     p = orc.Precond(s, nH, policy, lo, hi, factor=False)
     sp, sd, sv = p.stars()
     fn = s.free_nodes()
-    elems = np.array([[_elem_exact(x[f, k], nH) for k in range(dim)] for f in fn])
     expect = {}
     for vid in range((nH + 1) ** dim):
         v = [(vid // (nH + 1) ** k) % (nH + 1) for k in range(dim)]
         on_gamma = any(((lo >> k) & 1 and v[k] == 0) or ((hi >> k) & 1 and v[k] == nH) for k in range(dim))
         if policy == 1 and on_gamma:
             continue
-        # nodes in elements whose closure contains the mesh node y_v
-        mem = [i for i in range(len(fn)) if all(v[k] - 1 <= elems[i][k] <= v[k] for k in range(dim))]
+        mem = [i for i in range(len(fn)) if all(_in_support(x[fn[i], k], v[k], nH) for k in range(dim))]
         if mem:
             expect[vid] = mem
     assert list(sv) == sorted(expect)
     for j, vid in enumerate(sv):
         assert list(sd[sp[j]:sp[j + 1]]) == expect[vid]
     if policy == 0:
-        assert np.all(np.bincount(sd, minlength=s.n) == 2 ** dim)
+        # a node lies in 2 stars per axis where x_k nH is not an integer, else 1
+        mult = [int(np.prod([1 if (Fraction(x[f, k]) * nH).denominator == 1 else 2 for k in range(dim)]))
+                for f in fn]
+        assert np.array_equal(np.bincount(sd, minlength=s.n), mult)
+        if kind == "grid" and nH == 4:
+            assert min(mult) == 1 and max(mult) == 4
 
 
 def test_q1_reproduction_and_coarse_matrix(orc):
@@ -148,6 +168,57 @@ def test_q1_reproduction_and_coarse_matrix(orc):
     c = np.cos(np.arange(p.m0))
     vv = Pd @ c
     assert abs(c @ K0 @ c - vv @ K @ vv) <= 1e-11 * (vv @ K @ vv)
+
+
+def test_coarse_dofs_with_boundary_values(orc):
+    """Coarse dofs (Sec. 2.3): the mesh nodes off Gamma whose basis function is
+    positive at some free node. Checked by brute force, and through a bilinear
+    g that does not vanish on Gamma: the restricted coarse interpolant plus the
+    Gamma nodes' terms, sum_v g(y_v) phi_v(x) with phi_v written out from the
+    tensor hat, reproduces g at every free node."""
+    net = small_net(orc, lo=1, hi=0)
+    x, _, _ = net.arrays()
+    s = orc.System(net, 0)
+    nH = 4
+    p = orc.Precond(s, nH, 0, 1, 0)
+    fn = s.free_nodes()
+    xf = x[fn]
+    verts = [(a, b) for b in range(nH + 1) for a in range(nH + 1)]  # lexicographic, x fastest
+
+    def phi(v, z):
+        return np.maximum(0.0, 1 - np.abs(z[:, 0] * nH - v[0])) * np.maximum(0.0, 1 - np.abs(z[:, 1] * nH - v[1]))
+
+    expect = [a + b * (nH + 1) for (a, b) in verts if a != 0 and (phi((a, b), xf) > 0).any()]
+    cv = p.coarse_vertices()
+    assert list(cv) == expect and p.m0 == len(expect)
+
+    def g(z):
+        return 0.5 + z[:, 0] + 0.3 * z[:, 1] + 0.2 * z[:, 0] * z[:, 1]
+
+    y = np.stack([(cv % (nH + 1)) / nH, (cv // (nH + 1)) / nH], 1)
+    gam = sum(g(np.array([[0.0, b / nH]]))[0] * phi((0, b), xf) for b in range(nH + 1))
+    assert np.allclose(p.P_dense() @ g(y) + gam, g(xf), rtol=0, atol=1e-14)
+    assert np.abs(gam).max() > 0.1  # the Gamma terms matter
+
+
+def test_mesh_nodes_on_grid_nodes(orc):
+    """Grid n = 6 with nH = 12: every grid node is a mesh node, whose support
+    holds that node only; the mesh nodes between grid lines have no node in
+    their support and are dropped. So P = I, K_0 = K, every local space is one
+    node, and B = K^-1 + diag(K)^-1."""
+    n, nH = 6, 12
+    net = _grid(orc, n, 3, 3)
+    s = orc.System(net, 0)
+    p = orc.Precond(s, nH, 0, 3, 3)
+    assert p.m0 == (n - 1) ** 2 and p.nstars == (n - 1) ** 2
+    sp, sd, _ = p.stars()
+    assert np.array_equal(np.diff(sp), np.ones(p.nstars, dtype=np.int64))
+    assert np.array_equal(p.P_dense(), np.eye(s.n))
+    K = s.dense()
+    assert np.allclose(p.K0_dense(), K, rtol=0, atol=1e-12 * np.abs(K).max())
+    r = np.cos(np.arange(s.n))
+    ref = np.linalg.solve(K, r) + r / np.diag(K)
+    assert np.allclose(p.apply_B(r), ref, rtol=0, atol=1e-12 * np.abs(ref).max())
 
 
 def _dense_B(p, n):
@@ -223,18 +294,22 @@ def test_pcg_against_dense_direct_and_theory(orc):
     assert it2 == it and np.array_equal(u2, u)
 
 
-def test_single_element_two_eigenvalues(orc):
-    """nH = 1: one element, every local space holds all free dofs, so
-    BK = 2^d I + P_0 has two eigenvalues and PCG ends in two steps."""
-    net = small_net(orc)
+def test_single_element_one_step(orc):
+    """nH = 1 on a grid with Dirichlet on all of the boundary: every free node
+    lies strictly inside the one element, so each of the four local spaces is
+    the whole space and the coarse space is empty (all mesh nodes on Gamma):
+    BK = 4 I and PCG ends in one step with the exact solution."""
+    net = _grid(orc, 8, 3, 3)
     s = orc.System(net, 0)
-    p = orc.Precond(s, 1)
-    assert p.nstars == 4
+    p = orc.Precond(s, 1, 0, 3, 3)
+    assert p.nstars == 4 and p.m0 == 0
+    r = np.sin(np.arange(s.n))
+    K = s.dense()
+    assert np.allclose(p.apply_B(K @ r), 4 * r, rtol=0, atol=1e-12 * np.abs(r).max())
     f = W.rhs(s.n, 1, seed=2)[:, 0]
     u, it, info = p.pcg(f, rtol=1e-12)
-    assert it <= 2
-    K = s.dense()
-    assert np.linalg.norm(K @ u - f) <= 1e-11 * np.linalg.norm(f)
+    assert it == 1
+    assert np.linalg.norm(K @ u - f) <= 1e-12 * np.linalg.norm(f)
 
 
 @pytest.mark.slow
