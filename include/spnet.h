@@ -132,8 +132,10 @@ void sn_system_destroy(sn_system sys);
  * (half-open boxes, closed at the upper face of Omega). Coarse dofs: mesh nodes
  * not on Gamma whose Q1 basis function is non-zero at some free node, in
  * lexicographic order (x fastest), times ncomp. Local space of mesh node v: the
- * free nodes with v_k-1 <= e_k <= v_k for all k (the nodes of the patch U(y_v)),
- * empty ones dropped, in ascending mesh node order.
+ * free nodes at which its basis function is positive, |x_k nH - v_k| < 1 for all
+ * k (the support of phi_v, which Sec. 5 identifies with the patch U(y_v); a node
+ * on a face of T_H lies only in the stars of that face's mesh nodes), empty ones
+ * dropped, in ascending mesh node order.
  * dir_lo/dir_hi give Gamma as in sn_network_from_segments.
  */
 sn_status sn_precond_build(sn_system sys, int nH, int star_policy, int dir_lo, int dir_hi,
@@ -181,7 +183,8 @@ typedef struct {
                                 kept in LDS or cache), plus per position its dof index, the FP64
                                 gather of r and the slot write; see sn_engine_info for the split
                                 an engine runs */
-  int64_t sweep_bytes_sn;    /* the same with every star on the supernodal path */
+  int64_t sweep_bytes_sn;    /* the same with every star the supernodal layout
+                                holds on the supernodal path */
   int64_t spmv_bytes;        /* algorithmic bytes of one y = K x (values, columns, x, y) */
   int64_t sweep_flops;       /* 4 flops per structural non-zero of the minimum degree factors */
   double max_pivot_ratio;    /* max over stars and layouts of (largest / smallest Cholesky pivot),
@@ -302,9 +305,11 @@ sn_status sn_precond_engine_info(sn_precond pre, int k, sn_engine_info *info);
  * measured when the preconditioner first solves (the candidate that solves all
  * stars fastest) and then kept for every batch width, since the two kernels
  * round differently and a column's iterates must not depend on its batch.
- * n_sn >= 0 fixes it instead: the n_sn stars with the most positions (and
- * every star whose band exceeds 1024) run the supernodal kernel, the others
- * the band kernel; n_sn < 0 returns to measuring. Drops the preconditioner's
+ * n_sn >= 0 fixes it instead: of the n_sn stars with the most positions those
+ * the supernodal layout holds (16-bit local indices: fewer than 65536
+ * positions and update slots), and every star whose band exceeds 1024, run the
+ * supernodal kernel, the others the band kernel; n_sn < 0 returns to
+ * measuring. A star that fits neither layout fails the factorisation. Drops the preconditioner's
  * solve engines (the next solve creates them); engines a server already holds
  * keep their split until they are evicted. Errors: SN_EINVAL if not factored.
  */

@@ -897,6 +897,7 @@ struct DeviceState {
   DBuf<unsigned char> blob;
   DBuf<int64_t> st_blob;
   std::vector<uint32_t> h_idx, h_val, h_nu;  // per star: blob part bytes, u-slots
+  std::vector<uint8_t> h_sn_ok;               // per star: the supernodal layout holds it
   std::vector<int64_t> h_bytes_band, h_bytes_sn;  // per star: algorithmic bytes of one solve of one column
   // stars on the supernodal path besides those the band kernel cannot take:
   // measured when the first engine is created (or set by the caller) and then
@@ -1088,6 +1089,12 @@ void pack_stream(const std::vector<int32_t> &width, const std::vector<double> &v
 // One star's supernodal blob: header, level table, position records, 16-bit index lists
 // (padded to 16 bytes: the index part), then the values of the S_k in T
 // (padded to 16 bytes).
+// The supernodal layout indexes positions and update slots with 16 bits and
+// the values of a star with 31.
+bool sn_layout_fits(const SnFactor &F) {
+  return F.n < 65536 && F.nu < 65536 && (int64_t)F.S.size() < ((int64_t)1 << 31);
+}
+
 template <typename T>
 void pack_blob(const SnFactor &F, const std::vector<int32_t> &bpos, std::vector<unsigned char> &out,
                uint32_t &idx_bytes, uint32_t &val_bytes) {
@@ -1168,6 +1175,7 @@ void upload_stars(DeviceState &d, const Precond &pre, const HostFactors &hf, sn_
   d.h_idx.assign((size_t)ns, 0);
   d.h_val.assign((size_t)ns, 0);
   d.h_nu.assign((size_t)ns, 0);
+  d.h_sn_ok.assign((size_t)ns, 0);
   d.h_bytes_band.assign((size_t)ns, 0);
   d.h_bytes_sn.assign((size_t)ns, 0);
   int64_t tot = 0, nnz_md = 0, nnz_rcm = 0, env = 0, stored = 0, idx_tot = 0;
@@ -1199,22 +1207,31 @@ void upload_stars(DeviceState &d, const Precond &pre, const HostFactors &hf, sn_
       f_inv.push_back((T)finv[p]);
       b_inv.push_back((T)binv[p]);
     }
-    // supernodal blob; bpos maps its positions to the band positions (slots)
-    std::vector<int32_t> band_of((size_t)F.n), bpos((size_t)F.n);
-    for (int p = 0; p < F.n; ++p) band_of[F.perm[p]] = p;
-    for (int p = 0; p < F.n; ++p) bpos[p] = band_of[F.sn.perm[p]];
-    st_blob[s] = (int64_t)blob.size();
-    pack_blob<T>(F.sn, bpos, blob, d.h_idx[s], d.h_val[s]);
-    d.h_nu[s] = (uint32_t)F.sn.nu;
-    d.maxlev = std::max(d.maxlev, F.sn.nlev);
+    // supernodal blob, when the layout holds the star (else the star stays on
+    // the band path); bpos maps its positions to the band positions (slots)
     d.h_bytes_band[s] = 2 * F.nnz_rcm * sT + (int64_t)F.n * (4 + 8 + sT);
-    d.h_bytes_sn[s] = F.sn.nnz * sT + (int64_t)F.n * (4 + 8 + sT);
+    d.h_sn_ok[s] = sn_layout_fits(F.sn) ? 1 : 0;
+    if (q <= 0 && !d.h_sn_ok[s])
+      fail(SN_EINVAL, "star " + std::to_string(s) + " fits neither local-solve layout (band " +
+                          std::to_string(F.band) + ", " + std::to_string(F.sn.nu) + " supernodal updates)");
+    st_blob[s] = (int64_t)blob.size();
+    if (d.h_sn_ok[s]) {
+      std::vector<int32_t> band_of((size_t)F.n), bpos((size_t)F.n);
+      for (int p = 0; p < F.n; ++p) band_of[F.perm[p]] = p;
+      for (int p = 0; p < F.n; ++p) bpos[p] = band_of[F.sn.perm[p]];
+      pack_blob<T>(F.sn, bpos, blob, d.h_idx[s], d.h_val[s]);
+      d.h_nu[s] = (uint32_t)F.sn.nu;
+      d.maxlev = std::max(d.maxlev, F.sn.nlev);
+      d.h_bytes_sn[s] = F.sn.nnz * sT + (int64_t)F.n * (4 + 8 + sT);
+      stored += (int64_t)F.sn.S.size();
+      idx_tot += d.h_idx[s];
+    } else {
+      d.h_bytes_sn[s] = d.h_bytes_band[s];
+    }
     tot += F.n;
     nnz_md += F.sn.nnz;
     nnz_rcm += F.nnz_rcm;
     env += F.env;
-    stored += (int64_t)F.sn.S.size();
-    idx_tot += d.h_idx[s];
   }
   if (tot >= (int64_t)1 << 31 || (int64_t)std::max(f_val.size(), b_val.size()) >= (int64_t)1 << 31)
     fail(SN_EINVAL, "star streams too large for 32-bit offsets");
@@ -1916,10 +1933,11 @@ void load_block(Engine &e, double *dst, const double *src_dev, int k, hipStream_
   });
 }
 
-// Split of the stars between the two local-solve kernels: the `nsn` stars
-// with the longest band sweeps (2n dependent steps) and every star whose band
-// no window covers go to the supernodal path, the others to the band path
-// (narrow and wide windows in separate launches, longest first).
+// Split of the stars between the two local-solve kernels: of the `nsn` stars
+// with the longest band sweeps (2n dependent steps) those the supernodal
+// layout holds, and every star whose band no window covers, go to the
+// supernodal path, the others to the band path (narrow and wide windows in
+// separate launches, longest first).
 void plan_split(Engine &e, int64_t nsn) {
   DeviceState &d = *e.d;
   std::vector<int32_t> by_len((size_t)d.nstars);
@@ -1930,7 +1948,7 @@ void plan_split(Engine &e, int64_t nsn) {
   e.sweep_bytes = 0;
   for (int64_t i = 0; i < d.nstars; ++i) {
     const int32_t s = by_len[i];
-    if (d.h_q[s] == 0 || i < nsn) {
+    if (d.h_q[s] == 0 || (i < nsn && d.h_sn_ok[s])) {
       e.sn_list.push_back(s);
       e.sweep_bytes += d.h_bytes_sn[s];
     } else {

@@ -189,15 +189,15 @@ def test_server_rejects_oversized_requests(S, pres):
     assert ei.value.code == S.SN_EINVAL
 
 
-def test_failed_device_setup_fails_only_that_request(S, pres):
-    """A request whose factors cannot be laid out on the device (a star of
-    51,639 dofs sends more than 65,535 updates, beyond the 16-bit local
-    indices; the check runs on the host before any kernel) fails alone: the
-    requests queued beside it still complete, and the failed one reports its
-    error once."""
-    seg = W.fiber_segments(2, 6000, 0.06, seed=3)
-    net = S.Network.from_segments(2, seg, merge_tol=W.merge_tol(0.06), dir_lo=1, dir_hi=1)
-    bad = S.Precond(S.System(net), 2, S.STARS_ALL, 1, 1)
+def test_failed_factorisation_fails_only_that_request(S, pres):
+    """A request whose preconditioner cannot be factored (one element, nH = 1,
+    on a 301 x 301 grid: its local spaces hold 90,000 dofs, beyond the 65,535
+    positions a star may have; the check runs in the host factor worker before
+    any device work) fails alone: the requests queued beside it still
+    complete, and the failed one reports its error once."""
+    x, e = W.grid_network(300)
+    net = S.Network.from_arrays(x, e, W.boundary_flags(x, 1, 1, 1e-4))
+    bad = S.Precond(S.System(net), 1, S.STARS_ALL, 1, 1)
     srv = S.Server(max_columns=4)
     tb = srv.submit(bad, _rhs(bad, 1, 1))
     good = [srv.submit(pres["p2d_2k"], _rhs(pres["p2d_2k"], 2, 51)),
@@ -218,7 +218,7 @@ def test_failed_device_setup_fails_only_that_request(S, pres):
                     done[t] = r
         if failed is not None and len(done) == 2:
             break
-    assert failed is not None and failed.code == S.SN_EINVAL and "16-bit" in str(failed)
+    assert failed is not None and failed.code == S.SN_EINVAL and "65536 or more dofs" in str(failed)
     assert len(done) == 2
     for u, infos in done.values():
         assert all(x["converged"] and x["res_true"] <= 1.0001e-8 for x in infos)

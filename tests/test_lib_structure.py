@@ -184,3 +184,15 @@ def test_non_spd_star_is_reported(S):
     with pytest.raises(S.SpnetError) as ei:
         pre.factor(S.FP64)
     assert ei.value.code in (S.SN_ENOTSPD, S.SN_EDEVICE)
+
+
+def test_star_beyond_position_limit_is_reported(S):
+    """A local space with 65,536 or more dofs (nH = 1 on a 301 x 301 grid holds
+    90,000) is refused by the host factorisation with SN_EINVAL, before any
+    device work."""
+    x, e = W.grid_network(300)
+    net = S.Network.from_arrays(x, e, W.boundary_flags(x, 1, 1, 1e-4))
+    pre = S.Precond(S.System(net), 1, S.STARS_ALL, 1, 1)
+    with pytest.raises(S.SpnetError) as ei:
+        pre.factor(S.FP64)
+    assert ei.value.code == S.SN_EINVAL and "65536 or more dofs" in str(ei.value)
