@@ -239,6 +239,14 @@ sn_status sn_precond_set_star_split(sn_precond pre, int64_t n_sn) {
   });
 }
 
+sn_status sn_precond_set_coarse_launch(sn_precond pre, int mode) {
+  return guarded([&] {
+    REQUIRE(pre && pre->p->dev, "null argument or not factored");
+    REQUIRE(mode >= -1 && mode <= 5, "mode must be in -1..5");
+    spnet::device_set_coarse_launch(*pre->p, mode);
+  });
+}
+
 sn_status sn_precond_engine_info(sn_precond pre, int k, sn_engine_info *info) {
   return guarded([&] {
     REQUIRE(pre && info && pre->p->dev, "null argument or not factored");

@@ -741,6 +741,95 @@ __global__ __launch_bounds__(64 * kMmWaves) void k_coarse_mm(const TA *__restric
   }
 }
 
+// The same product with one wavefront per four rows, for launches that share
+// the device with the star sweeps (a one-wavefront workgroup takes whatever
+// wave slot a SIMD has left). The wavefront runs the eight column parts of the
+// workgroup form itself, QB parts at a time (their chunk loads in flight
+// together), keeps each part's accumulators apart, and adds them in the
+// workgroup form's order (part, then block) through lane shuffles, so every
+// output equals the workgroup form's bit for bit (a chunk past a part's end is
+// read in bounds and multiplied by zero, which leaves an accumulator as it is).
+template <typename TA, int KC>
+__global__ __launch_bounds__(64) void k_coarse_mm1(const TA *__restrict__ Kinv, int ld,
+                                                   const double *__restrict__ rH, double *cvec, int m0,
+                                                   const CgScalars *sc, int sel) {
+  static_assert(KC >= 1 && KC <= 16, "up to four groups of four columns");
+  constexpr int NG = (KC + 3) / 4;
+  constexpr int NP = kMmWaves / 2;  // column parts of the workgroup form
+  constexpr int QB = NG == 1 ? 4 : 2;
+  if (!any_selected<KC>(sc, sel, 0u)) return;
+  const int lane = threadIdx.x & 63;
+  const int i = lane & 3, y = (lane >> 2) & 3, k = lane >> 4;
+  const int row0 = blockIdx.x * 4;
+  const int chunks = ld / 64, cpw = (chunks + NP - 1) / NP;
+  const int col_l = 16 * y + 4 * k;
+  const TA *arow = Kinv + (size_t)(row0 + i) * ld + col_l;
+  double acc[NP][NG];
+#pragma unroll
+  for (int q = 0; q < NP; ++q)
+#pragma unroll
+    for (int g = 0; g < NG; ++g) acc[q][g] = 0.0;
+  for (int t = 0; t < cpw; ++t) {
+#pragma unroll
+    for (int q0 = 0; q0 < NP; q0 += QB) {
+      TA a[QB][4];
+      double b[QB][NG][4];
+#pragma unroll
+      for (int u = 0; u < QB; ++u) {
+        const int cq = (q0 + u) * cpw + t;
+        const int cc = min(cq, chunks - 1);
+        MmLoad<TA>::load(arow + (size_t)cc * 64, a[u]);
+        const int kb = cc * 64 + col_l;
+        if constexpr (KC == 1) {
+          const double2 p = *reinterpret_cast<const double2 *>(rH + kb);
+          const double2 r2 = *reinterpret_cast<const double2 *>(rH + kb + 2);
+          b[u][0][0] = p.x;
+          b[u][0][1] = p.y;
+          b[u][0][2] = r2.x;
+          b[u][0][3] = r2.y;
+        } else if constexpr (NG == 1) {
+#pragma unroll
+          for (int s = 0; s < 4; ++s) b[u][0][s] = rH[(size_t)(kb + s) * KC + min(i, KC - 1)];
+        } else {
+#pragma unroll
+          for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int g = 0; g < NG; g += 2) {
+              const double2 v = *reinterpret_cast<const double2 *>(rH + (size_t)(kb + s) * KC + NG * i + g);
+              b[u][g][s] = v.x;
+              b[u][g + 1][s] = v.y;
+            }
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int u = 0; u < QB; ++u) {
+        const double m = (q0 + u) * cpw + t < chunks ? 1.0 : 0.0;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const double av = (double)a[u][s] * m;
+#pragma unroll
+          for (int g = 0; g < NG; ++g)
+            acc[q0 + u][g] = __builtin_amdgcn_mfma_f64_4x4x4f64(av, b[u][g][s], acc[q0 + u][g], 0, 0, 0);
+        }
+      }
+    }
+  }
+  // lane 16 i' + 4 y' + j' holds block y', row i', column j' of each group;
+  // every lane forms the sum of its row and column over parts and blocks
+  const int ir = lane >> 4, jc = lane & 3;
+#pragma unroll
+  for (int g = 0; g < NG; ++g) {
+    double sum = 0.0;
+#pragma unroll
+    for (int q = 0; q < NP; ++q)
+#pragma unroll
+      for (int yb = 0; yb < 4; ++yb) sum += __shfl(acc[q][g], 16 * ir + 4 * yb + jc, 64);
+    const int col = NG * jc + g, grow = row0 + ir;
+    if (y == 0 && col < KC && grow < m0) cvec[(size_t)grow * KC + col] = sum;
+  }
+}
+
 // a.b partials per column
 template <int KC>
 __global__ __launch_bounds__(kBlock) void k_dot(const double *a, const double *b, int n, double *partials,
@@ -904,6 +993,7 @@ struct DeviceState {
   // shared by every engine, since the two kernels round differently and a
   // column's iterates must not depend on its batch; -1: not yet chosen
   int64_t split = -1;
+  int32_t coarse_launch = -1;  // fixed coarse kernel and placement (kernel + 2 placement), -1: measured
   // coarse
   // K_0^{-1}, symmetric, zero-padded to ld0 x ld0 (ld0 a multiple of 64): FP32 in the mixed form
   // unless the coarse factor's pivot ratio rules it out, else FP64
@@ -960,6 +1050,8 @@ struct Engine {
   int32_t star_cw = 1, star_nteam = 1, star_lcap = 0;
   double star_us = 0.0;
   bool coarse_first = false;  // coarse solve before the sweeps rather than beside them
+  bool coarse_w1 = false;     // one-wavefront coarse kernel (else 16-wavefront workgroups)
+  bool coarse_late = false;   // beside the sweeps: queued after them (else before)
   double b_us = 0.0;
   bool sc_dirty = false;         // host_sc changed since the last upload
   hipStream_t own = nullptr;     // the engine's stream (and graph capture)
@@ -1686,9 +1778,16 @@ void launch_B(Engine &e, const double *r, double *z, int sel, bool dot, hipStrea
         }
         HIPCHK(hipEventRecord(ev.first, cs));
       }
-      if (d.coarse32)
+      const unsigned g1 = (unsigned)(d.ld0 / 4);
+      if (d.coarse32 && e.coarse_w1)
+        hipLaunchKernelGGL((k_coarse_mm1<float, KC>), dim3(g1), dim3(64), 0, cs, d.Kinv32.p, (int)d.ld0, e.rH.p,
+                           e.c.p, (int)d.m0, e.sc.p, sel);
+      else if (d.coarse32)
         hipLaunchKernelGGL((k_coarse_mm<float, KC>), dim3(gb), dim3(64 * kMmWaves), 0, cs, d.Kinv32.p, (int)d.ld0,
                            e.rH.p, e.c.p, (int)d.m0, e.sc.p, sel);
+      else if (e.coarse_w1)
+        hipLaunchKernelGGL((k_coarse_mm1<double, KC>), dim3(g1), dim3(64), 0, cs, d.Kinv64.p, (int)d.ld0, e.rH.p,
+                           e.c.p, (int)d.m0, e.sc.p, sel);
       else
         hipLaunchKernelGGL((k_coarse_mm<double, KC>), dim3(gb), dim3(64 * kMmWaves), 0, cs, d.Kinv64.p, (int)d.ld0,
                            e.rH.p, e.c.p, (int)d.m0, e.sc.p, sel);
@@ -1707,11 +1806,18 @@ void launch_B(Engine &e, const double *r, double *z, int sel, bool dot, hipStrea
   } else if (d.m0 > 0) {
     // the coarse solve is independent of the local solves (the preconditioner
     // is additive): it runs on its own stream beside the star sweeps
+    // (queued before the sweeps, or after them so that the sweeps' long
+    // stars start first and the coarse wavefronts fill the SIMDs they leave)
     HIPCHK(hipEventRecord(e.fork2, s));
     HIPCHK(hipStreamWaitEvent(e.aux2, e.fork2, 0));
-    coarse(e.aux2);
+    if (e.coarse_late) {
+      launch_stars(e, r, sel, s);
+      coarse(e.aux2);
+    } else {
+      coarse(e.aux2);
+      launch_stars(e, r, sel, s);
+    }
     HIPCHK(hipEventRecord(e.join2, e.aux2));
-    launch_stars(e, r, sel, s);
     HIPCHK(hipStreamWaitEvent(s, e.join2, 0));
   } else {
     launch_stars(e, r, sel, s);
@@ -2115,14 +2221,25 @@ void tune_stars(Engine &e) {
     best = bb;
   }
   e.star_us = best;
-  // the coarse solve beside the sweeps (sharing the device) or before them; the
-  // second half of an iteration is timed: with the coarse solve first the
-  // restriction also runs the convergence test, beside it a one-block kernel
-  // does (no column is active here, so neither changes a column's state)
+  // the coarse kernel (16-wavefront workgroups or one wavefront per four rows:
+  // the same bits) and its placement: before the sweeps, or beside them on a
+  // second stream, queued before or after them. The second half of an
+  // iteration is timed: with the coarse solve first the restriction also runs
+  // the convergence test, beside it a one-block kernel does (no column is
+  // active here, so neither changes a column's state). A candidate must beat
+  // the best so far by 2%.
   if (d.m0 > 0) {
-    double tb[2] = {0.0, 0.0};
-    for (int order = 0; order < 2; ++order) {
-      e.coarse_first = order == 1;
+    auto set_mode = [&](int mode) {
+      e.coarse_w1 = (mode & 1) != 0;
+      e.coarse_first = mode / 2 == 0;
+      e.coarse_late = mode / 2 == 2;
+    };
+    double bbest = 1e30;
+    int bmode = 2;
+    const std::vector<int> modes =
+        d.coarse_launch >= 0 ? std::vector<int>{d.coarse_launch} : std::vector<int>{2, 0, 3, 1, 4, 5};
+    for (const int mode : modes) {
+      set_mode(mode);
       auto half = [&]() {
         if (!e.coarse_first)
           with_kc(e.kc, [&](auto K) {
@@ -2139,10 +2256,14 @@ void tune_stars(Engine &e) {
       HIPCHK(hipEventSynchronize(t1));
       float ms = 0.f;
       HIPCHK(hipEventElapsedTime(&ms, t0, t1));
-      tb[order] = 1e3 * ms / 3.0;
+      const double us = 1e3 * ms / 3.0;
+      if (us < 0.98 * bbest) {
+        bbest = us;
+        bmode = mode;
+      }
     }
-    e.coarse_first = tb[1] < 0.98 * tb[0];
-    e.b_us = std::min(tb[0], tb[1]);
+    set_mode(bmode);
+    e.b_us = bbest;
   }
   (void)hipEventDestroy(t0);
   (void)hipEventDestroy(t1);
@@ -2357,6 +2478,15 @@ void device_set_star_split(Precond &pre, int64_t n_sn) {
   d.split = n_sn < 0 ? -1 : std::min<int64_t>(n_sn, d.nstars);
 }
 
+void device_set_coarse_launch(Precond &pre, int mode) {
+  DeviceState &d = *pre.dev;
+  for (auto &e : d.solve_engine) {
+    if (e) wait_tick(*e);
+    e.reset();
+  }
+  d.coarse_launch = mode < 0 ? -1 : mode;
+}
+
 void device_engine_info(Precond &pre, int k, sn_engine_info *info) {
   Engine &e = solve_engine(pre, k);
   std::memset(info, 0, sizeof(*info));
@@ -2370,6 +2500,8 @@ void device_engine_info(Precond &pre, int k, sn_engine_info *info) {
   info->star_big_lds_bytes = e.sl[1].lds;
   info->star_global = e.sl[2].count;
   info->coarse_first = e.coarse_first ? 1 : 0;
+  info->coarse_kernel = e.coarse_w1 ? 1 : 0;
+  info->coarse_late = e.coarse_late ? 1 : 0;
   info->sweep_bytes = e.sweep_bytes;
   info->star_sweep_us = e.star_us;
   info->b_apply_us = e.b_us;
