@@ -559,10 +559,17 @@ typedef struct orc_sys {
   int64_t *rowptr;
   int32_t *col;
   double *val;
+  /* free rows of K against the dofs of the Dirichlet nodes (columns are
+   * node * ncomp + component): the lifting term of non-zero Dirichlet data */
+  int64_t nnz_d;
+  int64_t *rowptr_d;
+  int32_t *col_d;
+  double *val_d;
   int32_t *node_free;  /* node -> free node index or -1 */
   int32_t *free_node;  /* free node index -> node */
   int64_t n_free_nodes;
   double *x;           /* node coordinates */
+  double *mass;        /* (M 1)(x) at every node, eq. 2.1 */
 } orc_sys;
 
 typedef struct { int64_t r, c, seq; double v; } triple;
@@ -579,24 +586,36 @@ void orc_sys_free(orc_sys *s) {
   free(s->rowptr);
   free(s->col);
   free(s->val);
+  free(s->rowptr_d);
+  free(s->col_d);
+  free(s->val_d);
   free(s->node_free);
   free(s->free_node);
   free(s->x);
+  free(s->mass);
   free(s);
 }
 
-/*
- * model 0: heat conduction, (K v, v) = 1/2 sum_x sum_{y~x} gamma_xy (v(x)-v(y))^2/|x-y|
- *          (eq. 3.3). Each edge adds w (e_x - e_y)(e_x - e_y)^T with w = gamma/|e|.
- * model 1: tensile truss, n = d = 3 (eq. 3.4) plus an isotropic 1e-6/|e| term:
- *          each edge adds (1/|e|)(t t^T + 1e-6 I) in the blocks xx, yy (+) and xy, yx (-).
- * gamma may be NULL (all ones). Dirichlet rows and columns are removed (v in V).
- */
-int orc_sys_build(const orc_net *net, int model, const double *gamma, orc_sys **out) {
+typedef struct {
+  triple *T;
+  int64_t n, cap;
+} triples;
+
+static void tpush(triples *t, int64_t r, int64_t c, int64_t seq, double v) {
+  if (t->n == t->cap) {
+    t->cap = 2 * t->cap + 1024;
+    t->T = realloc(t->T, (size_t)t->cap * sizeof(triple));
+    if (!t->T) {
+      fprintf(stderr, "oracle: out of memory\n");
+      abort();
+    }
+  }
+  t->T[t->n++] = (triple){r, c, seq, v};
+}
+
+/* shared start of every model: free numbering, coordinates, lumped mass */
+static orc_sys *sys_begin(const orc_net *net, int nc) {
   int dim = net->dim;
-  int nc = model == 0 ? 1 : 3;
-  if (model != 0 && model != 1) return orc_fail(ORC_EINVAL, "model must be 0 or 1");
-  if (model == 1 && dim != 3) return orc_fail(ORC_EINVAL, "truss model needs dim 3");
   orc_sys *s = zalloc(1, sizeof(orc_sys));
   s->dim = dim;
   s->ncomp = nc;
@@ -612,17 +631,83 @@ int orc_sys_build(const orc_net *net, int model, const double *gamma, orc_sys **
       nf++;
     }
   }
-  if (nf == net->n_nodes) {
-    orc_sys_free(s);
-    return orc_fail(ORC_ESINGULAR, "no Dirichlet node: K is singular on V");
-  }
   s->n_free_nodes = nf;
   s->n = nf * nc;
   s->x = zalloc((size_t)(net->n_nodes ? net->n_nodes : 1) * dim, sizeof(double));
   memcpy(s->x, net->x, (size_t)net->n_nodes * dim * sizeof(double));
+  /* (M_x 1, 1) = 1/2 sum_{y~x} |x - y| (eq. 2.1) */
+  s->mass = zalloc((size_t)(net->n_nodes ? net->n_nodes : 1), sizeof(double));
+  for (int64_t k = 0; k < net->n_edges; k++) {
+    int32_t u = net->e[2 * k], v = net->e[2 * k + 1];
+    double len = sqrt(dist2(dim, net->x + (size_t)u * dim, net->x + (size_t)v * dim));
+    s->mass[u] += 0.5 * len;
+    s->mass[v] += 0.5 * len;
+  }
+  return s;
+}
 
-  int64_t cap = net->n_edges * 4 * nc * nc + 1, nt = 0;
-  triple *T = zalloc((size_t)cap, sizeof(triple));
+/* triples (free row, node dof column) -> K on the free dofs and the block of
+ * Dirichlet columns; equal positions summed in the order of their seq */
+static void sys_finish(orc_sys *s, triples *t) {
+  int nc = s->ncomp;
+  qsort(t->T, (size_t)t->n, sizeof(triple), cmp_triple);
+  s->rowptr = zalloc((size_t)s->n + 1, sizeof(int64_t));
+  s->rowptr_d = zalloc((size_t)s->n + 1, sizeof(int64_t));
+  s->col = zalloc((size_t)(t->n ? t->n : 1), sizeof(int32_t));
+  s->val = zalloc((size_t)(t->n ? t->n : 1), sizeof(double));
+  s->col_d = zalloc((size_t)(t->n ? t->n : 1), sizeof(int32_t));
+  s->val_d = zalloc((size_t)(t->n ? t->n : 1), sizeof(double));
+  int64_t nnz = 0, nnz_d = 0;
+  for (int64_t q = 0; q < t->n; q++) {
+    const triple *a = &t->T[q];
+    int same = q > 0 && a->r == t->T[q - 1].r && a->c == t->T[q - 1].c;
+    int32_t fc = s->node_free[a->c / nc];
+    if (fc >= 0) {
+      if (same) s->val[nnz - 1] += a->v;
+      else {
+        s->col[nnz] = (int32_t)((int64_t)fc * nc + a->c % nc);
+        s->val[nnz] = a->v;
+        s->rowptr[a->r + 1]++;
+        nnz++;
+      }
+    } else {
+      if (same) s->val_d[nnz_d - 1] += a->v;
+      else {
+        s->col_d[nnz_d] = (int32_t)a->c;
+        s->val_d[nnz_d] = a->v;
+        s->rowptr_d[a->r + 1]++;
+        nnz_d++;
+      }
+    }
+  }
+  for (int64_t i = 0; i < s->n; i++) {
+    s->rowptr[i + 1] += s->rowptr[i];
+    s->rowptr_d[i + 1] += s->rowptr_d[i];
+  }
+  s->nnz = nnz;
+  s->nnz_d = nnz_d;
+  free(t->T);
+  t->T = NULL;
+}
+
+/*
+ * model 0: heat conduction, (K v, v) = 1/2 sum_x sum_{y~x} gamma_xy (v(x)-v(y))^2/|x-y|
+ *          (eq. 3.3). Each edge adds w (e_x - e_y)(e_x - e_y)^T with w = gamma/|e|.
+ * model 1: tensile truss, n = d = 3 (eq. 3.4) plus an isotropic 1e-6/|e| term:
+ *          each edge adds (1/|e|)(t t^T + 1e-6 I) in the blocks xx, yy (+) and xy, yx (-).
+ * gamma may be NULL (all ones). Dirichlet rows and columns are removed (v in V).
+ */
+int orc_sys_build(const orc_net *net, int model, const double *gamma, orc_sys **out) {
+  int dim = net->dim;
+  int nc = model == 0 ? 1 : 3;
+  if (model != 0 && model != 1) return orc_fail(ORC_EINVAL, "model must be 0 or 1");
+  if (model == 1 && dim != 3) return orc_fail(ORC_EINVAL, "truss model needs dim 3");
+  orc_sys *s = sys_begin(net, nc);
+  if (s->n_free_nodes == net->n_nodes) {
+    orc_sys_free(s);
+    return orc_fail(ORC_ESINGULAR, "no Dirichlet node: K is singular on V");
+  }
+  triples t = {NULL, 0, 0};
   for (int64_t k = 0; k < net->n_edges; k++) {
     int32_t u = net->e[2 * k], v = net->e[2 * k + 1];
     const double *xu = net->x + (size_t)u * dim, *xv = net->x + (size_t)v * dim;
@@ -632,44 +717,189 @@ int orc_sys_build(const orc_net *net, int model, const double *gamma, orc_sys **
     if (model == 0) {
       blk[0] = g / len;
     } else {
-      double t[3];
-      for (int a = 0; a < 3; a++) t[a] = (xv[a] - xu[a]) / len;
+      double tv[3];
+      for (int a = 0; a < 3; a++) tv[a] = (xv[a] - xu[a]) / len;
       for (int a = 0; a < 3; a++)
         for (int b = 0; b < 3; b++)
-          blk[a * 3 + b] = g * (t[a] * t[b]) / len + (a == b ? 1e-6 / len : 0.0);
+          blk[a * 3 + b] = g * (tv[a] * tv[b]) / len + (a == b ? 1e-6 / len : 0.0);
     }
     int32_t fu = s->node_free[u], fv = s->node_free[v];
     for (int a = 0; a < nc; a++)
       for (int b = 0; b < nc; b++) {
         double w = blk[a * nc + b];
-        if (fu >= 0) T[nt++] = (triple){(int64_t)fu * nc + a, (int64_t)fu * nc + b, 4 * k, w};
-        if (fv >= 0) T[nt++] = (triple){(int64_t)fv * nc + a, (int64_t)fv * nc + b, 4 * k + 1, w};
-        if (fu >= 0 && fv >= 0) {
-          T[nt++] = (triple){(int64_t)fu * nc + a, (int64_t)fv * nc + b, 4 * k + 2, -w};
-          T[nt++] = (triple){(int64_t)fv * nc + a, (int64_t)fu * nc + b, 4 * k + 3, -w};
+        if (fu >= 0) {
+          tpush(&t, (int64_t)fu * nc + a, (int64_t)u * nc + b, 4 * k, w);
+          tpush(&t, (int64_t)fu * nc + a, (int64_t)v * nc + b, 4 * k + 2, -w);
+        }
+        if (fv >= 0) {
+          tpush(&t, (int64_t)fv * nc + a, (int64_t)v * nc + b, 4 * k + 1, w);
+          tpush(&t, (int64_t)fv * nc + a, (int64_t)u * nc + b, 4 * k + 3, -w);
         }
       }
   }
-  qsort(T, (size_t)nt, sizeof(triple), cmp_triple);
-  s->rowptr = zalloc((size_t)s->n + 1, sizeof(int64_t));
-  s->col = zalloc((size_t)(nt ? nt : 1), sizeof(int32_t));
-  s->val = zalloc((size_t)(nt ? nt : 1), sizeof(double));
-  int64_t nnz = 0;
-  for (int64_t q = 0; q < nt; q++) {
-    if (nnz > 0 && q > 0 && T[q].r == T[q - 1].r && T[q].c == T[q - 1].c) {
-      s->val[nnz - 1] += T[q].v;
-    } else {
-      s->col[nnz] = (int32_t)T[q].c;
-      s->val[nnz] = T[q].v;
-      s->rowptr[T[q].r + 1]++;
-      nnz++;
-    }
-  }
-  for (int64_t i = 0; i < s->n; i++) s->rowptr[i + 1] += s->rowptr[i];
-  s->nnz = nnz;
-  free(T);
+  sys_finish(s, &t);
   *out = s;
   return ORC_OK;
+}
+
+static void cross3(const double *a, const double *b, double *c) {
+  c[0] = a[1] * b[2] - a[2] * b[1];
+  c[1] = a[2] * b[0] - a[0] * b[2];
+  c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+/*
+ * Beam model (Example 3.3 with the constants of Sec. 6.3), n = ncomp
+ * components (n = 2: in-plane problem of a 2D network, Sec. 6.3.1; n = 3: 2D
+ * or 3D network). With d_xy = (x - y)/|x - y| and L_xy = |x - y|:
+ *
+ *   (K v, v) = sum_x 1/2 sum_{y~x} g1 ((v(x) - v(y)) . d_xy)^2 / L_xy          (eq. 3.4)
+ *            + sum_x sum_{y~x, z~x, y != z} sum_k g_xyz (L_xy + L_xz)/2 a_k^2     (eq. 3.5)
+ *   a_k = (v(y) - v(x)) . eta_y^k / L_xy + (v(z) - v(x)) . eta_z^k / L_xz,
+ *   g_xyz = g1 r_w^2 / (4 (L_xy + L_xz)^2).
+ *
+ * eta^1 (k = 1, only for n = 3) is one unit vector normal to both edges: e_3
+ * for a 2D network, the normalised d_xy x d_xz in 3D (any unit normal of
+ * d_xy when the edges are parallel). For k = 2 this build takes
+ * eta_y^2 = d_xy x eta^1 and eta_z^2 = eta^1 x d_xz: the printed
+ * eta_w^2 = d_xw x eta^1 for both edges would make a_2 twice the rotation of
+ * a rigid motion about eta^1, while with the second sign flipped a_2 is the
+ * change of the angle between the two edges (zero for rigid motions) and, on
+ * a straight fiber, its curvature. The pair sum runs over ordered pairs, as
+ * printed. Every term is a rank-one element w c c^T on the dofs of x, y, z.
+ */
+int orc_sys_build_beam(const orc_net *net, int ncomp, double gamma1, double r_w, orc_sys **out) {
+  int dim = net->dim;
+  if (ncomp != 2 && ncomp != 3) return orc_fail(ORC_EINVAL, "beam model needs 2 or 3 components");
+  if (ncomp == 2 && dim != 2) return orc_fail(ORC_EINVAL, "2 components need a 2D network");
+  if (!(gamma1 > 0.0) || !(r_w >= 0.0)) return orc_fail(ORC_EINVAL, "beam constants must be positive");
+  int nc = ncomp;
+  orc_sys *s = sys_begin(net, nc);
+  if (s->n_free_nodes == net->n_nodes) {
+    orc_sys_free(s);
+    return orc_fail(ORC_ESINGULAR, "no Dirichlet node: K is singular on V");
+  }
+  int64_t N = net->n_nodes, E = net->n_edges;
+  /* neighbours of every node, in edge order */
+  int64_t *nb0 = zalloc((size_t)N + 1, sizeof(int64_t));
+  for (int64_t k = 0; k < E; k++) {
+    nb0[net->e[2 * k] + 1]++;
+    nb0[net->e[2 * k + 1] + 1]++;
+  }
+  for (int64_t i = 0; i < N; i++) nb0[i + 1] += nb0[i];
+  int32_t *nb = zalloc((size_t)(nb0[N] ? nb0[N] : 1), sizeof(int32_t));
+  int64_t *fillp = zalloc((size_t)(N ? N : 1), sizeof(int64_t));
+  for (int64_t k = 0; k < E; k++) {
+    int32_t u = net->e[2 * k], v = net->e[2 * k + 1];
+    nb[nb0[u] + fillp[u]++] = v;
+    nb[nb0[v] + fillp[v]++] = u;
+  }
+  free(fillp);
+  triples t = {NULL, 0, 0};
+  int64_t seq = 0;
+  /* tensile part, eq. 3.4: each edge adds g1/L (d d^T) in the blocks uu, vv and minus it in uv, vu */
+  for (int64_t k = 0; k < E; k++) {
+    int32_t u = net->e[2 * k], v = net->e[2 * k + 1];
+    double d[3] = {0.0, 0.0, 0.0};
+    double len = sqrt(dist2(dim, net->x + (size_t)u * dim, net->x + (size_t)v * dim));
+    for (int a = 0; a < dim; a++) d[a] = (net->x[(size_t)u * dim + a] - net->x[(size_t)v * dim + a]) / len;
+    int32_t ends[2] = {u, v};
+    for (int p = 0; p < 2; p++) {
+      int32_t row_node = ends[p];
+      int32_t f = s->node_free[row_node];
+      if (f < 0) continue;
+      for (int q = 0; q < 2; q++) {
+        double sg = p == q ? 1.0 : -1.0;
+        for (int a = 0; a < nc; a++)
+          for (int b = 0; b < nc; b++)
+            tpush(&t, (int64_t)f * nc + a, (int64_t)ends[q] * nc + b, seq, sg * gamma1 * d[a] * d[b] / len);
+      }
+    }
+    seq++;
+  }
+  /* bending part, eq. 3.5 */
+  for (int64_t x = 0; x < N; x++) {
+    const double *px = net->x + (size_t)x * dim;
+    for (int64_t iy = nb0[x]; iy < nb0[x + 1]; iy++)
+      for (int64_t iz = nb0[x]; iz < nb0[x + 1]; iz++) {
+        int32_t y = nb[iy], z = nb[iz];
+        if (y == z) continue;
+        const double *py = net->x + (size_t)y * dim, *pz = net->x + (size_t)z * dim;
+        double dy[3] = {0.0, 0.0, 0.0}, dz[3] = {0.0, 0.0, 0.0};
+        double ly = sqrt(dist2(dim, px, py)), lz = sqrt(dist2(dim, px, pz));
+        for (int a = 0; a < dim; a++) {
+          dy[a] = (px[a] - py[a]) / ly;
+          dz[a] = (px[a] - pz[a]) / lz;
+        }
+        double e1[3] = {0.0, 0.0, 1.0};
+        if (dim == 3) {
+          cross3(dy, dz, e1);
+          double nn = sqrt(dot3(3, e1, e1));
+          if (nn > 1e-12) {
+            for (int a = 0; a < 3; a++) e1[a] /= nn;
+          } else {
+            /* parallel edges: the axis least aligned with d_xy, made normal to it */
+            int am = 0;
+            for (int a = 1; a < 3; a++)
+              if (fabs(dy[a]) < fabs(dy[am])) am = a;
+            double ax[3] = {0.0, 0.0, 0.0};
+            ax[am] = 1.0;
+            cross3(dy, ax, e1);
+            nn = sqrt(dot3(3, e1, e1));
+            for (int a = 0; a < 3; a++) e1[a] /= nn;
+          }
+        }
+        double ey[2][3], ez[2][3];
+        for (int a = 0; a < 3; a++) ey[0][a] = ez[0][a] = e1[a];
+        cross3(dy, e1, ey[1]);
+        cross3(e1, dz, ez[1]);
+        double w = gamma1 * r_w * r_w / (4.0 * (ly + lz) * (ly + lz)) * (ly + lz) / 2.0;
+        int32_t nodes[3] = {(int32_t)x, y, z};
+        for (int kk = (nc == 3 ? 0 : 1); kk < 2; kk++) {
+          /* c over (x, y, z) x components */
+          double c[3][3];
+          for (int a = 0; a < nc; a++) {
+            c[1][a] = ey[kk][a] / ly;
+            c[2][a] = ez[kk][a] / lz;
+            c[0][a] = -(c[1][a] + c[2][a]);
+          }
+          for (int p = 0; p < 3; p++) {
+            int32_t f = s->node_free[nodes[p]];
+            if (f < 0) continue;
+            for (int q = 0; q < 3; q++)
+              for (int a = 0; a < nc; a++)
+                for (int b = 0; b < nc; b++)
+                  tpush(&t, (int64_t)f * nc + a, (int64_t)nodes[q] * nc + b, seq, w * c[p][a] * c[q][b]);
+          }
+          seq++;
+        }
+      }
+  }
+  free(nb0);
+  free(nb);
+  sys_finish(s, &t);
+  *out = s;
+  return ORC_OK;
+}
+
+/* y = (K g) on the free rows, g given on every node (n_nodes x ncomp): the
+ * term a non-zero Dirichlet lifting moves to the right-hand side (Sec. 6.3) */
+void orc_sys_apply_full(const orc_sys *s, const double *g, double *y) {
+  int nc = s->ncomp;
+  for (int64_t i = 0; i < s->n; i++) {
+    double acc = 0.0;
+    for (int64_t q = s->rowptr[i]; q < s->rowptr[i + 1]; q++) {
+      int64_t fc = s->col[q] / nc, comp = s->col[q] % nc;
+      acc += s->val[q] * g[(int64_t)s->free_node[fc] * nc + comp];
+    }
+    for (int64_t q = s->rowptr_d[i]; q < s->rowptr_d[i + 1]; q++) acc += s->val_d[q] * g[s->col_d[q]];
+    y[i] = acc;
+  }
+}
+
+/* (M 1)(x) at every free node (eq. 2.1) */
+void orc_sys_mass(const orc_sys *s, double *m) {
+  for (int64_t f = 0; f < s->n_free_nodes; f++) m[f] = s->mass[s->free_node[f]];
 }
 
 void orc_sys_sizes(const orc_sys *s, int64_t *n, int64_t *nnz, int64_t *n_free_nodes) {

@@ -46,6 +46,9 @@ def lib():
         L.orc_net_get.argtypes = [P, P, P, P]
         L.orc_net_free.argtypes = [P]
         L.orc_sys_build.argtypes = [P, C.c_int, P, C.POINTER(P)]
+        L.orc_sys_build_beam.argtypes = [P, C.c_int, dbl, dbl, C.POINTER(P)]
+        L.orc_sys_apply_full.argtypes = [P, P, P]
+        L.orc_sys_mass.argtypes = [P, P]
         L.orc_sys_sizes.argtypes = [P, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)]
         L.orc_sys_get_csr.argtypes = [P, P, P, P]
         L.orc_sys_get_free_nodes.argtypes = [P, P]
@@ -132,20 +135,42 @@ class Network:
             self.h = None
 
 
-class System:
-    """K restricted to the free dofs (model 0: heat eq. 3.3, model 1: truss eq. 3.4)."""
+MODEL_HEAT, MODEL_TRUSS, MODEL_BEAM = 0, 1, 2
 
-    def __init__(self, net: Network, model: int = 0, gamma=None):
+
+class System:
+    """K restricted to the free dofs (model 0: heat eq. 3.3, model 1: truss eq.
+    3.4, model 2: beams, eq. 3.4 + eq. 3.5 with ncomp components, tensile
+    stiffness gamma1 and wire radius r_w as in Sec. 6.3)."""
+
+    def __init__(self, net: Network, model: int = 0, gamma=None, ncomp=3, gamma1=1.0, r_w=0.0):
         self.net = net
         h = P()
-        g = None if gamma is None else np.ascontiguousarray(gamma, dtype=np.float64)
-        _check(lib().orc_sys_build(net.h, model, _ptr(g), C.byref(h)))
+        if model == MODEL_BEAM:
+            _check(lib().orc_sys_build_beam(net.h, int(ncomp), float(gamma1), float(r_w), C.byref(h)))
+        else:
+            g = None if gamma is None else np.ascontiguousarray(gamma, dtype=np.float64)
+            _check(lib().orc_sys_build(net.h, model, _ptr(g), C.byref(h)))
         self.h = h
         n, nnz, nf = i64(), i64(), i64()
         lib().orc_sys_sizes(self.h, C.byref(n), C.byref(nnz), C.byref(nf))
         self.n, self.nnz, self.n_free_nodes = n.value, nnz.value, nf.value
         self.model = model
-        self.ncomp = 1 if model == 0 else 3
+        self.ncomp = {0: 1, 1: 3}.get(model, ncomp)
+
+    def apply_full(self, g):
+        """(K g) on the free rows for g on every node, shape (n_nodes, ncomp)
+        or flat: the lifting term of non-zero Dirichlet data (Sec. 6.3)."""
+        g = np.ascontiguousarray(g, dtype=np.float64).ravel()
+        y = np.zeros(self.n)
+        lib().orc_sys_apply_full(self.h, _ptr(g), _ptr(y))
+        return y
+
+    def mass(self):
+        """(M 1)(x) at every free node (eq. 2.1)."""
+        m = np.zeros(self.n_free_nodes)
+        lib().orc_sys_mass(self.h, _ptr(m))
+        return m
 
     def csr(self):
         rp = np.zeros(self.n + 1, dtype=np.int64)
