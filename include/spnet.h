@@ -110,10 +110,40 @@ void sn_network_destroy(sn_network net);
 #define SN_MODEL_HEAT 0  /* scalar: each edge adds gamma/|e| (e_x-e_y)(e_x-e_y)^T, eq. 3.3 */
 #define SN_MODEL_TRUSS 1 /* 3 dofs per node, dim 3: each edge adds (gamma/|e|) t t^T + (1e-6/|e|) I
                             in the xx, yy blocks and minus that in xy, yx (eq. 3.4) */
+#define SN_MODEL_BEAM 2  /* tensile eq. 3.4 plus bending eq. 3.5: see sn_assemble_beam */
 
 /* gamma: n_edges conductivities / stiffnesses, or NULL for all ones.
  * Errors: SN_ESINGULAR if the network has no Dirichlet node. */
 sn_status sn_assemble(sn_network net, int model, const double *gamma, sn_system *out);
+
+/*
+ * Beam model (Example 3.3 with the constants of Sec. 6.3) with ncomp = 2
+ * (in-plane displacements of a 2D network, Sec. 6.3.1) or 3 components (2D or
+ * 3D network). With d_xy = (x - y)/|x - y|:
+ *   tensile (eq. 3.4): each edge adds gamma1/|e| d d^T in the blocks xx, yy and
+ *     minus it in xy, yx;
+ *   bending (eq. 3.5): every centre x and ordered pair (y, z) of distinct
+ *     neighbours adds w a_k^2 per term k, w = gamma1 r_w^2 / (4 (|x-y| +
+ *     |x-z|)^2) * (|x-y| + |x-z|)/2, a_k = (v(y)-v(x)).eta_y^k/|x-y| +
+ *     (v(z)-v(x)).eta_z^k/|x-z|; eta^1 (k = 1, three components only) is a unit
+ *     normal of both edges (e_3 for a 2D network), eta_y^2 = d_xy x eta^1 and
+ *     eta_z^2 = eta^1 x d_xz (the orientation for which a_2 is the change of the
+ *     angle between the edges, so rigid motions carry no in-plane bending).
+ * gamma1 = A E of the wire, wire_radius = r_w. A straight fiber then bends
+ * like an Euler-Bernoulli beam of stiffness gamma1 r_w^2 / 8.
+ * Errors: SN_EINVAL (ncomp, constants, ncomp = 2 on a 3D network),
+ * SN_ESINGULAR if the network has no Dirichlet node.
+ */
+sn_status sn_assemble_beam(sn_network net, int ncomp, double gamma1, double wire_radius, sn_system *out);
+
+/* y (n_dofs) = the free rows of K applied to g given on every node
+ * (n_nodes x ncomp, node-major), Dirichlet nodes included: the term that a
+ * non-zero Dirichlet lifting moves to the right-hand side (for u-hat = u + g
+ * solve K u = f - y on V, Sec. 6.3). Host pointers. Errors: SN_EINVAL for a
+ * non-finite g. */
+sn_status sn_system_apply_full(sn_system sys, const double *g, double *y);
+/* (M 1)(x) = 1/2 sum_{y~x} |x - y| at every free node (eq. 2.1), n_free_nodes entries */
+sn_status sn_system_mass(sn_system sys, double *m);
 sn_status sn_system_info(sn_system sys, int64_t *n_dofs, int64_t *nnz, int *ncomp, int64_t *n_free_nodes);
 /* K in CSR over the free dofs: rowptr (n+1), col (nnz, ascending per row), val (nnz). */
 sn_status sn_system_export_csr(sn_system sys, int64_t *rowptr, int32_t *col, double *val);

@@ -102,6 +102,30 @@ sn_status sn_assemble(sn_network net, int model, const double *gamma, sn_system 
   });
 }
 
+sn_status sn_assemble_beam(sn_network net, int ncomp, double gamma1, double wire_radius, sn_system *out) {
+  return guarded([&] {
+    REQUIRE(net && out, "null argument");
+    auto sys = spnet::assemble_beam(net->p, ncomp, gamma1, wire_radius);
+    *out = new sn_system_s{sys};
+  });
+}
+
+sn_status sn_system_apply_full(sn_system sys, const double *g, double *y) {
+  return guarded([&] {
+    REQUIRE(sys && g && y, "null argument");
+    const int64_t nd = sys->p->net->n_nodes() * sys->p->ncomp;
+    for (int64_t i = 0; i < nd; ++i) REQUIRE(std::isfinite(g[i]), "non-finite value in g");
+    spnet::apply_full(*sys->p, g, y);
+  });
+}
+
+sn_status sn_system_mass(sn_system sys, double *m) {
+  return guarded([&] {
+    REQUIRE(sys && m, "null argument");
+    std::copy(sys->p->mass.begin(), sys->p->mass.end(), m);
+  });
+}
+
 sn_status sn_system_info(sn_system sys, int64_t *n_dofs, int64_t *nnz, int *ncomp, int64_t *n_free_nodes) {
   return guarded([&] {
     REQUIRE(sys, "null system");

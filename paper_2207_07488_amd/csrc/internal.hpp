@@ -37,6 +37,11 @@ struct System {
   std::vector<int64_t> rowptr;       // CSR over dofs
   std::vector<int32_t> col;
   std::vector<double> val;
+  // free rows against the dofs of Dirichlet nodes (columns node * ncomp + component)
+  std::vector<int64_t> rowptr_d;
+  std::vector<int32_t> col_d;
+  std::vector<double> val_d;
+  std::vector<double> mass;          // (M 1)(x) per free node, eq. 2.1
 };
 
 struct DeviceState;  // defined in device.hip
@@ -69,6 +74,8 @@ std::shared_ptr<Network> build_network_from_segments(int dim, int64_t nseg, cons
                                                      double merge_tol, int dir_lo, int dir_hi, double band);
 // assemble.cpp
 std::shared_ptr<System> assemble(std::shared_ptr<const Network> net, int model, const double *gamma);
+std::shared_ptr<System> assemble_beam(std::shared_ptr<const Network> net, int ncomp, double g1, double rw);
+void apply_full(const System &sys, const double *g, double *y);
 // spaces.cpp
 std::unique_ptr<Precond> build_spaces(std::shared_ptr<const System> sys, int nH, int policy, int dir_lo,
                                       int dir_hi);

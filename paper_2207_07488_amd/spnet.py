@@ -13,7 +13,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libspnet.so")
 
 SN_OK, SN_EINVAL, SN_ENOMEM, SN_EDEVICE, SN_ESINGULAR, SN_ENOTSPD, SN_ENOCONV, SN_EBUSY = 0, -1, -2, -3, -4, -5, -6, -7
-MODEL_HEAT, MODEL_TRUSS = 0, 1
+MODEL_HEAT, MODEL_TRUSS, MODEL_BEAM = 0, 1, 2
 STARS_ALL, STARS_FREE = 0, 1
 FP64, FP32_STARS, FP32_STARS_COARSE = 0, 1, 2
 
@@ -92,6 +92,9 @@ SIGNATURES = {
     "sn_network_export": (C.c_int, [_P, _P, _P, _P]),
     "sn_network_destroy": (None, [_P]),
     "sn_assemble": (C.c_int, [_P, C.c_int, _P, C.POINTER(_P)]),
+    "sn_assemble_beam": (C.c_int, [_P, C.c_int, _dbl, _dbl, C.POINTER(_P)]),
+    "sn_system_apply_full": (C.c_int, [_P, _P, _P]),
+    "sn_system_mass": (C.c_int, [_P, _P]),
     "sn_system_info": (C.c_int, [_P, C.POINTER(_i64), C.POINTER(_i64), C.POINTER(C.c_int), C.POINTER(_i64)]),
     "sn_system_export_csr": (C.c_int, [_P, _P, _P, _P]),
     "sn_system_free_nodes": (C.c_int, [_P, _P]),
@@ -201,12 +204,17 @@ class Network:
 
 
 class System:
-    """K on the free dofs: heat model (eq. 3.3) or truss model (eq. 3.4)."""
+    """K on the free dofs: heat model (eq. 3.3), truss model (eq. 3.4) or beam
+    model (eq. 3.4 + eq. 3.5 with ncomp components, tensile stiffness gamma1 and
+    wire radius r_w, Sec. 6.3)."""
 
-    def __init__(self, net: Network, model=MODEL_HEAT, gamma=None):
-        g = None if gamma is None else _np(gamma, np.float64)
+    def __init__(self, net: Network, model=MODEL_HEAT, gamma=None, ncomp=3, gamma1=1.0, r_w=0.0):
         h = _P()
-        _check(lib().sn_assemble(net.h, model, _ptr(g), C.byref(h)))
+        if model == MODEL_BEAM:
+            _check(lib().sn_assemble_beam(net.h, int(ncomp), float(gamma1), float(r_w), C.byref(h)))
+        else:
+            g = None if gamma is None else _np(gamma, np.float64)
+            _check(lib().sn_assemble(net.h, model, _ptr(g), C.byref(h)))
         self.h, self.net, self.model = h, net, model
         n, nnz, nc, nf = _i64(), _i64(), C.c_int(), _i64()
         _check(lib().sn_system_info(self.h, C.byref(n), C.byref(nnz), C.byref(nc), C.byref(nf)))
@@ -223,6 +231,22 @@ class System:
         f = np.zeros(self.n_free_nodes, dtype=np.int32)
         _check(lib().sn_system_free_nodes(self.h, _ptr(f)))
         return f
+
+    def apply_full(self, g):
+        """Free rows of K applied to g on every node ((n_nodes, ncomp) or flat):
+        the right-hand-side term of a non-zero Dirichlet lifting."""
+        g = _np(g, np.float64).ravel()
+        if g.size != self.net.n_nodes * self.ncomp:
+            raise ValueError("g needs n_nodes x ncomp values")
+        y = np.zeros(self.n)
+        _check(lib().sn_system_apply_full(self.h, _ptr(g), _ptr(y)))
+        return y
+
+    def mass(self):
+        """(M 1)(x) at every free node (eq. 2.1)."""
+        m = np.zeros(self.n_free_nodes)
+        _check(lib().sn_system_mass(self.h, _ptr(m)))
+        return m
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:

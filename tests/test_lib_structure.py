@@ -196,3 +196,56 @@ def test_star_beyond_position_limit_is_reported(S):
     with pytest.raises(S.SpnetError) as ei:
         pre.factor(S.FP64)
     assert ei.value.code == S.SN_EINVAL and "65536 or more dofs" in str(ei.value)
+
+
+# (dim, n_segments, length, contact_eps, dir_lo, dir_hi, nH, ncomp, seed)
+BEAM_CASES = {
+    "beam2d_n2": (2, 400, 0.15, 0.0, 1, 1, 4, 2, 7),
+    "beam2d_n3": (2, 400, 0.15, 0.0, 1, 1, 4, 3, 8),
+    "beam3d": (3, 800, 0.3, 0.03, 4, 4, 3, 3, 9),
+}
+
+
+@pytest.mark.parametrize("name", list(BEAM_CASES))
+def test_beam_structure_lifting_and_mass_vs_oracle(S, orc, name):
+    """The beam model (eq. 3.4 + eq. 3.5): CSR structure bit-exact against the
+    oracle, values to rounding; the lifting term and the lumped mass alike."""
+    dim, nseg, l, eps, lo, hi, nH, nc, seed = BEAM_CASES[name]
+    seg = W.fiber_segments(dim, nseg, l, seed=seed)
+    kw = dict(contact_eps=eps, merge_tol=W.merge_tol(l), dir_lo=lo, dir_hi=hi)
+    on, gn = orc.Network.from_segments(dim, seg, **kw), S.Network.from_segments(dim, seg, **kw)
+    bk = dict(ncomp=nc, gamma1=4.123e6, r_w=2.5e-3)
+    osys, gsys = orc.System(on, orc.MODEL_BEAM, **bk), S.System(gn, S.MODEL_BEAM, **bk)
+    (orp, oci, ov), (grp, gci, gv) = osys.csr(), gsys.csr()
+    assert np.array_equal(orp, grp) and np.array_equal(oci, gci)
+    assert np.abs(ov - gv).max() <= 1e-13 * np.abs(ov).max()
+    x, _, _ = on.arrays()
+    g = np.zeros((len(x), nc))
+    g[:, 0] = 0.2 * x[:, 0]
+    g[:, -1] += np.sin(5 * x[:, 1])
+    # sums of terms up to ~1e3 times larger than the result (stiff short edges):
+    # equal to the rounding of a different summation order
+    yo, yg = osys.apply_full(g), gsys.apply_full(g)
+    assert np.abs(yo - yg).max() <= 1e-11 * np.abs(yo).max()
+    assert np.abs(osys.mass() - gsys.mass()).max() <= 1e-15 * osys.mass().max()
+    opre = orc.Precond(osys, nH, 0, lo, hi, factor=False)
+    gpre = S.Precond(gsys, nH, 0, lo, hi)
+    for a, b in zip(opre.stars(), gpre.stars()):
+        assert np.array_equal(a, b)
+
+
+def test_beam_error_paths(S):
+    x, e = W.grid_network(4)
+    net = S.Network.from_arrays(x, e, W.boundary_flags(x, 1, 1, 1e-3))
+    for nc, g1, rw in ((4, 1.0, 0.1), (2, -1.0, 0.1), (2, 1.0, float("nan"))):
+        with pytest.raises(S.SpnetError) as ei:
+            S.System(net, S.MODEL_BEAM, ncomp=nc, gamma1=g1, r_w=rw)
+        assert ei.value.code == S.SN_EINVAL
+    sysm = S.System(net, S.MODEL_BEAM, ncomp=2, gamma1=1.0, r_w=0.1)
+    with pytest.raises(ValueError):
+        sysm.apply_full(np.zeros(3))
+    g = np.zeros((len(x), 2))
+    g[0, 0] = np.inf
+    with pytest.raises(S.SpnetError) as ei:
+        sysm.apply_full(g)
+    assert ei.value.code == S.SN_EINVAL
