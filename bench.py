@@ -9,8 +9,10 @@ A step is one full PCG solve (u0 = 0 to ||r|| <= 1e-8 ||f||) of one right-hand
 side already resident in HBM, iterations replayed from captured HIP graphs.
 Beside the headline: the mesh-size sweep, batched right-hand sides, the small
 2D network with 1,024 right-hand sides, the 3D fiber network (100,000
-segments), the 3D truss network with 16 right-hand sides, the serving mix, and
-the FP64 oracle timed on the host (one core and all cores). Prints one JSON
+segments), the 3D truss network with 16 right-hand sides, the heat experiment
+of Sec. 6.2 on the Example 3.7 grid, the in-plane structural problem of Sec.
+6.3.1 (beam model, lifted Dirichlet data), the serving mix, and the FP64
+oracle timed on the host (one core and all cores). Prints one JSON
 line; progress goes to stderr.
 """
 from __future__ import annotations
@@ -276,6 +278,69 @@ def c4_leg(S, W, torch, steps):
     return out
 
 
+def f1_leg(S, W, torch):
+    """The heat experiment of Sec. 6.2 on the GPU: the Example 3.7 grid with
+    (2^9 + 1)^2 nodes, f = M1, Dirichlet on all of the boundary, FP64 and mixed
+    solves at H^-1 = 4 .. 32 (the rates of Table 6.2 are pinned by the tests;
+    here: iterations and throughput)."""
+    x, e = W.grid_network(512)
+    net = S.Network.from_arrays(x, e, W.boundary_flags(x, 3, 3, 0.25 / 512))
+    sysm = S.System(net)
+    f = torch.from_numpy(sysm.mass()).cuda()
+    out = {"workload": "grid_513x513_f_M1", "dofs": sysm.n}
+    for nH in (4, 8, 16, 32):
+        row = {}
+        for name, prec in (("plain", S.FP64), ("mixed", S.FP32_STARS)):
+            pre = S.Precond(sysm, nH, S.STARS_ALL, 3, 3, precision=prec)
+            pre.solve(f, rtol=1e-8, use_graph=True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(3):
+                _, info = pre.solve(f, rtol=1e-8, use_graph=True)
+            torch.cuda.synchronize()
+            row[name] = {"solves_per_s": rate(3, time.perf_counter() - t0), "iterations": int(info[0]["iters"]),
+                         "res_true": info[0]["res_true"], "max_star_dofs": pre.factor_info()["max_star_dofs"]}
+            del pre
+        out[f"H=1/{nH}"] = row
+    return out
+
+
+def f2_leg(S, W, torch):
+    """The in-plane tensile problem of Sec. 6.3.1 on the 20,000-segment 2D
+    network: beam model (eq. 3.4 + eq. 3.5, steel wire of radius 2.5 mm,
+    gamma1 = A E), Gamma = {x_1 = 0 or 1}, u-hat = u + g with g = (0.2 x_1, 0),
+    f = -(K g); FP64 and mixed solves at H = 1/16 and 1/32. rate_est is the
+    mean residual reduction per iteration, (1e-8)^(1/iterations)."""
+    import numpy as np
+    p = W.PRESETS["fiber2d_20k"]
+    seg = W.fiber_segments(2, p["n_segments"], p["length"], p["seed"])
+    net = S.Network.from_segments(2, seg, merge_tol=W.merge_tol(p["length"]), dir_lo=1, dir_hi=1, band=W.BAND)
+    g1 = 3.141592653589793 * 2.5e-3 ** 2 * 210e9
+    sysm = S.System(net, S.MODEL_BEAM, ncomp=2, gamma1=g1, r_w=2.5e-3)
+    x, _, _ = net.arrays()
+    g = np.zeros((net.n_nodes, 2))
+    g[:, 0] = 0.2 * x[:, 0]
+    f = torch.from_numpy(-sysm.apply_full(g)).cuda()
+    out = {"workload": "struct2d_20k_tensile", "dofs": sysm.n, "nnz": sysm.nnz}
+    for nH in (16, 32):
+        row = {}
+        for name, prec in (("plain", S.FP64), ("mixed", S.FP32_STARS)):
+            pre = S.Precond(sysm, nH, S.STARS_ALL, 1, 1, precision=prec)
+            pre.solve(f, rtol=1e-8, max_iter=2000, use_graph=True, raise_on_noconv=False)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, info = pre.solve(f, rtol=1e-8, max_iter=2000, use_graph=True, raise_on_noconv=False)
+            torch.cuda.synchronize()
+            it = int(info[0]["iters"])
+            row[name] = {"solves_per_s": rate(1, time.perf_counter() - t0), "iterations": it,
+                         "converged": bool(info[0]["converged"]), "res_true": info[0]["res_true"],
+                         "rate_est": round(1e-8 ** (1.0 / max(it, 1)), 3),
+                         "star_precision": pre.factor_info()["star_precision"]}
+            del pre
+        out[f"H=1/{nH}"] = row
+    return out
+
+
 def cpu_oracle_leg(O, W, seg, tol, preset, nH, f_host, rtol, threads):
     """The FP64 oracle on the host: one solve on one core, and independent
     solves (other right-hand sides of the same network) on `threads` cores at
@@ -476,9 +541,9 @@ def main():
     }
 
     if not args.no_configs:
-        for name, leg in (("c1", c1_leg), ("c3", c3_leg), ("c4", c4_leg)):
+        for name, leg in (("c1", c1_leg), ("c3", c3_leg), ("c4", c4_leg), ("f1", f1_leg), ("f2", f2_leg)):
             try:
-                out[name] = leg(S, W, torch, args.steps)
+                out[name] = leg(S, W, torch, args.steps) if name[0] == "c" else leg(S, W, torch)
             except Exception as ex:  # report, keep the other legs
                 out[name] = {"error": str(ex)}
             log(f"{name} leg done")
