@@ -13,7 +13,10 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SO = os.path.join(_HERE, "liboracle.so")
+# ORACLE_SANITIZE=1 builds and loads an AddressSanitizer / UndefinedBehaviorSanitizer
+# variant (run with LD_PRELOAD=$(gcc -print-file-name=libasan.so))
+_SAN = os.environ.get("ORACLE_SANITIZE") == "1"
+_SO = os.path.join(_HERE, "liboracle_san.so" if _SAN else "liboracle.so")
 _SRC = os.path.join(_HERE, "oracle.c")
 
 i64, i32, dbl, u8 = C.c_int64, C.c_int32, C.c_double, C.c_uint8
@@ -24,7 +27,9 @@ def build(force: bool = False) -> str:
     """Compile oracle.c with gcc (plain C11, -ffp-contract=off)."""
     if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
         tmp = _SO + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-ffp-contract=off", "-fPIC", "-shared",
+        san = ["-fsanitize=address,undefined", "-fno-omit-frame-pointer", "-fno-sanitize-recover=undefined"] if _SAN \
+            else []
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-ffp-contract=off", "-fPIC", "-shared", *san,
                                "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _SO)
     return _SO

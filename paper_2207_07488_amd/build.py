@@ -81,5 +81,39 @@ def build(verbose: bool = False, force: bool = True) -> str:
     return LIB
 
 
+SAN_LIB = os.path.join(HERE, "libspnet_san.so")
+SAN_FLAGS = ["-fsanitize=address,undefined", "-fno-omit-frame-pointer", "-fno-sanitize-recover=undefined"]
+
+
+def build_sanitized(verbose: bool = False) -> str:
+    """libspnet_san.so: the host sources with AddressSanitizer and
+    UndefinedBehaviorSanitizer (g++), linked with the device objects of the
+    normal build (built first if missing) and gcc's sanitizer runtimes. Load it
+    with SPNET_LIB=<path> and LD_PRELOAD=$(gcc -print-file-name=libasan.so);
+    host code only (network, assembly, spaces, factorisation, ABI, server)."""
+    dev_objs = [os.path.join(BUILD, s + ".o") for s in DEVICE_SOURCES]
+    dev_objs += [os.path.join(BUILD, f"star_{t}_{kc}.o") for t, kc in STAR_VARIANTS]
+    if not all(os.path.exists(o) for o in dev_objs):
+        build(verbose=verbose, force=False)
+    san = os.path.join(BUILD, "san")
+    os.makedirs(san, exist_ok=True)
+    jobs, objs = [], []
+    for src in HOST_SOURCES:
+        obj = os.path.join(san, src + ".o")
+        objs.append(obj)
+        jobs.append(["g++", *HOST_FLAGS, *SAN_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
+    with ThreadPoolExecutor(max_workers=min(int(os.environ.get("MAX_JOBS", "8")), len(jobs))) as ex:
+        list(ex.map(_run, jobs))
+    tmp = SAN_LIB + ".tmp"
+    _run([HIPCC, "-shared", "--offload-arch=gfx950", "-o", tmp, *objs, *dev_objs, "-lpthread", "-lasan", "-lubsan"])
+    os.replace(tmp, SAN_LIB)
+    if verbose:
+        print("built", SAN_LIB)
+    return SAN_LIB
+
+
 if __name__ == "__main__":
-    build(verbose=True, force="--incremental" not in sys.argv)
+    if "--sanitize" in sys.argv:
+        build_sanitized(verbose=True)
+    else:
+        build(verbose=True, force="--incremental" not in sys.argv)

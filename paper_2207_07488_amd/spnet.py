@@ -10,7 +10,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libspnet.so")
+# SPNET_LIB selects another build of the library (the sanitizer build of build.py)
+LIB_PATH = os.environ.get("SPNET_LIB") or os.path.join(_HERE, "libspnet.so")
 
 SN_OK, SN_EINVAL, SN_ENOMEM, SN_EDEVICE, SN_ESINGULAR, SN_ENOTSPD, SN_ENOCONV, SN_EBUSY = 0, -1, -2, -3, -4, -5, -6, -7
 MODEL_HEAT, MODEL_TRUSS, MODEL_BEAM = 0, 1, 2
