@@ -323,7 +323,8 @@ typedef struct {
   int32_t coarse_first;  /* 1: the coarse solve runs before the local solves (and its restriction
                             also runs the convergence test), 0: beside them on a second stream */
   int32_t coarse_kernel; /* 0: the coarse product in 16-wavefront workgroups of 8 rows, 1: one
-                            wavefront per 4 rows (the same results bit for bit) */
+                            wavefront per 4 rows (the same results bit for bit), 2: the packed
+                            symmetric kernel */
   int32_t coarse_late;   /* beside the local solves: 1 queued after them, 0 before */
   int64_t sweep_bytes;   /* algorithmic bytes of one application of the local solves to one column
                             with this split (see sn_factor_info.sweep_bytes) */
@@ -350,13 +351,17 @@ sn_status sn_precond_set_star_split(sn_precond pre, int64_t n_sn);
 
 /*
  * The coarse kernel and its placement beside the local solves (the product
- * c = K_0^-1 r_H, Sec. 4.1). By default both are measured when an engine is
- * created. mode = kernel + 2 placement fixes them instead: kernel 0 runs
+ * c = K_0^-1 r_H, Sec. 4.1). By default the packed symmetric kernel runs and
+ * its placement is measured when an engine is created. mode = kernel +
+ * 2 placement fixes a dense kernel and its placement instead: kernel 0 runs
  * 16-wavefront workgroups of 8 rows, 1 one wavefront per 4 rows (every output
  * the same bit for bit); placement 0 runs the coarse solve before the local
  * solves, 1 beside them on a second stream queued before them, 2 queued after
- * them. mode = -1 returns to measuring. Drops the preconditioner's solve
- * engines. Errors: SN_EINVAL if not factored or mode outside -1..5.
+ * them. mode = 6 + placement runs the packed symmetric kernel (the upper
+ * triangle in 64 x 64 tiles, half the bytes; it rounds differently from the
+ * dense kernels, so it is chosen per preconditioner, never per batch width).
+ * mode = -1 returns to measuring. Drops the preconditioner's solve engines.
+ * Errors: SN_EINVAL if not factored or mode outside -1..8.
  */
 sn_status sn_precond_set_coarse_launch(sn_precond pre, int mode);
 

@@ -266,7 +266,7 @@ sn_status sn_precond_set_star_split(sn_precond pre, int64_t n_sn) {
 sn_status sn_precond_set_coarse_launch(sn_precond pre, int mode) {
   return guarded([&] {
     REQUIRE(pre && pre->p->dev, "null argument or not factored");
-    REQUIRE(mode >= -1 && mode <= 5, "mode must be in -1..5");
+    REQUIRE(mode >= -1 && mode <= 8, "mode must be in -1..8");
     spnet::device_set_coarse_launch(*pre->p, mode);
   });
 }

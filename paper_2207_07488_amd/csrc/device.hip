@@ -830,6 +830,123 @@ __global__ __launch_bounds__(64) void k_coarse_mm1(const TA *__restrict__ Kinv, 
   }
 }
 
+// The product with the symmetric inverse stored once: the upper triangle in
+// 64 x 64 tiles (I <= J), each tile in 16 strips of 4 rows, strip p holding for
+// lane l = 16 k + 4 y + i the four values of row 4 p + i, columns
+// 16 y + 4 k .. + 3 (one 16- or 32-byte load per lane, a whole strip per
+// load instruction). One wavefront per tile computes
+//   A_IJ r_J   (the strip's rows; the same MFMA operands as k_coarse_mm)
+//   A_IJ^T r_I (I < J: the values moved to lane 16 i + 4 y + k, which makes
+//               them the A operand of the transposed 4 x 4 products)
+// and writes them as the (I, J) and (J, I) blocks of 64 x KC partial sums;
+// k_coarse_fold adds the blocks of each row in order. Every column is computed
+// by the same instructions whatever KC is.
+constexpr int kSymTile = 64 * 64;
+
+template <typename TA, int KC>
+__global__ __launch_bounds__(64) void k_coarse_sym(const TA *__restrict__ Ks, const int2 *__restrict__ tiles, int T,
+                                                   const double *__restrict__ rH, double *part,
+                                                   const CgScalars *sc, int sel) {
+  static_assert(KC >= 1 && KC <= 16, "up to four groups of four columns");
+  constexpr int NG = (KC + 3) / 4;
+  if (!any_selected<KC>(sc, sel, 0u)) return;
+  const int lane = threadIdx.x & 63;
+  const int i = lane & 3, y = (lane >> 2) & 3, k = lane >> 4;
+  const int2 t = tiles[blockIdx.x];
+  const int I = t.x, J = t.y;
+  const TA *tp = Ks + (size_t)blockIdx.x * kSymTile + lane * 4;
+  auto col_of = [&](int j, int g) { return KC == 1 ? 0 : (NG == 1 ? min(j, KC - 1) : NG * j + g); };
+  // B operand of the direct product: r_J at rows 16 y + 4 k + s
+  double bn[4][NG];
+#pragma unroll
+  for (int s = 0; s < 4; ++s)
+#pragma unroll
+    for (int g = 0; g < NG; ++g) bn[s][g] = rH[(size_t)(64 * J + 16 * y + 4 * k + s) * KC + col_of(i, g)];
+  const int src = 16 * i + 4 * y + k;  // lane whose value is this lane's transposed operand
+  const int ir = lane >> 4, jc = lane & 3;
+  double acc_t[4][NG];
+#pragma unroll
+  for (int s = 0; s < 4; ++s)
+#pragma unroll
+    for (int g = 0; g < NG; ++g) acc_t[s][g] = 0.0;
+  double *pdir = part + ((size_t)I * T + J) * 64 * KC;
+  // the whole tile is loaded before the first product (one wavefront per
+  // tile and about two tiles per SIMD: the loads are the parallelism)
+  constexpr int H = (NG >= 3) ? 2 : 1;  // halves for the widest batches (registers)
+#pragma unroll 1
+  for (int h = 0; h < H; ++h) {
+    constexpr int QN = 16 / H;
+    TA a[QN][4];
+    double bt[QN][NG];
+#pragma unroll
+    for (int q = 0; q < QN; ++q) {
+      MmLoad<TA>::load(tp + (size_t)(QN * h + q) * 256, a[q]);
+#pragma unroll
+      for (int g = 0; g < NG; ++g) bt[q][g] = rH[(size_t)(64 * I + 4 * (QN * h + q) + k) * KC + col_of(i, g)];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int q = 0; q < QN; ++q) {
+      const int p = QN * h + q;
+      double an[NG];
+#pragma unroll
+      for (int g = 0; g < NG; ++g) an[g] = 0.0;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const double av = (double)a[q][s];
+#pragma unroll
+        for (int g = 0; g < NG; ++g) an[g] = __builtin_amdgcn_mfma_f64_4x4x4f64(av, bn[s][g], an[g], 0, 0, 0);
+      }
+      // rows 4 p + ir: the four blocks added in order
+#pragma unroll
+      for (int g = 0; g < NG; ++g) {
+        double sum = 0.0;
+#pragma unroll
+        for (int yb = 0; yb < 4; ++yb) sum += __shfl(an[g], 16 * ir + 4 * yb + jc, 64);
+        const int col = NG * jc + g;
+        if (y == 0 && col < KC) pdir[(size_t)(4 * p + ir) * KC + col] = sum;
+      }
+      if (I != J) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const double at = __shfl((double)a[q][s], src, 64);
+#pragma unroll
+          for (int g = 0; g < NG; ++g)
+            acc_t[s][g] = __builtin_amdgcn_mfma_f64_4x4x4f64(at, bt[q][g], acc_t[s][g], 0, 0, 0);
+        }
+      }
+    }
+  }
+  if (I != J) {
+    // lane 16 i' + 4 y' + j holds rows 16 y' + 4 i' + s of the (J, I) block
+    double *ptr = part + ((size_t)J * T + I) * 64 * KC;
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int g = 0; g < NG; ++g) {
+        const int col = NG * jc + g;
+        if (col < KC) ptr[(size_t)(16 * y + 4 * ir + s) * KC + col] = acc_t[s][g];
+      }
+  }
+}
+
+// c (rows below m0) = the sum of the T partial blocks of each block row: one
+// wavefront per output, lane l adding blocks l, l + 64, ... in turn, then the
+// wavefront's fixed reduction tree (the same order for every KC)
+template <int KC>
+__global__ __launch_bounds__(kBlock) void k_coarse_fold(const double *__restrict__ part, int T, double *cvec, int m0,
+                                                        const CgScalars *sc, int sel) {
+  if (!any_selected<KC>(sc, sel, 0u)) return;
+  const int w = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (w >= m0 * KC) return;
+  const int row = w / KC, col = w % KC, R = row >> 6, r = row & 63;
+  const double *pp = part + ((size_t)R * T * 64 + r) * KC + col;
+  double v = 0.0;
+  for (int C = lane; C < T; C += 64) v += pp[(size_t)C * 64 * KC];
+  v = wave_sum(v);
+  if (lane == 0) cvec[(size_t)row * KC + col] = v;
+}
+
 // a.b partials per column
 template <int KC>
 __global__ __launch_bounds__(kBlock) void k_dot(const double *a, const double *b, int n, double *partials,
@@ -999,6 +1116,11 @@ struct DeviceState {
   // unless the coarse factor's pivot ratio rules it out, else FP64
   DBuf<double> Kinv64, PTw, Pw;
   DBuf<float> Kinv32;
+  // the same inverse stored once, in 64 x 64 tiles of its upper triangle
+  DBuf<double> Ksym64;
+  DBuf<float> Ksym32;
+  DBuf<int2> sym_tiles;  // (I, J) of every tile
+  int32_t sym_T = 0;     // ld0 / 64
   int64_t ld0 = 0;
   bool coarse32 = false;
   DBuf<int32_t> PTptr, PTdof, Pc;
@@ -1024,6 +1146,7 @@ struct Engine {
   DeviceState *d = nullptr;
   int kc = 1;
   DBuf<double> u, r, p, q, z, f, rH, c, partials, partials2;
+  DBuf<double> cpart;  // 64 x KC partial blocks of the packed coarse product (T x T)
   DBuf<CgScalars> sc;
   DBuf<float> slots32;
   DBuf<double> slots64;
@@ -1051,6 +1174,7 @@ struct Engine {
   double star_us = 0.0;
   bool coarse_first = false;  // coarse solve before the sweeps rather than beside them
   bool coarse_w1 = false;     // one-wavefront coarse kernel (else 16-wavefront workgroups)
+  bool coarse_sym = false;    // the packed symmetric coarse kernel (fixed per preconditioner)
   bool coarse_late = false;   // beside the sweeps: queued after them (else before)
   double b_us = 0.0;
   bool sc_dirty = false;         // host_sc changed since the last upload
@@ -1520,6 +1644,37 @@ void device_setup(Precond &pre, const HostFactors &hf, int precision) {
         for (int64_t j = 0; j < m0; ++j) A[(size_t)(i * ld + j)] = sym(i, j);
       d->Kinv64.upload(A);
     }
+    // tiles (I <= J) of the upper triangle: strip p, lane l = 16 k + 4 y + i,
+    // value s is row 4 p + i, column 16 y + 4 k + s of the tile
+    {
+      const int64_t T = ld / 64;
+      d->sym_T = (int32_t)T;
+      std::vector<int2> tiles;
+      for (int64_t I = 0; I < T; ++I)
+        for (int64_t J = I; J < T; ++J) tiles.push_back(make_int2((int)I, (int)J));
+      auto fill_tiles = [&](auto *out) {
+        for (size_t q = 0; q < tiles.size(); ++q)
+          for (int p = 0; p < 16; ++p)
+            for (int l = 0; l < 64; ++l)
+              for (int sv = 0; sv < 4; ++sv) {
+                const int ii = l & 3, yy = (l >> 2) & 3, kk = l >> 4;
+                const int64_t row = 64 * (int64_t)tiles[q].x + 4 * p + ii;
+                const int64_t col = 64 * (int64_t)tiles[q].y + 16 * yy + 4 * kk + sv;
+                const double v = row < m0 && col < m0 ? sym(row, col) : 0.0;
+                out[q * kSymTile + (size_t)p * 256 + (size_t)l * 4 + sv] = (std::remove_pointer_t<decltype(out)>)v;
+              }
+      };
+      if (d->coarse32) {
+        std::vector<float> A(tiles.size() * kSymTile);
+        fill_tiles(A.data());
+        d->Ksym32.upload(A);
+      } else {
+        std::vector<double> A(tiles.size() * kSymTile);
+        fill_tiles(A.data());
+        d->Ksym64.upload(A);
+      }
+      d->sym_tiles.upload(tiles);
+    }
     // P per dof (npad x nv) and P^T as CSR over coarse dofs
     std::vector<int32_t> Pc((size_t)npad * nv, -1);
     std::vector<double> Pw((size_t)npad * nv, 0.0);
@@ -1563,13 +1718,14 @@ void device_setup(Precond &pre, const HostFactors &hf, int precision) {
                        d->b_hdr.bytes() + d->f_inv32.bytes() + d->b_inv32.bytes() + d->f_val32.bytes() +
                        d->b_val32.bytes() + d->f_inv64.bytes() + d->b_inv64.bytes() + d->f_val64.bytes() +
                        d->b_val64.bytes() + d->blob.bytes() + d->st_blob.bytes() + d->Kinv64.bytes() +
-                       d->Kinv32.bytes() + d->Pc.bytes() + d->Pw.bytes() + d->PTptr.bytes() + d->PTdof.bytes() +
+                       d->Kinv32.bytes() + d->Ksym64.bytes() + d->Ksym32.bytes() + d->sym_tiles.bytes() +
+                       d->Pc.bytes() + d->Pw.bytes() + d->PTptr.bytes() + d->PTdof.bytes() +
                        d->PTw.bytes());
   const int64_t nnz = (int64_t)sys.col.size();
   fi.spmv_bytes = nnz * (8 + 4 + 8) + n * 8;
   fi.max_pivot_ratio = max_ratio;
   fi.star_precision = precision;
-  fi.coarse_bytes = (int64_t)(d->Kinv64.bytes() + d->Kinv32.bytes());
+  fi.coarse_bytes = (int64_t)(d->Kinv64.bytes() + d->Kinv32.bytes() + d->Ksym64.bytes() + d->Ksym32.bytes());
   fi.coarse_precision = d->coarse32 ? SN_PREC_FP32_STARS_COARSE : SN_PREC_FP64;
   fi.coarse_pivot_ratio = hf.coarse_pivot_ratio;
   fi.device_bytes = d->bytes;
@@ -1779,7 +1935,17 @@ void launch_B(Engine &e, const double *r, double *z, int sel, bool dot, hipStrea
         HIPCHK(hipEventRecord(ev.first, cs));
       }
       const unsigned g1 = (unsigned)(d.ld0 / 4);
-      if (d.coarse32 && e.coarse_w1)
+      const unsigned gs = (unsigned)((int64_t)d.sym_T * (d.sym_T + 1) / 2);
+      if (e.coarse_sym) {
+        if (d.coarse32)
+          hipLaunchKernelGGL((k_coarse_sym<float, KC>), dim3(gs), dim3(64), 0, cs, d.Ksym32.p, d.sym_tiles.p,
+                             (int)d.sym_T, e.rH.p, e.cpart.p, e.sc.p, sel);
+        else
+          hipLaunchKernelGGL((k_coarse_sym<double, KC>), dim3(gs), dim3(64), 0, cs, d.Ksym64.p, d.sym_tiles.p,
+                             (int)d.sym_T, e.rH.p, e.cpart.p, e.sc.p, sel);
+        hipLaunchKernelGGL(k_coarse_fold<KC>, dim3(nblk(d.m0 * KC * 64)), dim3(kBlock), 0, cs, e.cpart.p,
+                           (int)d.sym_T, e.c.p, (int)d.m0, e.sc.p, sel);
+      } else if (d.coarse32 && e.coarse_w1)
         hipLaunchKernelGGL((k_coarse_mm1<float, KC>), dim3(g1), dim3(64), 0, cs, d.Kinv32.p, (int)d.ld0, e.rH.p,
                            e.c.p, (int)d.m0, e.sc.p, sel);
       else if (d.coarse32)
@@ -2221,23 +2387,28 @@ void tune_stars(Engine &e) {
     best = bb;
   }
   e.star_us = best;
-  // the coarse kernel (16-wavefront workgroups or one wavefront per four rows:
-  // the same bits) and its placement: before the sweeps, or beside them on a
-  // second stream, queued before or after them. The second half of an
-  // iteration is timed: with the coarse solve first the restriction also runs
-  // the convergence test, beside it a one-block kernel does (no column is
-  // active here, so neither changes a column's state). A candidate must beat
-  // the best so far by 2%.
+  // the coarse kernel's placement: before the sweeps, or beside them on a
+  // second stream, queued before or after them (the packed kernel unless a
+  // launch is fixed; the dense kernels are chosen only explicitly, since they
+  // round differently). The second half of an iteration is timed: with the
+  // coarse solve first the restriction also runs the convergence test, beside
+  // it a one-block kernel does (no column is active here, so neither changes a
+  // column's state). A candidate must beat the best so far by 2%.
   if (d.m0 > 0) {
     auto set_mode = [&](int mode) {
-      e.coarse_w1 = (mode & 1) != 0;
-      e.coarse_first = mode / 2 == 0;
-      e.coarse_late = mode / 2 == 2;
+      // 0..5: dense kernel (mode & 1) and placement (mode / 2); 6..8: packed, placement mode - 6
+      e.coarse_sym = mode >= 6;
+      e.coarse_w1 = !e.coarse_sym && (mode & 1) != 0;
+      const int place = e.coarse_sym ? mode - 6 : mode / 2;
+      e.coarse_first = place == 0;
+      e.coarse_late = place == 2;
     };
     double bbest = 1e30;
-    int bmode = 2;
+    // measured: the packed kernel in its three placements (all three give the
+    // same bits, so every batch width of the preconditioner rounds alike)
     const std::vector<int> modes =
-        d.coarse_launch >= 0 ? std::vector<int>{d.coarse_launch} : std::vector<int>{2, 0, 3, 1, 4, 5};
+        d.coarse_launch >= 0 ? std::vector<int>{d.coarse_launch} : std::vector<int>{7, 6, 8};
+    int bmode = modes.front();
     for (const int mode : modes) {
       set_mode(mode);
       auto half = [&]() {
@@ -2287,8 +2458,9 @@ int64_t engine_footprint(const Precond &pre, int kc) {
   const int64_t m0 = (std::max<int64_t>(pre.m0, 1) + 63) / 64 * 64;
   const int prec = pre.dev ? pre.finfo.star_precision : pre.precision;
   const int64_t ts = prec == SN_PREC_FP64 ? 8 : 4;
-  return (6 * npad * kc + 2 * m0 * kc + (int64_t)2 * kc * kMaxGrid) * 8 + kc * (int64_t)sizeof(CgScalars) +
-         (int64_t)pre.star_dofs.size() * kc * ts;
+  const int64_t T = pre.m0 > 0 ? m0 / 64 : 0;
+  return (6 * npad * kc + 2 * m0 * kc + (int64_t)2 * kc * kMaxGrid + T * T * 64 * kc) * 8 +
+         kc * (int64_t)sizeof(CgScalars) + (int64_t)pre.star_dofs.size() * kc * ts;
 }
 
 Engine *engine_create(Precond &pre, int kc) {
@@ -2312,6 +2484,10 @@ Engine *engine_create(Precond &pre, int kc) {
   e->c.alloc(nm);
   e->rH.zero();
   e->c.zero();
+  if (d.sym_T > 0) {
+    e->cpart.alloc((size_t)d.sym_T * d.sym_T * 64 * kc);
+    e->cpart.zero();
+  }
   e->partials.alloc((size_t)kc * kMaxGrid);
   e->partials.zero();
   e->partials2.alloc((size_t)kc * kMaxGrid);
@@ -2500,7 +2676,7 @@ void device_engine_info(Precond &pre, int k, sn_engine_info *info) {
   info->star_big_lds_bytes = e.sl[1].lds;
   info->star_global = e.sl[2].count;
   info->coarse_first = e.coarse_first ? 1 : 0;
-  info->coarse_kernel = e.coarse_w1 ? 1 : 0;
+  info->coarse_kernel = e.coarse_sym ? 2 : (e.coarse_w1 ? 1 : 0);
   info->coarse_late = e.coarse_late ? 1 : 0;
   info->sweep_bytes = e.sweep_bytes;
   info->star_sweep_us = e.star_us;

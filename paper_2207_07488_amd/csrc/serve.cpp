@@ -93,6 +93,7 @@ namespace {
 int64_t factor_estimate(const Precond &pre, const HostFactors &hf, int precision) {
   // both star layouts (band streams, supernodal blobs with about 20 bytes of
   // index per position and update), per-position arrays, matrix, coarse operator
+  // (dense and packed)
   const int64_t ts = precision == SN_PREC_FP64 ? 8 : 4;
   int64_t vals = 0, pos = 0, upd = 0;
   for (const auto &F : hf.stars) {
@@ -102,7 +103,7 @@ int64_t factor_estimate(const Precond &pre, const HostFactors &hf, int precision
   }
   const int64_t n = pre.sys->n, nnz = (int64_t)pre.sys->col.size();
   return (vals * ts + pos * (40 + 2 * ts) + upd * 8 + n * pre.nvert_per_elem * 16 + nnz * 12 +
-          pre.m0 * pre.m0 * 8) * 13 / 10;
+          pre.m0 * pre.m0 * 12) * 13 / 10;  // the coarse inverse dense and packed
 }
 
 // start the host factorisation of pre on a worker thread (once)

@@ -398,3 +398,36 @@ def test_coarse_kernels_and_placements_agree_bitwise(S, orc, name, prec):
         else:
             assert torch.equal(u1, ref[0]) and torch.equal(U, ref[1]), mode
     gpre.set_coarse_launch(-1)
+
+
+@pytest.mark.parametrize("name,prec", [("fiber2d_2k", "FP64"), ("fiber2d_2k", "FP32_STARS_COARSE"),
+                                       ("truss3d_1500", "FP64")])
+def test_packed_coarse_kernel(S, orc, name, prec):
+    """The packed symmetric coarse kernel (upper triangle in 64 x 64 tiles):
+    the same iterates bit for bit in every placement, for one column and in a
+    batch of five; against the dense kernel the same to rounding, and apply_B
+    against the oracle as in the other parity tests."""
+    import torch
+    opre, gpre = _pair(S, orc, name, getattr(S, prec))
+    F = torch.from_numpy(W.rhs(opre.sys.n, 5, seed=21)).cuda()
+    gpre.set_coarse_launch(0)
+    ud, _ = gpre.solve(F[:, :1].contiguous(), fixed_iters=12, use_graph=True)
+    ref = None
+    for mode in (6, 7, 8):
+        gpre.set_coarse_launch(mode)
+        ei = gpre.engine_info(1)
+        assert ei["coarse_kernel"] == 2 and ei["coarse_first"] == int(mode == 6) and ei["coarse_late"] == int(mode == 8)
+        u1, _ = gpre.solve(F[:, :1].contiguous(), fixed_iters=12, use_graph=True)
+        U, _ = gpre.solve(F, fixed_iters=12, use_graph=True)
+        if ref is None:
+            ref = (u1, U)
+            assert torch.equal(U[:, :1], u1)
+        else:
+            assert torch.equal(u1, ref[0]) and torch.equal(U, ref[1]), mode
+    tol = _tol(orc, name, opre) if prec == "FP64" else 1e-6
+    assert _close(ref[0].cpu().numpy()[:, 0], ud.cpu().numpy()[:, 0], max(tol, 1e-12))
+    r = W.rhs(opre.sys.n, 1, seed=4)[:, 0]
+    z = gpre.apply_B(r)
+    zo = opre.apply_B(r)
+    assert _close(z, zo, _tol(orc, name, opre) if prec == "FP64" else 5e-3)
+    gpre.set_coarse_launch(-1)
