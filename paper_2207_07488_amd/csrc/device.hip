@@ -2250,9 +2250,12 @@ void plan_sn(Engine &e, int lcap, int cw, int nteam) {
   std::vector<int32_t> o[3];
   std::vector<int64_t> vs((size_t)d.nstars, -1);
   int64_t l1 = 0, vbytes = 0;
+  // more wavefronts than column chunks: the workgroup solves the chunks
+  // together, with one set of vectors
+  const int64_t vsets = nteam > e.kc / cw ? 1 : nteam;
   for (const int32_t s : e.sn_list) {
     const int64_t xb = (d.h_n[s] * cw * ts + 15) & ~15, ub = (d.h_nu[s] * cw * ts + 15) & ~15;
-    const int64_t need = d.h_idx[s] + nteam * (2 * xb + ub);
+    const int64_t need = d.h_idx[s] + vsets * (2 * xb + ub);
     if (need <= lcap) {
       o[0].push_back(s);
     } else if (need <= kMaxLds) {
@@ -2337,14 +2340,21 @@ void tune_stars(Engine &e) {
   //    preconditioner)
   if (d.split < 0) {
     int64_t bsplit = 0;
+    // each candidate with one wavefront per column chunk and with four
+    // wavefronts solving the chunks together
+    std::vector<int> teams{nt};
+    for (const int w : {4, 16})
+      if (w > e.kc / cw) teams.push_back(w);
     for (const double f : {0.01, 0.025, 0.05, 0.1, 0.2, 0.4, 1.0}) {
       const int64_t k = std::max<int64_t>(1, (int64_t)std::llround(f * d.nstars));
       plan_split(e, k);
-      plan_sn(e, lcap, cw, nt);
-      const double us = time_it();
-      if (us < 0.98 * best) {
-        best = us;
-        bsplit = k;
+      for (const int w : teams) {
+        plan_sn(e, lcap, cw, w);
+        const double us = time_it();
+        if (us < 0.98 * best) {
+          best = us;
+          bsplit = k;
+        }
       }
     }
     d.split = bsplit;
@@ -2354,7 +2364,9 @@ void tune_stars(Engine &e) {
   if (e.n_sn > 0) {
     std::vector<std::pair<int, int>> shapes;  // (cw, nteam)
     for (int c = 1; c <= std::min(e.kc, 4); c *= 2)
-      for (int w = 1; w <= std::min(e.kc / c, 4); w *= 2) shapes.push_back({c, w});
+      for (int w = 1; w <= 16; w *= 2)
+        if (w <= std::min(e.kc / c, 4) || (w > e.kc / c && w >= 4))  // w > kc / c: the chunks solved together
+          shapes.push_back({c, w});
     const int caps[] = {12 << 10, 16 << 10, 24 << 10, 32 << 10, 48 << 10, 64 << 10};
     double sbest = 1e30;
     auto try_sn = [&](int cap, int c, int w) {

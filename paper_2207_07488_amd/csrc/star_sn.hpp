@@ -259,9 +259,12 @@ __device__ __forceinline__ void gather(T *x, const double *__restrict__ r, const
   }
 }
 
+// One star per workgroup (see the header of this file); lds: the workgroup's
+// dynamic LDS. k_sn runs up to four wavefronts, k_sn_wide up to sixteen (more
+// wavefronts than column chunks solve the chunks together).
 template <typename T, int KC, int CW>
-__global__ __launch_bounds__(256) void k_sn(SnArgs a, const double *__restrict__ r, const CgScalars *sc, int sel) {
-  extern __shared__ __align__(16) unsigned char lds[];
+__device__ __forceinline__ void sn_star(unsigned char *lds, const SnArgs &a, const double *__restrict__ r,
+                                        const CgScalars *sc, int sel) {
   const int st = a.order[blockIdx.x];
   const unsigned char *gb = a.blob + a.st_blob[st];
   const SnHeader hd = *reinterpret_cast<const SnHeader *>(gb);
@@ -281,7 +284,11 @@ __global__ __launch_bounds__(256) void k_sn(SnArgs a, const double *__restrict__
   const uint32_t xb = (uint32_t)((n * CW * (int)sizeof(T) + 15) & ~15);
   const uint32_t ub = (uint32_t)((nu * CW * (int)sizeof(T) + 15) & ~15);
   const uint32_t vec = 2 * xb + ub;
-  const bool vl = hd.idx_bytes + hd.val_bytes + (uint32_t)nteam * vec <= (uint32_t)a.lds_bytes;
+  // more wavefronts than column chunks: the whole workgroup solves one chunk
+  // after the other (one set of vectors, workgroup barriers between phases)
+  const bool coop = nteam > NCH;
+  const uint32_t vsets = coop ? 1u : (uint32_t)nteam;
+  const bool vl = hd.idx_bytes + hd.val_bytes + vsets * vec <= (uint32_t)a.lds_bytes;
   const uint32_t staged = hd.idx_bytes + (vl ? hd.val_bytes : 0u);
   {
     // index part (and values) to LDS, 16 bytes per thread and load, sixteen
@@ -308,12 +315,30 @@ __global__ __launch_bounds__(256) void k_sn(SnArgs a, const double *__restrict__
   B.R = reinterpret_cast<const uint16_t *>(lds + hd.off_R);
   B.alist = reinterpret_cast<const uint16_t *>(lds + hd.off_alist);
   B.bpos = reinterpret_cast<const uint16_t *>(lds + hd.off_bpos);
-  unsigned char *tv = lds + staged + (uint32_t)team * vec;
+  unsigned char *tv = lds + staged + (coop ? 0u : (uint32_t)team * vec);
   T *x = reinterpret_cast<T *>(tv), *y = reinterpret_cast<T *>(tv + xb), *u = reinterpret_cast<T *>(tv + 2 * xb);
   const int32_t *dofs = a.pos_dof + a.st_pos[st];
   T *out = static_cast<T *>(a.slots) + (size_t)a.st_pos[st] * KC;
   __syncthreads();
   B.lv_pos = (int)B.lev[min(lane, nlev)];
+  if (coop) {
+    const int tid = (int)threadIdx.x, NT = (int)blockDim.x;
+    for (int ch = 0; ch < NCH; ++ch) {
+      if (!((chunks >> ch) & 1u)) continue;
+      const int col0 = ch * CW;
+      gather<T, KC, CW>(x, r, dofs, B.bpos, n, col0, tid, NT);
+      __syncthreads();
+      if (vl) team_solve<T, CW, true>(B, reinterpret_cast<const T *>(lds + hd.idx_bytes), nlev, x, y, u);
+      else team_solve<T, CW, true>(B, reinterpret_cast<const T *>(gb + hd.idx_bytes), nlev, x, y, u);
+      for (int p = tid; p < n; p += NT) {
+        Row<T, CW> o;
+        o.load(x + (size_t)p * CW);
+        o.store(out + (size_t)B.bpos[p] * KC + col0);
+      }
+      __syncthreads();
+    }
+    return;
+  }
   for (int ch = team; ch < NCH; ch += nteam) {
     if (!((chunks >> ch) & 1u)) continue;
     const int col0 = ch * CW;
@@ -329,6 +354,19 @@ __global__ __launch_bounds__(256) void k_sn(SnArgs a, const double *__restrict__
     }
     team_sync();
   }
+}
+
+template <typename T, int KC, int CW>
+__global__ __launch_bounds__(256) void k_sn(SnArgs a, const double *__restrict__ r, const CgScalars *sc, int sel) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  sn_star<T, KC, CW>(lds, a, r, sc, sel);
+}
+
+template <typename T, int KC, int CW>
+__global__ __launch_bounds__(1024) void k_sn_wide(SnArgs a, const double *__restrict__ r, const CgScalars *sc,
+                                                  int sel) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  sn_star<T, KC, CW>(lds, a, r, sc, sel);
 }
 
 // Stars too large for LDS: the whole workgroup solves one column chunk after
@@ -382,11 +420,19 @@ void launch_sn_t(const SnArgs &a, int nteam, bool global, const double *r, const
     hipLaunchKernelGGL((k_sn_global<T, KC, CW>), dim3(a.nstars), dim3(256), 0, s, a, r, sc, sel);
     return;
   }
-  // allow the kernel the whole LDS of a compute unit (once per instantiation)
+  // allow the kernels the whole LDS of a compute unit (once per instantiation)
   static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_sn<T, KC, CW>),
                                                      hipFuncAttributeMaxDynamicSharedMemorySize, kStarMaxLds);
-  if (attr != hipSuccess) fail(SN_EDEVICE, std::string("star kernel LDS limit: ") + hipGetErrorString(attr));
-  hipLaunchKernelGGL((k_sn<T, KC, CW>), dim3(a.nstars), dim3(64 * nteam), (size_t)a.lds_bytes, s, a, r, sc, sel);
+  static const hipError_t attr_w = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_sn_wide<T, KC, CW>),
+                                                       hipFuncAttributeMaxDynamicSharedMemorySize, kStarMaxLds);
+  if (attr != hipSuccess || attr_w != hipSuccess)
+    fail(SN_EDEVICE, std::string("star kernel LDS limit: ") + hipGetErrorString(attr != hipSuccess ? attr : attr_w));
+  if (nteam < 1 || nteam > 16) fail(SN_EINVAL, "1 to 16 wavefronts per star");
+  if (nteam <= 4)
+    hipLaunchKernelGGL((k_sn<T, KC, CW>), dim3(a.nstars), dim3(64 * nteam), (size_t)a.lds_bytes, s, a, r, sc, sel);
+  else
+    hipLaunchKernelGGL((k_sn_wide<T, KC, CW>), dim3(a.nstars), dim3(64 * nteam), (size_t)a.lds_bytes, s, a, r, sc,
+                       sel);
 }
 
 }  // namespace spnet
