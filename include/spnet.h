@@ -104,6 +104,35 @@ sn_status sn_network_info(sn_network net, int *dim, int64_t *n_nodes, int64_t *n
 sn_status sn_network_export(sn_network net, double *coords, int32_t *edges, uint8_t *dirichlet);
 void sn_network_destroy(sn_network net);
 
+/*
+ * Homogeneity and connectivity of the network (Assumption 3.4), the sigma and
+ * mu of Tables 6.1 and 6.3 (Sec. 6.1, Sec. 6.2.1). Host computation.
+ *   nb       [0,1]^dim is split into nb^dim boxes of side h = 1/nb (1..1024,
+ *            at most 2^24 boxes), numbered lexicographically, axis 0 fastest.
+ *   r0       the distance within which a disconnected box subgraph may be
+ *            joined (Assumption 3.4.2); r0 <= 0 takes the longest edge.
+ *   sigma    out: max / min over the boxes of the mass density, the lumped
+ *            mass (M 1)(x) = 1/2 sum_{y~x} |x-y| (eq. 2.1) summed over the
+ *            nodes of each half-open box (Sec. 2.3) and divided by h^dim
+ *            (inf when a box holds no node).
+ *   mu       out: max over the boxes of mu_box = 1 / (h sqrt(lambda_2)),
+ *            lambda_2 the second eigenvalue of L u = lambda M u (L: the 1/|e|
+ *            weighted Laplacian of eq. 2.2, M: the lumped mass of the
+ *            subgraph's own edges) on the subgraph of every edge with an end
+ *            point in the closed box; where that subgraph falls apart, a
+ *            breadth-first search from the component of its smallest node id,
+ *            through nodes within r0 of the box (adjacency in edge order),
+ *            adds the edges of the first path that reaches another component,
+ *            until it is connected. A box that cannot be joined gives inf, a box
+ *            with no edge 0 (the bound of Lemma 3.5).
+ *   density  optional (NULL), nb^dim doubles: the density of every box.
+ *   mu_box   optional (NULL), nb^dim doubles: mu_box of every box.
+ * Errors: SN_EINVAL for nb out of range or non-finite r0, SN_EINVAL when a
+ * box's shifted Laplacian cannot be factored.
+ */
+sn_status sn_network_diagnostics(sn_network net, int nb, double r0, double *sigma, double *mu,
+                                 double *density, double *mu_box);
+
 /* ------------------------------------------------------------------ */
 /* 2. Assembly (Examples 3.2 / 3.3)                                     */
 /* ------------------------------------------------------------------ */

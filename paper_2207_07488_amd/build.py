@@ -15,7 +15,7 @@ LIB = os.path.join(HERE, "libspnet.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 HIPCC = os.path.join(ROCM, "bin", "hipcc")
 
-HOST_SOURCES = ["network.cpp", "assemble.cpp", "spaces.cpp", "factor.cpp", "api.cpp", "serve.cpp"]
+HOST_SOURCES = ["network.cpp", "assemble.cpp", "spaces.cpp", "factor.cpp", "diagnostics.cpp", "api.cpp", "serve.cpp"]
 DEVICE_SOURCES = ["device.hip"]
 # the star kernel launcher, once per factor precision and column count
 STAR_VARIANTS = [(t, kc) for t in ("float", "double") for kc in (1, 2, 4, 8, 16)]

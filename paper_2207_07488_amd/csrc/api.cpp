@@ -94,6 +94,16 @@ sn_status sn_network_export(sn_network net, double *coords, int32_t *edges, uint
 
 void sn_network_destroy(sn_network net) { delete net; }
 
+sn_status sn_network_diagnostics(sn_network net, int nb, double r0, double *sigma, double *mu, double *density,
+                                 double *mu_box) {
+  return guarded([&] {
+    REQUIRE(net, "null network");
+    REQUIRE(sigma && mu, "null output");
+    REQUIRE(std::isfinite(r0), "r0 must be finite");
+    spnet::network_diagnostics(*net->p, nb, r0, sigma, mu, density, mu_box);
+  });
+}
+
 sn_status sn_assemble(sn_network net, int model, const double *gamma, sn_system *out) {
   return guarded([&] {
     REQUIRE(net && out, "null argument");

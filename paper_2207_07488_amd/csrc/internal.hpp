@@ -76,6 +76,9 @@ std::shared_ptr<Network> build_network_from_segments(int dim, int64_t nseg, cons
 std::shared_ptr<System> assemble(std::shared_ptr<const Network> net, int model, const double *gamma);
 std::shared_ptr<System> assemble_beam(std::shared_ptr<const Network> net, int ncomp, double g1, double rw);
 void apply_full(const System &sys, const double *g, double *y);
+// diagnostics.cpp: homogeneity and connectivity per box (Assumption 3.4)
+void network_diagnostics(const Network &net, int nb, double r0, double *sigma, double *mu, double *density,
+                         double *mu_box);
 // spaces.cpp
 std::unique_ptr<Precond> build_spaces(std::shared_ptr<const System> sys, int nH, int policy, int dir_lo,
                                       int dir_hi);

@@ -92,6 +92,7 @@ SIGNATURES = {
     "sn_network_info": (C.c_int, [_P, C.POINTER(C.c_int), C.POINTER(_i64), C.POINTER(_i64)]),
     "sn_network_export": (C.c_int, [_P, _P, _P, _P]),
     "sn_network_destroy": (None, [_P]),
+    "sn_network_diagnostics": (C.c_int, [_P, C.c_int, _dbl, C.POINTER(_dbl), C.POINTER(_dbl), _P, _P]),
     "sn_assemble": (C.c_int, [_P, C.c_int, _P, C.POINTER(_P)]),
     "sn_assemble_beam": (C.c_int, [_P, C.c_int, _dbl, _dbl, C.POINTER(_P)]),
     "sn_system_apply_full": (C.c_int, [_P, _P, _P]),
@@ -197,6 +198,17 @@ class Network:
         d = np.zeros(self.n_nodes, dtype=np.uint8)
         _check(lib().sn_network_export(self.h, _ptr(x), _ptr(e), _ptr(d)))
         return x, e, d
+
+    def diagnostics(self, nb, r0=None):
+        """Homogeneity and connectivity over nb^dim boxes (Assumption 3.4):
+        (sigma, mu, density per box, mu per box); r0 None takes the longest edge."""
+        nbox = int(nb) ** self.dim
+        dens = np.zeros(nbox)
+        mus = np.zeros(nbox)
+        sig, mu = _dbl(), _dbl()
+        _check(lib().sn_network_diagnostics(self.h, int(nb), 0.0 if r0 is None else float(r0), C.byref(sig),
+                                            C.byref(mu), _ptr(dens), _ptr(mus)))
+        return sig.value, mu.value, dens, mus
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:
