@@ -11,7 +11,8 @@ Beside the headline: the mesh-size sweep, batched right-hand sides, the small
 2D network with 1,024 right-hand sides, the 3D fiber network (100,000
 segments), the 3D truss network with 16 right-hand sides, the heat experiment
 of Sec. 6.2 on the Example 3.7 grid, the in-plane structural problem of Sec.
-6.3.1 (beam model, lifted Dirichlet data), the serving mix, and the FP64
+6.3.1 (beam model, lifted Dirichlet data), the network diagnostics of
+Assumption 3.4 (host), the serving mix, and the FP64
 oracle timed on the host (one core and all cores). Prints one JSON
 line; progress goes to stderr.
 """
@@ -341,6 +342,28 @@ def f2_leg(S, W, torch):
     return out
 
 
+def f4_leg(S, W, torch):
+    """Network diagnostics of Assumption 3.4 (host code of the library): sigma
+    and mu of the Example 3.7 grid with (2^9 + 1)^2 nodes over boxes of side H
+    (Table 6.3) and of the 20,000-segment 2D network over boxes of side 2R with
+    joining paths within 1/64 (the measure of Table 6.1), with their times."""
+    x, e = W.grid_network(512)
+    grid = S.Network.from_arrays(x, e, W.boundary_flags(x, 3, 3, 0.25 / 512))
+    p = W.PRESETS["fiber2d_20k"]
+    seg = W.fiber_segments(2, p["n_segments"], p["length"], p["seed"])
+    fib = S.Network.from_segments(2, seg, merge_tol=W.merge_tol(p["length"]), dir_lo=3, dir_hi=3, band=W.BAND)
+    out = {"grid_513x513": {}, "fiber2d_20k": {}}
+    for name, net, sizes, r0 in (("grid_513x513", grid, (4, 8, 16, 32), None),
+                                 ("fiber2d_20k", fib, (2, 4, 8, 16, 32), 1.0 / 64)):
+        for nb in sizes:
+            t0 = time.perf_counter()
+            sigma, mu, _, _ = net.diagnostics(nb, r0)
+            key = f"H=1/{nb}" if r0 is None else f"R=1/{2 * nb}"
+            out[name][key] = {"sigma": round(sigma, 3), "mu": round(mu, 3),
+                              "seconds": round(time.perf_counter() - t0, 3)}
+    return out
+
+
 def cpu_oracle_leg(O, W, seg, tol, preset, nH, f_host, rtol, threads):
     """The FP64 oracle on the host: one solve on one core, and independent
     solves (other right-hand sides of the same network) on `threads` cores at
@@ -541,7 +564,8 @@ def main():
     }
 
     if not args.no_configs:
-        for name, leg in (("c1", c1_leg), ("c3", c3_leg), ("c4", c4_leg), ("f1", f1_leg), ("f2", f2_leg)):
+        for name, leg in (("c1", c1_leg), ("c3", c3_leg), ("c4", c4_leg), ("f1", f1_leg), ("f2", f2_leg),
+                         ("f4", f4_leg)):
             try:
                 out[name] = leg(S, W, torch, args.steps) if name[0] == "c" else leg(S, W, torch)
             except Exception as ex:  # report, keep the other legs

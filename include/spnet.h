@@ -336,8 +336,10 @@ sn_status sn_precond_kernel_stats(sn_precond pre, sn_kernel_stats *stats);
  *     carrying star_cols_per_wave of the k columns in turn; the workgroups of
  *     its main launch get star_lds_bytes of LDS, the star_big stars whose index
  *     part and vectors need more run with star_big_lds_bytes each, and the
- *     star_global stars that exceed the LDS of a compute unit are solved by
- *     256-thread workgroups from global memory.
+ *     star_global stars that exceed the LDS of a compute unit are solved from
+ *     global memory by workgroups of star_global_waves wavefronts;
+ *   the band wavefronts of the longest stars may run at raised issue priority
+ *     (star_band_prio).
  */
 typedef struct {
   int32_t star_sn;
@@ -349,6 +351,9 @@ typedef struct {
   int32_t star_big;
   int32_t star_big_lds_bytes;
   int32_t star_global;
+  int32_t star_band_prio; /* the band wavefronts of the star_band_prio longest stars of each band launch
+                             run at raised instruction-issue priority (0: none) */
+  int32_t star_global_waves; /* wavefronts per star of the star_global stars (4 or 16) */
   int32_t coarse_first;  /* 1: the coarse solve runs before the local solves (and its restriction
                             also runs the convergence test), 0: beside them on a second stream */
   int32_t coarse_kernel; /* 0: the coarse product in 16-wavefront workgroups of 8 rows, 1: one

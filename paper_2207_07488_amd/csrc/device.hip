@@ -1163,6 +1163,7 @@ struct Engine {
   int32_t n_narrow = 0, n_wide = 0;
   int32_t star_cap = 0, star_lds = 0;          // resident band wavefronts per SIMD (0: no limit) and its LDS reservation
   bool star_lv = true;                         // band working vectors in LDS (where they fit)
+  int32_t star_prio = 0;                       // band wavefronts of the longest stars at raised issue priority
   // supernodal launches: 0 (lds_cap per workgroup), 1 (more LDS), 2 (global memory)
   struct StarLaunch {
     DBuf<int32_t> order;
@@ -1171,6 +1172,7 @@ struct Engine {
   DBuf<unsigned char> vscratch;                // vectors of the launch-2 stars
   DBuf<int64_t> st_vs;
   int32_t star_cw = 1, star_nteam = 1, star_lcap = 0;
+  int32_t star_gteam = 4;                      // wavefronts per star of the global-memory launch (4 or 16)
   double star_us = 0.0;
   bool coarse_first = false;  // coarse solve before the sweeps rather than beside them
   bool coarse_w1 = false;     // one-wavefront coarse kernel (else 16-wavefront workgroups)
@@ -1807,6 +1809,7 @@ StarArgs band_args(DeviceState &d, Engine &e, bool wide) {
   a.lds_reserve = e.star_lds;
   a.maxn = d.maxn;
   a.use_lds = e.star_lv ? 1 : 0;
+  a.n_prio = e.star_prio;
   if (d.precision == SN_PREC_FP32_STARS) {
     a.f_inv = d.f_inv32.p;
     a.b_inv = d.b_inv32.p;
@@ -1868,8 +1871,9 @@ void launch_sn(Engine &e, const double *r, int sel, hipStream_t s) {
   for (int which = 2; which >= 0; --which) {
     if (e.sl[which].count == 0) continue;
     const SnArgs a = sn_args(d, e, which);
-    if (f32) launch_sn_kc<float>(e.kc, e.star_cw, a, e.star_nteam, which == 2, r, e.sc.p, sel, s);
-    else launch_sn_kc<double>(e.kc, e.star_cw, a, e.star_nteam, which == 2, r, e.sc.p, sel, s);
+    const int nt = which == 2 ? e.star_gteam : e.star_nteam;
+    if (f32) launch_sn_kc<float>(e.kc, e.star_cw, a, nt, which == 2, r, e.sc.p, sel, s);
+    else launch_sn_kc<double>(e.kc, e.star_cw, a, nt, which == 2, r, e.sc.p, sel, s);
   }
 }
 
@@ -2381,6 +2385,14 @@ void tune_stars(Engine &e) {
     };
     for (int cap : caps) try_sn(cap, cw, nt);
     for (auto &sh : shapes) try_sn(lcap, sh.first, sh.second);
+    plan_sn(e, lcap, cw, nt);
+    // the stars solved from global memory: four or sixteen wavefronts each
+    if (e.sl[2].count > 0) {
+      e.star_gteam = 16;
+      const double us = time_it();
+      if (us < 0.98 * sbest) sbest = us;
+      else e.star_gteam = 4;
+    }
     best = sbest;
   }
   plan_sn(e, lcap, cw, nt);
@@ -2397,6 +2409,19 @@ void tune_stars(Engine &e) {
     }
     set_cap(bcap);
     best = bb;
+    // 5. issue priority for the wavefronts of the longest band stars (the
+    //    same arithmetic, a different schedule)
+    int bprio = 0;
+    for (const int np : {16, 64, 256, 1024}) {
+      if (np > std::max(e.n_narrow, e.n_wide)) break;
+      e.star_prio = np;
+      const double us = time_it();
+      if (us < 0.98 * best) {
+        best = us;
+        bprio = np;
+      }
+    }
+    e.star_prio = bprio;
   }
   e.star_us = best;
   // the coarse kernel's placement: before the sweeps, or beside them on a
@@ -2687,6 +2712,8 @@ void device_engine_info(Precond &pre, int k, sn_engine_info *info) {
   info->star_big = e.sl[1].count;
   info->star_big_lds_bytes = e.sl[1].lds;
   info->star_global = e.sl[2].count;
+  info->star_band_prio = e.star_prio;
+  info->star_global_waves = e.star_gteam;
   info->coarse_first = e.coarse_first ? 1 : 0;
   info->coarse_kernel = e.coarse_sym ? 2 : (e.coarse_w1 ? 1 : 0);
   info->coarse_late = e.coarse_late ? 1 : 0;

@@ -122,6 +122,7 @@ struct StarArgs {
   int32_t lds_reserve;                       // dynamic LDS per workgroup: caps waves per CU
   int32_t maxn;                              // largest star (positions)
   int32_t use_lds;                           // working vectors in LDS where they fit
+  int32_t n_prio;                            // the first n_prio stars of order run at raised issue priority
   void *slots;                               // T, per position and column (position-major)
 };
 

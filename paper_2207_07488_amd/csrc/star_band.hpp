@@ -352,6 +352,9 @@ __global__ __launch_bounds__(64, (star_min_waves<T, WIDE, KC, LV>())) void k_sta
   }
   const int wv = blockIdx.x;
   if (wv >= a.nstars) return;
+  // the wavefronts of the longest stars may win instruction issue over the
+  // shorter stars sharing their SIMD (the engine measures whether it pays)
+  if (wv < a.n_prio) __builtin_amdgcn_s_setprio(3);
   const int st = a.order[wv];
   const int n = a.st_n[st], vb = a.st_vb[st], Q = a.st_q[st];
   const int lane = threadIdx.x;

@@ -369,11 +369,11 @@ __global__ __launch_bounds__(1024) void k_sn_wide(SnArgs a, const double *__rest
   sn_star<T, KC, CW>(lds, a, r, sc, sel);
 }
 
-// Stars too large for LDS: the whole workgroup solves one column chunk after
-// the other with the factor read from the blob and the vectors in the global
-// scratch at a.vscratch + a.st_vs[star].
+// Stars too large for LDS: the whole workgroup (4 or 16 wavefronts) solves one
+// column chunk after the other with the factor read from the blob and the
+// vectors in the global scratch at a.vscratch + a.st_vs[star].
 template <typename T, int KC, int CW>
-__global__ __launch_bounds__(256) void k_sn_global(SnArgs a, const double *__restrict__ r, const CgScalars *sc,
+__global__ __launch_bounds__(1024) void k_sn_global(SnArgs a, const double *__restrict__ r, const CgScalars *sc,
                                                      int sel) {
   const int st = a.order[blockIdx.x];
   const unsigned char *gb = a.blob + a.st_blob[st];
@@ -417,7 +417,8 @@ void launch_sn_t(const SnArgs &a, int nteam, bool global, const double *r, const
                  hipStream_t s) {
   if (a.nstars <= 0) return;
   if (global) {
-    hipLaunchKernelGGL((k_sn_global<T, KC, CW>), dim3(a.nstars), dim3(256), 0, s, a, r, sc, sel);
+    if (nteam != 4 && nteam != 16) fail(SN_EINVAL, "4 or 16 wavefronts per star solved from global memory");
+    hipLaunchKernelGGL((k_sn_global<T, KC, CW>), dim3(a.nstars), dim3(64 * nteam), 0, s, a, r, sc, sel);
     return;
   }
   // allow the kernels the whole LDS of a compute unit (once per instantiation)

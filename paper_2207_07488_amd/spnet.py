@@ -54,7 +54,9 @@ class EngineInfo(C.Structure):
     _fields_ = [("star_sn", C.c_int32), ("star_waves_per_simd", C.c_int32), ("star_band_lds", C.c_int32),
                 ("star_lds_bytes", C.c_int32), ("star_cols_per_wave", C.c_int32), ("star_waves", C.c_int32),
                 ("star_big", C.c_int32), ("star_big_lds_bytes", C.c_int32), ("star_global", C.c_int32),
-                ("coarse_first", C.c_int32), ("coarse_kernel", C.c_int32), ("coarse_late", C.c_int32),
+                ("star_band_prio", C.c_int32), ("star_global_waves", C.c_int32), ("coarse_first", C.c_int32),
+                ("coarse_kernel", C.c_int32),
+                ("coarse_late", C.c_int32),
                 ("sweep_bytes", C.c_int64), ("star_sweep_us", C.c_double),
                 ("b_apply_us", C.c_double)]
 
