@@ -273,6 +273,14 @@ sn_status sn_precond_set_star_split(sn_precond pre, int64_t n_sn) {
   });
 }
 
+sn_status sn_precond_set_sn_beyond_lds(sn_precond pre, int mode) {
+  return guarded([&] {
+    REQUIRE(pre && pre->p->dev, "null argument or not factored");
+    REQUIRE(mode >= -1 && mode <= 1, "mode must be in -1..1");
+    spnet::device_set_sn_beyond_lds(*pre->p, mode);
+  });
+}
+
 sn_status sn_precond_set_coarse_launch(sn_precond pre, int mode) {
   return guarded([&] {
     REQUIRE(pre && pre->p->dev, "null argument or not factored");

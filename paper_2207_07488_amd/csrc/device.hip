@@ -1111,6 +1111,7 @@ struct DeviceState {
   // column's iterates must not depend on its batch; -1: not yet chosen
   int64_t split = -1;
   int32_t coarse_launch = -1;  // fixed coarse kernel and placement (kernel + 2 placement), -1: measured
+  int32_t sn_beyond = -1;      // supernodal stars beyond LDS: 0 global memory, 1 vectors in LDS, -1 measured
   // coarse
   // K_0^{-1}, symmetric, zero-padded to ld0 x ld0 (ld0 a multiple of 64): FP32 in the mixed form
   // unless the coarse factor's pivot ratio rules it out, else FP64
@@ -1173,6 +1174,8 @@ struct Engine {
   DBuf<int64_t> st_vs;
   int32_t star_cw = 1, star_nteam = 1, star_lcap = 0;
   int32_t star_gteam = 4;                      // wavefronts per star of the global-memory launch (4 or 16)
+  bool sn_iglobal = false;                     // stars beyond LDS: vectors in LDS, index part in global memory
+  int32_t star_iglobal = 0;                    // such stars in the plan
   double star_us = 0.0;
   bool coarse_first = false;  // coarse solve before the sweeps rather than beside them
   bool coarse_w1 = false;     // one-wavefront coarse kernel (else 16-wavefront workgroups)
@@ -2254,17 +2257,23 @@ void plan_sn(Engine &e, int lcap, int cw, int nteam) {
   std::vector<int32_t> o[3];
   std::vector<int64_t> vs((size_t)d.nstars, -1);
   int64_t l1 = 0, vbytes = 0;
+  int32_t nig = 0;
   // more wavefronts than column chunks: the workgroup solves the chunks
   // together, with one set of vectors
   const int64_t vsets = nteam > e.kc / cw ? 1 : nteam;
   for (const int32_t s : e.sn_list) {
     const int64_t xb = (d.h_n[s] * cw * ts + 15) & ~15, ub = (d.h_nu[s] * cw * ts + 15) & ~15;
-    const int64_t need = d.h_idx[s] + vsets * (2 * xb + ub);
+    const int64_t vec = vsets * (2 * xb + ub), need = d.h_idx[s] + vec;
     if (need <= lcap) {
       o[0].push_back(s);
     } else if (need <= kMaxLds) {
       o[1].push_back(s);
       l1 = std::max(l1, std::min(kMaxLds, need + d.h_val[s]));
+    } else if (e.sn_iglobal && vec <= kMaxLds) {
+      // vectors in LDS, index part and values read from global memory
+      o[1].push_back(s);
+      l1 = std::max(l1, vec);
+      ++nig;
     } else {
       o[2].push_back(s);
       vs[s] = vbytes;
@@ -2286,6 +2295,7 @@ void plan_sn(Engine &e, int lcap, int cw, int nteam) {
   e.star_cw = cw;
   e.star_nteam = nteam;
   e.star_lcap = lcap;
+  e.star_iglobal = nig;
 }
 
 // The local-solve launch shape is measured: every candidate solves all stars
@@ -2341,7 +2351,9 @@ void tune_stars(Engine &e) {
     if (!e.star_lv) best = us;
   }
   // 2. the split: the longest stars to the supernodal path (once per
-  //    preconditioner)
+  //    preconditioner); stars beyond LDS keep their vectors there unless the
+  //    caller fixed otherwise
+  e.sn_iglobal = d.sn_beyond != 0;
   if (d.split < 0) {
     int64_t bsplit = 0;
     // each candidate with one wavefront per column chunk and with four
@@ -2386,6 +2398,25 @@ void tune_stars(Engine &e) {
     for (int cap : caps) try_sn(cap, cw, nt);
     for (auto &sh : shapes) try_sn(lcap, sh.first, sh.second);
     plan_sn(e, lcap, cw, nt);
+    // the stars beyond LDS: vectors in LDS with the index part and values
+    // read from global memory, or everything in global memory
+    if (d.sn_beyond >= 0) {
+      e.sn_iglobal = d.sn_beyond == 1;
+      plan_sn(e, lcap, cw, nt);
+    } else {
+      e.sn_iglobal = true;
+      plan_sn(e, lcap, cw, nt);
+      if (e.star_iglobal > 0) {
+        // both settings give the same bits: keep the faster
+        const double t_ig = time_it();
+        e.sn_iglobal = false;
+        plan_sn(e, lcap, cw, nt);
+        const double t_g = time_it();
+        e.sn_iglobal = t_ig <= t_g;
+        sbest = std::min(sbest, std::min(t_ig, t_g));
+        plan_sn(e, lcap, cw, nt);
+      }
+    }
     // the stars solved from global memory: four or sixteen wavefronts each
     if (e.sl[2].count > 0) {
       e.star_gteam = 16;
@@ -2691,6 +2722,15 @@ void device_set_star_split(Precond &pre, int64_t n_sn) {
   d.split = n_sn < 0 ? -1 : std::min<int64_t>(n_sn, d.nstars);
 }
 
+void device_set_sn_beyond_lds(Precond &pre, int mode) {
+  DeviceState &d = *pre.dev;
+  for (auto &e : d.solve_engine) {
+    if (e) wait_tick(*e);
+    e.reset();
+  }
+  d.sn_beyond = mode < 0 ? -1 : mode;
+}
+
 void device_set_coarse_launch(Precond &pre, int mode) {
   DeviceState &d = *pre.dev;
   for (auto &e : d.solve_engine) {
@@ -2714,6 +2754,7 @@ void device_engine_info(Precond &pre, int k, sn_engine_info *info) {
   info->star_global = e.sl[2].count;
   info->star_band_prio = e.star_prio;
   info->star_global_waves = e.star_gteam;
+  info->star_big_index_global = e.star_iglobal;
   info->coarse_first = e.coarse_first ? 1 : 0;
   info->coarse_kernel = e.coarse_sym ? 2 : (e.coarse_w1 ? 1 : 0);
   info->coarse_late = e.coarse_late ? 1 : 0;

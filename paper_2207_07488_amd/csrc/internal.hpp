@@ -153,6 +153,7 @@ int64_t device_bytes(const Precond &pre);
 void device_engine_info(Precond &pre, int k, sn_engine_info *info);
 void device_set_star_split(Precond &pre, int64_t n_sn);
 void device_set_coarse_launch(Precond &pre, int mode);
+void device_set_sn_beyond_lds(Precond &pre, int mode);
 
 // ---------------------------------------------------------------------------
 // Engine: the device workspace of kc PCG columns (independent recurrences, one

@@ -5,8 +5,9 @@
 //
 // One workgroup per star; its wavefronts ("teams") take the star's column
 // chunks of CW columns in turn and share the star's factor, which is staged in
-// LDS once (index part always, values when they fit the launch's LDS size)
-// and read from there by both solves.
+// LDS once (the index part when it fits beside the vectors, the values when
+// they fit too) and read from there by both solves; what is not staged is read
+// from global memory.
 //
 // The factor of a star (see factor.cpp) is level-scheduled: its supernodes are
 // grouped by height in the supernodal tree and positions are numbered level by
@@ -288,8 +289,11 @@ __device__ __forceinline__ void sn_star(unsigned char *lds, const SnArgs &a, con
   // after the other (one set of vectors, workgroup barriers between phases)
   const bool coop = nteam > NCH;
   const uint32_t vsets = coop ? 1u : (uint32_t)nteam;
-  const bool vl = hd.idx_bytes + hd.val_bytes + vsets * vec <= (uint32_t)a.lds_bytes;
-  const uint32_t staged = hd.idx_bytes + (vl ? hd.val_bytes : 0u);
+  // the index part is staged when it fits beside the vectors (else it is read
+  // from global memory), the values when they fit too
+  const bool il = hd.idx_bytes + vsets * vec <= (uint32_t)a.lds_bytes;
+  const bool vl = il && hd.idx_bytes + hd.val_bytes + vsets * vec <= (uint32_t)a.lds_bytes;
+  const uint32_t staged = il ? hd.idx_bytes + (vl ? hd.val_bytes : 0u) : 0u;
   {
     // index part (and values) to LDS, 16 bytes per thread and load, sixteen
     // loads per thread in flight
@@ -308,13 +312,14 @@ __device__ __forceinline__ void sn_star(unsigned char *lds, const SnArgs &a, con
       for (int q = 0; q < 16; ++q) dst[min(i0 + q * bs, n16 - 1)] = v[q];
     }
   }
+  const unsigned char *ib = il ? lds : gb;
   SnView B;
-  B.lev = reinterpret_cast<const uint32_t *>(lds + hd.off_lev);
+  B.lev = reinterpret_cast<const uint32_t *>(ib + hd.off_lev);
   B.lv_reg = nlev < 64;
-  B.pos = reinterpret_cast<const SnPos *>(lds + hd.off_pos);
-  B.R = reinterpret_cast<const uint16_t *>(lds + hd.off_R);
-  B.alist = reinterpret_cast<const uint16_t *>(lds + hd.off_alist);
-  B.bpos = reinterpret_cast<const uint16_t *>(lds + hd.off_bpos);
+  B.pos = reinterpret_cast<const SnPos *>(ib + hd.off_pos);
+  B.R = reinterpret_cast<const uint16_t *>(ib + hd.off_R);
+  B.alist = reinterpret_cast<const uint16_t *>(ib + hd.off_alist);
+  B.bpos = reinterpret_cast<const uint16_t *>(ib + hd.off_bpos);
   unsigned char *tv = lds + staged + (coop ? 0u : (uint32_t)team * vec);
   T *x = reinterpret_cast<T *>(tv), *y = reinterpret_cast<T *>(tv + xb), *u = reinterpret_cast<T *>(tv + 2 * xb);
   const int32_t *dofs = a.pos_dof + a.st_pos[st];

@@ -54,7 +54,8 @@ class EngineInfo(C.Structure):
     _fields_ = [("star_sn", C.c_int32), ("star_waves_per_simd", C.c_int32), ("star_band_lds", C.c_int32),
                 ("star_lds_bytes", C.c_int32), ("star_cols_per_wave", C.c_int32), ("star_waves", C.c_int32),
                 ("star_big", C.c_int32), ("star_big_lds_bytes", C.c_int32), ("star_global", C.c_int32),
-                ("star_band_prio", C.c_int32), ("star_global_waves", C.c_int32), ("coarse_first", C.c_int32),
+                ("star_band_prio", C.c_int32), ("star_global_waves", C.c_int32),
+                ("star_big_index_global", C.c_int32), ("coarse_first", C.c_int32),
                 ("coarse_kernel", C.c_int32),
                 ("coarse_late", C.c_int32),
                 ("sweep_bytes", C.c_int64), ("star_sweep_us", C.c_double),
@@ -117,6 +118,7 @@ SIGNATURES = {
     "sn_precond_engine_info": (C.c_int, [_P, C.c_int, C.POINTER(EngineInfo)]),
     "sn_precond_set_star_split": (C.c_int, [_P, _i64]),
     "sn_precond_set_coarse_launch": (C.c_int, [_P, C.c_int]),
+    "sn_precond_set_sn_beyond_lds": (C.c_int, [_P, C.c_int]),
     "sn_apply_K": (C.c_int, [_P, C.c_int, _P, _P, C.c_int, _P]),
     "sn_apply_B": (C.c_int, [_P, C.c_int, _P, _P, C.c_int, _P]),
     "sn_apply_K_noalloc": (C.c_int, [_P, C.c_int, _P, _P, _P]),
@@ -318,6 +320,10 @@ class Precond:
         """Fix the stars on the supernodal path (the n_sn with most positions);
         n_sn < 0: measure it at the next solve."""
         _check(lib().sn_precond_set_star_split(self.h, int(n_sn)))
+
+    def set_sn_beyond_lds(self, mode):
+        """Supernodal stars beyond LDS: 0 global memory, 1 vectors in LDS, -1 measured."""
+        _check(lib().sn_precond_set_sn_beyond_lds(self.h, int(mode)))
 
     def set_coarse_launch(self, mode):
         """Fix the coarse kernel and placement (kernel + 2 placement, see the C

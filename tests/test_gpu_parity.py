@@ -298,7 +298,10 @@ def test_local_solve_paths(S, orc, name, split):
 
 def test_supernodal_stars_beyond_lds(S, orc):
     """Stars of thousands of dofs with 16 FP64 columns need more LDS than a
-    compute unit has: they are solved from global memory, to the same bar."""
+    compute unit has: they are solved from global memory (mode 0), or with
+    their vectors in LDS and the index part and values read from global memory
+    (mode 1, where the vectors alone fit), to the same bar and to the same bits
+    in both modes."""
     dim, nseg, l, eps, lo, hi, _, model = CASES["fiber2d_2k"]
     seg = W.fiber_segments(dim, nseg, l, seed=1)
     on = orc.Network.from_segments(dim, seg, merge_tol=W.merge_tol(l), dir_lo=lo, dir_hi=hi)
@@ -307,10 +310,31 @@ def test_supernodal_stars_beyond_lds(S, orc):
     gpre = S.Precond(S.System(gn, model), 2, S.STARS_ALL, lo, hi, precision=S.FP64)
     gpre.set_star_split(gpre.nstars)
     R = W.rhs(opre.sys.n, 16, seed=5)
+    gpre.set_sn_beyond_lds(0)
     Z = gpre.apply_B(R)
-    assert gpre.engine_info(16)["star_global"] > 0
+    e0 = gpre.engine_info(16)
+    assert e0["star_global"] > 0
     for c in (0, 9, 15):
         assert _close(Z[:, c], opre.apply_B(R[:, c]), 1e-10), c
+    # sixteen FP64 columns: the vectors of a star move to LDS only where they fit
+    gpre.set_sn_beyond_lds(1)
+    Z1 = gpre.apply_B(R)
+    e1 = gpre.engine_info(16)
+    assert e1["star_global"] + e1["star_big_index_global"] == e0["star_global"]
+    assert np.array_equal(Z1, Z)
+    # one column: the stars beyond LDS keep only their vectors there
+    r = R[:, :1].copy()
+    gpre.set_sn_beyond_lds(0)
+    z0 = gpre.apply_B(r)
+    g0 = gpre.engine_info(1)["star_global"]
+    gpre.set_sn_beyond_lds(1)
+    z1 = gpre.apply_B(r)
+    ei = gpre.engine_info(1)
+    print("one column:", g0, {k: ei[k] for k in ("star_big", "star_big_index_global", "star_global")}, flush=True)
+    assert ei["star_big_index_global"] > 0 and ei["star_global"] + ei["star_big_index_global"] == g0
+    assert np.array_equal(z1, z0)
+    assert _close(z1[:, 0], opre.apply_B(r[:, 0]), 1e-10)
+    gpre.set_sn_beyond_lds(-1)
 
 
 def test_residual_replacement(S, orc):
