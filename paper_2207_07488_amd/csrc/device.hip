@@ -409,6 +409,16 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(double *u, double *r, cons
     any |= on[c];
   }
   if (!any) return;
+  // the first element's operands are fetched before the partials are added,
+  // so that both latencies overlap
+  const int i0 = blockIdx.x * kBlock + threadIdx.x;
+  Vec<KC> uv, rv, pv, qv;
+  if (i0 < n) {
+    uv.load(u + (size_t)i0 * KC);
+    rv.load(r + (size_t)i0 * KC);
+    pv.load(p + (size_t)i0 * KC);
+    qv.load(q + (size_t)i0 * KC);
+  }
   double a[KC];
   if constexpr (kFuseScalars<KC>) {
     double tot[KC];
@@ -427,12 +437,13 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(double *u, double *r, cons
   }
   Vec<KC> rr;
   rr.zero();
-  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
-    Vec<KC> uv, rv, pv, qv;
-    uv.load(u + (size_t)i * KC);
-    rv.load(r + (size_t)i * KC);
-    pv.load(p + (size_t)i * KC);
-    qv.load(q + (size_t)i * KC);
+  for (int i = i0; i < n; i += gridDim.x * kBlock) {
+    if (i != i0) {
+      uv.load(u + (size_t)i * KC);
+      rv.load(r + (size_t)i * KC);
+      pv.load(p + (size_t)i * KC);
+      qv.load(q + (size_t)i * KC);
+    }
 #pragma unroll
     for (int c = 0; c < KC; ++c) {
       if (!on[c]) continue;
@@ -525,6 +536,13 @@ __global__ __launch_bounds__(kBlock) void k_p_update(double *p, const double *z,
     any |= on[c];
   }
   if (!any) return;
+  // the first element's operands are fetched before the partials are added
+  const int i0 = blockIdx.x * kBlock + threadIdx.x;
+  Vec<KC> pv, zv;
+  if (i0 < n) {
+    pv.load(p + (size_t)i0 * KC);
+    zv.load(z + (size_t)i0 * KC);
+  }
   double b[KC];
   if constexpr (kFuseScalars<KC>) {
     double tot[KC];
@@ -545,10 +563,11 @@ __global__ __launch_bounds__(kBlock) void k_p_update(double *p, const double *z,
 #pragma unroll
     for (int c = 0; c < KC; ++c) b[c] = sc[c].beta;
   }
-  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
-    Vec<KC> pv, zv;
-    pv.load(p + (size_t)i * KC);
-    zv.load(z + (size_t)i * KC);
+  for (int i = i0; i < n; i += gridDim.x * kBlock) {
+    if (i != i0) {
+      pv.load(p + (size_t)i * KC);
+      zv.load(z + (size_t)i * KC);
+    }
 #pragma unroll
     for (int c = 0; c < KC; ++c)
       if (on[c]) pv.v[c] = __builtin_fma(b[c], pv.v[c], zv.v[c]);
