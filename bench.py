@@ -100,7 +100,8 @@ def serving_leg(n_requests, rate, pool_size=8, seed=5, load=0.7):
     resident by one untimed request per network first. First the saturation
     throughput: every request submitted at once. Then arrivals at `load` times
     that request rate (or at `rate` if given); latency runs from the scheduled
-    arrival to the poll that returns the result."""
+    arrival to the poll that returns the result. The server's own host thread
+    steps it; the benchmark thread only submits and collects."""
     import numpy as np
     from paper_2207_07488_amd import spnet as S
     from paper_2207_07488_amd import workloads as W
@@ -113,11 +114,13 @@ def serving_leg(n_requests, rate, pool_size=8, seed=5, load=0.7):
                                       band=W.BAND)
         pres.append(S.Precond(S.System(net), p["nH"], S.STARS_ALL, p["dir_lo"], p["dir_hi"]))
     srv = S.Server(max_columns=8, iters_per_tick=4, precision=S.FP32_STARS)
+    srv.run(True)
     # resident factors, engines and captured graphs (untimed)
     warm = [srv.submit(pre, W.rhs(pre.sys.n, 1, seed=1)) for pre in pres]
-    while warm:
-        srv.step()
-        warm = [t for t in warm if srv.poll(t) is None]
+    for t in warm:
+        if not srv.wait(t, timeout=600):
+            raise RuntimeError("serving warm-up did not finish")
+        srv.poll(t)
     pick = W.uniform01(seed + 2, 0, 2 * n_requests)
     reqs = []
     for i in range(n_requests):
@@ -126,6 +129,8 @@ def serving_leg(n_requests, rate, pool_size=8, seed=5, load=0.7):
         reqs.append((j, k, W.rhs(pres[j].sys.n, k, seed=100 + i)))
 
     def run(arrivals):
+        # the server's own host thread steps it; this thread submits at the
+        # arrival times and collects results as they become ready
         pending, lat, iters, worst = {}, [], [], 0.0
         nxt, solved = 0, 0
         t0 = time.perf_counter()
@@ -135,7 +140,13 @@ def serving_leg(n_requests, rate, pool_size=8, seed=5, load=0.7):
                 j, k, F = reqs[nxt]
                 pending[srv.submit(pres[j], F)] = (nxt, k)
                 nxt += 1
-            srv.step()
+            wait_s = arrivals[nxt] - (time.perf_counter() - t0) if nxt < n_requests else 60.0
+            if pending:
+                if not srv.wait(0, timeout=max(0.0, wait_s)):
+                    continue
+            else:
+                time.sleep(max(0.0, wait_s))
+                continue
             for t in list(pending):
                 r = srv.poll(t)
                 if r is None:
@@ -145,8 +156,6 @@ def serving_leg(n_requests, rate, pool_size=8, seed=5, load=0.7):
                 iters.extend(x["iters"] for x in r[1])
                 worst = max(worst, max(x["res_true"] for x in r[1]))
                 solved += k
-            if nxt < n_requests and not pending:
-                time.sleep(max(0.0, arrivals[nxt] - (time.perf_counter() - t0)))
         return time.perf_counter() - t0, lat, iters, worst, solved
 
     run(np.zeros(n_requests))  # untimed pass: every engine's graphs and tick shapes exist afterwards
@@ -156,6 +165,7 @@ def serving_leg(n_requests, rate, pool_size=8, seed=5, load=0.7):
     arrivals = W.poisson_arrivals(n_requests, arr_rate, seed + 1)
     makespan, lat, iters, worst, solved = run(arrivals)
     used, neng = srv.usage()
+    srv.run(False)
     srv.close()
     return {"requests": n_requests, "rhs_solved": solved,
             "saturation": {"solves_per_s": round(solved / sat_s, 2), "requests_per_s": round(sat_req_rate, 2),

@@ -451,7 +451,10 @@ sn_status sn_apply_B(sn_precond pre, int k, const double *r, double *z, int devi
  * new engine does not fit in hbm_budget, idle engines are evicted (least
  * recently used first) together with the factors the server uploaded for
  * them. Unfactored preconditioners are factored on host worker threads while
- * other requests iterate. A server handle is used from one thread at a time.
+ * other requests iterate. Either the caller steps the server (sn_server_step,
+ * or sn_server_wait, which steps until a result is ready) or the server's own
+ * host thread does (sn_server_run). Calls on one server are serialised by a
+ * lock, so submit, poll and wait may come from several threads.
  */
 typedef struct {
   int64_t hbm_budget;     /* bytes of device memory for engines and the factors the server uploads */
@@ -487,6 +490,25 @@ sn_status sn_server_step(sn_server srv, int32_t *n_active, int32_t *n_queued);
  * (SN_OK when done) and keeps the result. A request that failed returns its
  * error once. */
 sn_status sn_server_poll(sn_server srv, uint64_t ticket, double *u, sn_solve_info *info);
+/*
+ * enable = 1: start the server's own host thread, which steps the server
+ * (without blocking between steps) while requests are queued or iterating
+ * and sleeps otherwise; the HIP device current in the calling thread is made
+ * current in it. enable = 0: stop and join it (iterations already queued stay
+ * queued; later steps continue them). While the thread runs, sn_server_step
+ * returns SN_EBUSY. If the thread meets a device error it fails every pending
+ * request with that error and stops; later submissions return it.
+ */
+sn_status sn_server_run(sn_server srv, int enable);
+/*
+ * Wait until request `ticket` is done or has failed (ticket = 0: until some
+ * request is, whose result has not been collected yet), at most timeout_s
+ * seconds; the result stays for sn_server_poll. Without the server's thread
+ * the calling thread steps the server meanwhile. SN_OK when a result is
+ * ready, SN_EBUSY on timeout (or when nothing is pending), SN_EINVAL for an
+ * unknown ticket.
+ */
+sn_status sn_server_wait(sn_server srv, uint64_t ticket, double timeout_s);
 /* Device bytes the server holds (engines and the factors it uploaded). */
 sn_status sn_server_usage(sn_server srv, int64_t *device_bytes, int32_t *n_engines);
 void sn_server_destroy(sn_server srv);

@@ -2732,6 +2732,14 @@ void device_stats(Precond &pre, sn_kernel_stats *st) {
 
 int64_t device_bytes(const Precond &pre) { return pre.dev ? pre.dev->bytes : 0; }
 
+int device_current() {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  return dev;
+}
+
+void device_bind(int dev) { HIPCHK(hipSetDevice(dev)); }
+
 void device_set_star_split(Precond &pre, int64_t n_sn) {
   DeviceState &d = *pre.dev;
   for (auto &e : d.solve_engine) {

@@ -188,6 +188,9 @@ void engine_admit(Engine *e, int k, const int32_t *cols, const double *f, const 
 void engine_tick(Engine *e, int iters, bool use_graph);
 bool engine_query(Engine *e);  // the last tick has completed
 void engine_wait(Engine *e);
+// the calling host thread's current HIP device, and making `dev` current
+int device_current();
+void device_bind(int dev);
 void engine_status(const Engine *e, ColumnStatus *out);  // kc entries, as of the last completed tick
 // copy column c of u to host (stride ld) and free the column
 void engine_retire(Engine *e, int c, double *u, int64_t ld);

@@ -4,10 +4,12 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <condition_variable>
 #include <cstring>
 #include <deque>
 #include <future>
 #include <map>
+#include <mutex>
 #include <thread>
 #include <unordered_map>
 #include <vector>
@@ -69,6 +71,14 @@ struct sn_server_s {
   std::vector<std::unique_ptr<EngineSlot>> engines;
   // host factorisations in flight or done, per preconditioner
   std::unordered_map<Precond *, std::shared_future<std::shared_ptr<HostFactors>>> factoring;
+  // every call holds mu; the driver thread (sn_server_run) steps the server
+  // while there is work and sleeps on cv_work otherwise; cv_done wakes waiters
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::thread driver;
+  bool driving = false, stop = false;
+  sn_status drive_err = SN_OK;
+  std::string drive_msg;
 
   int64_t used() const {
     int64_t b = 0;
@@ -80,7 +90,26 @@ struct sn_server_s {
       if (e->pre.get() == p) return e.get();
     return nullptr;
   }
+  bool has_work() const {
+    if (!queue.empty()) return true;
+    for (auto &e : engines)
+      if (e->ticking || e->active_columns() > 0) return true;
+    return false;
+  }
+  void stop_driver() {
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      if (!driving) return;
+      stop = true;
+    }
+    cv_work.notify_all();
+    driver.join();
+    std::lock_guard<std::mutex> lk(mu);
+    driving = false;
+    stop = false;
+  }
   ~sn_server_s() {
+    stop_driver();
     for (auto &e : engines)
       if (e->eng) spnet::engine_wait(e->eng);
     for (auto &f : factoring) f.second.wait();
@@ -223,6 +252,139 @@ void retire_finished(sn_server_s &S, EngineSlot &e) {
   }
 }
 
+// One scheduling step (see sn_server_step). block: wait for the first tick
+// to complete (or a host factorisation, when nothing iterates); else only
+// look. Returns whether anything changed.
+bool step_once(sn_server_s &S, bool block) {
+  ++S.tick_no;
+  bool any_ticking = false, progressed = false;
+  for (auto &e : S.engines) any_ticking |= e->ticking;
+  // 1. engines whose tick has completed: retire their converged columns.
+  //    Engines advance independently: a small network does not wait for the
+  //    ticks of a large one.
+  do {
+    for (auto &e : S.engines)
+      if (e->ticking && spnet::engine_query(e->eng)) {
+        e->ticking = false;
+        retire_finished(S, *e);
+        progressed = true;
+      }
+    if (block && any_ticking && !progressed) std::this_thread::yield();
+  } while (block && any_ticking && !progressed);
+  // nothing iterates but requests wait for their host factorisation: wait
+  // for the first of those to finish, so that a blocking step makes progress
+  if (block && !any_ticking) {
+    bool running = false;
+    for (auto &e : S.engines) running |= e->active_columns() > 0;
+    if (!running)
+      for (Request *r : S.queue) {
+        auto it = S.factoring.find(r->pre.get());
+        if (it != S.factoring.end()) {
+          it->second.wait();
+          break;
+        }
+      }
+  }
+  // 2. admit queued requests that fit (in arrival order; a request that
+  //    cannot start yet does not hold back later ones)
+  for (auto it = S.queue.begin(); it != S.queue.end();) {
+    Request *r = *it;
+    EngineSlot *e = engine_for(S, r);
+    if (r->state == Request::FAILED) {
+      it = S.queue.erase(it);
+      progressed = true;
+      continue;
+    }
+    if (!e || e->ticking) {
+      ++it;
+      continue;
+    }
+    std::vector<int32_t> cols;
+    for (int c = 0; c < S.o.max_columns && (int)cols.size() < r->k; ++c)
+      if (!e->col_req[c]) cols.push_back(c);
+    if ((int)cols.size() < r->k) {
+      ++it;
+      continue;
+    }
+    std::vector<double> rt((size_t)r->k, r->rtol);
+    std::vector<int64_t> mi((size_t)r->k, r->max_iter);
+    spnet::engine_admit(e->eng, r->k, cols.data(), r->f.data(), rt.data(), mi.data());
+    for (int j = 0; j < r->k; ++j) {
+      e->col_req[cols[j]] = r;
+      e->col_j[cols[j]] = j;
+    }
+    r->remaining = r->k;
+    r->state = Request::RUNNING;
+    r->t_admit = std::chrono::steady_clock::now();
+    r->f.clear();
+    r->f.shrink_to_fit();
+    it = S.queue.erase(it);
+    progressed = true;
+  }
+  // 3. queue the next iterations of every idle engine with running columns
+  for (auto &e : S.engines)
+    if (!e->ticking && e->active_columns() > 0) {
+      spnet::engine_tick(e->eng, S.o.iters_per_tick, S.o.use_graph != 0);
+      e->ticking = true;
+      e->last_tick = S.tick_no;
+      progressed = true;
+    }
+  return progressed;
+}
+
+void counts(sn_server_s &S, int32_t *n_active, int32_t *n_queued) {
+  int32_t act = 0;
+  for (auto &kv : S.reqs) act += kv.second->state == Request::RUNNING;
+  if (n_active) *n_active = act;
+  if (n_queued) *n_queued = (int32_t)S.queue.size();
+}
+
+// The driver thread: steps the server while it has work (without blocking,
+// so that calls from other threads get the lock between steps), sleeps on
+// cv_work otherwise. A device error stops it
+// and fails every request not yet done.
+void drive(sn_server_s *S, int device) {
+  std::unique_lock<std::mutex> lk(S->mu);
+  try {
+    spnet::device_bind(device);
+  } catch (const spnet::Error &e) {
+    S->drive_err = e.code;
+    S->drive_msg = e.what();
+    S->stop = true;
+  }
+  while (!S->stop) {
+    if (!S->has_work()) {
+      S->cv_work.wait(lk);
+      continue;
+    }
+    bool progressed = false;
+    try {
+      progressed = step_once(*S, false);
+    } catch (const spnet::Error &e) {
+      S->drive_err = e.code;
+      S->drive_msg = e.what();
+    } catch (const std::exception &e) {
+      S->drive_err = SN_EDEVICE;
+      S->drive_msg = e.what();
+    }
+    if (S->drive_err != SN_OK) {
+      for (auto &kv : S->reqs)
+        if (kv.second->state == Request::QUEUED || kv.second->state == Request::RUNNING)
+          fail_request(kv.second.get(), S->drive_err, "server thread stopped: " + S->drive_msg);
+      S->queue.clear();
+      S->cv_done.notify_all();
+      break;
+    }
+    if (progressed) S->cv_done.notify_all();
+    // let other callers take the lock between steps; while ticks are in
+    // flight the thread spins (a sleep would add the timer's slack, tens of
+    // microseconds, to every tick)
+    lk.unlock();
+    std::this_thread::yield();
+    lk.lock();
+  }
+}
+
 }  // namespace
 
 extern "C" {
@@ -268,6 +430,8 @@ sn_status sn_server_submit(sn_server srv, sn_precond pre, int k, const double *f
     if (pre->p->dev &&
         spnet::engine_footprint(*pre->p, srv->o.max_columns) > srv->o.hbm_budget)
       spnet::fail(SN_EBUSY, "request exceeds the server's device-memory budget");
+    std::lock_guard<std::mutex> lk(srv->mu);
+    if (srv->drive_err != SN_OK) spnet::fail(srv->drive_err, "server thread stopped: " + srv->drive_msg);
     auto r = std::make_unique<Request>();
     r->ticket = srv->next_ticket++;
     r->pre = pre->p;
@@ -282,87 +446,18 @@ sn_status sn_server_submit(sn_server srv, sn_precond pre, int k, const double *f
     srv->queue.push_back(r.get());
     *ticket = r->ticket;
     srv->reqs[r->ticket] = std::move(r);
+    srv->cv_work.notify_all();
   });
 }
 
 sn_status sn_server_step(sn_server srv, int32_t *n_active, int32_t *n_queued) {
   return spnet::guarded([&] {
     if (!srv) spnet::fail(SN_EINVAL, "null server");
-    sn_server_s &S = *srv;
-    ++S.tick_no;
-    // 1. engines whose tick has completed: retire their converged columns.
-    //    Engines advance independently: a small network does not wait for the
-    //    ticks of a large one. When none has completed yet, wait for the first.
-    bool any_ticking = false, progressed = false;
-    for (auto &e : S.engines) any_ticking |= e->ticking;
-    while (any_ticking && !progressed) {
-      for (auto &e : S.engines)
-        if (e->ticking && spnet::engine_query(e->eng)) {
-          e->ticking = false;
-          retire_finished(S, *e);
-          progressed = true;
-        }
-      if (!progressed) std::this_thread::yield();
-    }
-    // nothing iterates but requests wait for their host factorisation: wait
-    // for the first of those to finish, so that a step always makes progress
-    if (!any_ticking) {
-      bool running = false;
-      for (auto &e : S.engines) running |= e->active_columns() > 0;
-      if (!running)
-        for (Request *r : S.queue) {
-          auto it = S.factoring.find(r->pre.get());
-          if (it != S.factoring.end()) {
-            it->second.wait();
-            break;
-          }
-        }
-    }
-    // 2. admit queued requests that fit (in arrival order; a request that
-    //    cannot start yet does not hold back later ones)
-    for (auto it = S.queue.begin(); it != S.queue.end();) {
-      Request *r = *it;
-      EngineSlot *e = engine_for(S, r);
-      if (r->state == Request::FAILED) {
-        it = S.queue.erase(it);
-        continue;
-      }
-      if (!e || e->ticking) {
-        ++it;
-        continue;
-      }
-      std::vector<int32_t> cols;
-      for (int c = 0; c < S.o.max_columns && (int)cols.size() < r->k; ++c)
-        if (!e->col_req[c]) cols.push_back(c);
-      if ((int)cols.size() < r->k) {
-        ++it;
-        continue;
-      }
-      std::vector<double> rt((size_t)r->k, r->rtol);
-      std::vector<int64_t> mi((size_t)r->k, r->max_iter);
-      spnet::engine_admit(e->eng, r->k, cols.data(), r->f.data(), rt.data(), mi.data());
-      for (int j = 0; j < r->k; ++j) {
-        e->col_req[cols[j]] = r;
-        e->col_j[cols[j]] = j;
-      }
-      r->remaining = r->k;
-      r->state = Request::RUNNING;
-      r->t_admit = std::chrono::steady_clock::now();
-      r->f.clear();
-      r->f.shrink_to_fit();
-      it = S.queue.erase(it);
-    }
-    // 3. queue the next iterations of every idle engine with running columns
-    for (auto &e : S.engines)
-      if (!e->ticking && e->active_columns() > 0) {
-        spnet::engine_tick(e->eng, S.o.iters_per_tick, S.o.use_graph != 0);
-        e->ticking = true;
-        e->last_tick = S.tick_no;
-      }
-    int32_t act = 0;
-    for (auto &kv : S.reqs) act += kv.second->state == Request::RUNNING;
-    if (n_active) *n_active = act;
-    if (n_queued) *n_queued = (int32_t)S.queue.size();
+    std::lock_guard<std::mutex> lk(srv->mu);
+    if (srv->driving) spnet::fail(SN_EBUSY, "the server's own thread steps it (sn_server_run)");
+    step_once(*srv, true);
+    srv->cv_done.notify_all();
+    counts(*srv, n_active, n_queued);
   });
 }
 
@@ -370,23 +465,29 @@ sn_status sn_server_poll(sn_server srv, uint64_t ticket, double *u, sn_solve_inf
   sn_status rc = SN_OK;
   const sn_status g = spnet::guarded([&] {
     if (!srv) spnet::fail(SN_EINVAL, "null server");
-    auto it = srv->reqs.find(ticket);
-    if (it == srv->reqs.end()) spnet::fail(SN_EINVAL, "unknown ticket");
-    Request &r = *it->second;
-    if (r.state == Request::FAILED) {
-      const sn_status code = r.err;
-      const std::string msg = r.msg;
+    std::unique_ptr<Request> done;
+    {
+      std::lock_guard<std::mutex> lk(srv->mu);
+      auto it = srv->reqs.find(ticket);
+      if (it == srv->reqs.end()) spnet::fail(SN_EINVAL, "unknown ticket");
+      Request &r = *it->second;
+      if (r.state == Request::FAILED) {
+        const sn_status code = r.err;
+        const std::string msg = r.msg;
+        srv->reqs.erase(it);
+        spnet::fail(code, msg);
+      }
+      if (r.state != Request::DONE) {
+        rc = SN_EBUSY;
+        return;
+      }
+      if (!u && !info) return;  // status query: the result stays
+      // the result leaves the server; it is copied out without the lock
+      done = std::move(it->second);
       srv->reqs.erase(it);
-      spnet::fail(code, msg);
     }
-    if (r.state != Request::DONE) {
-      rc = SN_EBUSY;
-      return;
-    }
-    if (!u && !info) return;  // status query: the result stays
-    if (u) std::memcpy(u, r.u.data(), r.u.size() * sizeof(double));
-    if (info) std::memcpy(info, r.info.data(), r.info.size() * sizeof(sn_solve_info));
-    srv->reqs.erase(it);
+    if (u) std::memcpy(u, done->u.data(), done->u.size() * sizeof(double));
+    if (info) std::memcpy(info, done->info.data(), done->info.size() * sizeof(sn_solve_info));
   });
   return g != SN_OK ? g : rc;
 }
@@ -394,9 +495,64 @@ sn_status sn_server_poll(sn_server srv, uint64_t ticket, double *u, sn_solve_inf
 sn_status sn_server_usage(sn_server srv, int64_t *device_bytes, int32_t *n_engines) {
   return spnet::guarded([&] {
     if (!srv) spnet::fail(SN_EINVAL, "null server");
+    std::lock_guard<std::mutex> lk(srv->mu);
     if (device_bytes) *device_bytes = srv->used();
     if (n_engines) *n_engines = (int32_t)srv->engines.size();
   });
+}
+
+sn_status sn_server_run(sn_server srv, int enable) {
+  return spnet::guarded([&] {
+    if (!srv) spnet::fail(SN_EINVAL, "null server");
+    if (!enable) {
+      srv->stop_driver();
+      return;
+    }
+    std::lock_guard<std::mutex> lk(srv->mu);
+    if (srv->driving) return;
+    if (srv->drive_err != SN_OK) spnet::fail(srv->drive_err, "server thread stopped: " + srv->drive_msg);
+    const int device = spnet::device_current();
+    srv->stop = false;
+    srv->driver = std::thread(drive, srv, device);
+    srv->driving = true;
+  });
+}
+
+sn_status sn_server_wait(sn_server srv, uint64_t ticket, double timeout_s) {
+  sn_status rc = SN_OK;
+  const sn_status g = spnet::guarded([&] {
+    if (!srv) spnet::fail(SN_EINVAL, "null server");
+    if (!(timeout_s >= 0.0)) spnet::fail(SN_EINVAL, "timeout must be non-negative");
+    std::unique_lock<std::mutex> lk(srv->mu);
+    auto finished = [&]() {
+      if (ticket != 0) {
+        auto it = srv->reqs.find(ticket);
+        if (it == srv->reqs.end()) spnet::fail(SN_EINVAL, "unknown ticket");
+        return it->second->state == Request::DONE || it->second->state == Request::FAILED;
+      }
+      for (auto &kv : srv->reqs)
+        if (kv.second->state == Request::DONE || kv.second->state == Request::FAILED) return true;
+      return false;
+    };
+    const auto until = std::chrono::steady_clock::now() +
+                       std::chrono::duration_cast<std::chrono::steady_clock::duration>(
+                           std::chrono::duration<double>(std::min(timeout_s, 1e6)));
+    while (!finished()) {
+      if (srv->driving) {
+        if (srv->cv_done.wait_until(lk, until) == std::cv_status::timeout && !finished()) {
+          rc = SN_EBUSY;
+          return;
+        }
+      } else {
+        if (!srv->has_work() || std::chrono::steady_clock::now() >= until) {
+          rc = SN_EBUSY;
+          return;
+        }
+        step_once(*srv, true);
+      }
+    }
+  });
+  return g != SN_OK ? g : rc;
 }
 
 void sn_server_destroy(sn_server srv) { delete srv; }

@@ -128,6 +128,8 @@ SIGNATURES = {
     "sn_server_step": (C.c_int, [_P, C.POINTER(_i32), C.POINTER(_i32)]),
     "sn_server_poll": (C.c_int, [_P, C.c_uint64, _P, C.POINTER(SolveInfo)]),
     "sn_server_usage": (C.c_int, [_P, C.POINTER(_i64), C.POINTER(_i32)]),
+    "sn_server_run": (C.c_int, [_P, C.c_int]),
+    "sn_server_wait": (C.c_int, [_P, C.c_uint64, _dbl]),
     "sn_server_destroy": (None, [_P]),
 }
 
@@ -455,6 +457,20 @@ class Server:
         b, n = _i64(), _i32()
         _check(lib().sn_server_usage(self.h, C.byref(b), C.byref(n)))
         return b.value, n.value
+
+    def run(self, enable=True):
+        """Start (or stop) the server's own host thread that steps it."""
+        _check(lib().sn_server_run(self.h, int(bool(enable))))
+
+    def wait(self, ticket=0, timeout=60.0):
+        """Block until `ticket` (0: any request) has a result, at most `timeout`
+        seconds; True when a result is ready, False on timeout. The result stays
+        for poll()."""
+        rc = lib().sn_server_wait(self.h, int(ticket), float(timeout))
+        if rc == SN_EBUSY:
+            return False
+        _check(rc)
+        return True
 
     def close(self):
         if getattr(self, "h", None) and _lib is not None:

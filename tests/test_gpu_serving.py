@@ -95,6 +95,52 @@ def test_same_alone_and_in_the_mix(S, pres):
         assert all(x["converged"] for x in info_mix)
 
 
+def test_server_thread_and_wait(S, pres):
+    """The server's own host thread steps it (sn_server_run): requests submitted
+    from this thread while it runs, some from a second Python thread, give the
+    same results bit for bit as alone; sn_server_step is refused meanwhile;
+    wait(0) returns once any result is ready; after the thread stops, wait()
+    steps the server from the calling thread."""
+    import threading
+    alone = _alone(S, pres)
+    srv = S.Server(max_columns=8, iters_per_tick=4)
+    srv.run(True)
+    srv.run(True)  # already running: no second thread
+    with pytest.raises(S.SpnetError) as ei:
+        srv.step()
+    assert ei.value.code == S.SN_EBUSY
+    tickets = [None] * len(REQUESTS)
+
+    def submit(idx):
+        for i in idx:
+            name, k, seed = REQUESTS[i]
+            tickets[i] = srv.submit(pres[name], _rhs(pres[name], k, seed))
+
+    th = threading.Thread(target=submit, args=(range(1, len(REQUESTS), 2),))
+    th.start()
+    submit(range(0, len(REQUESTS), 2))
+    th.join()
+    assert srv.wait(0, timeout=120)
+    got = {}
+    for t in tickets:
+        assert srv.wait(t, timeout=120)
+        got[t] = srv.poll(t)
+    for i, t in enumerate(tickets):
+        u, info = got[t]
+        u_alone, info_alone = alone[i]
+        assert [x["iters"] for x in info] == [x["iters"] for x in info_alone]
+        assert np.array_equal(u.reshape(u_alone.shape), u_alone), REQUESTS[i]
+    srv.run(False)
+    # without the thread, wait() steps the server itself
+    name, k, seed = REQUESTS[0]
+    t = srv.submit(pres[name], _rhs(pres[name], k, seed))
+    assert srv.wait(t, timeout=120)
+    u, info = srv.poll(t)
+    assert np.array_equal(u.reshape(alone[0][0].shape), alone[0][0])
+    assert not srv.wait(0, timeout=0.01)  # nothing pending
+    srv.close()
+
+
 def test_requests_admitted_together_into_one_engine(S, pres):
     """Several requests on one network submitted before a step start in the same
     engine at once; each converges as it does alone (regression: a later
