@@ -949,21 +949,45 @@ __global__ __launch_bounds__(64) void k_coarse_sym(const TA *__restrict__ Ks, co
   }
 }
 
-// c (rows below m0) = the sum of the T partial blocks of each block row: one
-// wavefront per output, lane l adding blocks l, l + 64, ... in turn, then the
-// wavefront's fixed reduction tree (the same order for every KC)
+// c (rows below m0) = the sum of the T partial blocks of each block row R:
+// one workgroup of four wavefronts per block row; lane r of wavefront w adds
+// row r of the blocks C = w, w + 4, w + 8, ... in that order (one coalesced
+// access per lane and block, eight blocks in flight), then the four wavefront
+// sums are added in the order w = 0, 1, 2, 3 (the same order for every KC).
 template <int KC>
 __global__ __launch_bounds__(kBlock) void k_coarse_fold(const double *__restrict__ part, int T, double *cvec, int m0,
                                                         const CgScalars *sc, int sel) {
+  static_assert(kBlock == 256, "four wavefronts per block row");
   if (!any_selected<KC>(sc, sel, 0u)) return;
-  const int w = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
-  if (w >= m0 * KC) return;
-  const int row = w / KC, col = w % KC, R = row >> 6, r = row & 63;
-  const double *pp = part + ((size_t)R * T * 64 + r) * KC + col;
-  double v = 0.0;
-  for (int C = lane; C < T; C += 64) v += pp[(size_t)C * 64 * KC];
-  v = wave_sum(v);
-  if (lane == 0) cvec[(size_t)row * KC + col] = v;
+  __shared__ double red[3][64 * KC];
+  const int R = blockIdx.x, w = threadIdx.x >> 6, r = threadIdx.x & 63;
+  const double *pp = part + ((size_t)R * T * 64 + r) * KC;
+  Vec<KC> acc;
+  acc.zero();
+  for (int C0 = w; C0 < T; C0 += 32) {
+    Vec<KC> v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u].load(pp + (size_t)min(C0 + 4 * u, T - 1) * 64 * KC);
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (C0 + 4 * u < T) {
+#pragma unroll
+        for (int c = 0; c < KC; ++c) acc.v[c] += v[u].v[c];
+      }
+  }
+  if (w > 0) {
+#pragma unroll
+    for (int c = 0; c < KC; ++c) red[w - 1][r * KC + c] = acc.v[c];
+  }
+  __syncthreads();
+  if (w == 0) {
+#pragma unroll
+    for (int ww = 0; ww < 3; ++ww)
+#pragma unroll
+      for (int c = 0; c < KC; ++c) acc.v[c] += red[ww][r * KC + c];
+    const int row = R * 64 + r;
+    if (row < m0) acc.store(cvec + (size_t)row * KC);
+  }
 }
 
 // a.b partials per column
@@ -1969,7 +1993,7 @@ void launch_B(Engine &e, const double *r, double *z, int sel, bool dot, hipStrea
         else
           hipLaunchKernelGGL((k_coarse_sym<double, KC>), dim3(gs), dim3(64), 0, cs, d.Ksym64.p, d.sym_tiles.p,
                              (int)d.sym_T, e.rH.p, e.cpart.p, e.sc.p, sel);
-        hipLaunchKernelGGL(k_coarse_fold<KC>, dim3(nblk(d.m0 * KC * 64)), dim3(kBlock), 0, cs, e.cpart.p,
+        hipLaunchKernelGGL(k_coarse_fold<KC>, dim3((unsigned)d.sym_T), dim3(kBlock), 0, cs, e.cpart.p,
                            (int)d.sym_T, e.c.p, (int)d.m0, e.sc.p, sel);
       } else if (d.coarse32 && e.coarse_w1)
         hipLaunchKernelGGL((k_coarse_mm1<float, KC>), dim3(g1), dim3(64), 0, cs, d.Kinv32.p, (int)d.ld0, e.rH.p,
