@@ -354,8 +354,8 @@ typedef struct {
   int32_t star_band_prio; /* the band wavefronts of the star_band_prio longest stars of each band launch
                              run at raised instruction-issue priority (0: none) */
   int32_t star_global_waves; /* wavefronts per star of the star_global stars (4 or 16) */
-  int32_t star_big_index_global; /* of the star_big stars, those whose vectors alone take the LDS (their
-                                    index part and values are read from global memory) */
+  int32_t star_big_index_global; /* of the star_big stars, those whose vectors (or x and y alone) take the
+                                    LDS, their index part, values (and update slots) read from global memory */
   int32_t coarse_first;  /* 1: the coarse solve runs before the local solves (and its restriction
                             also runs the convergence test), 0: beside them on a second stream */
   int32_t coarse_kernel; /* 0: the coarse product in 16-wavefront workgroups of 8 rows, 1: one
@@ -389,8 +389,9 @@ sn_status sn_precond_set_star_split(sn_precond pre, int64_t n_sn);
  * Where the supernodal stars whose index part and vectors together exceed the
  * LDS of a compute unit keep their data. mode = 0: everything in global memory
  * (star_global); mode = 1: the vectors in LDS and the index part and values
- * read from global memory wherever the vectors alone fit (star_big_index_global,
- * the others stay in global memory); mode = -1 (default): both are measured
+ * read from global memory wherever the vectors alone fit, else (workgroup
+ * teams) x and y in LDS and the update slots in global memory
+ * (star_big_index_global; the others stay in global memory); mode = -1 (default): both are measured
  * when an engine is created and the faster kept. Both give the same results
  * bit for bit. Drops the preconditioner's solve engines. Errors: SN_EINVAL if
  * not factored or mode outside -1..1.

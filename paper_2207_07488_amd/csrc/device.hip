@@ -2317,6 +2317,14 @@ void plan_sn(Engine &e, int lcap, int cw, int nteam) {
       o[1].push_back(s);
       l1 = std::max(l1, vec);
       ++nig;
+    } else if (e.sn_iglobal && vsets == 1 && nteam > e.kc / cw && 2 * xb <= kMaxLds) {
+      // x and y in LDS, the update slots in global memory (workgroup teams
+      // only: their phases end in workgroup barriers)
+      o[1].push_back(s);
+      l1 = std::max(l1, 2 * xb);
+      vs[s] = vbytes;
+      vbytes += ub;
+      ++nig;
     } else {
       o[2].push_back(s);
       vs[s] = vbytes;
@@ -2570,8 +2578,18 @@ int64_t engine_footprint(const Precond &pre, int kc) {
   const int prec = pre.dev ? pre.finfo.star_precision : pre.precision;
   const int64_t ts = prec == SN_PREC_FP64 ? 8 : 4;
   const int64_t T = pre.m0 > 0 ? m0 / 64 : 0;
+  // vectors of the supernodal stars kept in global memory: at most x, y and
+  // the update slots of every star (about twice as many updates as positions
+  // before factoring)
+  int64_t vsc = 0;
+  if (pre.dev) {
+    for (size_t st = 0; st < pre.dev->h_n.size(); ++st)
+      vsc += ((2 * (int64_t)pre.dev->h_n[st] + (int64_t)pre.dev->h_nu[st]) * kc * ts + 48);
+  } else {
+    vsc = (int64_t)pre.star_dofs.size() * 5 * kc * ts;
+  }
   return (6 * npad * kc + 2 * m0 * kc + (int64_t)2 * kc * kMaxGrid + T * T * 64 * kc) * 8 +
-         kc * (int64_t)sizeof(CgScalars) + (int64_t)pre.star_dofs.size() * kc * ts;
+         kc * (int64_t)sizeof(CgScalars) + (int64_t)pre.star_dofs.size() * kc * ts + vsc;
 }
 
 Engine *engine_create(Precond &pre, int kc) {

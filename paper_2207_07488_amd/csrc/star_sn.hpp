@@ -290,8 +290,10 @@ __device__ __forceinline__ void sn_star(unsigned char *lds, const SnArgs &a, con
   const bool coop = nteam > NCH;
   const uint32_t vsets = coop ? 1u : (uint32_t)nteam;
   // the index part is staged when it fits beside the vectors (else it is read
-  // from global memory), the values when they fit too
+  // from global memory), the values when they fit too; the update slots stay
+  // in global memory (a.vscratch) when x and y alone take the LDS
   const bool il = hd.idx_bytes + vsets * vec <= (uint32_t)a.lds_bytes;
+  const bool ul = il || vsets * vec <= (uint32_t)a.lds_bytes;
   const bool vl = il && hd.idx_bytes + hd.val_bytes + vsets * vec <= (uint32_t)a.lds_bytes;
   const uint32_t staged = il ? hd.idx_bytes + (vl ? hd.val_bytes : 0u) : 0u;
   {
@@ -321,7 +323,8 @@ __device__ __forceinline__ void sn_star(unsigned char *lds, const SnArgs &a, con
   B.alist = reinterpret_cast<const uint16_t *>(ib + hd.off_alist);
   B.bpos = reinterpret_cast<const uint16_t *>(ib + hd.off_bpos);
   unsigned char *tv = lds + staged + (coop ? 0u : (uint32_t)team * vec);
-  T *x = reinterpret_cast<T *>(tv), *y = reinterpret_cast<T *>(tv + xb), *u = reinterpret_cast<T *>(tv + 2 * xb);
+  T *x = reinterpret_cast<T *>(tv), *y = reinterpret_cast<T *>(tv + xb);
+  T *u = ul ? reinterpret_cast<T *>(tv + 2 * xb) : reinterpret_cast<T *>(a.vscratch + a.st_vs[st]);
   const int32_t *dofs = a.pos_dof + a.st_pos[st];
   T *out = static_cast<T *>(a.slots) + (size_t)a.st_pos[st] * KC;
   __syncthreads();
