@@ -356,6 +356,7 @@ typedef struct {
   int32_t star_global_waves; /* wavefronts per star of the star_global stars (4 or 16) */
   int32_t star_big_index_global; /* of the star_big stars, those whose vectors (or x and y alone) take the
                                     LDS, their index part, values (and update slots) read from global memory */
+  int32_t star_twins;     /* band stars swept as two chains (sn_precond_set_band_twins) */
   int32_t coarse_first;  /* 1: the coarse solve runs before the local solves (and its restriction
                             also runs the convergence test), 0: beside them on a second stream */
   int32_t coarse_kernel; /* 0: the coarse product in 16-wavefront workgroups of 8 rows, 1: one
@@ -397,6 +398,22 @@ sn_status sn_precond_set_star_split(sn_precond pre, int64_t n_sn);
  * not factored or mode outside -1..1.
  */
 sn_status sn_precond_set_sn_beyond_lds(sn_precond pre, int mode);
+
+/*
+ * The two-chain form of the band sweeps for the longest stars. A star's RCM
+ * order is cut into a top part, a separator (the positions coupled to the top
+ * part) and a bottom part; one factor in the order (top, bottom, separator) is
+ * swept as two chains by two wavefronts of one workgroup, (top, separator) and
+ * (bottom reversed, separator), which meet at the separator, so a long star's
+ * dependent chain is about half as long. Stars of at least 512 positions get
+ * this factor when a cut saves a quarter of the steps without widening the
+ * window. By default whether to use it, and from which star size on, is
+ * measured when the preconditioner first solves and kept for every batch width
+ * (it rounds differently); min_positions > 0 uses it for the stars of at least
+ * that many positions, 0 never, -1 returns to measuring. Drops the
+ * preconditioner's solve engines. Errors: SN_EINVAL if not factored.
+ */
+sn_status sn_precond_set_band_twins(sn_precond pre, int64_t min_positions);
 
 /*
  * The coarse kernel and its placement beside the local solves (the product

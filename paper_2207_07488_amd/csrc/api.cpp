@@ -273,6 +273,13 @@ sn_status sn_precond_set_star_split(sn_precond pre, int64_t n_sn) {
   });
 }
 
+sn_status sn_precond_set_band_twins(sn_precond pre, int64_t min_positions) {
+  return guarded([&] {
+    REQUIRE(pre && pre->p->dev, "null argument or not factored");
+    spnet::device_set_band_twins(*pre->p, min_positions);
+  });
+}
+
 sn_status sn_precond_set_sn_beyond_lds(sn_precond pre, int mode) {
   return guarded([&] {
     REQUIRE(pre && pre->p->dev, "null argument or not factored");

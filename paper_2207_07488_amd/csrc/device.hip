@@ -1148,6 +1148,17 @@ struct DeviceState {
   std::vector<uint32_t> h_idx, h_val, h_nu;  // per star: blob part bytes, u-slots
   std::vector<uint8_t> h_sn_ok;               // per star: the supernodal layout holds it
   std::vector<int64_t> h_bytes_band, h_bytes_sn;  // per star: algorithmic bytes of one solve of one column
+  // two-chain band stars: per star its twin id (-1: none), per twin its chain
+  // length and algorithmic bytes; the chains are units nstars + 2 t (+ 1) of
+  // the per-star device arrays
+  std::vector<int32_t> h_twin, h_twin_len;
+  std::vector<int64_t> h_bytes_twin;
+  DBuf<int32_t> tw_star, tw_K, pos_map;
+  int32_t ntwin = 0;
+  // twins on: stars with at least twin_min positions and a two-chain factor
+  // run k_star_twin; per preconditioner like the split (the two forms round
+  // differently); -1: measured at the first engine, 0: off
+  int64_t twin_min = -1;
   // stars on the supernodal path besides those the band kernel cannot take:
   // measured when the first engine is created (or set by the caller) and then
   // shared by every engine, since the two kernels round differently and a
@@ -1155,6 +1166,7 @@ struct DeviceState {
   int64_t split = -1;
   int32_t coarse_launch = -1;  // fixed coarse kernel and placement (kernel + 2 placement), -1: measured
   int32_t sn_beyond = -1;      // supernodal stars beyond LDS: 0 global memory, 1 vectors in LDS, -1 measured
+  int64_t twin_force = -1;     // caller's twin threshold (0 off, > 0 positions), -1: measured
   // coarse
   // K_0^{-1}, symmetric, zero-padded to ld0 x ld0 (ld0 a multiple of 64): FP32 in the mixed form
   // unless the coarse factor's pivot ratio rules it out, else FP64
@@ -1205,6 +1217,11 @@ struct Engine {
   // band launches: stars of the band path, narrow and wide windows, longest first
   DBuf<int32_t> b_narrow, b_wide;
   int32_t n_narrow = 0, n_wide = 0;
+  // two-chain stars (twin ids, longest first), their vectors
+  DBuf<int32_t> b_twin;
+  int32_t n_twin = 0;
+  DBuf<int64_t> tw_vs;
+  DBuf<unsigned char> tw_scratch;
   int32_t star_cap = 0, star_lds = 0;          // resident band wavefronts per SIMD (0: no limit) and its LDS reservation
   bool star_lv = true;                         // band working vectors in LDS (where they fit)
   int32_t star_prio = 0;                       // band wavefronts of the longest stars at raised issue priority
@@ -1230,6 +1247,8 @@ struct Engine {
   hipStream_t aux = nullptr;     // wide band stars run beside the narrow ones
   hipStream_t aux2 = nullptr;    // the coarse solve runs beside the star sweeps
   hipStream_t aux3 = nullptr;    // the supernodal stars run beside the band ones
+  hipStream_t aux4 = nullptr;    // the two-chain stars run beside the other band stars
+  hipEvent_t fork4 = nullptr, join4 = nullptr;
   hipEvent_t fork = nullptr, join = nullptr, fork2 = nullptr, join2 = nullptr, fork3 = nullptr, join3 = nullptr;
   hipEvent_t tick_done = nullptr;
   bool in_flight = false;
@@ -1250,6 +1269,9 @@ struct Engine {
     if (fork3) (void)hipEventDestroy(fork3);
     if (join3) (void)hipEventDestroy(join3);
     if (aux3) (void)hipStreamDestroy(aux3);
+    if (fork4) (void)hipEventDestroy(fork4);
+    if (join4) (void)hipEventDestroy(join4);
+    if (aux4) (void)hipStreamDestroy(aux4);
     if (tick_done) (void)hipEventDestroy(tick_done);
     if (aux2) (void)hipStreamDestroy(aux2);
     if (aux) (void)hipStreamDestroy(aux);
@@ -1497,7 +1519,55 @@ void upload_stars(DeviceState &d, const Precond &pre, const HostFactors &hf, sn_
     nnz_rcm += F.nnz_rcm;
     env += F.env;
   }
-  if (tot >= (int64_t)1 << 31 || (int64_t)std::max(f_val.size(), b_val.size()) >= (int64_t)1 << 31)
+  // the two chains of every star that has them (windows of 1-2 registers),
+  // after the stars' own entries; pos_map gives each chain position the band
+  // position it owns in its star (pads and the second chain's separator copy
+  // own none)
+  std::vector<int32_t> tw_star, tw_K, pos_map((size_t)tot, -1);
+  d.h_twin.assign((size_t)ns, -1);
+  d.h_twin_len.clear();
+  d.h_bytes_twin.clear();
+  int64_t ext = tot;
+  for (int64_t s = 0; s < ns; ++s) {
+    const StarFactor &F = hf.stars[s];
+    const BandTwin &TW = F.twin;
+    if (TW.K <= 0) continue;
+    const int q2 = window_regs(std::max({TW.c[0].band, TW.c[1].band, 1}));
+    if (q2 < 1 || q2 > 2) continue;
+    const int32_t t = (int32_t)tw_star.size();
+    const int32_t n2 = TW.K + TW.s;
+    tw_star.push_back((int32_t)s);
+    tw_K.push_back(TW.K);
+    d.h_twin[s] = t;
+    d.h_twin_len.push_back(n2);
+    d.h_bytes_twin.push_back(2 * (TW.c[0].nnz + TW.c[1].nnz) * sT + (int64_t)F.n * (4 + 8 + sT));
+    const int32_t *dofs = &pre.star_dofs[pre.star_ptr[s]];
+    for (int c = 0; c < 2; ++c) {
+      const BandChain &C = TW.c[c];
+      st_n.push_back(n2);
+      st_vb.push_back((int32_t)ext);
+      st_q.push_back(q2);
+      st_gb.push_back((int32_t)f_hdr.size());
+      st_fb.push_back((int64_t)f_val.size());
+      st_bb.push_back((int64_t)b_val.size());
+      std::vector<double> binv((size_t)n2);
+      for (int p = 0; p < n2; ++p) binv[p] = C.invdiag[n2 - 1 - p];
+      pack_stream<T>(C.width_fwd, C.colvals, C.invdiag, SG, q2, f_val, f_hdr);
+      pack_stream<T>(C.width_bwd, C.rowvals, binv, SG, q2, b_val, b_hdr);
+      if (f_hdr.size() != b_hdr.size()) fail(SN_EINVAL, "internal: header arrays out of step");
+      for (int p = 0; p < n2; ++p) {
+        const int32_t bp = C.bpos[p];
+        const bool own = bp >= 0 && !(c == 1 && p >= TW.K);
+        pos_dof.push_back(own ? d.iperm_h[dofs[F.perm[bp]]] : -1);
+        pos_map.push_back(own ? bp : -1);
+        f_inv.push_back((T)C.invdiag[p]);
+        b_inv.push_back((T)binv[p]);
+      }
+      ext += n2;
+    }
+  }
+  d.ntwin = (int32_t)tw_star.size();
+  if (ext >= (int64_t)1 << 31 || (int64_t)std::max(f_val.size(), b_val.size()) >= (int64_t)1 << 31)
     fail(SN_EINVAL, "star streams too large for 32-bit offsets");
   // zero region: band lanes past a group's width load from here (64*Q lanes of
   // SG values, Q <= 16)
@@ -1526,6 +1596,9 @@ void upload_stars(DeviceState &d, const Precond &pre, const HostFactors &hf, sn_
   d.st_fb.upload(st_fb);
   d.st_bb.upload(st_bb);
   d.pos_dof.upload(pos_dof);
+  d.pos_map.upload(pos_map);
+  d.tw_star.upload(tw_star);
+  d.tw_K.upload(tw_K);
   d.f_hdr.upload(f_hdr);
   d.b_hdr.upload(b_hdr);
   d.slot_of.upload(slot_of);
@@ -1837,6 +1910,18 @@ void with_kc(int kc, F &&f) {
   }
 }
 
+template <typename T>
+static void launch_twin_kc(int kc, const StarArgs &a, const double *r, const CgScalars *sc, int sel, hipStream_t s) {
+  switch (kc) {
+    case 1: launch_twin_t<T, 1>(a, r, sc, sel, s); break;
+    case 2: launch_twin_t<T, 2>(a, r, sc, sel, s); break;
+    case 4: launch_twin_t<T, 4>(a, r, sc, sel, s); break;
+    case 8: launch_twin_t<T, 8>(a, r, sc, sel, s); break;
+    case 16: launch_twin_t<T, 16>(a, r, sc, sel, s); break;
+    default: fail(SN_EINVAL, "unsupported column count");
+  }
+}
+
 StarArgs band_args(DeviceState &d, Engine &e, bool wide) {
   StarArgs a{};
   a.nstars = wide ? e.n_wide : e.n_narrow;
@@ -1856,6 +1941,12 @@ StarArgs band_args(DeviceState &d, Engine &e, bool wide) {
   a.maxn = d.maxn;
   a.use_lds = e.star_lv ? 1 : 0;
   a.n_prio = e.star_prio;
+  a.unit0 = d.nstars;
+  a.tw_star = d.tw_star.p;
+  a.tw_K = d.tw_K.p;
+  a.pos_map = d.pos_map.p;
+  a.tw_vs = e.tw_vs.p;
+  a.tw_scratch = e.tw_scratch.p;
   if (d.precision == SN_PREC_FP32_STARS) {
     a.f_inv = d.f_inv32.p;
     a.b_inv = d.b_inv32.p;
@@ -1896,6 +1987,21 @@ void launch_band(Engine &e, const double *r, int sel, hipStream_t s) {
     if (f32) launch_band_kc<float>(e.kc, a, wide, r, e.sc.p, sel, st);
     else launch_band_kc<double>(e.kc, a, wide, r, e.sc.p, sel, st);
   };
+  // the two-chain stars (the longest) first, beside the others on aux4
+  if (e.n_twin > 0) {
+    StarArgs a = band_args(d, e, false);
+    a.nstars = e.n_twin;
+    a.order = e.b_twin.p;
+    const bool alone = e.n_wide == 0 && e.n_narrow == 0;
+    const hipStream_t ts = alone ? s : e.aux4;
+    if (!alone) {
+      HIPCHK(hipEventRecord(e.fork4, s));
+      HIPCHK(hipStreamWaitEvent(e.aux4, e.fork4, 0));
+    }
+    if (f32) launch_twin_kc<float>(e.kc, a, r, e.sc.p, sel, ts);
+    else launch_twin_kc<double>(e.kc, a, r, e.sc.p, sel, ts);
+    if (!alone) HIPCHK(hipEventRecord(e.join4, e.aux4));
+  }
   if (e.n_wide > 0 && e.n_narrow > 0) {
     HIPCHK(hipEventRecord(e.fork, s));
     HIPCHK(hipStreamWaitEvent(e.aux, e.fork, 0));
@@ -1908,6 +2014,7 @@ void launch_band(Engine &e, const double *r, int sel, hipStream_t s) {
   } else if (e.n_narrow > 0) {
     L(false, s);
   }
+  if (e.n_twin > 0 && (e.n_wide > 0 || e.n_narrow > 0)) HIPCHK(hipStreamWaitEvent(s, e.join4, 0));
 }
 
 // supernodal solves: the launches that need the most resources first
@@ -1939,7 +2046,7 @@ void launch_stars(Engine &e, const double *r, int sel, hipStream_t s) {
     }
     HIPCHK(hipEventRecord(ev.first, s));
   }
-  const bool band = e.n_narrow + e.n_wide > 0, sn = e.n_sn > 0;
+  const bool band = e.n_narrow + e.n_wide + e.n_twin > 0, sn = e.n_sn > 0;
   if (band && sn) {
     HIPCHK(hipEventRecord(e.fork3, s));
     HIPCHK(hipStreamWaitEvent(e.aux3, e.fork3, 0));
@@ -2265,7 +2372,9 @@ void plan_split(Engine &e, int64_t nsn) {
   std::vector<int32_t> by_len((size_t)d.nstars);
   for (int32_t s = 0; s < d.nstars; ++s) by_len[s] = s;
   std::stable_sort(by_len.begin(), by_len.end(), [&](int32_t a, int32_t b) { return d.h_n[a] > d.h_n[b]; });
-  std::vector<int32_t> narrow, wide;
+  std::vector<int32_t> narrow, wide, twin;
+  std::vector<int64_t> vs;
+  int64_t tw_pos = 0;
   e.sn_list.clear();
   e.sweep_bytes = 0;
   for (int64_t i = 0; i < d.nstars; ++i) {
@@ -2273,11 +2382,30 @@ void plan_split(Engine &e, int64_t nsn) {
     if (d.h_q[s] == 0 || (i < nsn && d.h_sn_ok[s])) {
       e.sn_list.push_back(s);
       e.sweep_bytes += d.h_bytes_sn[s];
+    } else if (d.twin_min > 0 && d.h_twin[s] >= 0 && d.h_n[s] >= d.twin_min) {
+      const int32_t t = d.h_twin[s];
+      twin.push_back(t);
+      e.sweep_bytes += d.h_bytes_twin[t];
     } else {
       (d.h_q[s] <= 2 ? narrow : wide).push_back(s);
       e.sweep_bytes += d.h_bytes_band[s];
     }
   }
+  // vectors of the twin stars: two chains each, per twin in twin-id order
+  vs.assign((size_t)d.ntwin, 0);
+  for (const int32_t t : twin) {
+    vs[t] = tw_pos;
+    tw_pos += 2 * (int64_t)d.h_twin_len[t];
+  }
+  const int64_t ts = d.precision == SN_PREC_FP32_STARS ? 4 : 8;
+  const int64_t need = tw_pos * e.kc * ts;
+  if ((int64_t)e.tw_scratch.n < need) {
+    e.tw_scratch.alloc((size_t)need);
+    e.bytes += need;
+  }
+  e.tw_vs.upload(vs);
+  e.b_twin.upload(twin);
+  e.n_twin = (int32_t)twin.size();
   e.b_narrow.upload(narrow);
   e.b_wide.upload(wide);
   e.n_narrow = (int32_t)narrow.size();
@@ -2381,6 +2509,7 @@ void tune_stars(Engine &e) {
   };
   // supernodal defaults
   int lcap = 24 << 10, cw = std::min(e.kc, 4), nt = 1;
+  if (d.twin_force >= 0) d.twin_min = d.twin_force;
   // 1. band occupancy and vector placement, all stars on the band path
   plan_split(e, 0);
   plan_sn(e, lcap, cw, nt);
@@ -2505,6 +2634,28 @@ void tune_stars(Engine &e) {
     }
     e.star_prio = bprio;
   }
+  // 6. the two-chain form for the longest band stars (once per
+  //    preconditioner: it rounds differently from the single chain)
+  if (d.twin_min < 0) {
+    int64_t bmin = 0;
+    int32_t maxn = 0;
+    for (int32_t s = 0; s < d.nstars; ++s)
+      if (d.h_twin[s] >= 0) maxn = std::max(maxn, d.h_n[s]);
+    if (maxn > 0 && e.n_narrow + e.n_wide > 0) {
+      for (const double f : {0.8, 0.6, 0.45, 0.3}) {
+        d.twin_min = std::max<int64_t>(1, std::llround(f * maxn));
+        plan_split(e, d.split);
+        if (e.n_twin == 0) continue;
+        const double us = time_it();
+        if (us < 0.98 * best) {
+          best = us;
+          bmin = d.twin_min;
+        }
+      }
+    }
+    d.twin_min = bmin;
+    plan_split(e, d.split);
+  }
   e.star_us = best;
   // the coarse kernel's placement: before the sweeps, or beside them on a
   // second stream, queued before or after them (the packed kernel unless a
@@ -2585,6 +2736,7 @@ int64_t engine_footprint(const Precond &pre, int kc) {
   if (pre.dev) {
     for (size_t st = 0; st < pre.dev->h_n.size(); ++st)
       vsc += ((2 * (int64_t)pre.dev->h_n[st] + (int64_t)pre.dev->h_nu[st]) * kc * ts + 48);
+    for (const int32_t len : pre.dev->h_twin_len) vsc += 2 * (int64_t)len * kc * ts;  // two-chain vectors
   } else {
     vsc = (int64_t)pre.star_dofs.size() * 5 * kc * ts;
   }
@@ -2638,6 +2790,9 @@ Engine *engine_create(Precond &pre, int kc) {
   HIPCHK(hipEventCreateWithFlags(&e->join, hipEventDisableTiming));
   HIPCHK(hipStreamCreateWithFlags(&e->aux2, hipStreamNonBlocking));
   HIPCHK(hipStreamCreateWithFlags(&e->aux3, hipStreamNonBlocking));
+  HIPCHK(hipStreamCreateWithFlags(&e->aux4, hipStreamNonBlocking));
+  HIPCHK(hipEventCreateWithFlags(&e->fork4, hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&e->join4, hipEventDisableTiming));
   HIPCHK(hipEventCreateWithFlags(&e->fork3, hipEventDisableTiming));
   HIPCHK(hipEventCreateWithFlags(&e->join3, hipEventDisableTiming));
   HIPCHK(hipEventCreateWithFlags(&e->fork2, hipEventDisableTiming));
@@ -2791,6 +2946,16 @@ void device_set_star_split(Precond &pre, int64_t n_sn) {
   d.split = n_sn < 0 ? -1 : std::min<int64_t>(n_sn, d.nstars);
 }
 
+void device_set_band_twins(Precond &pre, int64_t min_positions) {
+  DeviceState &d = *pre.dev;
+  for (auto &e : d.solve_engine) {
+    if (e) wait_tick(*e);
+    e.reset();
+  }
+  d.twin_force = min_positions < 0 ? -1 : min_positions;
+  d.twin_min = d.twin_force;
+}
+
 void device_set_sn_beyond_lds(Precond &pre, int mode) {
   DeviceState &d = *pre.dev;
   for (auto &e : d.solve_engine) {
@@ -2824,6 +2989,7 @@ void device_engine_info(Precond &pre, int k, sn_engine_info *info) {
   info->star_band_prio = e.star_prio;
   info->star_global_waves = e.star_gteam;
   info->star_big_index_global = e.star_iglobal;
+  info->star_twins = e.n_twin;
   info->coarse_first = e.coarse_first ? 1 : 0;
   info->coarse_kernel = e.coarse_sym ? 2 : (e.coarse_w1 ? 1 : 0);
   info->coarse_late = e.coarse_late ? 1 : 0;

@@ -124,6 +124,12 @@ struct StarArgs {
   int32_t use_lds;                           // working vectors in LDS where they fit
   int32_t n_prio;                            // the first n_prio stars of order run at raised issue priority
   void *slots;                               // T, per position and column (position-major)
+  // two-chain stars (k_star_twin; order then lists twin ids)
+  int32_t unit0;                             // the chains of twin t are units unit0 + 2 t and unit0 + 2 t + 1
+  const int32_t *tw_star, *tw_K;             // per twin: its star, the step where the chains meet
+  const int32_t *pos_map;                    // per chain position: the star's band position, -1: not owned
+  const int64_t *tw_vs;                      // per twin: first position of its two vectors in tw_scratch
+  void *tw_scratch;                          // T, the chains' working vectors
 };
 
 // one band launch over the stars of a.order, narrow (windows of 1-2
@@ -132,6 +138,9 @@ struct StarArgs {
 // per precision and column count
 template <typename T, int KC>
 void launch_star_t(const StarArgs &a, bool wide, const double *r, const CgScalars *sc, int sel, hipStream_t s);
+// one launch over the two-chain stars of a.order (twin ids)
+template <typename T, int KC>
+void launch_twin_t(const StarArgs &a, const double *r, const CgScalars *sc, int sel, hipStream_t s);
 
 // Device layout of one star's supernodal factor (a "blob", 16-byte aligned;
 // see factor.cpp and star_sn.hpp). The index part (header, level table,

@@ -173,6 +173,8 @@ std::vector<int32_t> rcm(const LocalGraph &g) {
   return cm;  // position -> local index
 }
 
+void band_twin(const LocalGraph &g, const std::vector<int32_t> &pos, StarFactor &F);
+
 void factor_star(const System &sys, const int32_t *dofs, int32_t m, std::vector<int32_t> &where, StarFactor &F,
                  int64_t star_id) {
   LocalGraph g = extract_local_graph(sys, dofs, m, where);
@@ -258,8 +260,191 @@ void factor_star(const System &sys, const int32_t *dofs, int32_t m, std::vector<
     if (j == 0 || dj > dmax) dmax = dj;
   }
   F.pivot_ratio = m > 0 ? dmax / dmin : 1.0;
+  band_twin(g, pos, F);
 }
 
+
+// Stars from this many positions on also get the two-chain band factor
+// (shorter stars are not helped by it: their launch is bound by how many
+// chains a SIMD interleaves, not by the longest chain).
+constexpr int32_t kTwinMin = 512;
+
+// The envelope of one chain: first[i] = the lowest chain position coupled to
+// row i or to a later row (a monotone profile), the separator rows (from K
+// on) reaching back to K at least so that both chains hold all of L_ss.
+void chain_profile(const LocalGraph &g, const std::vector<int32_t> &bpos, const std::vector<int32_t> &perm,
+                   const std::vector<int32_t> &cpos, int32_t K, std::vector<int32_t> &first) {
+  const int32_t n = (int32_t)bpos.size();
+  first.resize((size_t)n);
+  for (int32_t i = 0; i < n; ++i) {
+    first[i] = i;
+    if (bpos[i] < 0) continue;
+    const int32_t a = perm[bpos[i]];
+    for (int32_t q = g.ptr[a]; q < g.ptr[a + 1]; ++q) {
+      const int32_t j = cpos[g.adj[q]];
+      if (j >= 0 && j < i) first[i] = std::min(first[i], j);
+    }
+  }
+  for (int32_t i = K; i < n; ++i) first[i] = std::min(first[i], K);
+  for (int32_t i = n - 2; i >= 0; --i) first[i] = std::min(first[i], first[i + 1]);
+}
+
+// The two-chain form of the band factor (see BandTwin). Among the cuts k whose
+// chains keep the star's window (envelope width within the same multiple of
+// 64) the one with the shortest chain K + s is taken; no split when it saves
+// less than a quarter of the steps.
+void band_twin(const LocalGraph &g, const std::vector<int32_t> &pos, StarFactor &F) {
+  const int32_t m = F.n;
+  F.twin = BandTwin{};
+  if (m < kTwinMin) return;
+  // reach[k]: the last position coupled to a position before k
+  std::vector<int32_t> reach((size_t)m + 1, -1);
+  for (int32_t p = 0; p < m; ++p) {
+    int32_t mx = p;
+    const int32_t a = F.perm[p];
+    for (int32_t q = g.ptr[a]; q < g.ptr[a + 1]; ++q) mx = std::max(mx, pos[g.adj[q]]);
+    reach[p + 1] = std::max(reach[p], mx);
+  }
+  const int32_t wlim = std::max(64, (F.band + 63) / 64 * 64);
+  std::vector<std::pair<int32_t, int32_t>> cand;  // (chain length, k)
+  for (int32_t k = 1; k < m; ++k) {
+    const int32_t s = std::max(0, reach[k] + 1 - k), nb = m - k - s;
+    if (nb < 1 || s > wlim) continue;
+    const int32_t K = (std::max(k, nb) + 63) / 64 * 64;
+    if (4 * (K + s) > 3 * m) continue;
+    cand.push_back({K + s, k});
+  }
+  std::sort(cand.begin(), cand.end());
+  for (size_t ci = 0; ci < cand.size() && ci < 24; ++ci) {
+    const int32_t k = cand[ci].second;
+    const int32_t s = std::max(0, reach[k] + 1 - k), nb = m - k - s;
+    const int32_t K = (std::max(k, nb) + 63) / 64 * 64, n = K + s;
+    BandTwin T;
+    T.K = K;
+    T.s = s;
+    std::vector<int32_t> first[2], last[2], cpos[2];
+    std::vector<int64_t> coff[2];
+    std::vector<double> A[2];
+    bool ok = true;
+    for (int c = 0; c < 2 && ok; ++c) {
+      BandChain &C = T.c[c];
+      C.bpos.assign((size_t)n, -1);
+      const int32_t pad = c == 0 ? K - k : K - nb;
+      if (c == 0)
+        for (int32_t t = 0; t < k; ++t) C.bpos[pad + t] = t;
+      else
+        for (int32_t t = 0; t < nb; ++t) C.bpos[pad + t] = m - 1 - t;
+      for (int32_t t = 0; t < s; ++t) C.bpos[K + t] = k + t;
+      cpos[c].assign((size_t)m, -1);
+      for (int32_t i = 0; i < n; ++i)
+        if (C.bpos[i] >= 0) cpos[c][F.perm[C.bpos[i]]] = i;
+      chain_profile(g, C.bpos, F.perm, cpos[c], K, first[c]);
+      last[c].resize((size_t)n);
+      int32_t i = n - 1;
+      for (int32_t j = n - 1; j >= 0; --j) {
+        while (i > j && first[c][i] > j) --i;
+        last[c][j] = std::max(i, j);
+      }
+      C.band = 0;
+      for (int32_t j = 0; j < n; ++j) C.band = std::max(C.band, std::max(last[c][j] - j, j - first[c][j]));
+      if (C.band > wlim) ok = false;
+    }
+    if (!ok) continue;
+    // values: chain 0 holds the top-top, top-separator and separator-separator
+    // entries, chain 1 the bottom-bottom and bottom-separator ones; pads get 1
+    for (int c = 0; c < 2 && ok; ++c) {
+      BandChain &C = T.c[c];
+      coff[c].assign((size_t)n + 1, 0);
+      for (int32_t j = 0; j < n; ++j) coff[c][j + 1] = coff[c][j] + (last[c][j] - j + 1);
+      A[c].assign((size_t)coff[c][n], 0.0);
+      for (int32_t i = 0; i < n; ++i) {
+        if (C.bpos[i] < 0) {
+          A[c][coff[c][i]] = 1.0;
+          continue;
+        }
+        const int32_t a = F.perm[C.bpos[i]];
+        for (int32_t q = g.dptr[a]; q < g.dptr[a + 1]; ++q) {
+          const int32_t j = cpos[c][g.dcol[q]];
+          if (j < 0 || j > i) continue;
+          if (c == 1 && i >= K && j >= K) continue;
+          A[c][coff[c][j] + (i - j)] += g.dval[q];
+        }
+      }
+      // right-looking Cholesky of the columns before the separator; the
+      // separator block receives the chain's Schur complement update
+      for (int32_t j = 0; j < K; ++j) {
+        double *cj = &A[c][coff[c][j]];
+        if (!(cj[0] > 0.0)) {
+          ok = false;
+          break;
+        }
+        const double d = std::sqrt(cj[0]);
+        cj[0] = d;
+        const double inv = 1.0 / d;
+        for (int32_t t = 1; t <= last[c][j] - j; ++t) cj[t] *= inv;
+        for (int32_t cc = j + 1; cc <= last[c][j]; ++cc) {
+          const double l = cj[cc - j];
+          if (l == 0.0) continue;
+          double *col = &A[c][coff[c][cc]];
+          for (int32_t r = cc; r <= last[c][j]; ++r) col[r - cc] -= cj[r - j] * l;
+        }
+      }
+    }
+    if (!ok) continue;
+    // the separator block: A_ss minus both updates, factored once, copied to both chains
+    for (int32_t j = K; j < n && ok; ++j) {
+      double *c0 = &A[0][coff[0][j]];
+      const double *c1 = &A[1][coff[1][j]];
+      for (int32_t r = j; r < n; ++r) c0[r - j] += c1[r - j];
+      if (!(c0[0] > 0.0)) {
+        ok = false;
+        break;
+      }
+      const double d = std::sqrt(c0[0]);
+      c0[0] = d;
+      const double inv = 1.0 / d;
+      for (int32_t r = j + 1; r < n; ++r) c0[r - j] *= inv;
+      for (int32_t cc = j + 1; cc < n; ++cc) {
+        const double l = c0[cc - j];
+        double *col = &A[0][coff[0][cc]];
+        for (int32_t r = cc; r < n; ++r) col[r - cc] -= c0[r - j] * l;
+      }
+    }
+    if (!ok) continue;
+    for (int32_t j = K; j < n; ++j)
+      for (int32_t r = j; r < n; ++r) A[1][coff[1][j] + (r - j)] = A[0][coff[0][j] + (r - j)];
+    // streams, as for the single band factor
+    for (int c = 0; c < 2; ++c) {
+      BandChain &C = T.c[c];
+      C.width_fwd.resize((size_t)n);
+      C.width_bwd.resize((size_t)n);
+      C.invdiag.resize((size_t)n);
+      C.nnz = 0;
+      for (int32_t j = 0; j < n; ++j) {
+        const int32_t w = last[c][j] - j;
+        C.width_fwd[j] = w;
+        C.invdiag[j] = 1.0 / A[c][coff[c][j]];
+        if (C.bpos[j] >= 0) ++C.nnz;
+        for (int32_t t = 1; t <= w; ++t) {
+          const double v = A[c][coff[c][j] + t];
+          C.colvals.push_back(v);
+          if (v != 0.0) ++C.nnz;
+        }
+      }
+      for (int32_t st = 0; st < n; ++st) {
+        const int32_t i = n - 1 - st;
+        const int32_t w = i - first[c][i];
+        C.width_bwd[st] = w;
+        for (int32_t t = 0; t < w; ++t) {
+          const int32_t cc = i - 1 - t;
+          C.rowvals.push_back(A[c][coff[c][cc] + (i - cc)]);
+        }
+      }
+    }
+    F.twin = std::move(T);
+    return;
+  }
+}
 
 // Structural non-zeros of the Cholesky factor of A (incl. the diagonal) in
 // the given order (order[p] = local index at position p): the elimination tree

@@ -108,6 +108,30 @@ struct SnFactor {
   double pivot_ratio = 1.0;         // largest / smallest pivot L_jj^2
 };
 
+// The band factor split into two chains that a pair of wavefronts sweeps side
+// by side. The reverse Cuthill-McKee positions are cut into a top part [0, k),
+// a separator [k, k+s) (the positions coupled to the top part) and a bottom
+// part [k+s, n). Chain 0 runs pads, the top part, the separator; chain 1 runs
+// pads, the bottom part in reverse, the separator (each chain K + s steps, K
+// a multiple of 64, the pads identity rows). L in the order (top, bottom,
+// separator) has no entries between the top and the bottom part, so the two
+// chains are the rows and columns (top, separator) and (bottom, separator) of
+// one factor and share its separator block L_ss: the forward sweeps run apart
+// until step K, where their partial sums of the separator rows are added,
+// then both finish the separator identically; the backward sweeps start from
+// the same separator values and run apart.
+struct BandChain {
+  int32_t band = 0;                 // max width of the envelope
+  std::vector<int32_t> bpos;        // chain position -> band position of the star, -1: pad
+  std::vector<int32_t> width_fwd, width_bwd;
+  std::vector<double> invdiag, colvals, rowvals;
+  int64_t nnz = 0;                  // non-zeros of the chain's factor (incl. diagonal, pads excluded)
+};
+struct BandTwin {
+  int32_t K = 0, s = 0;             // K = 0: no split
+  BandChain c[2];
+};
+
 // Both layouts of one local matrix. Band (reverse Cuthill-McKee order, the
 // envelope factor): the forward stream walks the columns of L from the first,
 // the backward stream walks the rows of L from the last, each listing the
@@ -126,6 +150,7 @@ struct StarFactor {
   int64_t nnz_rcm = 0;              // structural non-zeros of L in the band order (incl. diagonal)
   double pivot_ratio = 1.0;         // largest / smallest pivot L_jj^2 (envelope factor)
   SnFactor sn;                      // the supernodal factor of the same matrix
+  BandTwin twin;                    // the band factor as two chains (long stars only)
 };
 
 struct HostFactors {
@@ -154,6 +179,7 @@ void device_engine_info(Precond &pre, int k, sn_engine_info *info);
 void device_set_star_split(Precond &pre, int64_t n_sn);
 void device_set_coarse_launch(Precond &pre, int mode);
 void device_set_sn_beyond_lds(Precond &pre, int mode);
+void device_set_band_twins(Precond &pre, int64_t min_positions);
 
 // ---------------------------------------------------------------------------
 // Engine: the device workspace of kc PCG columns (independent recurrences, one

@@ -143,10 +143,15 @@ typedef const __attribute__((address_space(4))) uint32_t *const_u32_ptr;
 // One sweep over the n steps of a stream for CW columns c0..c0+CW-1 of the
 // star's slot segment `sl` (KC values per position). REV reads and writes the
 // vector in reverse position order.
-template <typename T, int KC, int CW, int Q, int RG, bool REV>
+// TW: the sweep is one chain of a two-chain star (k_star_twin): at the block
+// starting at step twin_k the forward sweeps of both chains exchange their
+// window through xbuf (LDS) and add the partner's partial sums of the
+// separator rows (every row of the window from twin_k on is a separator row
+// or past the end, and the other chain's are zero until then).
+template <typename T, int KC, int CW, int Q, int RG, bool REV, bool TW = false>
 __device__ __forceinline__ void sweep(T *sl, int c0, int n, const uint16_t *__restrict__ hdr_g,
                                       const T *__restrict__ inv, const T *__restrict__ vals, uint32_t sbase,
-                                      uint32_t zbase) {
+                                      uint32_t zbase, int twin_k = -1, T *xbuf = nullptr) {
   using P = Pack<T>;
   using V = typename P::V;
   constexpr int SG = P::SG, GPB = 64 / SG;
@@ -219,6 +224,22 @@ __device__ __forceinline__ void sweep(T *sl, int c0, int n, const uint16_t *__re
       constexpr int H = decltype(hc_)::value;
       const int jb = jb0 + 64 * H;
       if (jb >= n) return;
+      if constexpr (TW && !REV) {
+        if (jb == twin_k) {
+          constexpr int XW = (Q + 1) * CW * 64;
+          T *mine = xbuf + (size_t)(threadIdx.x >> 6) * XW;
+          const T *other = xbuf + (size_t)(1 - (threadIdx.x >> 6)) * XW;
+#pragma unroll
+          for (int q = 0; q <= Q; ++q)
+#pragma unroll
+            for (int c = 0; c < CW; ++c) mine[(q * CW + c) * 64 + lane] = R[q][c];
+          __syncthreads();
+#pragma unroll
+          for (int q = 0; q <= Q; ++q)
+#pragma unroll
+            for (int c = 0; c < CW; ++c) R[q][c] += other[(q * CW + c) * 64 + lane];
+        }
+      }
       const uint32_t wnext = hw[(jb / 64 + 1) * WPB + wl];
       const T hinvN = jb + 64 + lane < n ? inv[jb + 64 + lane] : T(0);
       T incN[CW];
@@ -302,8 +323,9 @@ constexpr int pass_columns() {
   return KC < cap ? KC : cap;
 }
 
-template <typename T, int KC, int Q>
-__device__ __forceinline__ void star_solve(const StarArgs &a, int st, int n, T *sl) {
+template <typename T, int KC, int Q, bool TW = false>
+__device__ __forceinline__ void star_solve(const StarArgs &a, int st, int n, T *sl, int twin_k = -1,
+                                           T *xbuf = nullptr) {
   constexpr int GPB = 64 / Pack<T>::SG;
   constexpr int CW = pass_columns<T, Q, KC>();
   // ring of 16-byte group loads: 16 slots (64 registers; 32 at eight columns
@@ -319,7 +341,8 @@ __device__ __forceinline__ void star_solve(const StarArgs &a, int st, int n, T *
   const T *fval = static_cast<const T *>(a.f_val), *bval = static_cast<const T *>(a.b_val);
   const uint32_t fb = (uint32_t)a.st_fb[st], bb = (uint32_t)a.st_bb[st];
   for (int c0 = 0; c0 < KC; c0 += CW) {
-    sweep<T, KC, CW, Q, RG, false>(sl, c0, n, a.f_hdr + gbase, finv, fval, fb, (uint32_t)a.f_zero);
+    sweep<T, KC, CW, Q, RG, false, TW>(sl, c0, n, a.f_hdr + gbase, finv, fval, fb, (uint32_t)a.f_zero, twin_k,
+                                        xbuf);
     __syncthreads();
     sweep<T, KC, CW, Q, RG, true>(sl, c0, n, a.b_hdr + gbase, binv, bval, bb, (uint32_t)a.b_zero);
     __syncthreads();
@@ -419,6 +442,71 @@ void launch_star_t(const StarArgs &a, bool wide, const double *r, const CgScalar
   const size_t lds = (size_t)a.lds_reserve;
   if (wide) hipLaunchKernelGGL((k_star<T, true, KC, false>), dim3(a.nstars), dim3(64), lds, s, a, r, sc, sel);
   else hipLaunchKernelGGL((k_star<T, false, KC, false>), dim3(a.nstars), dim3(64), lds, s, a, r, sc, sel);
+}
+
+// Two-chain stars (see BandTwin in the host code): one workgroup of two
+// wavefronts per star, wavefront w sweeping chain w (unit a.unit0 + 2 t + w of
+// the per-star arrays) on its own vector in a.tw_scratch; the forward sweeps
+// meet at step K (tw_K); at the end each chain writes the rows it owns to the
+// star's slots in band order (pos_map, -1 for pads and the separator copy).
+template <typename T, int KC>
+__global__ __launch_bounds__(128, (star_min_waves<T, false, KC, false>())) void k_star_twin(
+    StarArgs a, const double *__restrict__ r, const CgScalars *sc, int sel) {
+  extern __shared__ __align__(16) unsigned char star_lds[];
+  if (sel != SEL_ALL) {
+    bool any = false;
+#pragma unroll
+    for (int c = 0; c < KC; ++c) any |= column_selected(sc[c], sel, 0u, c);
+    if (!any) return;
+  }
+  if ((int)blockIdx.x >= a.nstars) return;
+  const int t = a.order[blockIdx.x];
+  const int w = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
+  const int unit = a.unit0 + 2 * t + w;
+  const int n = a.st_n[unit], vb = a.st_vb[unit], Q = a.st_q[unit];
+  T *vec = static_cast<T *>(a.tw_scratch) + ((size_t)a.tw_vs[t] + (size_t)w * n) * KC;
+  T *xbuf = reinterpret_cast<T *>(star_lds);
+  // gather r in chain order; pads and the second chain's separator rows start at 0
+  constexpr int U = KC <= 2 ? 16 : 32 / KC;
+  const int32_t *dofs = a.pos_dof + vb;
+  for (int p0 = 0; p0 < n; p0 += 64 * U) {
+    int idx[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) idx[u] = dofs[min(p0 + 64 * u + lane, n - 1)];
+    Row<double, KC> val[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) val[u].load(r + (size_t)max(idx[u], 0) * KC);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int p = p0 + 64 * u + lane;
+      if (p < n) {
+        Row<T, KC> o;
+#pragma unroll
+        for (int c = 0; c < KC; ++c) o.v[c] = idx[u] >= 0 ? (T)val[u].v[c] : T(0);
+        o.store(vec + (size_t)p * KC);
+      }
+    }
+  }
+  __syncthreads();
+  if (Q == 1) star_solve<T, KC, 1, true>(a, unit, n, vec, a.tw_K[t], xbuf);
+  else star_solve<T, KC, 2, true>(a, unit, n, vec, a.tw_K[t], xbuf);
+  T *sl = static_cast<T *>(a.slots) + (size_t)a.st_vb[a.tw_star[t]] * KC;
+  for (int p = lane; p < n; p += 64) {
+    const int m = a.pos_map[vb + p];
+    if (m >= 0) {
+      Row<T, KC> o;
+      o.load(vec + (size_t)p * KC);
+      o.store(sl + (size_t)m * KC);
+    }
+  }
+}
+
+template <typename T, int KC>
+void launch_twin_t(const StarArgs &a, const double *r, const CgScalars *sc, int sel, hipStream_t s) {
+  if (a.nstars <= 0) return;
+  constexpr int c1 = pass_columns<T, 1, KC>(), c2 = pass_columns<T, 2, KC>();
+  constexpr size_t lds = 2 * 3 * (size_t)(c1 > c2 ? c1 : c2) * 64 * sizeof(T);
+  hipLaunchKernelGGL((k_star_twin<T, KC>), dim3(a.nstars), dim3(128), lds, s, a, r, sc, sel);
 }
 
 }  // namespace spnet

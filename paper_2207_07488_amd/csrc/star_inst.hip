@@ -16,6 +16,7 @@
 namespace spnet {
 template void launch_star_t<STAR_T, STAR_KC>(const StarArgs &, bool, const double *, const CgScalars *, int,
                                              hipStream_t);
+template void launch_twin_t<STAR_T, STAR_KC>(const StarArgs &, const double *, const CgScalars *, int, hipStream_t);
 template void launch_sn_t<STAR_T, STAR_KC, 1>(const SnArgs &, int, bool, const double *, const CgScalars *,
                                                 int, hipStream_t);
 #if STAR_KC >= 2

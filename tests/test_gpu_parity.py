@@ -25,6 +25,8 @@ CASES = {
     "fiber3d_6k": (3, 6000, 0.12, 0.012, 4, 4, 4, 0),
     "truss3d_1500": (3, 1500, 0.25, 0.025, 4, 0, 4, 1),
 }
+# stars of 500-2000 positions (two-chain band stars)
+TWIN_CASE = (2, 2000, 0.08, 0.0, 1, 1, 4, 0)
 _KAPPA = {}
 
 
@@ -58,8 +60,8 @@ def S():
     return spnet
 
 
-def _pair(S, orc, name, precision, seed=1, policy=0):
-    dim, nseg, l, eps, lo, hi, nH, model = CASES[name]
+def _pair(S, orc, name, precision, seed=1, policy=0, case=None):
+    dim, nseg, l, eps, lo, hi, nH, model = case if case is not None else CASES[name]
     seg = W.fiber_segments(dim, nseg, l, seed=seed)
     on = orc.Network.from_segments(dim, seg, contact_eps=eps, merge_tol=W.merge_tol(l), dir_lo=lo, dir_hi=hi)
     osys = orc.System(on, model)
@@ -335,6 +337,35 @@ def test_supernodal_stars_beyond_lds(S, orc):
     assert np.array_equal(z1, z0)
     assert _close(z1[:, 0], opre.apply_B(r[:, 0]), 1e-10)
     gpre.set_sn_beyond_lds(-1)
+
+
+@pytest.mark.parametrize("prec", ["FP64", "FP32_STARS"])
+def test_band_twins(S, orc, prec):
+    """The longest stars swept as two chains meeting at a separator: B r to the
+    same bar against the oracle (per star), the same bits in a batch of four
+    columns as alone, and the number of such stars reported."""
+    opre, gpre = _pair(S, orc, None, getattr(S, prec), case=TWIN_CASE)
+    gpre.set_star_split(0)
+    gpre.set_band_twins(1)
+    R = W.rhs(opre.sys.n, 4, seed=11)
+    z = gpre.apply_B(R[:, 0])
+    ei = gpre.engine_info(1)
+    print("twins:", ei["star_twins"], "of", gpre.nstars, flush=True)
+    assert ei["star_twins"] > 0
+    ref = opre.apply_B(R[:, 0])
+    tol = 5e-3 if gpre.factor_info()["star_precision"] == S.FP32_STARS else 1e-10
+    assert _close(z, ref, tol) and _close_per_star(z, ref, opre, tol) == []
+    Z = gpre.apply_B(R)
+    assert gpre.engine_info(4)["star_twins"] == ei["star_twins"]
+    assert np.array_equal(Z[:, 0], z)
+    for c in range(4):
+        assert _close(Z[:, c], opre.apply_B(R[:, c]), tol), c
+    # without the two-chain form: the same operator to rounding
+    gpre.set_band_twins(0)
+    z0 = gpre.apply_B(R[:, 0])
+    assert gpre.engine_info(1)["star_twins"] == 0
+    assert _close(z0, z, tol)
+    gpre.set_band_twins(-1)
 
 
 def test_residual_replacement(S, orc):
