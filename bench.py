@@ -485,7 +485,8 @@ def main():
                 row[name] = {"solves_per_s": round(max(3, args.steps // 4) / r["total_s"], 2),
                              "iterations": int(r["iters"][-1]), "res_true": r["info"][0]["res_true"],
                              "local_solves_us": pre.engine_info(1)["star_sweep_us"],
-                             "stars_supernodal": pre.engine_info(1)["star_sn"]}
+                             "stars_supernodal": pre.engine_info(1)["star_sn"],
+                             "stars_two_chain": pre.engine_info(1)["star_twins"]}
                 row["stars"], row["m0"] = pre.nstars, pre.m0
                 row["max_star_dofs"] = pre.factor_info()["max_star_dofs"]
                 del pre
