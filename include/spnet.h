@@ -65,6 +65,29 @@ typedef struct sn_system_s *sn_system;
 typedef struct sn_precond_s *sn_precond;
 typedef struct sn_server_s *sn_server;
 
+/*
+ * Device allocator hook. Every device buffer the library keeps (matrix,
+ * factors, coarse operator, engine vectors and slots, staging of host
+ * arguments) is then taken from alloc(bytes, device, ctx) and given back
+ * through free_(ptr, bytes, device, ctx), with `device` the HIP device that
+ * is current during the call; this lets a caller put the library's memory in
+ * its own pool (for example PyTorch's caching allocator). alloc must return
+ * device memory on that device aligned to 256 bytes, or NULL, which the
+ * calling function reports as SN_ENOMEM; a misaligned pointer is handed back
+ * to free_ at once and reported as SN_EINVAL. Both callbacks may be called
+ * from any thread that uses the library, the server's own thread included,
+ * and must not call into the library. The hook is process-wide and applies to
+ * allocations made after the call; every buffer is released through the pair
+ * that allocated it, so the hook may change while handles live. alloc and
+ * free_ both NULL restores hipMalloc / hipFree; exactly one NULL is SN_EINVAL.
+ * Before free_ the library waits for the work queued on that device. Not
+ * covered: pinned host staging, HIP graph and runtime internals, and the
+ * fixed workspace of sn_apply_K_noalloc.
+ */
+typedef void *(*sn_alloc_fn)(size_t bytes, int device, void *ctx);
+typedef void (*sn_free_fn)(void *ptr, size_t bytes, int device, void *ctx);
+sn_status sn_set_allocator(sn_alloc_fn alloc, sn_free_fn free_, void *ctx);
+
 /* Message of the last failing call on this thread (never NULL). */
 const char *sn_last_error(void);
 /* Library version string. */

@@ -43,6 +43,10 @@ extern "C" {
 const char *sn_last_error(void) { return g_err.c_str(); }
 const char *sn_version(void) { return "spnet 0.1 gfx950"; }
 
+sn_status sn_set_allocator(sn_alloc_fn alloc, sn_free_fn free_, void *ctx) {
+  return guarded([&] { spnet::set_device_allocator(alloc, free_, ctx); });
+}
+
 sn_status sn_network_from_segments(int dim, int64_t n_segments, const double *segments, double contact_eps,
                                    double merge_tol, int dir_lo, int dir_hi, double band, sn_network *out) {
   return guarded([&] {

@@ -1087,20 +1087,67 @@ __global__ __launch_bounds__(kBlock) void k_col_out(double *dst, const double *s
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
+namespace {
+// The caller's device allocator (sn_set_allocator), or none: hipMalloc.
+struct Allocator {
+  sn_alloc_fn alloc = nullptr;
+  sn_free_fn free = nullptr;
+  void *ctx = nullptr;
+};
+std::mutex g_alloc_mu;
+Allocator g_alloc;
+
+Allocator current_allocator() {
+  std::lock_guard<std::mutex> g(g_alloc_mu);
+  return g_alloc;
+}
+
+// Device memory of `bytes` from the current allocator on the current device;
+// `owner` and `dev` record where it must go back.
+void *device_alloc(size_t bytes, Allocator &owner, int &dev) {
+  owner = current_allocator();
+  HIPCHK(hipGetDevice(&dev));
+  void *p = nullptr;
+  if (!owner.alloc) {
+    if (hipMalloc(&p, bytes) != hipSuccess) p = nullptr;
+  } else {
+    p = owner.alloc(bytes, dev, owner.ctx);
+    if (p && reinterpret_cast<uintptr_t>(p) % 256 != 0) {
+      owner.free(p, bytes, dev, owner.ctx);
+      fail(SN_EINVAL, "the device allocator returned a pointer not aligned to 256 bytes");
+    }
+  }
+  if (!p) fail(SN_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+  return p;
+}
+
+// hipFree waits for the device; a caller's pool may hand the block out again
+// at once, so the library's queued work on that device is drained first.
+void device_free(void *p, size_t bytes, const Allocator &owner, int dev) {
+  if (!p) return;
+  if (owner.free) {
+    int cur = 0;
+    if (hipGetDevice(&cur) == hipSuccess && cur != dev) (void)hipSetDevice(dev);
+    (void)hipDeviceSynchronize();
+    if (cur != dev) (void)hipSetDevice(cur);
+    owner.free(p, bytes, dev, owner.ctx);
+  } else {
+    (void)hipFree(p);
+  }
+}
+}  // namespace
+
 template <typename T>
 struct DBuf {
   T *p = nullptr;
   size_t n = 0;
+  Allocator owner;
+  int dev = 0;
   void alloc(size_t cnt) {
     release();
-    n = cnt;
     if (cnt) {
-      const hipError_t e = hipMalloc(&p, cnt * sizeof(T));
-      if (e != hipSuccess) {
-        p = nullptr;
-        n = 0;
-        fail(SN_ENOMEM, "device allocation of " + std::to_string(cnt * sizeof(T)) + " bytes failed");
-      }
+      p = static_cast<T *>(device_alloc(cnt * sizeof(T), owner, dev));
+      n = cnt;
     }
   }
   void upload(const std::vector<T> &h) {
@@ -1111,13 +1158,19 @@ struct DBuf {
     if (n) HIPCHK(hipMemset(p, 0, n * sizeof(T)));
   }
   void release() {
-    if (p) (void)hipFree(p);
+    device_free(p, n * sizeof(T), owner, dev);
     p = nullptr;
     n = 0;
   }
   size_t bytes() const { return n * sizeof(T); }
   ~DBuf() { release(); }
 };
+
+void set_device_allocator(sn_alloc_fn alloc, sn_free_fn free_, void *ctx) {
+  if ((alloc == nullptr) != (free_ == nullptr)) fail(SN_EINVAL, "alloc and free_ must both be set or both be NULL");
+  std::lock_guard<std::mutex> g(g_alloc_mu);
+  g_alloc = Allocator{alloc, free_, alloc ? ctx : nullptr};
+}
 
 struct DeviceState {
   int device = 0;

@@ -172,6 +172,7 @@ void device_apply_K(Precond &pre, int k, const double *x, double *y, int device_
 void device_apply_B(Precond &pre, int k, const double *r, double *z, int device_ptrs, void *stream);
 void device_apply_K_noalloc(Precond &pre, int k, const double *x, double *y, void *stream);
 void device_release(DeviceState *d);
+void set_device_allocator(sn_alloc_fn alloc, sn_free_fn free_, void *ctx);
 void device_profile(Precond &pre, int enable);
 void device_stats(Precond &pre, sn_kernel_stats *st);
 int64_t device_bytes(const Precond &pre);

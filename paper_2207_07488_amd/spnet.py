@@ -78,6 +78,11 @@ class ServerOpts(C.Structure):
                 ("precision", C.c_int32), ("use_graph", C.c_int32)]
 
 
+# sn_alloc_fn / sn_free_fn of include/spnet.h
+ALLOC_FN = C.CFUNCTYPE(_P, C.c_size_t, C.c_int, _P)
+FREE_FN = C.CFUNCTYPE(None, _P, C.c_size_t, C.c_int, _P)
+
+
 class SpnetError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"spnet status {code}: {msg}")
@@ -89,6 +94,7 @@ _lib = None
 # name -> (restype, argtypes); the exported surface of include/spnet.h
 SIGNATURES = {
     "sn_last_error": (C.c_char_p, []),
+    "sn_set_allocator": (C.c_int, [ALLOC_FN, FREE_FN, _P]),
     "sn_version": (C.c_char_p, []),
     "sn_network_from_segments": (C.c_int, [C.c_int, _i64, _P, _dbl, _dbl, C.c_int, C.c_int, _dbl, C.POINTER(_P)]),
     "sn_network_from_arrays": (C.c_int, [C.c_int, _i64, _P, _i64, _P, _P, C.POINTER(_P)]),
@@ -169,6 +175,53 @@ def _ptr(a):
 
 def _is_torch(x):
     return type(x).__module__.startswith("torch")
+
+
+# the callbacks the library holds (ctypes frees a callback object that nothing references)
+_allocator = None
+
+
+def set_allocator(alloc=None, free=None):
+    """sn_set_allocator: alloc(nbytes, device) -> device address (0 when out of memory) and
+    free(address, nbytes, device) take the library's device buffers from now on; with both None
+    the library returns to hipMalloc / hipFree."""
+    global _allocator
+    L = lib()
+    if alloc is None and free is None:
+        _check(L.sn_set_allocator(C.cast(None, ALLOC_FN), C.cast(None, FREE_FN), None))
+        _allocator = None
+        return
+    if alloc is None or free is None:
+        raise ValueError("alloc and free must both be given or both be None")
+
+    def _a(nbytes, device, ctx):
+        try:
+            return int(alloc(int(nbytes), int(device)) or 0)
+        except Exception:  # an exception cannot cross the C boundary: report out of memory
+            return 0
+
+    def _f(ptr, nbytes, device, ctx):
+        free(int(ptr), int(nbytes), int(device))
+
+    cbs = (ALLOC_FN(_a), FREE_FN(_f))
+    _check(L.sn_set_allocator(cbs[0], cbs[1], None))
+    _allocator = cbs
+
+
+def use_torch_allocator(enable=True):
+    """Give the library's device buffers from PyTorch's caching allocator (enable=False: hipMalloc)."""
+    if not enable:
+        set_allocator(None, None)
+        return
+    import torch
+
+    def alloc(nbytes, device):
+        return torch.cuda.caching_allocator_alloc(nbytes, device)
+
+    def free(ptr, nbytes, device):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    set_allocator(alloc, free)
 
 
 class Network:

@@ -173,6 +173,20 @@ def test_factor_refuses_without_a_device(S):
     assert ei.value.code == S.SN_EDEVICE
 
 
+def test_allocator_hook_arguments(S):
+    """sn_set_allocator: both callbacks or neither; a Python allocator is accepted and removed."""
+    L = S.lib()
+    rc = L.sn_set_allocator(S.ALLOC_FN(lambda n, d, c: 0), C.cast(None, S.FREE_FN), None)
+    assert rc == S.SN_EINVAL and b"both" in L.sn_last_error()
+    rc = L.sn_set_allocator(C.cast(None, S.ALLOC_FN), S.FREE_FN(lambda p, n, d, c: None), None)
+    assert rc == S.SN_EINVAL
+    with pytest.raises(ValueError):
+        S.set_allocator(lambda n, d: 0, None)
+    S.set_allocator(lambda n, d: 0, lambda p, n, d: None)
+    S.set_allocator(None, None)
+    assert L.sn_set_allocator(C.cast(None, S.ALLOC_FN), C.cast(None, S.FREE_FN), None) == S.SN_OK
+
+
 def test_non_spd_star_is_reported(S):
     """A star holding a whole component without a Dirichlet node has a singular
     local matrix: factorisation reports SN_ENOTSPD before any device work."""
