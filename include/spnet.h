@@ -386,6 +386,8 @@ typedef struct {
                             wavefront per 4 rows (the same results bit for bit), 2: the packed
                             symmetric kernel */
   int32_t coarse_late;   /* beside the local solves: 1 queued after them, 0 before */
+  int32_t star_band_queue; /* > 0: the narrow band sweeps run as one persistent launch of that many
+                              wavefronts taking the stars from a queue (sn_precond_set_band_queue) */
   int64_t sweep_bytes;   /* algorithmic bytes of one application of the local solves to one column
                             with this split (see sn_factor_info.sweep_bytes) */
   double star_sweep_us;  /* time of all local solves, microseconds per application of B */
@@ -421,6 +423,21 @@ sn_status sn_precond_set_star_split(sn_precond pre, int64_t n_sn);
  * not factored or mode outside -1..1.
  */
 sn_status sn_precond_set_sn_beyond_lds(sn_precond pre, int mode);
+
+/*
+ * Persistent band sweeps: the band stars with windows of one or two registers
+ * (the short ones) are swept by one launch of `waves` resident wavefronts,
+ * each taking the next star of the length-sorted list (longest first) from a
+ * queue in device memory until none is left, instead of one workgroup per
+ * star. waves = 0: one workgroup per star; waves < 0 (default): measured when
+ * an engine is created (one to six wavefronts per SIMD against one workgroup
+ * per star, the fastest kept). Both forms sweep every star with the same
+ * instructions, so the results are the same bit for bit. The queue belongs to
+ * the engine, so launches of one engine must not overlap (as for all of its
+ * buffers). Drops the preconditioner's solve engines. Errors: SN_EINVAL if not
+ * factored.
+ */
+sn_status sn_precond_set_band_queue(sn_precond pre, int32_t waves);
 
 /*
  * The two-chain form of the band sweeps for the longest stars. A star's RCM

@@ -284,6 +284,13 @@ sn_status sn_precond_set_band_twins(sn_precond pre, int64_t min_positions) {
   });
 }
 
+sn_status sn_precond_set_band_queue(sn_precond pre, int32_t waves) {
+  return guarded([&] {
+    REQUIRE(pre && pre->p->dev, "null argument or not factored");
+    spnet::device_set_band_queue(*pre->p, waves);
+  });
+}
+
 sn_status sn_precond_set_sn_beyond_lds(sn_precond pre, int mode) {
   return guarded([&] {
     REQUIRE(pre && pre->p->dev, "null argument or not factored");

@@ -1220,6 +1220,7 @@ struct DeviceState {
   int32_t coarse_launch = -1;  // fixed coarse kernel and placement (kernel + 2 placement), -1: measured
   int32_t sn_beyond = -1;      // supernodal stars beyond LDS: 0 global memory, 1 vectors in LDS, -1 measured
   int64_t twin_force = -1;     // caller's twin threshold (0 off, > 0 positions), -1: measured
+  int32_t queue_force = -1;    // caller's persistent band wavefronts (0 off), -1: measured
   // coarse
   // K_0^{-1}, symmetric, zero-padded to ld0 x ld0 (ld0 a multiple of 64): FP32 in the mixed form
   // unless the coarse factor's pivot ratio rules it out, else FP64
@@ -1278,6 +1279,8 @@ struct Engine {
   int32_t star_cap = 0, star_lds = 0;          // resident band wavefronts per SIMD (0: no limit) and its LDS reservation
   bool star_lv = true;                         // band working vectors in LDS (where they fit)
   int32_t star_prio = 0;                       // band wavefronts of the longest stars at raised issue priority
+  int32_t star_resident = 0;                   // > 0: narrow band sweeps as that many persistent wavefronts
+  DBuf<int32_t> squeue;                        // their star queues (counters, zero between launches)
   // supernodal launches: 0 (lds_cap per workgroup), 1 (more LDS), 2 (global memory)
   struct StarLaunch {
     DBuf<int32_t> order;
@@ -1994,6 +1997,8 @@ StarArgs band_args(DeviceState &d, Engine &e, bool wide) {
   a.maxn = d.maxn;
   a.use_lds = e.star_lv ? 1 : 0;
   a.n_prio = e.star_prio;
+  a.n_resident = wide ? 0 : e.star_resident;
+  a.queue = e.squeue.p;
   a.unit0 = d.nstars;
   a.tw_star = d.tw_star.p;
   a.tw_K = d.tw_K.p;
@@ -2709,6 +2714,28 @@ void tune_stars(Engine &e) {
     d.twin_min = bmin;
     plan_split(e, d.split);
   }
+  // 7. the narrow band sweeps as one persistent launch: 1-6 resident
+  //    wavefronts per SIMD taking the stars, longest first, from a queue (the
+  //    same arithmetic, a different schedule)
+  e.star_resident = 0;
+  if (d.queue_force >= 0) {
+    e.star_resident = d.queue_force;
+  } else if (e.n_narrow > 0) {
+    int cus = 0;
+    HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, d.device));
+    int bres = 0;
+    for (const int per_simd : {1, 2, 3, 4, 6}) {
+      const int nres = per_simd * 4 * cus;
+      if (nres >= e.n_narrow) break;
+      e.star_resident = nres;
+      const double us = time_it();
+      if (us < 0.98 * best) {
+        best = us;
+        bres = nres;
+      }
+    }
+    e.star_resident = bres;
+  }
   e.star_us = best;
   // the coarse kernel's placement: before the sweeps, or beside them on a
   // second stream, queued before or after them (the packed kernel unless a
@@ -2822,6 +2849,8 @@ Engine *engine_create(Precond &pre, int kc) {
     e->cpart.alloc((size_t)d.sym_T * d.sym_T * 64 * kc);
     e->cpart.zero();
   }
+  e->squeue.alloc((size_t)kQueueStride * (kQueues + 1));
+  e->squeue.zero();
   e->partials.alloc((size_t)kc * kMaxGrid);
   e->partials.zero();
   e->partials2.alloc((size_t)kc * kMaxGrid);
@@ -3009,6 +3038,15 @@ void device_set_band_twins(Precond &pre, int64_t min_positions) {
   d.twin_min = d.twin_force;
 }
 
+void device_set_band_queue(Precond &pre, int32_t waves) {
+  DeviceState &d = *pre.dev;
+  for (auto &e : d.solve_engine) {
+    if (e) wait_tick(*e);
+    e.reset();
+  }
+  d.queue_force = waves < 0 ? -1 : waves;
+}
+
 void device_set_sn_beyond_lds(Precond &pre, int mode) {
   DeviceState &d = *pre.dev;
   for (auto &e : d.solve_engine) {
@@ -3040,6 +3078,7 @@ void device_engine_info(Precond &pre, int k, sn_engine_info *info) {
   info->star_big_lds_bytes = e.sl[1].lds;
   info->star_global = e.sl[2].count;
   info->star_band_prio = e.star_prio;
+  info->star_band_queue = e.star_resident;
   info->star_global_waves = e.star_gteam;
   info->star_big_index_global = e.star_iglobal;
   info->star_twins = e.n_twin;

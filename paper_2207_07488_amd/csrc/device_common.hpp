@@ -105,6 +105,11 @@ struct Row {
 };
 
 // Arguments of the band sweep kernel (see star_band.hpp).
+// counters of the persistent band sweeps' star queues (k_star_queue): up to
+// kQueues queues, one int32 each kQueueStride entries apart, then the count of
+// wavefronts that have left
+constexpr int kQueues = 8, kQueueStride = 64;
+
 struct StarArgs {
   int32_t nstars;
   const int32_t *order;    // stars, longest first
@@ -123,6 +128,8 @@ struct StarArgs {
   int32_t maxn;                              // largest star (positions)
   int32_t use_lds;                           // working vectors in LDS where they fit
   int32_t n_prio;                            // the first n_prio stars of order run at raised issue priority
+  int32_t n_resident;                        // > 0: narrow sweeps as that many persistent wavefronts
+  int32_t *queue;                            // their queue counters (k_star_queue; all 0 at rest)
   void *slots;                               // T, per position and column (position-major)
   // two-chain stars (k_star_twin; order then lists twin ids)
   int32_t unit0;                             // the chains of twin t are units unit0 + 2 t and unit0 + 2 t + 1

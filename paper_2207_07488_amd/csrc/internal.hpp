@@ -181,6 +181,7 @@ void device_set_star_split(Precond &pre, int64_t n_sn);
 void device_set_coarse_launch(Precond &pre, int mode);
 void device_set_sn_beyond_lds(Precond &pre, int mode);
 void device_set_band_twins(Precond &pre, int64_t min_positions);
+void device_set_band_queue(Precond &pre, int32_t waves);
 
 // ---------------------------------------------------------------------------
 // Engine: the device workspace of kc PCG columns (independent recurrences, one

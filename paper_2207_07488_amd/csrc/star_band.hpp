@@ -363,22 +363,11 @@ constexpr int star_min_waves() {
   return !WIDE && (sizeof(T) == 4 ? KC <= 2 : (KC == 1 && LV)) ? 4 : 1;
 }
 
+// one star on one wavefront: gather r[S_j] into its working vector, both
+// sweeps, z_j to the star's slots
 template <typename T, bool WIDE, int KC, bool LV>
-__global__ __launch_bounds__(64, (star_min_waves<T, WIDE, KC, LV>())) void k_star(StarArgs a, const double *__restrict__ r,
-                                                                              const CgScalars *sc, int sel) {
-  extern __shared__ __align__(16) unsigned char star_lds[];
-  if (sel != SEL_ALL) {
-    bool any = false;
-#pragma unroll
-    for (int c = 0; c < KC; ++c) any |= column_selected(sc[c], sel, 0u, c);
-    if (!any) return;
-  }
-  const int wv = blockIdx.x;
-  if (wv >= a.nstars) return;
-  // the wavefronts of the longest stars may win instruction issue over the
-  // shorter stars sharing their SIMD (the engine measures whether it pays)
-  if (wv < a.n_prio) __builtin_amdgcn_s_setprio(3);
-  const int st = a.order[wv];
+__device__ __forceinline__ void band_star(const StarArgs &a, int st, const double *__restrict__ r,
+                                          unsigned char *star_lds) {
   const int n = a.st_n[st], vb = a.st_vb[st], Q = a.st_q[st];
   const int lane = threadIdx.x;
   T *sl = static_cast<T *>(a.slots) + (size_t)vb * KC;
@@ -424,6 +413,70 @@ __global__ __launch_bounds__(64, (star_min_waves<T, WIDE, KC, LV>())) void k_sta
   }
 }
 
+template <int KC>
+__device__ __forceinline__ bool star_columns_idle(const CgScalars *sc, int sel) {
+  if (sel == SEL_ALL) return false;
+  bool any = false;
+#pragma unroll
+  for (int c = 0; c < KC; ++c) any |= column_selected(sc[c], sel, 0u, c);
+  return !any;
+}
+
+// one workgroup (one wavefront) per star of a.order; the hardware dispatcher
+// hands the next star to a SIMD as soon as one finishes
+template <typename T, bool WIDE, int KC, bool LV>
+__global__ __launch_bounds__(64, (star_min_waves<T, WIDE, KC, LV>())) void k_star(StarArgs a, const double *__restrict__ r,
+                                                                              const CgScalars *sc, int sel) {
+  extern __shared__ __align__(16) unsigned char star_lds[];
+  if (star_columns_idle<KC>(sc, sel)) return;
+  const int wv = blockIdx.x;
+  if (wv >= a.nstars) return;
+  // the wavefronts of the longest stars may win instruction issue over the
+  // shorter stars sharing their SIMD (the engine measures whether it pays)
+  if (wv < a.n_prio) __builtin_amdgcn_s_setprio(3);
+  band_star<T, WIDE, KC, LV>(a, a.order[wv], r, star_lds);
+}
+
+// Persistent form of the narrow-window sweeps: gridDim.x resident wavefronts
+// sweep the stars of a.order (sorted by length, longest first). Wavefront w
+// takes star w first, then stars from one of Nq = min(8, gridDim.x) queues in
+// global memory: queue g = w mod Nq hands out the entries g + Nq k of a.order,
+// k counting on from the number of wavefronts of its group (every group has at
+// least one), so that the draws of the wavefronts spread over Nq counters
+// (a.queue[kQueueStride g], each in a line of its own) instead of serialising
+// on one. a.queue[kQueueStride kQueues] counts the wavefronts that have left;
+// every wavefront leaves once its queue is exhausted (no wait on another
+// wavefront), and the last one to leave sets all counters back to zero for
+// the next launch on the stream. Every star is swept exactly as in k_star, so
+// both give the same bits.
+template <typename T, int KC, bool LV>
+__global__ __launch_bounds__(64, (star_min_waves<T, false, KC, LV>())) void k_star_queue(
+    StarArgs a, const double *__restrict__ r, const CgScalars *sc, int sel) {
+  extern __shared__ __align__(16) unsigned char star_lds[];
+  if (star_columns_idle<KC>(sc, sel)) return;
+  int32_t *q = a.queue;
+  const int nqs = min(kQueues, (int)gridDim.x);
+  const int lane = (int)threadIdx.x, w = (int)blockIdx.x, g = w % nqs;
+  const int group = ((int)gridDim.x - g + nqs - 1) / nqs;  // wavefronts of queue g (at least one)
+  int wv = w;
+  while (wv < a.nstars) {
+    if (wv < a.n_prio) __builtin_amdgcn_s_setprio(3);
+    else __builtin_amdgcn_s_setprio(0);
+    band_star<T, false, KC, LV>(a, a.order[wv], r, star_lds);
+    __syncthreads();  // the next star's gather reuses the LDS vector
+    int k = 0;
+    if (lane == 0) k = atomicAdd(q + kQueueStride * g, 1);
+    k = __builtin_amdgcn_readfirstlane(k);
+    wv = g + nqs * (group + k);
+  }
+  if (lane == 0) {
+    __threadfence();
+    if (atomicAdd(q + kQueueStride * kQueues, 1) == (int)gridDim.x - 1) {
+      for (int i = 0; i <= kQueues; ++i) atomicExch(q + kQueueStride * i, 0);
+    }
+  }
+}
+
 template <typename T, int KC>
 void launch_star_t(const StarArgs &a, bool wide, const double *r, const CgScalars *sc, int sel, hipStream_t s) {
   if (a.nstars <= 0) return;
@@ -431,16 +484,22 @@ void launch_star_t(const StarArgs &a, bool wide, const double *r, const CgScalar
   // 32 KB (up to eight columns); the LDS reservation, if larger, limits how many
   // stars share a CU
   const size_t need = ((size_t)a.maxn * KC * sizeof(T) + 15) / 16 * 16;
+  // the persistent form (narrow windows only): a.n_resident wavefronts, at
+  // most one per star
+  const bool queue = !wide && a.n_resident > 0 && a.queue != nullptr;
+  const unsigned nq = (unsigned)std::min(a.n_resident, a.nstars);
   if constexpr (KC <= 8) {
     if (a.use_lds && need <= 32768) {
       const size_t lds = std::max<size_t>((size_t)a.lds_reserve, need);
-      if (wide) hipLaunchKernelGGL((k_star<T, true, KC, true>), dim3(a.nstars), dim3(64), lds, s, a, r, sc, sel);
+      if (queue) hipLaunchKernelGGL((k_star_queue<T, KC, true>), dim3(nq), dim3(64), lds, s, a, r, sc, sel);
+      else if (wide) hipLaunchKernelGGL((k_star<T, true, KC, true>), dim3(a.nstars), dim3(64), lds, s, a, r, sc, sel);
       else hipLaunchKernelGGL((k_star<T, false, KC, true>), dim3(a.nstars), dim3(64), lds, s, a, r, sc, sel);
       return;
     }
   }
   const size_t lds = (size_t)a.lds_reserve;
-  if (wide) hipLaunchKernelGGL((k_star<T, true, KC, false>), dim3(a.nstars), dim3(64), lds, s, a, r, sc, sel);
+  if (queue) hipLaunchKernelGGL((k_star_queue<T, KC, false>), dim3(nq), dim3(64), lds, s, a, r, sc, sel);
+  else if (wide) hipLaunchKernelGGL((k_star<T, true, KC, false>), dim3(a.nstars), dim3(64), lds, s, a, r, sc, sel);
   else hipLaunchKernelGGL((k_star<T, false, KC, false>), dim3(a.nstars), dim3(64), lds, s, a, r, sc, sel);
 }
 

@@ -57,7 +57,7 @@ class EngineInfo(C.Structure):
                 ("star_band_prio", C.c_int32), ("star_global_waves", C.c_int32),
                 ("star_big_index_global", C.c_int32), ("star_twins", C.c_int32), ("coarse_first", C.c_int32),
                 ("coarse_kernel", C.c_int32),
-                ("coarse_late", C.c_int32),
+                ("coarse_late", C.c_int32), ("star_band_queue", C.c_int32),
                 ("sweep_bytes", C.c_int64), ("star_sweep_us", C.c_double),
                 ("b_apply_us", C.c_double)]
 
@@ -126,6 +126,7 @@ SIGNATURES = {
     "sn_precond_set_coarse_launch": (C.c_int, [_P, C.c_int]),
     "sn_precond_set_sn_beyond_lds": (C.c_int, [_P, C.c_int]),
     "sn_precond_set_band_twins": (C.c_int, [_P, _i64]),
+    "sn_precond_set_band_queue": (C.c_int, [_P, _i32]),
     "sn_apply_K": (C.c_int, [_P, C.c_int, _P, _P, C.c_int, _P]),
     "sn_apply_B": (C.c_int, [_P, C.c_int, _P, _P, C.c_int, _P]),
     "sn_apply_K_noalloc": (C.c_int, [_P, C.c_int, _P, _P, _P]),
@@ -380,6 +381,10 @@ class Precond:
     def set_band_twins(self, min_positions):
         """Two-chain band sweeps for stars of at least min_positions (0 never, -1 measured)."""
         _check(lib().sn_precond_set_band_twins(self.h, int(min_positions)))
+
+    def set_band_queue(self, waves):
+        """Narrow band sweeps as one persistent launch of `waves` wavefronts (0 off, -1 measured)."""
+        _check(lib().sn_precond_set_band_queue(self.h, int(waves)))
 
     def set_sn_beyond_lds(self, mode):
         """Supernodal stars beyond LDS: 0 global memory, 1 vectors in LDS, -1 measured."""

@@ -368,6 +368,39 @@ def test_band_twins(S, orc, prec):
     gpre.set_band_twins(-1)
 
 
+@pytest.mark.parametrize("prec", ["FP64", "FP32_STARS"])
+def test_band_queue(S, orc, prec):
+    """The narrow band sweeps as one persistent launch taking the stars from a
+    queue: the same bits as one workgroup per star for 1, 7 and more wavefronts
+    than stars, in one and four columns, eagerly and on every replay of captured
+    graphs (the queue must be back at zero after each launch)."""
+    opre, gpre = _pair(S, orc, "fiber2d_2k", getattr(S, prec))
+    gpre.set_star_split(0)
+    gpre.set_band_twins(0)
+    gpre.set_band_queue(0)
+    R = W.rhs(opre.sys.n, 4, seed=13)
+    z_ref = gpre.apply_B(R[:, 0])
+    Z_ref = gpre.apply_B(R)
+    u_ref, i_ref = gpre.solve(R[:, 1], rtol=1e-8)
+    assert gpre.engine_info(1)["star_band_queue"] == 0
+    tol = 5e-3 if gpre.factor_info()["star_precision"] == S.FP32_STARS else 1e-10
+    assert _close(z_ref, opre.apply_B(R[:, 0]), tol)
+    for waves in (1, 7, 100000):
+        gpre.set_band_queue(waves)
+        for rep in range(2):
+            assert np.array_equal(gpre.apply_B(R[:, 0]), z_ref), (waves, rep)
+            assert np.array_equal(gpre.apply_B(R), Z_ref), (waves, rep)
+        assert gpre.engine_info(1)["star_band_queue"] == waves
+        for rep in range(3):
+            u, i = gpre.solve(R[:, 1], rtol=1e-8, use_graph=True)
+            assert i[0]["iters"] == i_ref[0]["iters"] and np.array_equal(u, u_ref), (waves, rep)
+    gpre.set_band_queue(-1)
+    u, i = gpre.solve(R[:, 1], rtol=1e-8)
+    print("measured band queue:", gpre.engine_info(1)["star_band_queue"], "wavefronts for",
+          gpre.nstars, "stars", flush=True)
+    assert np.array_equal(u, u_ref)
+
+
 def test_residual_replacement(S, orc):
     """Periodic residual replacement (r <- f - K u at the first read-back after
     every 5 iterations; with check_every = 1 a queued block holds at most 4, so
