@@ -664,6 +664,34 @@ struct MmLoad<double> {
     a[3] = v.y;
   }
 };
+// the packed coarse product streams its tiles once per application: loads
+// marked non-temporal, so that they displace less of the local solves' factor
+// streams from the caches
+template <typename TA>
+struct MmLoadNT;
+template <>
+struct MmLoadNT<double> {
+  typedef double d2 __attribute__((ext_vector_type(2)));
+  static __device__ __forceinline__ void load(const double *p, double (&a)[4]) {
+    const d2 u = __builtin_nontemporal_load(reinterpret_cast<const d2 *>(p));
+    const d2 v = __builtin_nontemporal_load(reinterpret_cast<const d2 *>(p + 2));
+    a[0] = u.x;
+    a[1] = u.y;
+    a[2] = v.x;
+    a[3] = v.y;
+  }
+};
+template <>
+struct MmLoadNT<float> {
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ void load(const float *p, float (&a)[4]) {
+    const f4 u = __builtin_nontemporal_load(reinterpret_cast<const f4 *>(p));
+    a[0] = u.x;
+    a[1] = u.y;
+    a[2] = u.z;
+    a[3] = u.w;
+  }
+};
 // FP32 values stay FP32 until the product that uses them converts them
 template <>
 struct MmLoad<float> {
@@ -899,7 +927,7 @@ __global__ __launch_bounds__(64) void k_coarse_sym(const TA *__restrict__ Ks, co
     double bt[QN][NG];
 #pragma unroll
     for (int q = 0; q < QN; ++q) {
-      MmLoad<TA>::load(tp + (size_t)(QN * h + q) * 256, a[q]);
+      MmLoadNT<TA>::load(tp + (size_t)(QN * h + q) * 256, a[q]);
 #pragma unroll
       for (int g = 0; g < NG; ++g) bt[q][g] = rH[(size_t)(64 * I + 4 * (QN * h + q) + k) * KC + col_of(i, g)];
     }
