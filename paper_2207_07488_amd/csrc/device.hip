@@ -375,8 +375,9 @@ __global__ __launch_bounds__(kBlock) void k_spmv(Sell A, const double *__restric
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int e = base + min(c0 + u, len - 1) * kSlice + lane;
-        cl[u] = A.col[e];
-        a[u] = A.val[e] * (c0 + u < len ? 1.0 : 0.0);
+        // the matrix is read once per application: non-temporal loads
+        cl[u] = __builtin_nontemporal_load(A.col + e);
+        a[u] = __builtin_nontemporal_load(A.val + e) * (c0 + u < len ? 1.0 : 0.0);
       }
       Vec<KC> xv[U];
 #pragma unroll
@@ -613,8 +614,8 @@ __global__ __launch_bounds__(kBlock) void k_restrict(const int32_t *__restrict__
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int q = qb + 64 * u, qc = min(q, q1 - 1);
-      idx[u] = dof[qc];
-      wq[u] = w[qc] * (q < q1 ? 1.0 : 0.0);
+      idx[u] = __builtin_nontemporal_load(dof + qc);
+      wq[u] = __builtin_nontemporal_load(w + qc) * (q < q1 ? 1.0 : 0.0);
     }
     Vec<KC> rv[U];
 #pragma unroll
