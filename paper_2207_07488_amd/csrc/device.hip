@@ -476,10 +476,14 @@ __global__ __launch_bounds__(kBlock) void k_reduce(double *z, const double *r, c
     double pw[NV];
 #pragma unroll
     for (int b = 0; b < NV; b += 4) {
-      const int4 c4 = *reinterpret_cast<const int4 *>(Pc + (size_t)i * NV + b);
-      const int4 s4 = *reinterpret_cast<const int4 *>(slot_of + (size_t)i * NV + b);
-      const double2 w0 = *reinterpret_cast<const double2 *>(Pw + (size_t)i * NV + b);
-      const double2 w1 = *reinterpret_cast<const double2 *>(Pw + (size_t)i * NV + b + 2);
+      // the prolongation and slot lists are read once per application:
+      // non-temporal loads
+      typedef int i4 __attribute__((ext_vector_type(4)));
+      typedef double d2 __attribute__((ext_vector_type(2)));
+      const i4 c4 = __builtin_nontemporal_load(reinterpret_cast<const i4 *>(Pc + (size_t)i * NV + b));
+      const i4 s4 = __builtin_nontemporal_load(reinterpret_cast<const i4 *>(slot_of + (size_t)i * NV + b));
+      const d2 w0 = __builtin_nontemporal_load(reinterpret_cast<const d2 *>(Pw + (size_t)i * NV + b));
+      const d2 w1 = __builtin_nontemporal_load(reinterpret_cast<const d2 *>(Pw + (size_t)i * NV + b + 2));
       pc[b] = c4.x;
       pc[b + 1] = c4.y;
       pc[b + 2] = c4.z;
